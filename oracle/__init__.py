@@ -1,0 +1,258 @@
+"""FP64 CPU oracle of the residue-based ACT -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The product path (the HIP
+library and its Python binding) never imports, links or runs anything here,
+and nothing here imports the product path: the two share only the seeded
+workload generator, which holds none of the method's arithmetic.
+
+Two independent implementations live here:
+  * ``act_oracle.c`` (ctypes, built with gcc, FP64, no -ffast-math), the
+    step-by-step oracle: atoms, norms, correlations, arg-max, refinement,
+    matching pursuit, reconstruction;
+  * ``brute.py`` (numpy), an exhaustive dense-dictionary matching pursuit
+    for tiny grids, used to pin the C oracle's selection loop.
+
+Parity status per function (the pins are in tests/test_oracle_pins.py):
+  atoms / norms        pinned: closed-form Gaussian integral, scipy chirp, FFT
+  correlate / argmax   pinned: FFT special case, numpy brute force
+  objective / gradient pinned: central finite differences, scipy L-BFGS-B optimum
+  refine               pinned: off-grid recovery, scipy optimum, monotone J
+  decompose            pinned: MP identities, one-iteration recovery, brute force
+  reconstruct          pinned: a_P + r_P = s
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "act_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_act.so")
+
+FLAG_NONFINITE = 1
+FLAG_REFINE_REJECTED = 2
+FLAG_LINESEARCH = 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Axis(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("count", ctypes.c_int32), ("half_open", ctypes.c_int32)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("fs", ctypes.c_double), ("n", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("ax", _Axis * 4)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        d, i32, i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+        pd, pi32, pi64 = P(d), P(i32), P(i64)
+        pg = P(_Grid)
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_arange_count.argtypes = [d, d, d]
+        lib.oracle_arange_count.restype = i64
+        lib.oracle_axis_value.argtypes = [P(_Axis), i32]
+        lib.oracle_axis_value.restype = d
+        lib.oracle_grid_size.argtypes = [pg]
+        lib.oracle_grid_size.restype = i64
+        lib.oracle_grid_theta.argtypes = [pg, i64, pd]
+        lib.oracle_atom_raw.argtypes = [d, i32, pd, pd]
+        lib.oracle_atom_unit.argtypes = [d, i32, pd, pd]
+        lib.oracle_atom_unit.restype = d
+        lib.oracle_correlate.argtypes = [pg, pd, i64, i64, pd]
+        lib.oracle_norms.argtypes = [pg, i64, i64, pd]
+        lib.oracle_argmax.argtypes = [pd, i64, pd]
+        lib.oracle_argmax.restype = i64
+        lib.oracle_objective.argtypes = [d, i32, pd, pd, pd, pd]
+        lib.oracle_objective.restype = d
+        lib.oracle_refine.argtypes = [d, i32, pd, pd, pd, pd, pd, i32, pd, pd]
+        lib.oracle_refine.restype = ctypes.c_int
+        lib.oracle_refine_box.argtypes = [pg, pd, pd, pd]
+        lib.oracle_refine_scales.argtypes = [d, i32, pd, pd, pd, pd, pd]
+        lib.oracle_refine_many.argtypes = [pg, i32, pd, pd, i32, pd, pd, pi32]
+        lib.oracle_decompose.argtypes = [pg, i32, pd, i32, i32, pd, pd, pd, pd, pi64, pd, pd, pi32]
+        lib.oracle_reconstruct.argtypes = [d, i32, i32, pd, pd, pd]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray, ct=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_grid(grid) -> _Grid:
+    """ctypes grid from a workloads.Grid (fs, n, four axes)."""
+    g = _Grid()
+    g.fs = float(grid.fs)
+    g.n = int(grid.n)
+    for k, a in enumerate(grid.axes):
+        g.ax[k].lo, g.ax[k].hi = float(a.lo), float(a.hi)
+        g.ax[k].count, g.ax[k].half_open = int(a.count), int(bool(a.half_open))
+    return g
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def arange_count(start: float, stop: float, step: float) -> int:
+    return int(_load().oracle_arange_count(start, stop, step))
+
+
+def axis_values(axis) -> np.ndarray:
+    lib = _load()
+    a = _Axis(float(axis.lo), float(axis.hi), int(axis.count), int(bool(axis.half_open)))
+    return np.array([lib.oracle_axis_value(ctypes.byref(a), j) for j in range(axis.count)])
+
+
+def grid_size(grid) -> int:
+    g = make_grid(grid)
+    return int(_load().oracle_grid_size(ctypes.byref(g)))
+
+
+def grid_theta(grid, i: int) -> np.ndarray:
+    g = make_grid(grid)
+    out = np.zeros(4)
+    _load().oracle_grid_theta(ctypes.byref(g), int(i), _p(out))
+    return out
+
+
+def atom_raw(fs: float, n: int, theta) -> np.ndarray:
+    out = np.zeros(n)
+    _load().oracle_atom_raw(float(fs), int(n), _p(_f64(theta)), _p(out))
+    return out
+
+
+def atom_unit(fs: float, n: int, theta) -> Tuple[np.ndarray, float]:
+    out = np.zeros(n)
+    nrm = _load().oracle_atom_unit(float(fs), int(n), _p(_f64(theta)), _p(out))
+    return out, float(nrm)
+
+
+def correlate(grid, r, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+    g = make_grid(grid)
+    if count is None:
+        count = grid_size(grid) - begin
+    r = _f64(r)
+    assert r.shape == (grid.n,)
+    out = np.zeros(count)
+    _load().oracle_correlate(ctypes.byref(g), _p(r), int(begin), int(count), _p(out))
+    return out
+
+
+def norms(grid, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+    g = make_grid(grid)
+    if count is None:
+        count = grid_size(grid) - begin
+    out = np.zeros(count)
+    _load().oracle_norms(ctypes.byref(g), int(begin), int(count), _p(out))
+    return out
+
+
+def argmax(p) -> Tuple[int, float]:
+    p = _f64(p)
+    gap = ctypes.c_double(0.0)
+    i = _load().oracle_argmax(_p(p), p.size, ctypes.byref(gap))
+    return int(i), float(gap.value)
+
+
+def objective(fs: float, theta, r, want_dr: bool = False):
+    """(J, dJ/dtheta[4], dJ/dr or None) of J = <r,g>^2/<g,g>."""
+    r = _f64(r)
+    grad = np.zeros(4)
+    dr = np.zeros(r.size) if want_dr else None
+    J = _load().oracle_objective(float(fs), r.size, _p(_f64(theta)), _p(r), _p(grad),
+                                 _p(dr) if dr is not None else None)
+    return float(J), grad, dr
+
+
+def refine_box(grid):
+    g = make_grid(grid)
+    step, lo, hi = np.zeros(4), np.zeros(4), np.zeros(4)
+    _load().oracle_refine_box(ctypes.byref(g), _p(step), _p(lo), _p(hi))
+    return step, lo, hi
+
+
+def refine_scales(grid, theta0) -> np.ndarray:
+    step, lo, hi = refine_box(grid)
+    h = np.zeros(4)
+    _load().oracle_refine_scales(float(grid.fs), int(grid.n), _p(_f64(theta0)), _p(step), _p(lo),
+                                 _p(hi), _p(h))
+    return h
+
+
+def refine(grid, r, theta0, steps: int = 30):
+    """Refined theta, J(theta), flags for one residual and start point."""
+    step, lo, hi = refine_box(grid)
+    th = np.zeros(4)
+    J = ctypes.c_double(0.0)
+    fl = _load().oracle_refine(float(grid.fs), int(grid.n), _p(_f64(r)), _p(_f64(theta0)),
+                               _p(step), _p(lo), _p(hi), int(steps), _p(th), ctypes.byref(J))
+    return th, float(J.value), int(fl)
+
+
+def refine_many(grid, r, theta0, steps: int = 30):
+    r = _f64(r)
+    theta0 = _f64(theta0)
+    m = r.shape[0]
+    g = make_grid(grid)
+    th = np.zeros((m, 4))
+    J = np.zeros(m)
+    fl = np.zeros(m, dtype=np.int32)
+    _load().oracle_refine_many(ctypes.byref(g), m, _p(r), _p(theta0), int(steps), _p(th), _p(J),
+                               _p(fl, ctypes.c_int32))
+    return th, J, fl
+
+
+def decompose(grid, signals, order: int, refine_steps: int = 30):
+    """Residue-based MP of each row of ``signals`` ([B, N] or [N])."""
+    s = _f64(np.atleast_2d(signals))
+    B, n = s.shape
+    assert n == grid.n
+    g = make_grid(grid)
+    out = dict(
+        resid=np.zeros((B, n)), approx=np.zeros((B, n)), theta=np.zeros((B, order, 4)),
+        coef=np.zeros((B, order)), index=np.zeros((B, order), dtype=np.int64),
+        energy=np.zeros((B, order + 1)), gap=np.zeros((B, order)),
+        flags=np.zeros(B, dtype=np.int32))
+    _load().oracle_decompose(ctypes.byref(g), B, _p(s), int(order), int(refine_steps),
+                             _p(out["resid"]), _p(out["approx"]), _p(out["theta"]),
+                             _p(out["coef"]), _p(out["index"], ctypes.c_int64),
+                             _p(out["energy"]), _p(out["gap"]), _p(out["flags"], ctypes.c_int32))
+    return out
+
+
+def reconstruct(fs: float, n: int, theta, coef) -> np.ndarray:
+    theta = _f64(theta).reshape(-1, 4)
+    coef = _f64(coef).reshape(-1)
+    out = np.zeros(n)
+    _load().oracle_reconstruct(float(fs), int(n), theta.shape[0], _p(theta), _p(coef), _p(out))
+    return out
