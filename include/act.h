@@ -1,0 +1,198 @@
+/*
+ * act.h -- C ABI of the MI355X (gfx950) residue-based Adaptive Chirplet
+ * Transform library (libact.so).
+ *
+ * The library decomposes real signals as s ~ sum_k c_k g(theta_k*) by matching
+ * pursuit on the residual (Sec. III-A, Eq. (3)-(4)): for every order it
+ * correlates the residual with a unit-norm Gaussian chirplet dictionary
+ * (Eq. (1), real part, sampled on a 4-D grid of t_c, f_c, c, log dt), takes
+ * the arg-max of |<g_i, r_k>|, refines the winner's parameters by maximising
+ * <g(theta), r_k>^2 / <g,g>, computes c_k = <g*, r_k> with the refined unit
+ * atom, and subtracts the projection.  Several channels are batched in one
+ * call, as in the paper's stacked projection P = D X^T (Sec. IV-A, Sec. V-A).
+ *
+ * Conventions
+ *  - Units are SI: t_c in s, f_c in Hz, c in Hz/s (the coefficient of
+ *    (t - t_c)^2 in Eq. (1)), logdt = ln(dt / 1 s).  Samples are at t_n = n/fs.
+ *  - theta is stored as double[4] = (t_c, f_c, c, logdt).
+ *  - An axis is (lo, hi, count, half_open); its j-th value is
+ *    lo + j*((hi-lo)/d) with d = count (half_open != 0) or count-1 (the last
+ *    value of a closed axis is hi exactly; a one-value axis is lo).
+ *    A (start, stop, step) range as printed in the paper's parameter table is
+ *    the half-open axis (start, start + count*step, ceil((stop-start)/step), 1).
+ *  - Dictionary index i = ((i_tc*n_fc + i_fc)*n_c + i_c)*n_ld + i_ld; ties in
+ *    the arg-max go to the lowest index.
+ *  - Memory: every pointer argument named *_dev is device memory owned by the
+ *    caller and must stay valid until the work enqueued on `stream` completes.
+ *    The plan owns its tables and workspace.  `stream` is a hipStream_t (NULL
+ *    = the null stream).  Calls other than act_plan / act_plan_destroy only
+ *    enqueue work and return; errors found on the host are returned before
+ *    anything is enqueued.  Device-side conditions are reported per channel in
+ *    flags (ACT_FLAG_*), never by aborting.
+ *  - A plan is not re-entrant: do not use one plan from two streams at once.
+ *  - No function throws or aborts; on error the status says why and
+ *    act_last_error() returns a message (thread-local).
+ */
+#ifndef ACT_H
+#define ACT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ACT_OK = 0,
+    ACT_ERR_INVALID = 1,     /* bad argument (message in act_last_error) */
+    ACT_ERR_NOMEM = 2,       /* device allocation or byte budget exceeded */
+    ACT_ERR_HIP = 3,         /* a HIP runtime call failed */
+    ACT_ERR_UNSUPPORTED = 4  /* valid request this build does not implement */
+} act_status;
+
+typedef struct {
+    double lo, hi;
+    int32_t count, half_open;
+} act_axis;
+
+/* Sampling rate, signal length and the four parameter axes of a dictionary
+ * (Sec. III-A "sampling the parameter space within user-specified ranges";
+ * Table "Parameter ranges"). */
+typedef struct {
+    double fs_hz;
+    int32_t n_samples;
+    int32_t reserved;
+    act_axis tc_s, fc_hz, c_hz_per_s, logdt_ln_s;
+} act_grid;
+
+/* Dictionary source of the coarse search. */
+enum {
+    ACT_DICT_SYNTH = 0, /* atoms synthesised on the device inside the search */
+    ACT_DICT_TABLE = 1  /* atoms streamed from an HBM-resident table built by act_plan */
+};
+
+/* Arithmetic of the coarse search (rescoring, refinement, coefficients and
+ * updates are FP64 in every mode). */
+enum {
+    ACT_PREC_F64 = 0,  /* FP64 correlation (ACT_DICT_SYNTH only) */
+    ACT_PREC_F32 = 1,  /* FP32 correlation, certified FP64 rescoring of the candidates */
+    ACT_PREC_BF16 = 2  /* BF16 x BF16 -> FP32 MFMA correlation, certified FP64 rescoring */
+};
+
+/* Per-channel flags written by act_decompose / act_refine. */
+enum {
+    ACT_FLAG_NONFINITE = 1,       /* the input channel holds a NaN or an infinity */
+    ACT_FLAG_REFINE_REJECTED = 2, /* refinement would lower J; the grid theta was kept */
+    ACT_FLAG_CAND_OVERFLOW = 8,   /* more atoms than the candidate capacity lay inside the
+                                     certified margin; the search was re-run once with the
+                                     exact threshold (set only if even that overflowed) */
+    ACT_FLAG_RAGGED_EMPTY = 16    /* a ragged signal has no time centre (length < divisor) */
+};
+
+typedef struct {
+    act_grid grid;          /* ragged plans: the t_c axis is ignored, see ragged_tc_div */
+    int32_t dict;           /* ACT_DICT_* */
+    int32_t prec;           /* ACT_PREC_* */
+    int32_t max_batch;      /* most channels one call may pass (>= 1) */
+    int32_t cand_cap;       /* candidate list capacity per channel; 0 = 4096 */
+    int32_t refine_steps;   /* L-BFGS iterations per order in act_decompose; 0 = none */
+    int32_t ragged;         /* 1: channels have their own lengths (len_dev/off_dev) and
+                               grids with floor(len/ragged_tc_div) time centres */
+    int32_t ragged_tc_div;  /* samples per time centre of a ragged plan (e.g. 32) */
+    int32_t reserved;
+} act_plan_desc;
+
+typedef struct act_plan_s* act_plan_t;
+
+/* Builds a plan: validates the grid, uploads the axis values, and for
+ * ACT_DICT_TABLE synthesises every atom in FP64 on the device, normalises it
+ * to unit l2 norm over the n_samples present (Sec. III-A "normalized to unit
+ * l2 norm prior to search") and stores it as FP32 or BF16 rows; for
+ * ACT_DICT_SYNTH it builds the small factor tables the search kernels combine.
+ * Synchronises `stream` before returning.  On success *out owns all plan
+ * memory until act_plan_destroy.  Errors: ACT_ERR_INVALID (counts < 1, n < 1,
+ * fs <= 0, non-finite or reversed bounds, unknown dict/prec, F64 with a
+ * table, a table larger than the device), ACT_ERR_NOMEM, ACT_ERR_HIP. */
+act_status act_plan(const act_plan_desc* desc, void* stream, act_plan_t* out);
+
+/* Frees everything the plan owns (after synchronising its last stream).
+ * NULL is ignored. */
+void act_plan_destroy(act_plan_t plan);
+
+/* Plan facts: ACT_Q_ATOMS (dictionary size), ACT_Q_TABLE_BYTES (table bytes,
+ * 0 for synthesis), ACT_Q_N_PAD (padded row length of tables and shadows),
+ * ACT_Q_CAND_CAP, ACT_Q_WORKSPACE_BYTES.  Returns -1 for an unknown key. */
+enum { ACT_Q_ATOMS = 0, ACT_Q_TABLE_BYTES = 1, ACT_Q_N_PAD = 2, ACT_Q_CAND_CAP = 3,
+       ACT_Q_WORKSPACE_BYTES = 4 };
+int64_t act_plan_query(act_plan_t plan, int32_t key);
+
+/* Residue-based matching pursuit of `batch` channels for `order` orders
+ * (Sec. III-A, Fig. "simplified residue-driven ACT iteration"):
+ *   resid_dev   in: the signals, out: the residuals r_P.  f64, channel b at
+ *               [b*n_samples, (b+1)*n_samples) for a plain plan, at
+ *               [off[b], off[b]+len[b]) for a ragged plan.
+ *   approx_dev  out: a_P (same layout), or NULL.
+ *   len_dev, off_dev  ragged plans only (int32 lengths, int64 offsets); NULL otherwise.
+ *   theta_dev   out: [batch][order][4] refined parameters.
+ *   coef_dev    out: [batch][order] coefficients c_k = <g*, r_k>.
+ *   index_dev   out: [batch][order] flat grid index of the coarse winner.
+ *   energy_dev  out: [batch][order+1] |r_k|^2 (k = 0 is |s|^2); the normalised
+ *               residue of Eq. (5) is energy[k]/energy[0].
+ *   gap_dev     out: [batch][order] lower bound of (|p|_(1)-|p|_(2))/|p|_(1),
+ *               the relative margin of the coarse winner, or NULL.
+ *   flags_dev   out: [batch] ACT_FLAG_* bits.
+ * The whole pass runs on the device; the host enqueues it and returns.
+ * Errors: ACT_ERR_INVALID (batch outside [1, max_batch], order < 1, NULL
+ * required pointer, ragged pointers missing or given to a plain plan). */
+act_status act_decompose(act_plan_t plan, int32_t batch, const int32_t* len_dev,
+                         const int64_t* off_dev, double* resid_dev, double* approx_dev,
+                         int32_t order, double* theta_dev, double* coef_dev, int64_t* index_dev,
+                         double* energy_dev, double* gap_dev, int32_t* flags_dev, void* stream);
+
+/* Continuous refinement alone (Sec. III-A "BFGS refinement"), for m
+ * independent problems: from theta0 maximise J(theta) = <r, g(theta)>^2 /
+ * <g(theta), g(theta)> with the plan's L-BFGS (box = the plan grid's hull,
+ * coordinates scaled by the atom's resolution, at most `steps` iterations).
+ *   resid_dev [m][n_samples] f64, theta0_dev [m][4], theta_dev [m][4] out,
+ *   value_dev [m] out (J at theta), flags_dev [m] out or NULL.
+ * Errors: ACT_ERR_INVALID (m < 1, steps < 0, NULL pointers, ragged plan). */
+act_status act_refine(act_plan_t plan, int32_t m, const double* resid_dev,
+                      const double* theta0_dev, int32_t steps, double* theta_dev,
+                      double* value_dev, int32_t* flags_dev, void* stream);
+
+/* Forward and adjoint of the refinement objective for m (residual, theta)
+ * pairs: value J = <r,g>^2/<g,g>, dtheta = dJ/d(t_c, f_c, c, logdt) and
+ * optionally dr = dJ/dr = 2 <r, g_hat> g_hat.  dtype ACT_PREC_F64 (resid and
+ * dr are double) or ACT_PREC_F32 (resid and dr are float; theta, value and
+ * dtheta are double, the arithmetic is FP32).
+ *   resid_dev [m][n_samples], theta_dev [m][4], value_dev [m],
+ *   dtheta_dev [m][4], dr_dev [m][n_samples] or NULL.
+ * Errors: ACT_ERR_INVALID. */
+act_status act_value_and_grad(act_plan_t plan, int32_t m, int32_t dtype, const void* resid_dev,
+                              const double* theta_dev, double* value_dev, double* dtheta_dev,
+                              void* dr_dev, void* stream);
+
+/* Approximation sum_k c_k g_hat(theta_k) per channel (Eq. (3)), FP64.
+ * theta_dev [batch][order][4], coef_dev [batch][order]; out_dev has the
+ * layout of resid_dev in act_decompose (len/off for ragged plans).
+ * Errors: ACT_ERR_INVALID. */
+act_status act_reconstruct(act_plan_t plan, int32_t batch, int32_t order, const double* theta_dev,
+                           const double* coef_dev, const int32_t* len_dev, const int64_t* off_dev,
+                           double* out_dev, void* stream);
+
+/* Coarse-search scores in the plan's arithmetic, for checking: score[b][j] =
+ * <g_hat_{atom_begin+j}, r_b> for j < atom_count, as the search computes it
+ * (FP32 result for F32/BF16 plans, written as double).  resid_dev is
+ * [batch][n_samples] f64 (plain plans only).
+ * Errors: ACT_ERR_INVALID (range outside the dictionary, ragged plan). */
+act_status act_correlate(act_plan_t plan, int32_t batch, const double* resid_dev,
+                         int64_t atom_begin, int64_t atom_count, double* score_dev, void* stream);
+
+const char* act_status_string(act_status status);
+const char* act_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACT_H */

@@ -244,14 +244,20 @@ double oracle_objective(double fs, int32_t n, const double theta[4], const doubl
  *     memory 8 pairs; H0 = gamma*I, gamma = s'y/y'y of the newest pair
  *     (1 when empty); a pair is stored only if s'y > 1e-12 |s| |y|.
  *     Projected gradient pg: component j is zeroed when u_j sits on a bound
- *     and -g_j points outwards.  Stop when max|pg| <= 1e-10 * max(1, J).
+ *     and -g_j points outwards.  Stop when max|pg| <= 1e-11 * max(1, J).
  *     Direction d = two-loop(-g); components pointing out of the box at an
  *     active bound are zeroed; if g'd >= 0, d = -pg.
  *     Step: alpha0 = 1 when the memory holds a pair, else min(1, 1/max|d|);
- *     backtracking Armijo (c1 = 1e-4, alpha halves, at most 30 trials) on the
- *     projected point P(u + alpha d); a trial is accepted when
- *     dec = g'(u_new - u) < 0 and f_new <= f + c1 * dec.  A failed line
- *     search (FP64 can no longer resolve a decrease) ends the run.
+ *     backtracking (alpha halves, at most 30 trials) on the projected point
+ *     u_new = P(u + alpha d), with p = u_new - u, dec = g'p, dnew = g_new'p.
+ *     A trial is accepted when dec < 0 and either
+ *       Armijo:             f_new <= f + c1 dec (c1 = 1e-4), or
+ *       approximate Wolfe:  f_new <= f + 1e-12 |f| and
+ *                           0.9 dec <= dnew <= -0.8 dec
+ *     (Hager and Zhang's approximate Wolfe conditions with delta = 0.1,
+ *     sigma = 0.9), which keeps the iteration converging on the gradient once
+ *     FP64 no longer resolves the change of J.  A failed line search ends the
+ *     run.
  *   At most `steps` iterations.  The result is accepted only if
  *   J(theta*) >= J(theta0); otherwise theta0 is kept.
  * Returns a flag word (ORACLE_FLAG_*); writes theta* and J(theta*).
@@ -325,7 +331,7 @@ int oracle_refine(double fs, int32_t n, const double* r, const double theta0[4],
             if (fabs(pg[j]) > pgmax) pgmax = fabs(pg[j]);
         }
         double Jc = -f;
-        if (pgmax <= 1e-10 * (Jc > 1.0 ? Jc : 1.0)) break;
+        if (pgmax <= 1e-11 * (Jc > 1.0 ? Jc : 1.0)) break;
         /* two-loop recursion, newest pair first */
         double d[4], al[LBFGS_M];
         for (int j = 0; j < 4; ++j) d[j] = -g[j];
@@ -367,9 +373,14 @@ int oracle_refine(double fs, int32_t n, const double* r, const double theta0[4],
                 un[j] = v;
             }
             fn = refine_eval(fs, n, r, theta0, h, un, gn);
-            double dec = 0.0;
-            for (int j = 0; j < 4; ++j) dec += g[j] * (un[j] - u[j]);
-            if (dec < 0.0 && fn <= f + 1e-4 * dec) {
+            double dec = 0.0, dnew = 0.0;
+            for (int j = 0; j < 4; ++j) {
+                dec += g[j] * (un[j] - u[j]);
+                dnew += gn[j] * (un[j] - u[j]);
+            }
+            int armijo = fn <= f + 1e-4 * dec;
+            int approx_wolfe = fn <= f + 1e-12 * fabs(f) && dnew >= 0.9 * dec && dnew <= -0.8 * dec;
+            if (dec < 0.0 && (armijo || approx_wolfe)) {
                 ok = 1;
                 break;
             }

@@ -1,0 +1,276 @@
+"""Python binding of libact (the C ABI in include/act.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory and the current stream.  There is no CPU
+fallback: if libact.so is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+from .workloads import Grid
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libact.so")
+
+ACT_OK, ACT_ERR_INVALID, ACT_ERR_NOMEM, ACT_ERR_HIP, ACT_ERR_UNSUPPORTED = range(5)
+ACT_DICT_SYNTH, ACT_DICT_TABLE = 0, 1
+ACT_PREC_F64, ACT_PREC_F32, ACT_PREC_BF16 = 0, 1, 2
+FLAG_NONFINITE, FLAG_REFINE_REJECTED, FLAG_CAND_OVERFLOW, FLAG_RAGGED_EMPTY = 1, 2, 8, 16
+Q_ATOMS, Q_TABLE_BYTES, Q_N_PAD, Q_CAND_CAP, Q_WORKSPACE_BYTES = range(5)
+
+_DICTS = {"synth": ACT_DICT_SYNTH, "table": ACT_DICT_TABLE}
+_PRECS = {"f64": ACT_PREC_F64, "f32": ACT_PREC_F32, "bf16": ACT_PREC_BF16}
+
+
+class ActError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class _Axis(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("count", ctypes.c_int32), ("half_open", ctypes.c_int32)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("fs_hz", ctypes.c_double), ("n_samples", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tc_s", _Axis), ("fc_hz", _Axis),
+                ("c_hz_per_s", _Axis), ("logdt_ln_s", _Axis)]
+
+
+class _PlanDesc(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("dict", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
+                ("refine_steps", ctypes.c_int32), ("ragged", ctypes.c_int32),
+                ("ragged_tc_div", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_decompose", "act_refine",
+           "act_value_and_grad", "act_reconstruct", "act_correlate", "act_status_string",
+           "act_last_error")
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libact.so; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2607_16629_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.act_plan.argtypes = [ctypes.POINTER(_PlanDesc), vp, ctypes.POINTER(vp)]
+    lib.act_plan.restype = ctypes.c_int
+    lib.act_plan_destroy.argtypes = [vp]
+    lib.act_plan_destroy.restype = None
+    lib.act_plan_query.argtypes = [vp, i32]
+    lib.act_plan_query.restype = i64
+    lib.act_decompose.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.act_decompose.restype = ctypes.c_int
+    lib.act_refine.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp]
+    lib.act_refine.restype = ctypes.c_int
+    lib.act_value_and_grad.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.act_value_and_grad.restype = ctypes.c_int
+    lib.act_reconstruct.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.act_reconstruct.restype = ctypes.c_int
+    lib.act_correlate.argtypes = [vp, i32, vp, i64, i64, vp, vp]
+    lib.act_correlate.restype = ctypes.c_int
+    lib.act_status_string.argtypes = [ctypes.c_int]
+    lib.act_status_string.restype = ctypes.c_char_p
+    lib.act_last_error.argtypes = []
+    lib.act_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != ACT_OK:
+        lib = load()
+        raise ActError(status, f"{lib.act_status_string(status).decode()}: {lib.act_last_error().decode()}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _device_tensor(x, dtype) -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=dtype)
+    if not t.is_cuda:
+        t = t.cuda()
+    return t.contiguous()
+
+
+def make_desc(grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: int = 1,
+              cand_cap: int = 0, refine_steps: int = 30, ragged: bool = False,
+              ragged_tc_div: int = 32) -> _PlanDesc:
+    g = _Grid()
+    g.fs_hz = float(grid.fs)
+    g.n_samples = int(grid.n)
+    for name, a in zip(("tc_s", "fc_hz", "c_hz_per_s", "logdt_ln_s"), grid.axes):
+        setattr(g, name, _Axis(float(a.lo), float(a.hi), int(a.count), int(bool(a.half_open))))
+    desc = _PlanDesc()
+    desc.grid = g
+    desc.dict = _DICTS[dict_]
+    desc.prec = _PRECS[prec]
+    desc.max_batch = int(max_batch)
+    desc.cand_cap = int(cand_cap)
+    desc.refine_steps = int(refine_steps)
+    desc.ragged = int(bool(ragged))
+    desc.ragged_tc_div = int(ragged_tc_div)
+    return desc
+
+
+class Plan:
+    """Owns an act_plan_t.  See include/act.h for every call's contract."""
+
+    def __init__(self, grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: int = 1,
+                 cand_cap: int = 0, refine_steps: int = 30):
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libact needs a ROCm GPU; none is visible")
+        self.grid = grid
+        self.dict = dict_
+        self.prec = prec
+        self.max_batch = max_batch
+        self.refine_steps = refine_steps
+        self._desc = make_desc(grid, dict_, prec, max_batch, cand_cap, refine_steps)
+        h = ctypes.c_void_p()
+        _check(lib.act_plan(ctypes.byref(self._desc), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().act_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, key: int) -> int:
+        return int(load().act_plan_query(self._h, key))
+
+    @property
+    def atoms(self) -> int:
+        return self.query(Q_ATOMS)
+
+    @property
+    def n_pad(self) -> int:
+        return self.query(Q_N_PAD)
+
+    @property
+    def table_bytes(self) -> int:
+        return self.query(Q_TABLE_BYTES)
+
+    def alloc_outputs(self, batch: int, order: int, approx: bool = True):
+        dev = torch.device("cuda")
+        n = self.grid.n
+        return dict(
+            approx=torch.empty(batch, n, dtype=torch.float64, device=dev) if approx else None,
+            theta=torch.empty(batch, order, 4, dtype=torch.float64, device=dev),
+            coef=torch.empty(batch, order, dtype=torch.float64, device=dev),
+            index=torch.empty(batch, order, dtype=torch.int64, device=dev),
+            energy=torch.empty(batch, order + 1, dtype=torch.float64, device=dev),
+            gap=torch.empty(batch, order, dtype=torch.float64, device=dev),
+            flags=torch.empty(batch, dtype=torch.int32, device=dev))
+
+    def act_decompose(self, resid: torch.Tensor, order: int, out: dict):
+        """In-place on `resid` ([B, N] f64 CUDA): signals in, residuals out."""
+        assert resid.is_cuda and resid.dtype == torch.float64 and resid.is_contiguous()
+        B = resid.shape[0]
+        _check(load().act_decompose(
+            self._h, B, None, None, _ptr(resid), _ptr(out["approx"]), int(order),
+            _ptr(out["theta"]), _ptr(out["coef"]), _ptr(out["index"]), _ptr(out["energy"]),
+            _ptr(out["gap"]), _ptr(out["flags"]), _stream()))
+        return out
+
+    def decompose(self, signals, order: int, approx: bool = True) -> dict:
+        resid = _device_tensor(signals, torch.float64).reshape(-1, self.grid.n).clone()
+        out = self.alloc_outputs(resid.shape[0], order, approx)
+        self.act_decompose(resid, order, out)
+        out["resid"] = resid
+        return out
+
+    def act_refine(self, resid, theta0, steps: int):
+        resid = _device_tensor(resid, torch.float64).reshape(-1, self.grid.n)
+        theta0 = _device_tensor(theta0, torch.float64).reshape(-1, 4)
+        m = resid.shape[0]
+        theta = torch.empty(m, 4, dtype=torch.float64, device=resid.device)
+        value = torch.empty(m, dtype=torch.float64, device=resid.device)
+        flags = torch.empty(m, dtype=torch.int32, device=resid.device)
+        _check(load().act_refine(self._h, m, _ptr(resid), _ptr(theta0), int(steps), _ptr(theta),
+                                 _ptr(value), _ptr(flags), _stream()))
+        return theta, value, flags
+
+    def act_value_and_grad(self, resid: torch.Tensor, theta: torch.Tensor, want_dr: bool = True):
+        """J, dJ/dtheta, dJ/dr for each row; resid is f64 or f32 [m, N]."""
+        assert resid.is_cuda and resid.is_contiguous() and resid.dtype in (torch.float64, torch.float32)
+        theta = _device_tensor(theta, torch.float64).reshape(-1, 4)
+        m = resid.shape[0]
+        dtype = ACT_PREC_F64 if resid.dtype == torch.float64 else ACT_PREC_F32
+        value = torch.empty(m, dtype=torch.float64, device=resid.device)
+        dtheta = torch.empty(m, 4, dtype=torch.float64, device=resid.device)
+        dr = torch.empty_like(resid) if want_dr else None
+        _check(load().act_value_and_grad(self._h, m, dtype, _ptr(resid), _ptr(theta), _ptr(value),
+                                         _ptr(dtheta), _ptr(dr), _stream()))
+        return value, dtheta, dr
+
+    def act_reconstruct(self, theta, coef) -> torch.Tensor:
+        theta = _device_tensor(theta, torch.float64)
+        coef = _device_tensor(coef, torch.float64)
+        B, order = coef.shape
+        out = torch.empty(B, self.grid.n, dtype=torch.float64, device=coef.device)
+        _check(load().act_reconstruct(self._h, B, order, _ptr(theta), _ptr(coef), None, None,
+                                      _ptr(out), _stream()))
+        return out
+
+    def act_correlate(self, resid, begin: int, count: int) -> torch.Tensor:
+        resid = _device_tensor(resid, torch.float64).reshape(-1, self.grid.n)
+        B = resid.shape[0]
+        out = torch.empty(B, count, dtype=torch.float64, device=resid.device)
+        _check(load().act_correlate(self._h, B, _ptr(resid), int(begin), int(count), _ptr(out),
+                                    _stream()))
+        return out
+
+
+def act_plan(grid: Grid, **kw) -> Plan:
+    return Plan(grid, **kw)
+
+
+class ChirpletObjective(torch.autograd.Function):
+    """J(theta; r) = <r, g(theta)>^2 / <g, g> per row, with the hand-written
+    forward and adjoint kernels (act_value_and_grad) as forward and backward."""
+
+    @staticmethod
+    def forward(ctx, resid: torch.Tensor, theta: torch.Tensor, plan: Plan):
+        value, dtheta, dr = plan.act_value_and_grad(resid.contiguous(), theta.detach(),
+                                                    want_dr=resid.requires_grad)
+        ctx.save_for_backward(dtheta, dr if dr is not None else torch.empty(0, device=resid.device))
+        ctx.has_dr = dr is not None
+        return value.to(theta.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        dtheta, dr = ctx.saved_tensors
+        g = grad_out.to(torch.float64)
+        d_theta = (g[:, None] * dtheta).to(grad_out.dtype)
+        d_resid = (g[:, None].to(dr.dtype) * dr) if ctx.has_dr else None
+        return d_resid, d_theta, None
+
+
+def chirplet_objective(resid: torch.Tensor, theta: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return ChirpletObjective.apply(resid, theta, plan)

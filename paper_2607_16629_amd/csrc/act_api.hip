@@ -1,0 +1,134 @@
+// act_api.hip -- C ABI entry points: argument checks on the host, then the
+// stream-ordered launch sequence of the matching pursuit.
+#include <string>
+
+#include "act_common.h"
+
+namespace act {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace act
+
+using namespace act;
+
+extern "C" const char* act_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* act_status_string(act_status s) {
+    switch (s) {
+        case ACT_OK: return "ACT_OK";
+        case ACT_ERR_INVALID: return "ACT_ERR_INVALID";
+        case ACT_ERR_NOMEM: return "ACT_ERR_NOMEM";
+        case ACT_ERR_HIP: return "ACT_ERR_HIP";
+        case ACT_ERR_UNSUPPORTED: return "ACT_ERR_UNSUPPORTED";
+        default: return "ACT_ERR_UNKNOWN";
+    }
+}
+
+// One order of the residue-based pursuit for every channel (Sec. III-A, Fig.
+// "simplified residue-driven ACT iteration"):
+//   search (fused certified candidates) -> overflow check -> exact-threshold
+//   search of overflowed channels -> FP64 rescoring -> select, refine,
+//   coefficient, update.
+static act_status enqueue_order(act_plan_s* p, int batch, int k, int order, double* resid,
+                                double* approx, double* theta, double* coef, long long* index,
+                                double* energy, double* gap, int* flags, hipStream_t s) {
+    act_status st;
+    if ((st = launch_search(p, batch, 0, s)) != ACT_OK) return st;
+    if ((st = launch_overflow_check(p, batch, s)) != ACT_OK) return st;
+    if ((st = launch_search(p, batch, 1, s)) != ACT_OK) return st;
+    if ((st = launch_rescore(p, batch, resid, s)) != ACT_OK) return st;
+    return launch_select_refine_update(p, batch, k, order, resid, approx, theta, coef, index, energy,
+                                       gap, flags, s);
+}
+
+extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* len_dev,
+                                    const int64_t* off_dev, double* resid_dev, double* approx_dev,
+                                    int32_t order, double* theta_dev, double* coef_dev,
+                                    int64_t* index_dev, double* energy_dev, double* gap_dev,
+                                    int32_t* flags_dev, void* stream) {
+    ACT_REQUIRE(p != nullptr, "act_decompose: plan is NULL");
+    ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, "act_decompose: batch outside [1, max_batch]");
+    ACT_REQUIRE(order >= 1, "act_decompose: order must be >= 1");
+    ACT_REQUIRE(resid_dev && theta_dev && coef_dev && index_dev && energy_dev && flags_dev,
+                "act_decompose: NULL output pointer");
+    if (p->desc.ragged) {
+        ACT_REQUIRE(len_dev && off_dev, "act_decompose: ragged plans need len_dev and off_dev");
+    } else {
+        ACT_REQUIRE(!len_dev && !off_dev, "act_decompose: len_dev/off_dev are for ragged plans only");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    p->last_stream = s;
+    p->search_resid = resid_dev;
+    act_status st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, s);
+    if (st != ACT_OK) return st;
+    for (int k = 0; k < order; ++k) {
+        st = enqueue_order(p, batch, k, order, resid_dev, approx_dev, theta_dev, coef_dev,
+                           (long long*)index_dev, energy_dev, gap_dev, flags_dev, s);
+        if (st != ACT_OK) return st;
+    }
+    return ACT_OK;
+}
+
+extern "C" act_status act_refine(act_plan_t p, int32_t m, const double* resid_dev,
+                                 const double* theta0_dev, int32_t steps, double* theta_dev,
+                                 double* value_dev, int32_t* flags_dev, void* stream) {
+    ACT_REQUIRE(p != nullptr, "act_refine: plan is NULL");
+    ACT_REQUIRE(!p->desc.ragged, "act_refine: ragged plans are not supported");
+    ACT_REQUIRE(m >= 1 && steps >= 0, "act_refine: m must be >= 1 and steps >= 0");
+    ACT_REQUIRE(resid_dev && theta0_dev && theta_dev && value_dev, "act_refine: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    p->last_stream = s;
+    return launch_refine_many(p, m, resid_dev, theta0_dev, steps, theta_dev, value_dev, flags_dev, s);
+}
+
+extern "C" act_status act_value_and_grad(act_plan_t p, int32_t m, int32_t dtype,
+                                         const void* resid_dev, const double* theta_dev,
+                                         double* value_dev, double* dtheta_dev, void* dr_dev,
+                                         void* stream) {
+    ACT_REQUIRE(p != nullptr, "act_value_and_grad: plan is NULL");
+    ACT_REQUIRE(!p->desc.ragged, "act_value_and_grad: ragged plans are not supported");
+    ACT_REQUIRE(m >= 1, "act_value_and_grad: m must be >= 1");
+    ACT_REQUIRE(dtype == ACT_PREC_F64 || dtype == ACT_PREC_F32, "act_value_and_grad: dtype must be F64 or F32");
+    ACT_REQUIRE(resid_dev && theta_dev && value_dev && dtheta_dev, "act_value_and_grad: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    p->last_stream = s;
+    return launch_value_and_grad(p, m, dtype, resid_dev, theta_dev, value_dev, dtheta_dev, dr_dev, s);
+}
+
+extern "C" act_status act_reconstruct(act_plan_t p, int32_t batch, int32_t order,
+                                      const double* theta_dev, const double* coef_dev,
+                                      const int32_t* len_dev, const int64_t* off_dev,
+                                      double* out_dev, void* stream) {
+    ACT_REQUIRE(p != nullptr, "act_reconstruct: plan is NULL");
+    ACT_REQUIRE(batch >= 1 && order >= 0, "act_reconstruct: batch must be >= 1, order >= 0");
+    ACT_REQUIRE(theta_dev && coef_dev && out_dev, "act_reconstruct: NULL pointer");
+    if (p->desc.ragged) {
+        set_error("act_reconstruct: ragged plans are not implemented in this build");
+        return ACT_ERR_UNSUPPORTED;
+    }
+    ACT_REQUIRE(!len_dev && !off_dev, "act_reconstruct: len_dev/off_dev are for ragged plans only");
+    hipStream_t s = (hipStream_t)stream;
+    p->last_stream = s;
+    return launch_reconstruct(p, batch, order, theta_dev, coef_dev, out_dev, s);
+}
+
+extern "C" act_status act_correlate(act_plan_t p, int32_t batch, const double* resid_dev,
+                                    int64_t atom_begin, int64_t atom_count, double* score_dev,
+                                    void* stream) {
+    ACT_REQUIRE(p != nullptr, "act_correlate: plan is NULL");
+    ACT_REQUIRE(!p->desc.ragged, "act_correlate: ragged plans are not supported");
+    ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, "act_correlate: batch outside [1, max_batch]");
+    ACT_REQUIRE(atom_begin >= 0 && atom_count >= 1 && atom_begin + atom_count <= p->atoms,
+                "act_correlate: atom range outside the dictionary");
+    ACT_REQUIRE(resid_dev && score_dev, "act_correlate: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    p->last_stream = s;
+    if (p->desc.prec != ACT_PREC_F64) {
+        act_status st = launch_to_shadow(p, batch, resid_dev, s);
+        if (st != ACT_OK) return st;
+    }
+    return launch_correlate(p, batch, resid_dev, atom_begin, atom_count, score_dev, s);
+}

@@ -1,0 +1,195 @@
+// act_common.h -- internal declarations of libact (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/act.h"
+
+namespace act {
+
+constexpr int kWave = 64;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// --------------------------------------------------------------------------
+// host-side error plumbing
+// --------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define ACT_HIP(call)                                                               \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            ::act::set_error(std::string(#call) + ": " + hipGetErrorString(e_));    \
+            return ACT_ERR_HIP;                                                     \
+        }                                                                           \
+    } while (0)
+
+#define ACT_REQUIRE(cond, msg)                                                      \
+    do {                                                                            \
+        if (!(cond)) {                                                              \
+            ::act::set_error(msg);                                                  \
+            return ACT_ERR_INVALID;                                                 \
+        }                                                                           \
+    } while (0)
+
+// --------------------------------------------------------------------------
+// dictionary geometry passed to kernels by value
+// --------------------------------------------------------------------------
+struct GridDev {
+    double fs;            // sampling rate [Hz]
+    const double* axis;   // concatenated axis values: tc | fc | c | logdt
+    int n;                // samples per signal
+    int n_pad;            // padded row length (multiple of 256)
+    int cnt[4];           // n_tc, n_fc, n_c, n_ld
+    int off[4];           // offsets of each axis inside `axis`
+    long long atoms;      // n_tc*n_fc*n_c*n_ld
+};
+
+// grid-hull box and grid spacing used by the refinement
+struct BoxDev {
+    double step[4], lo[4], hi[4];
+};
+
+struct act_plan_impl;
+
+// flat index -> parameter vector (t_c, f_c, c, logdt); order of Sec. III-A
+__device__ __forceinline__ void grid_theta(const GridDev& g, long long i, double th[4]) {
+    int id[4];
+#pragma unroll
+    for (int a = 3; a >= 0; --a) {
+        id[a] = (int)(i % g.cnt[a]);
+        i /= g.cnt[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) th[a] = g.axis[g.off[a] + id[a]];
+}
+
+// One sample of the real Gaussian chirplet of Eq. (1) without its analytic
+// prefactor: exp(-(1/2)(tau/dt)^2) cos(2 pi (c tau^2 + f_c tau)), tau = t - t_c.
+// cospi keeps the phase reduction exact for the large phases of long signals.
+__device__ __forceinline__ double atom_sample64(double t, double tc, double fc, double c,
+                                                double inv_dt) {
+    double tau = t - tc;
+    double u = tau * inv_dt;
+    double e = exp(-0.5 * u * u);
+    double cyc = c * tau * tau + fc * tau;
+    return e * cospi(2.0 * cyc);
+}
+
+// sample time of index k
+__device__ __forceinline__ double sample_time(int k, double fs) { return (double)k / fs; }
+
+// --------------------------------------------------------------------------
+// reductions
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        T w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Sum NV doubles over a block of NT threads; every thread receives the totals.
+// `lds` must hold NV * (NT / 64) doubles.  Deterministic: fixed order.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+    constexpr int NW = NT / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) lds[j * NW + w] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) s += lds[j * NW + k];
+        v[j] = s;
+    }
+    __syncthreads();
+}
+
+// order-preserving bit patterns of non-negative floats / doubles
+__device__ __forceinline__ unsigned fbits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ float bitsf(unsigned u) { return __uint_as_float(u); }
+
+}  // namespace act
+
+// --------------------------------------------------------------------------
+// the plan (opaque to callers)
+// --------------------------------------------------------------------------
+struct act_plan_s {
+    act_plan_desc desc;
+    act::GridDev grid;        // grid of the plain plan (ragged: widest grid)
+    act::BoxDev box;
+    long long atoms = 0;
+    int n = 0, n_pad = 0, cap = 0, max_batch = 0;
+    double* axis_dev = nullptr;
+
+    // dictionary table (ACT_DICT_TABLE)
+    void* table = nullptr;
+    size_t table_bytes = 0;
+    double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
+
+    // per-channel workspace [max_batch]
+    void* shadow = nullptr;   // [B][n_pad] fp32 or bf16 copy of the residual
+    unsigned* cand_idx = nullptr;   // [B][cap]
+    float* cand_score = nullptr;    // [B][cap] search score
+    double* cand_p64 = nullptr;     // [B][cap] FP64 rescore
+    int* cand_count = nullptr;      // [B]
+    unsigned* gmax = nullptr;       // [B] bits of max |score|
+    double* ebound = nullptr;       // [B] certified score error bound
+    double* rnorm = nullptr;        // [B] |r|
+    int* need_rerun = nullptr;      // [B] candidate overflow -> exact-threshold search
+    size_t workspace_bytes = 0;
+
+    const double* search_resid = nullptr;  // FP64 residual the FP64 search reads
+    int chain = 0;                          // FP32 score FMA-chain length (certified margin)
+
+    hipStream_t last_stream = nullptr;
+};
+
+namespace act {
+// search launchers (act_search.hip)
+act_status launch_search(act_plan_s* p, int batch, int pass, hipStream_t s);
+act_status launch_correlate(act_plan_s* p, int batch, const double* resid, long long begin,
+                            long long count, double* out, hipStream_t s);
+// plan-time builders (act_plan.hip)
+act_status build_tables(act_plan_s* p, hipStream_t s);
+// per-channel kernels (act_refine.hip)
+act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
+                       int* flags, int order, hipStream_t s);
+act_status launch_rescore(act_plan_s* p, int batch, const double* resid, hipStream_t s);
+act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int order, double* resid,
+                                       double* approx, double* theta, double* coef,
+                                       long long* index, double* energy, double* gap, int* flags,
+                                       hipStream_t s);
+act_status launch_overflow_check(act_plan_s* p, int batch, hipStream_t s);
+act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const double* theta0,
+                              int steps, double* theta, double* value, int* flags, hipStream_t s);
+act_status launch_value_and_grad(act_plan_s* p, int m, int dtype, const void* resid,
+                                 const double* theta, double* value, double* dtheta, void* dr,
+                                 hipStream_t s);
+act_status launch_to_shadow(act_plan_s* p, int batch, const double* resid, hipStream_t s);
+int f32_chain_length(int n_pad);
+act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double* theta,
+                              const double* coef, double* out, hipStream_t s);
+}  // namespace act

@@ -1,0 +1,272 @@
+// act_plan.hip -- plan construction: grid validation, axis values, the HBM
+// dictionary table (FP64 synthesis -> unit norm -> FP32 / BF16 rows), and the
+// per-channel workspace.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "act_common.h"
+
+namespace act {
+
+// Axis value j: lo + j*((hi-lo)/d); d = count (half-open) or count-1 (closed,
+// last value hi exactly); a one-value axis is lo.  No contraction, so the
+// values are the IEEE results of exactly these operations.
+#pragma clang fp contract(off)
+static double axis_value(const act_axis& a, int j) {
+    if (a.count <= 1) return a.lo;
+    int d = a.half_open ? a.count : a.count - 1;
+    if (!a.half_open && j == a.count - 1) return a.hi;
+    double step = (a.hi - a.lo) / (double)d;
+    return a.lo + (double)j * step;
+}
+
+static double axis_step(const act_axis& a) {
+    if (a.count <= 1) return 1.0;
+    int d = a.half_open ? a.count : a.count - 1;
+    return (a.hi - a.lo) / (double)d;
+}
+#pragma clang fp contract(on)
+
+static inline unsigned short f32_to_bf16_rne(float x) {
+    unsigned u;
+    memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ unsigned short d_bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float d_bf16_to_f32(unsigned short h) {
+    return __uint_as_float(((unsigned)h) << 16);
+}
+
+// One wave per atom: FP64 synthesis of Eq. (1) over the n samples present,
+// unit l2 normalisation (Sec. III-A), rounding to the table type (RNE), and
+// the exact l2 norm of the rounding error, whose maximum over the dictionary
+// enters the certified margin of the search.
+template <typename TOut>
+__global__ void __launch_bounds__(256) k_build_table(GridDev g, TOut* __restrict__ table,
+                                                     unsigned long long* __restrict__ eg_bits) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const long long nwaves = (long long)gridDim.x * blockDim.x / kWave;
+    for (long long i = wave; i < g.atoms; i += nwaves) {
+        double th[4];
+        grid_theta(g, i, th);
+        const double inv_dt = 1.0 / exp(th[3]);
+        double q = 0.0;
+        for (int k = lane; k < g.n; k += kWave) {
+            double v = atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt);
+            q += v * v;
+        }
+        q = wave_sum(q);
+        const double nrm = sqrt(q);
+        const bool ok = nrm >= 1e-300;
+        double e2 = 0.0;
+        TOut* row = table + (size_t)i * g.n_pad;
+        for (int k = lane; k < g.n_pad; k += kWave) {
+            double v = 0.0;
+            if (ok && k < g.n) v = atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt) / nrm;
+            float f = (float)v;
+            double back;
+            if constexpr (sizeof(TOut) == 4) {
+                row[k] = f;
+                back = (double)f;
+            } else {
+                unsigned short h = d_bf16_rne(f);
+                row[k] = h;
+                back = (double)d_bf16_to_f32(h);
+            }
+            double d = back - v;
+            e2 += d * d;
+        }
+        e2 = wave_sum(e2);
+        if (lane == 0) atomicMax(eg_bits, (unsigned long long)__double_as_longlong(sqrt(e2)));
+    }
+}
+
+static act_status validate_axis(const act_axis& a, const char* name) {
+    std::string n(name);
+    ACT_REQUIRE(a.count >= 1, n + ": count must be >= 1");
+    ACT_REQUIRE(std::isfinite(a.lo) && std::isfinite(a.hi), n + ": bounds must be finite");
+    ACT_REQUIRE(a.count == 1 || a.hi >= a.lo, n + ": hi < lo");
+    return ACT_OK;
+}
+
+act_status build_tables(act_plan_s* p, hipStream_t s) {
+    if (p->desc.dict != ACT_DICT_TABLE) return ACT_OK;
+    unsigned long long* eg = nullptr;
+    ACT_HIP(hipMalloc((void**)&eg, sizeof(unsigned long long)));
+    ACT_HIP(hipMemsetAsync(eg, 0, sizeof(unsigned long long), s));
+    int dev = 0, cus = 0;
+    ACT_HIP(hipGetDevice(&dev));
+    ACT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    long long waves_needed = p->atoms;
+    int blocks = (int)std::min<long long>((waves_needed + 3) / 4, (long long)cus * 32);
+    if (p->desc.prec == ACT_PREC_F32)
+        hipLaunchKernelGGL(k_build_table<float>, dim3(blocks), dim3(256), 0, s, p->grid,
+                           (float*)p->table, eg);
+    else
+        hipLaunchKernelGGL(k_build_table<unsigned short>, dim3(blocks), dim3(256), 0, s, p->grid,
+                           (unsigned short*)p->table, eg);
+    ACT_HIP(hipGetLastError());
+    unsigned long long bits = 0;
+    ACT_HIP(hipMemcpyAsync(&bits, eg, sizeof bits, hipMemcpyDeviceToHost, s));
+    ACT_HIP(hipStreamSynchronize(s));
+    ACT_HIP(hipFree(eg));
+    double v;
+    memcpy(&v, &bits, sizeof v);
+    p->eg_max = v;
+    return ACT_OK;
+}
+
+static void free_plan(act_plan_s* p) {
+    if (!p) return;
+    if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
+    void* ptrs[] = {p->axis_dev, p->table, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+}  // namespace act
+
+using namespace act;
+
+extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan_t* out) {
+    ACT_REQUIRE(desc != nullptr && out != nullptr, "act_plan: desc and out must not be NULL");
+    *out = nullptr;
+    const act_grid& gr = desc->grid;
+    ACT_REQUIRE(std::isfinite(gr.fs_hz) && gr.fs_hz > 0, "act_plan: fs_hz must be > 0");
+    ACT_REQUIRE(gr.n_samples >= 1, "act_plan: n_samples must be >= 1");
+    act_status st;
+    if ((st = validate_axis(gr.tc_s, "tc_s")) != ACT_OK) return st;
+    if ((st = validate_axis(gr.fc_hz, "fc_hz")) != ACT_OK) return st;
+    if ((st = validate_axis(gr.c_hz_per_s, "c_hz_per_s")) != ACT_OK) return st;
+    if ((st = validate_axis(gr.logdt_ln_s, "logdt_ln_s")) != ACT_OK) return st;
+    ACT_REQUIRE(desc->dict == ACT_DICT_SYNTH || desc->dict == ACT_DICT_TABLE, "act_plan: unknown dict");
+    ACT_REQUIRE(desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32 || desc->prec == ACT_PREC_BF16,
+                "act_plan: unknown prec");
+    ACT_REQUIRE(!(desc->prec == ACT_PREC_F64 && desc->dict == ACT_DICT_TABLE),
+                "act_plan: ACT_PREC_F64 searches synthesise atoms; use ACT_DICT_SYNTH");
+    ACT_REQUIRE(desc->max_batch >= 1, "act_plan: max_batch must be >= 1");
+    ACT_REQUIRE(desc->cand_cap >= 0 && desc->refine_steps >= 0, "act_plan: negative cand_cap/refine_steps");
+    if (desc->ragged) {
+        set_error("act_plan: ragged plans are not implemented in this build");
+        return ACT_ERR_UNSUPPORTED;
+    }
+    if (desc->prec == ACT_PREC_BF16 || (desc->prec == ACT_PREC_F32 && desc->dict == ACT_DICT_SYNTH)) {
+        set_error("act_plan: this precision / dictionary pair is not implemented in this build");
+        return ACT_ERR_UNSUPPORTED;
+    }
+
+    act_plan_s* p = new act_plan_s();
+    p->desc = *desc;
+    hipStream_t s = (hipStream_t)stream;
+    p->n = gr.n_samples;
+    p->n_pad = (gr.n_samples + 255) / 256 * 256;
+    p->max_batch = desc->max_batch;
+    p->chain = f32_chain_length(p->n_pad);
+    p->cap = desc->cand_cap > 0 ? desc->cand_cap : 4096;
+    const act_axis* ax[4] = {&gr.tc_s, &gr.fc_hz, &gr.c_hz_per_s, &gr.logdt_ln_s};
+    long long atoms = 1;
+    int total = 0;
+    for (int a = 0; a < 4; ++a) {
+        atoms *= ax[a]->count;
+        p->grid.cnt[a] = ax[a]->count;
+        p->grid.off[a] = total;
+        total += ax[a]->count;
+        p->box.step[a] = axis_step(*ax[a]);
+        p->box.lo[a] = axis_value(*ax[a], 0);
+        p->box.hi[a] = axis_value(*ax[a], ax[a]->count - 1);
+    }
+    if (atoms >= (1LL << 32)) {
+        free_plan(p);
+        set_error("act_plan: more than 2^32 atoms");
+        return ACT_ERR_INVALID;
+    }
+    p->atoms = atoms;
+    std::vector<double> vals(total);
+    for (int a = 0; a < 4; ++a)
+        for (int j = 0; j < ax[a]->count; ++j) vals[p->grid.off[a] + j] = axis_value(*ax[a], j);
+
+    auto fail = [&](act_status code) {
+        free_plan(p);
+        return code;
+    };
+#define PLAN_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));                \
+            return fail(e_ == hipErrorOutOfMemory ? ACT_ERR_NOMEM : ACT_ERR_HIP);        \
+        }                                                                                \
+    } while (0)
+
+    PLAN_HIP(hipMalloc((void**)&p->axis_dev, sizeof(double) * total));
+    PLAN_HIP(hipMemcpyAsync(p->axis_dev, vals.data(), sizeof(double) * total, hipMemcpyHostToDevice, s));
+    p->grid.fs = gr.fs_hz;
+    p->grid.axis = p->axis_dev;
+    p->grid.n = p->n;
+    p->grid.n_pad = p->n_pad;
+    p->grid.atoms = atoms;
+
+    const size_t B = (size_t)p->max_batch, cap = (size_t)p->cap;
+    const size_t elt = desc->prec == ACT_PREC_BF16 ? 2 : 4;
+    if (desc->dict == ACT_DICT_TABLE) {
+        p->table_bytes = (size_t)atoms * p->n_pad * elt;
+        size_t free_b = 0, total_b = 0;
+        PLAN_HIP(hipMemGetInfo(&free_b, &total_b));
+        if (p->table_bytes + (64ull << 20) > free_b) {
+            set_error("act_plan: dictionary table of " + std::to_string(p->table_bytes) +
+                      " bytes does not fit in free device memory");
+            return fail(ACT_ERR_NOMEM);
+        }
+        PLAN_HIP(hipMalloc(&p->table, p->table_bytes));
+    }
+    PLAN_HIP(hipMalloc(&p->shadow, B * p->n_pad * elt));
+    PLAN_HIP(hipMemsetAsync(p->shadow, 0, B * p->n_pad * elt, s));
+    PLAN_HIP(hipMalloc((void**)&p->cand_idx, B * cap * sizeof(unsigned)));
+    PLAN_HIP(hipMalloc((void**)&p->cand_score, B * cap * sizeof(float)));
+    PLAN_HIP(hipMalloc((void**)&p->cand_p64, B * cap * sizeof(double)));
+    PLAN_HIP(hipMalloc((void**)&p->cand_count, B * sizeof(int)));
+    PLAN_HIP(hipMalloc((void**)&p->gmax, B * sizeof(unsigned)));
+    PLAN_HIP(hipMalloc((void**)&p->ebound, B * sizeof(double)));
+    PLAN_HIP(hipMalloc((void**)&p->rnorm, B * sizeof(double)));
+    PLAN_HIP(hipMalloc((void**)&p->need_rerun, B * sizeof(int)));
+    p->workspace_bytes = B * p->n_pad * elt + B * cap * 16 + B * 32;
+#undef PLAN_HIP
+
+    act_status bs = build_tables(p, s);
+    if (bs != ACT_OK) return fail(bs);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error(std::string("act_plan: ") + hipGetErrorString(e));
+        return fail(ACT_ERR_HIP);
+    }
+    p->last_stream = s;
+    *out = p;
+    return ACT_OK;
+}
+
+extern "C" void act_plan_destroy(act_plan_t plan) { free_plan(plan); }
+
+extern "C" int64_t act_plan_query(act_plan_t p, int32_t key) {
+    if (!p) return -1;
+    switch (key) {
+        case ACT_Q_ATOMS: return p->atoms;
+        case ACT_Q_TABLE_BYTES: return (int64_t)p->table_bytes;
+        case ACT_Q_N_PAD: return p->n_pad;
+        case ACT_Q_CAND_CAP: return p->cap;
+        case ACT_Q_WORKSPACE_BYTES: return (int64_t)p->workspace_bytes;
+        default: return -1;
+    }
+}

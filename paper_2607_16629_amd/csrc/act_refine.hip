@@ -1,0 +1,805 @@
+// act_refine.hip -- per-channel FP64 work of every matching-pursuit order:
+// certified FP64 rescoring of the search candidates, arg-max with the lowest
+// index on ties, continuous refinement (Sec. III-A "BFGS refinement") by
+// L-BFGS over the closed-form forward + adjoint of J(theta) = <r,g>^2/<g,g>,
+// the coefficient c_k = <g*, r_k> with the refined unit atom, and the residual /
+// approximation update of Eq. (4) with the energy |r_{k+1}|^2 (Eq. (5)).
+#include <math.h>
+
+#include "act_common.h"
+
+namespace act {
+
+struct PlanDev {
+    GridDev g;
+    BoxDev box;
+    int prec, cap, chain;
+    double eg_max;
+    void* shadow;
+    unsigned* cand_idx;
+    float* cand_score;
+    double* cand_p64;
+    int* cand_count;
+    unsigned* gmax;
+    double* ebound;
+    double* rnorm;
+    int* need_rerun;
+};
+
+static PlanDev view(const act_plan_s* p) {
+    PlanDev v;
+    v.g = p->grid;
+    v.box = p->box;
+    v.prec = p->desc.prec;
+    v.cap = p->cap;
+    v.chain = p->chain;
+    v.eg_max = p->eg_max;
+    v.shadow = p->shadow;
+    v.cand_idx = p->cand_idx;
+    v.cand_score = p->cand_score;
+    v.cand_p64 = p->cand_p64;
+    v.cand_count = p->cand_count;
+    v.gmax = p->gmax;
+    v.ebound = p->ebound;
+    v.rnorm = p->rnorm;
+    v.need_rerun = p->need_rerun;
+    return v;
+}
+
+constexpr int NT = 256;            // threads of every per-channel kernel
+constexpr int NW = NT / kWave;
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// Proven bound on |p~ - p| of one channel's search scores, where rn = |r|
+// and er = |r - shadow(r)| (the rounding of the search copy of r):
+//   p~ = fl( sum g~ r~ ),  g~ = g_hat + e_g (|e_g| <= eg_max),  r~ = r + e_r
+//   |sum g~ r~ - p| <= eg_max |r~| + |e_r|
+//   |fl(sum) - sum| <= gamma_m |g~| |r~|, gamma_m = m u / (1 - m u)   (chain m)
+// FP64 searches round the score to FP32 when storing it: u32 |r| + FP64 sums.
+__device__ double score_bound(const PlanDev& P, double rn, double er) {
+    const double u32 = 5.9604644775390625e-08;  // 2^-24
+    if (P.prec == ACT_PREC_F64) return 1.01 * (u32 + (P.g.n + 16) * 2.220446049250313e-16) * rn;
+    const double rt = rn + er;
+    const double m = (double)P.chain;
+    const double gam = m * u32 / (1.0 - m * u32);
+    return 1.01 * (P.eg_max * rt + er + gam * (1.0 + P.eg_max) * rt);
+}
+
+// E = |r|^2, the search copy of r (FP32 or BF16, zero padded) and its rounding
+// error; resets the channel's search state.  Block-wide; returns E.
+__device__ double refresh_channel(const PlanDev& P, int b, const double* r, double* red,
+                                  bool bad) {
+    double acc[2] = {0.0, 0.0};
+    for (int k = threadIdx.x; k < P.g.n_pad; k += NT) {
+        const double v = k < P.g.n ? r[k] : 0.0;
+        double back;
+        if (P.prec == ACT_PREC_BF16) {
+            unsigned short h = bf16_rne((float)v);
+            ((unsigned short*)P.shadow)[(size_t)b * P.g.n_pad + k] = h;
+            back = (double)__uint_as_float(((unsigned)h) << 16);
+        } else {
+            const float f = (float)v;
+            ((float*)P.shadow)[(size_t)b * P.g.n_pad + k] = f;
+            back = (double)f;
+        }
+        acc[0] += v * v;
+        const double d = v - back;
+        acc[1] += d * d;
+    }
+    block_sum<NT, 2>(acc, red);
+    if (threadIdx.x == 0) {
+        const double rn = sqrt(acc[0]);
+        P.rnorm[b] = rn;
+        P.ebound[b] = (bad || !(acc[0] > 0.0) || !isfinite(acc[0])) ? -1.0 : score_bound(P, rn, sqrt(acc[1]));
+        P.cand_count[b] = 0;
+        P.gmax[b] = 0u;
+        P.need_rerun[b] = 0;
+    }
+    return acc[0];
+}
+
+__global__ void __launch_bounds__(NT) k_init(PlanDev P, double* __restrict__ resid,
+                                             double* __restrict__ approx,
+                                             double* __restrict__ energy, int* __restrict__ flags,
+                                             int order) {
+    __shared__ double red[2 * NW];
+    const int b = blockIdx.x;
+    const double* r = resid + (size_t)b * P.g.n;
+    int bad = 0;
+    for (int k = threadIdx.x; k < P.g.n; k += NT) {
+        if (!isfinite(r[k])) bad = 1;
+        if (approx) approx[(size_t)b * P.g.n + k] = 0.0;
+    }
+    bad = __syncthreads_or(bad);
+    const double E = refresh_channel(P, b, r, red, bad != 0);
+    if (threadIdx.x == 0) {
+        energy[(size_t)b * (order + 1)] = E;
+        flags[b] = bad ? ACT_FLAG_NONFINITE : 0;
+    }
+}
+
+__global__ void k_to_shadow(PlanDev P, const double* __restrict__ resid) {
+    const int b = blockIdx.x;
+    for (int k = threadIdx.x; k < P.g.n_pad; k += blockDim.x) {
+        const double v = k < P.g.n ? resid[(size_t)b * P.g.n + k] : 0.0;
+        if (P.prec == ACT_PREC_BF16)
+            ((unsigned short*)P.shadow)[(size_t)b * P.g.n_pad + k] = bf16_rne((float)v);
+        else
+            ((float*)P.shadow)[(size_t)b * P.g.n_pad + k] = (float)v;
+    }
+}
+
+// Candidate overflow: a channel whose list overflowed is searched again with
+// the exact final threshold.
+__global__ void k_overflow(PlanDev P, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    if (P.cand_count[b] > P.cap) {
+        P.need_rerun[b] = 1;
+        P.cand_count[b] = 0;
+    } else {
+        P.need_rerun[b] = 0;
+    }
+}
+
+// FP64 rescoring: one wave per candidate whose search score lies inside the
+// certified margin of the channel's final maximum; others are marked NaN.
+__global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __restrict__ resid) {
+    const int b = blockIdx.y;
+    const double eb = P.ebound[b];
+    if (eb < 0.0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int cnt = min(P.cand_count[b], P.cap);
+    const double T = (double)bitsf(P.gmax[b]) - 2.0 * eb;
+    const double* r = resid + (size_t)b * P.g.n;
+    const int wpb = blockDim.x / kWave;
+    for (int j = blockIdx.x * wpb + threadIdx.x / kWave; j < cnt; j += gridDim.x * wpb) {
+        const size_t slot = (size_t)b * P.cap + j;
+        if ((double)fabsf(P.cand_score[slot]) < T) {
+            if (lane == 0) P.cand_p64[slot] = __longlong_as_double(0x7ff8000000000000LL);
+            continue;
+        }
+        double th[4];
+        grid_theta(P.g, (long long)P.cand_idx[slot], th);
+        const double inv_dt = 1.0 / exp(th[3]);
+        double s = 0.0, q = 0.0;
+        for (int k = lane; k < P.g.n; k += kWave) {
+            const double v = atom_sample64(sample_time(k, P.g.fs), th[0], th[1], th[2], inv_dt);
+            s += v * r[k];
+            q += v * v;
+        }
+        s = wave_sum(s);
+        q = wave_sum(q);
+        if (lane == 0) P.cand_p64[slot] = q > 0.0 ? s / sqrt(q) : 0.0;
+    }
+}
+
+// --------------------------------------------------------------------------
+// refinement objective, block-wide
+// --------------------------------------------------------------------------
+
+// J = s^2/q with s = <r,g>, q = <g,g>, and dJ/dtheta (SI units):
+//   dJ/dtheta_j = 2 s <r, d_j g>/q - 2 s^2 <g, d_j g>/q^2, where
+//   d_tc g = E[(tau/dt^2) C + 2 pi (2 c tau + f_c) S], d_fc g = -2 pi tau E S,
+//   d_c g = -2 pi tau^2 E S, d_logdt g = (tau^2/dt^2) E C.
+__device__ double eval_obj(const double* __restrict__ r, int n, double fs, const double th[4],
+                           double grad[4], double* red) {
+    const double tc = th[0], fc = th[1], c = th[2];
+    const double inv_dt = 1.0 / exp(th[3]);
+    const double idt2 = inv_dt * inv_dt;
+    double acc[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) acc[j] = 0.0;
+    for (int k = threadIdx.x; k < n; k += NT) {
+        const double tau = sample_time(k, fs) - tc;
+        const double u = tau * inv_dt;
+        const double e = exp(-0.5 * u * u);
+        double si, co;
+        sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
+        const double gk = e * co, es = e * si;
+        const double d0 = e * (tau * idt2 * co) + kTwoPi * (2.0 * c * tau + fc) * es;
+        const double d1 = -kTwoPi * tau * es;
+        const double d2 = -kTwoPi * tau * tau * es;
+        const double d3 = tau * tau * idt2 * gk;
+        const double rk = r[k];
+        acc[0] += rk * gk;
+        acc[1] += gk * gk;
+        acc[2] += rk * d0;
+        acc[3] += rk * d1;
+        acc[4] += rk * d2;
+        acc[5] += rk * d3;
+        acc[6] += gk * d0;
+        acc[7] += gk * d1;
+        acc[8] += gk * d2;
+        acc[9] += gk * d3;
+    }
+    block_sum<NT, 10>(acc, red);
+    const double s = acc[0], q = acc[1];
+    if (!(q > 0.0)) {
+        grad[0] = grad[1] = grad[2] = grad[3] = 0.0;
+        return 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) grad[j] = 2.0 * s * acc[2 + j] / q - 2.0 * s * s * acc[6 + j] / (q * q);
+    return s * s / q;
+}
+
+// Coordinate scales of the refinement: the unit atom's resolution along each
+// parameter, s_j = min(step_j, 1/sqrt(G_jj)), G_jj = (|d_j g|^2 - <g,d_j g>^2/q)/q;
+// 0 freezes an axis (single grid value or G_jj <= 0).
+__device__ void eval_scales(const double* __restrict__ r, const GridDev& g, const BoxDev& box,
+                            const double th[4], double h[4], double* red) {
+    (void)r;
+    const double tc = th[0], fc = th[1], c = th[2];
+    const double inv_dt = 1.0 / exp(th[3]);
+    const double idt2 = inv_dt * inv_dt;
+    double acc[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] = 0.0;
+    for (int k = threadIdx.x; k < g.n; k += NT) {
+        const double tau = sample_time(k, g.fs) - tc;
+        const double u = tau * inv_dt;
+        const double e = exp(-0.5 * u * u);
+        double si, co;
+        sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
+        const double gk = e * co, es = e * si;
+        double d[4];
+        d[0] = e * (tau * idt2 * co) + kTwoPi * (2.0 * c * tau + fc) * es;
+        d[1] = -kTwoPi * tau * es;
+        d[2] = -kTwoPi * tau * tau * es;
+        d[3] = tau * tau * idt2 * gk;
+        acc[0] += gk * gk;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[1 + j] += gk * d[j];
+            acc[5 + j] += d[j] * d[j];
+        }
+    }
+    block_sum<NT, 9>(acc, red);
+    const double q = acc[0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double G = q > 0.0 ? (acc[5 + j] - acc[1 + j] * acc[1 + j] / q) / q : 0.0;
+        if (!(box.hi[j] > box.lo[j]) || !(G > 0.0)) {
+            h[j] = 0.0;
+        } else {
+            const double rr = 1.0 / sqrt(G);
+            h[j] = rr < box.step[j] ? rr : box.step[j];
+        }
+    }
+}
+
+struct LbfgsMem {
+    double S[8][4], Y[8][4], RHO[8];
+};
+
+__device__ __forceinline__ double dot4(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+}
+
+// f(u) = -J(theta0 + h u) and its gradient in u
+__device__ double refine_eval(const double* r, const GridDev& g, const double th0[4],
+                              const double h[4], const double u[4], double gu[4], double* red) {
+    double th[4], gr[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) th[j] = th0[j] + h[j] * u[j];
+    const double J = eval_obj(r, g.n, g.fs, th, gr, red);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gu[j] = -h[j] * gr[j];
+    return -J;
+}
+
+// Limited-memory BFGS maximisation of J from a grid point, block-wide.  Every
+// thread runs the same scalar iteration on identical (block-reduced) values;
+// the pair memory lives in LDS and only thread 0 writes it.  Specification:
+// memory 8, H0 = gamma I with gamma = s'y/y'y of the newest pair; pairs kept
+// only if s'y > 1e-12|s||y|; projected-gradient stop max|pg| <= 1e-11 max(1,J);
+// out-of-box direction components zeroed at active bounds, steepest descent
+// if the direction is not a descent direction; first step min(1, 1/max|d|)
+// while the memory is empty, else 1; backtracking (halving, <= 30 trials) that
+// accepts a strict-descent trial by Armijo (c1 = 1e-4) or, once FP64 cannot
+// resolve the change of J (f_new <= f + 1e-12|f|), by Hager and Zhang's
+// approximate Wolfe slope test 0.9 dec <= dnew <= -0.8 dec; at most `steps`
+// iterations; the result is kept only if J does not drop.
+__device__ int refine_block(const double* __restrict__ r, const GridDev& g, const BoxDev& box,
+                            const double th0[4], int steps, double th_out[4], double* J_out,
+                            double* red, LbfgsMem* mem) {
+    double h[4], blo[4], bhi[4], u[4] = {0, 0, 0, 0}, gcur[4];
+    int flags = 0;
+    eval_scales(r, g, box, th0, h, red);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        blo[j] = h[j] == 0.0 ? 0.0 : (box.lo[j] - th0[j]) / h[j];
+        bhi[j] = h[j] == 0.0 ? 0.0 : (box.hi[j] - th0[j]) / h[j];
+    }
+    double f = refine_eval(r, g, th0, h, u, gcur, red);
+    const double f0 = f;
+    int nmem = 0, head = 0;
+    for (int it = 0; it < steps; ++it) {
+        double pg[4], pgmax = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            pg[j] = gcur[j];
+            if (u[j] <= blo[j] && gcur[j] > 0.0) pg[j] = 0.0;
+            if (u[j] >= bhi[j] && gcur[j] < 0.0) pg[j] = 0.0;
+            pgmax = fmax(pgmax, fabs(pg[j]));
+        }
+        const double Jc = -f;
+        if (pgmax <= 1e-11 * (Jc > 1.0 ? Jc : 1.0)) break;
+        double d[4], al[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[j] = -gcur[j];
+        for (int t = 0; t < nmem; ++t) {
+            const int slot = (head - 1 - t + 8) & 7;
+            const double a = mem->RHO[slot] * dot4(mem->S[slot], d);
+            al[t] = a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) d[j] -= a * mem->Y[slot][j];
+        }
+        double gamma = 1.0;
+        if (nmem > 0) {
+            const int nw = (head - 1 + 8) & 7;
+            gamma = dot4(mem->S[nw], mem->Y[nw]) / dot4(mem->Y[nw], mem->Y[nw]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[j] *= gamma;
+        for (int t = nmem - 1; t >= 0; --t) {
+            const int slot = (head - 1 - t + 8) & 7;
+            const double bb = mem->RHO[slot] * dot4(mem->Y[slot], d);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) d[j] += (al[t] - bb) * mem->S[slot][j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (h[j] == 0.0) d[j] = 0.0;
+            if (u[j] <= blo[j] && d[j] < 0.0) d[j] = 0.0;
+            if (u[j] >= bhi[j] && d[j] > 0.0) d[j] = 0.0;
+        }
+        if (dot4(gcur, d) >= 0.0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) d[j] = -pg[j];
+        }
+        double dmax = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dmax = fmax(dmax, fabs(d[j]));
+        double alpha = nmem > 0 ? 1.0 : (dmax > 1.0 ? 1.0 / dmax : 1.0);
+        double un[4], gn[4], fn = 0.0;
+        bool ok = false;
+        for (int t = 0; t < 30; ++t) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                double v = u[j] + alpha * d[j];
+                v = v < blo[j] ? blo[j] : v;
+                v = v > bhi[j] ? bhi[j] : v;
+                un[j] = v;
+            }
+            fn = refine_eval(r, g, th0, h, un, gn, red);
+            double dec = 0.0, dnew = 0.0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                dec += gcur[j] * (un[j] - u[j]);
+                dnew += gn[j] * (un[j] - u[j]);
+            }
+            const bool armijo = fn <= f + 1e-4 * dec;
+            const bool approx_wolfe = fn <= f + 1e-12 * fabs(f) && dnew >= 0.9 * dec && dnew <= -0.8 * dec;
+            if (dec < 0.0 && (armijo || approx_wolfe)) {
+                ok = true;
+                break;
+            }
+            alpha *= 0.5;
+        }
+        if (!ok) break;
+        double sv[4], yv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sv[j] = un[j] - u[j];
+            yv[j] = gn[j] - gcur[j];
+        }
+        const double sy = dot4(sv, yv);
+        if (sy > 1e-12 * sqrt(dot4(sv, sv)) * sqrt(dot4(yv, yv))) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    mem->S[head][j] = sv[j];
+                    mem->Y[head][j] = yv[j];
+                }
+                mem->RHO[head] = 1.0 / sy;
+            }
+            __syncthreads();
+            head = (head + 1) & 7;
+            if (nmem < 8) ++nmem;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            u[j] = un[j];
+            gcur[j] = gn[j];
+        }
+        f = fn;
+    }
+    if (-f >= -f0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) th_out[j] = th0[j] + h[j] * u[j];
+        *J_out = -f;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) th_out[j] = th0[j];
+        *J_out = -f0;
+        flags |= ACT_FLAG_REFINE_REJECTED;
+    }
+    return flags;
+}
+
+// --------------------------------------------------------------------------
+// select -> refine -> coefficient -> update, one block per channel
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_select_refine_update(
+    PlanDev P, int k, int order, int steps, double* __restrict__ resid, double* __restrict__ approx,
+    double* __restrict__ theta, double* __restrict__ coef, long long* __restrict__ index,
+    double* __restrict__ energy, double* __restrict__ gap, int* __restrict__ flags) {
+    __shared__ double red[10 * NW];
+    __shared__ LbfgsMem mem;
+    __shared__ double s_a1[NW], s_a2[NW];
+    __shared__ unsigned s_i1[NW];
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    double* r = resid + (size_t)b * P.g.n;
+    int fl = flags[b];
+    const double eb = P.ebound[b];
+    const size_t o = (size_t)b * order + k;
+
+    if (fl & ACT_FLAG_NONFINITE) {
+        if (threadIdx.x == 0) {
+            const double nan = __longlong_as_double(0x7ff8000000000000LL);
+            for (int j = 0; j < 4; ++j) theta[o * 4 + j] = nan;
+            coef[o] = 0.0;
+            index[o] = -1;
+            if (gap) gap[o] = 0.0;
+            energy[(size_t)b * (order + 1) + k + 1] = energy[(size_t)b * (order + 1) + k];
+        }
+        return;
+    }
+
+    // arg-max of |p64| over the rescored candidates; ties -> lowest atom index
+    double a1 = -1.0, a2 = -1.0;
+    unsigned i1 = 0xffffffffu;
+    if (eb >= 0.0) {
+        const int cnt_raw = P.cand_count[b];
+        const int cnt = min(cnt_raw, P.cap);
+        if (cnt_raw > P.cap) fl |= ACT_FLAG_CAND_OVERFLOW;
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const double v = P.cand_p64[(size_t)b * P.cap + j];
+            if (isnan(v)) continue;
+            const double a = fabs(v);
+            const unsigned id = P.cand_idx[(size_t)b * P.cap + j];
+            if (a > a1 || (a == a1 && id < i1)) {
+                a2 = a1;
+                a1 = a;
+                i1 = id;
+            } else if (a > a2) {
+                a2 = a;
+            }
+        }
+    }
+    // wave then block merge of (a1, i1, a2)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double oa1 = __shfl_xor(a1, off, kWave), oa2 = __shfl_xor(a2, off, kWave);
+        const unsigned oi1 = __shfl_xor(i1, off, kWave);
+        if (oa1 > a1 || (oa1 == a1 && oi1 < i1)) {
+            a2 = fmax(a1, oa2);
+            a1 = oa1;
+            i1 = oi1;
+        } else {
+            a2 = fmax(a2, oa1);
+        }
+    }
+    if (lane == 0) {
+        s_a1[w] = a1;
+        s_a2[w] = a2;
+        s_i1[w] = i1;
+    }
+    __syncthreads();
+    a1 = s_a1[0];
+    a2 = s_a2[0];
+    i1 = s_i1[0];
+    for (int q = 1; q < NW; ++q) {
+        const double oa1 = s_a1[q], oa2 = s_a2[q];
+        const unsigned oi1 = s_i1[q];
+        if (oa1 > a1 || (oa1 == a1 && oi1 < i1)) {
+            a2 = fmax(a1, oa2);
+            a1 = oa1;
+            i1 = oi1;
+        } else {
+            a2 = fmax(a2, oa1);
+        }
+    }
+    __syncthreads();
+    long long best = (eb >= 0.0 && i1 != 0xffffffffu) ? (long long)i1 : 0;
+    double g_gap = 0.0;
+    if (eb >= 0.0 && a1 > 0.0) {
+        // an atom outside the list has |p| < M - eb (its score was below M - 2 eb)
+        const double outside = (double)bitsf(P.gmax[b]) - eb;
+        const double runner = fmax(a2, outside);
+        g_gap = fmax(0.0, (a1 - runner) / a1);
+    }
+
+    double th0[4], th[4], J = 0.0;
+    grid_theta(P.g, best, th0);
+    if (steps > 0) {
+        fl |= refine_block(r, P.g, P.box, th0, steps, th, &J, red, &mem);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) th[j] = th0[j];
+    }
+
+    // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4))
+    const double inv_dt = 1.0 / exp(th[3]);
+    double acc[1] = {0.0};
+    for (int t = threadIdx.x; t < P.g.n; t += NT) {
+        const double v = atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt);
+        acc[0] += v * v;
+    }
+    block_sum<NT, 1>(acc, red);
+    const double nrm = sqrt(acc[0]);
+    const bool ok = nrm >= 1e-300;
+    acc[0] = 0.0;
+    for (int t = threadIdx.x; t < P.g.n; t += NT) {
+        const double v = ok ? atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
+        acc[0] += v * r[t];
+    }
+    block_sum<NT, 1>(acc, red);
+    const double ck = acc[0];
+    for (int t = threadIdx.x; t < P.g.n; t += NT) {
+        const double v = ok ? atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
+        r[t] = r[t] - ck * v;
+        if (approx) approx[(size_t)b * P.g.n + t] = approx[(size_t)b * P.g.n + t] + ck * v;
+    }
+    __syncthreads();
+    const double E = refresh_channel(P, b, r, red, false);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) theta[o * 4 + j] = th[j];
+        coef[o] = ck;
+        index[o] = best;
+        if (gap) gap[o] = g_gap;
+        energy[(size_t)b * (order + 1) + k + 1] = E;
+        flags[b] = fl;
+    }
+}
+
+// --------------------------------------------------------------------------
+// refinement alone, forward/adjoint alone, reconstruction
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_refine_many(GridDev g, BoxDev box,
+                                                    const double* __restrict__ resid,
+                                                    const double* __restrict__ theta0, int steps,
+                                                    double* __restrict__ theta,
+                                                    double* __restrict__ value,
+                                                    int* __restrict__ flags) {
+    __shared__ double red[10 * NW];
+    __shared__ LbfgsMem mem;
+    const int p = blockIdx.x;
+    const double* r = resid + (size_t)p * g.n;
+    double th0[4], th[4], J;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) th0[j] = theta0[p * 4 + j];
+    const int fl = refine_block(r, g, box, th0, steps, th, &J, red, &mem);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) theta[p * 4 + j] = th[j];
+        value[p] = J;
+        if (flags) flags[p] = fl;
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_vg_f64(GridDev g, const double* __restrict__ resid,
+                                               const double* __restrict__ theta,
+                                               double* __restrict__ value,
+                                               double* __restrict__ dtheta, double* __restrict__ dr) {
+    __shared__ double red[10 * NW];
+    const int p = blockIdx.x;
+    const double* r = resid + (size_t)p * g.n;
+    double th[4], gr[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) th[j] = theta[p * 4 + j];
+    const double J = eval_obj(r, g.n, g.fs, th, gr, red);
+    if (threadIdx.x == 0) {
+        value[p] = J;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dtheta[p * 4 + j] = gr[j];
+    }
+    if (dr) {
+        // dJ/dr = 2 (s/q) g = 2 <r, g_hat> g_hat
+        const double inv_dt = 1.0 / exp(th[3]);
+        double acc[2] = {0.0, 0.0};
+        for (int k = threadIdx.x; k < g.n; k += NT) {
+            const double v = atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt);
+            acc[0] += r[k] * v;
+            acc[1] += v * v;
+        }
+        block_sum<NT, 2>(acc, red);
+        const double f = acc[1] > 0.0 ? 2.0 * acc[0] / acc[1] : 0.0;
+        for (int k = threadIdx.x; k < g.n; k += NT)
+            dr[(size_t)p * g.n + k] = f * atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt);
+    }
+}
+
+// FP32 forward/adjoint: the phase in cycles is formed and reduced modulo 1 in
+// FP64 (an FP32 phase of a long chirp loses whole milliradians); the envelope,
+// trigonometry, products and sums are FP32.
+__device__ __forceinline__ void atom_terms_f32(double tau64, double c, double fc, float inv_dt,
+                                               float& e, float& co, float& si, float& tau) {
+    const double cyc = c * tau64 * tau64 + fc * tau64;
+    const float red_c = (float)(cyc - rint(cyc));
+    sincospif(2.0f * red_c, &si, &co);
+    tau = (float)tau64;
+    const float u = tau * inv_dt;
+    e = expf(-0.5f * u * u);
+}
+
+__global__ void __launch_bounds__(NT) k_vg_f32(GridDev g, const float* __restrict__ resid,
+                                               const double* __restrict__ theta,
+                                               double* __restrict__ value,
+                                               double* __restrict__ dtheta, float* __restrict__ dr) {
+    __shared__ double red[10 * NW];
+    const int p = blockIdx.x;
+    const float* r = resid + (size_t)p * g.n;
+    const double tc = theta[p * 4 + 0], fc = theta[p * 4 + 1], c = theta[p * 4 + 2];
+    const float inv_dt = (float)(1.0 / exp(theta[p * 4 + 3]));
+    const float idt2 = inv_dt * inv_dt;
+    const float twopi = 6.2831853071795865f, fcf = (float)fc, cf = (float)c;
+    float acc[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) acc[j] = 0.0f;
+    for (int k = threadIdx.x; k < g.n; k += NT) {
+        float e, co, si, tau;
+        atom_terms_f32(sample_time(k, g.fs) - tc, c, fc, inv_dt, e, co, si, tau);
+        const float gk = e * co, es = e * si;
+        const float d0 = e * (tau * idt2 * co) + twopi * (2.0f * cf * tau + fcf) * es;
+        const float d1 = -twopi * tau * es;
+        const float d2 = -twopi * tau * tau * es;
+        const float d3 = tau * tau * idt2 * gk;
+        const float rk = r[k];
+        acc[0] += rk * gk;
+        acc[1] += gk * gk;
+        acc[2] += rk * d0;
+        acc[3] += rk * d1;
+        acc[4] += rk * d2;
+        acc[5] += rk * d3;
+        acc[6] += gk * d0;
+        acc[7] += gk * d1;
+        acc[8] += gk * d2;
+        acc[9] += gk * d3;
+    }
+    // wave sums in FP32, the few cross-wave partials in FP64
+    double accd[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) accd[j] = (double)wave_sum(acc[j]);
+    {
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        if (lane == 0)
+            for (int j = 0; j < 10; ++j) red[j * NW + w] = accd[j];
+        __syncthreads();
+        for (int j = 0; j < 10; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < NW; ++q) s += red[j * NW + q];
+            accd[j] = (double)(float)s;
+        }
+        __syncthreads();
+    }
+    const double s = accd[0], q = accd[1];
+    const double J = q > 0.0 ? s * s / q : 0.0;
+    if (threadIdx.x == 0) {
+        value[p] = J;
+        for (int j = 0; j < 4; ++j)
+            dtheta[p * 4 + j] = q > 0.0 ? 2.0 * s * accd[2 + j] / q - 2.0 * s * s * accd[6 + j] / (q * q) : 0.0;
+    }
+    if (dr) {
+        const float f = q > 0.0 ? (float)(2.0 * s / q) : 0.0f;
+        for (int k = threadIdx.x; k < g.n; k += NT) {
+            float e, co, si, tau;
+            atom_terms_f32(sample_time(k, g.fs) - tc, c, fc, inv_dt, e, co, si, tau);
+            dr[(size_t)p * g.n + k] = f * (e * co);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_reconstruct(GridDev g, int order,
+                                                    const double* __restrict__ theta,
+                                                    const double* __restrict__ coef,
+                                                    double* __restrict__ out) {
+    __shared__ double red[NW];
+    const int b = blockIdx.x;
+    double* o = out + (size_t)b * g.n;
+    for (int t = threadIdx.x; t < g.n; t += NT) o[t] = 0.0;
+    for (int k = 0; k < order; ++k) {
+        const double* th = theta + ((size_t)b * order + k) * 4;
+        const double ck = coef[(size_t)b * order + k];
+        if (isnan(th[0])) continue;
+        const double inv_dt = 1.0 / exp(th[3]);
+        double acc[1] = {0.0};
+        for (int t = threadIdx.x; t < g.n; t += NT) {
+            const double v = atom_sample64(sample_time(t, g.fs), th[0], th[1], th[2], inv_dt);
+            acc[0] += v * v;
+        }
+        block_sum<NT, 1>(acc, red);
+        const double nrm = sqrt(acc[0]);
+        if (!(nrm >= 1e-300)) continue;
+        for (int t = threadIdx.x; t < g.n; t += NT)
+            o[t] = o[t] + ck * (atom_sample64(sample_time(t, g.fs), th[0], th[1], th[2], inv_dt) / nrm);
+    }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
+                       int* flags, int order, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(batch), dim3(NT), 0, s, view(p), resid, approx, energy, flags, order);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_to_shadow(act_plan_s* p, int batch, const double* resid, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_shadow, dim3(batch), dim3(256), 0, s, view(p), resid);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_overflow_check(act_plan_s* p, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_overflow, dim3((batch + 63) / 64), dim3(64), 0, s, view(p), batch);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_rescore(act_plan_s* p, int batch, const double* resid, hipStream_t s) {
+    hipLaunchKernelGGL(k_rescore, dim3(32, batch), dim3(256), 0, s, view(p), resid);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int order, double* resid,
+                                       double* approx, double* theta, double* coef,
+                                       long long* index, double* energy, double* gap, int* flags,
+                                       hipStream_t s) {
+    hipLaunchKernelGGL(k_select_refine_update, dim3(batch), dim3(NT), 0, s, view(p), k, order,
+                       p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const double* theta0,
+                              int steps, double* theta, double* value, int* flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_many, dim3(m), dim3(NT), 0, s, p->grid, p->box, resid, theta0, steps,
+                       theta, value, flags);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_value_and_grad(act_plan_s* p, int m, int dtype, const void* resid,
+                                 const double* theta, double* value, double* dtheta, void* dr,
+                                 hipStream_t s) {
+    if (dtype == ACT_PREC_F64)
+        hipLaunchKernelGGL(k_vg_f64, dim3(m), dim3(NT), 0, s, p->grid, (const double*)resid, theta,
+                           value, dtheta, (double*)dr);
+    else
+        hipLaunchKernelGGL(k_vg_f32, dim3(m), dim3(NT), 0, s, p->grid, (const float*)resid, theta,
+                           value, dtheta, (float*)dr);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double* theta,
+                              const double* coef, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reconstruct, dim3(batch), dim3(NT), 0, s, p->grid, order, theta, coef, out);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+}  // namespace act

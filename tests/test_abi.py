@@ -1,0 +1,100 @@
+"""CPU tests of the C ABI boundary: the library loads, exports every function
+that include/act.h declares, and rejects bad arguments on the host with
+ACT_ERR_INVALID before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2607_16629_amd import act as A
+from paper_2607_16629_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "act.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(act_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(A.LIB_PATH):
+        pytest.fail("libact.so is not built (run __graft_entry__.build())")
+    return A.load()
+
+
+def test_header_declares_the_named_calls():
+    names = declared_functions()
+    for required in ("act_plan", "act_decompose", "act_refine", "act_reconstruct",
+                     "act_value_and_grad", "act_correlate"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(A.EXPORTS) <= set(declared_functions())
+
+
+def test_struct_layout_matches_header():
+    # act_axis: 2 doubles + 2 int32; act_grid: double, 2 int32, 4 axes
+    assert ctypes.sizeof(A._Axis) == 24
+    assert ctypes.sizeof(A._Grid) == 16 + 4 * 24
+    assert ctypes.sizeof(A._PlanDesc) == ctypes.sizeof(A._Grid) + 8 * 4
+
+
+def _plan_status(lib, desc):
+    h = ctypes.c_void_p()
+    st = lib.act_plan(ctypes.byref(desc), None, ctypes.byref(h))
+    return st, lib.act_last_error().decode()
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda d: setattr(d.grid, "fs_hz", 0.0), "fs_hz"),
+    (lambda d: setattr(d.grid, "n_samples", 0), "n_samples"),
+    (lambda d: setattr(d.grid.fc_hz, "count", 0), "fc_hz"),
+    (lambda d: setattr(d.grid.c_hz_per_s, "hi", float("nan")), "c_hz_per_s"),
+    (lambda d: setattr(d.grid.logdt_ln_s, "hi", -10.0), "logdt_ln_s"),
+    (lambda d: setattr(d, "dict", 7), "dict"),
+    (lambda d: setattr(d, "prec", 9), "prec"),
+    (lambda d: setattr(d, "max_batch", 0), "max_batch"),
+    (lambda d: (setattr(d, "prec", A.ACT_PREC_F64), setattr(d, "dict", A.ACT_DICT_TABLE)), "F64"),
+])
+def test_plan_rejects_bad_descriptors_on_host(lib, mutate, needle):
+    desc = A.make_desc(W.eeg_grid(512, 32, 16, 16, 8))
+    mutate(desc)
+    st, msg = _plan_status(lib, desc)
+    assert st == A.ACT_ERR_INVALID
+    assert needle in msg
+
+
+def test_null_arguments_rejected(lib):
+    h = ctypes.c_void_p()
+    assert lib.act_plan(None, None, ctypes.byref(h)) == A.ACT_ERR_INVALID
+    assert lib.act_decompose(None, 1, None, None, None, None, 1, None, None, None, None, None,
+                             None, None) == A.ACT_ERR_INVALID
+    assert lib.act_refine(None, 1, None, None, 1, None, None, None, None) == A.ACT_ERR_INVALID
+    assert lib.act_reconstruct(None, 1, 1, None, None, None, None, None, None) == A.ACT_ERR_INVALID
+    assert lib.act_value_and_grad(None, 1, 0, None, None, None, None, None, None) == A.ACT_ERR_INVALID
+    assert lib.act_correlate(None, 1, None, 0, 1, None, None) == A.ACT_ERR_INVALID
+    assert lib.act_plan_query(None, 0) == -1
+    lib.act_plan_destroy(None)
+
+
+def test_status_strings(lib):
+    for s, name in enumerate(["ACT_OK", "ACT_ERR_INVALID", "ACT_ERR_NOMEM", "ACT_ERR_HIP",
+                              "ACT_ERR_UNSUPPORTED"]):
+        assert lib.act_status_string(s).decode() == name
+
+
+def test_binding_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        A.Plan(W.eeg_grid(512, 4, 4, 4, 2))
