@@ -188,6 +188,15 @@ act_status act_reconstruct(act_plan_t plan, int32_t batch, int32_t order, const 
 act_status act_correlate(act_plan_t plan, int32_t batch, const double* resid_dev,
                          int64_t atom_begin, int64_t atom_count, double* score_dev, void* stream);
 
+/* Phase timing of act_decompose, for measurement.  While enabled, every
+ * launch of each phase of an order -- 0: search, 1: exact-threshold rerun,
+ * 2: FP64 rescoring, 3: select/refine/update -- is bracketed by HIP events on
+ * the caller's stream.  act_timing_read synchronises on those events, writes
+ * the summed milliseconds ms[4] and launch counts launches[4] since the last
+ * read, and clears them.  Errors: ACT_ERR_INVALID (NULL plan or outputs). */
+act_status act_timing_enable(act_plan_t plan, int32_t enable);
+act_status act_timing_read(act_plan_t plan, double* ms, int64_t* launches);
+
 const char* act_status_string(act_status status);
 const char* act_last_error(void);
 

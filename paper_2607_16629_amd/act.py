@@ -52,8 +52,9 @@ class _PlanDesc(ctypes.Structure):
 
 
 EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_decompose", "act_refine",
-           "act_value_and_grad", "act_reconstruct", "act_correlate", "act_status_string",
-           "act_last_error")
+           "act_value_and_grad", "act_reconstruct", "act_correlate", "act_timing_enable",
+           "act_timing_read", "act_status_string", "act_last_error")
+PHASES = ("search", "rerun", "rescore", "select_refine_update")
 
 _lib = None
 
@@ -83,6 +84,10 @@ def load() -> ctypes.CDLL:
     lib.act_reconstruct.restype = ctypes.c_int
     lib.act_correlate.argtypes = [vp, i32, vp, i64, i64, vp, vp]
     lib.act_correlate.restype = ctypes.c_int
+    lib.act_timing_enable.argtypes = [vp, i32]
+    lib.act_timing_enable.restype = ctypes.c_int
+    lib.act_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64)]
+    lib.act_timing_read.restype = ctypes.c_int
     lib.act_status_string.argtypes = [ctypes.c_int]
     lib.act_status_string.restype = ctypes.c_char_p
     lib.act_last_error.argtypes = []
@@ -175,6 +180,16 @@ class Plan:
     @property
     def table_bytes(self) -> int:
         return self.query(Q_TABLE_BYTES)
+
+    def act_timing_enable(self, enable: bool = True):
+        _check(load().act_timing_enable(self._h, int(bool(enable))))
+
+    def act_timing_read(self) -> dict:
+        """{phase: (total ms, launches)} since the last read (synchronises)."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        _check(load().act_timing_read(self._h, ms, n))
+        return {PHASES[i]: (float(ms[i]), int(n[i])) for i in range(4)}
 
     def alloc_outputs(self, batch: int, order: int, approx: bool = True):
         dev = torch.device("cuda")

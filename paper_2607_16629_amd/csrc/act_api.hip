@@ -32,16 +32,62 @@ extern "C" const char* act_status_string(act_status s) {
 //   search (fused certified candidates) -> overflow check -> exact-threshold
 //   search of overflowed channels -> FP64 rescoring -> select, refine,
 //   coefficient, update.
+// Bracket one launch by a pair of events when timing is enabled.
+template <typename F>
+static act_status timed(act_plan_s* p, int phase, hipStream_t s, F&& launch) {
+    if (!p->timing) return launch();
+    if (p->ev_used == p->ev_pool.size()) {
+        hipEvent_t a, b;
+        ACT_HIP(hipEventCreate(&a));
+        ACT_HIP(hipEventCreate(&b));
+        p->ev_pool.push_back({a, b});
+        p->ev_phase.push_back(0);
+    }
+    auto& ev = p->ev_pool[p->ev_used];
+    p->ev_phase[p->ev_used] = phase;
+    ++p->ev_used;
+    ACT_HIP(hipEventRecord(ev.first, s));
+    act_status st = launch();
+    if (st != ACT_OK) return st;
+    ACT_HIP(hipEventRecord(ev.second, s));
+    return ACT_OK;
+}
+
 static act_status enqueue_order(act_plan_s* p, int batch, int k, int order, double* resid,
                                 double* approx, double* theta, double* coef, long long* index,
                                 double* energy, double* gap, int* flags, hipStream_t s) {
     act_status st;
-    if ((st = launch_search(p, batch, 0, s)) != ACT_OK) return st;
+    if ((st = timed(p, 0, s, [&] { return launch_search(p, batch, 0, s); })) != ACT_OK) return st;
     if ((st = launch_overflow_check(p, batch, s)) != ACT_OK) return st;
-    if ((st = launch_search(p, batch, 1, s)) != ACT_OK) return st;
-    if ((st = launch_rescore(p, batch, resid, s)) != ACT_OK) return st;
-    return launch_select_refine_update(p, batch, k, order, resid, approx, theta, coef, index, energy,
-                                       gap, flags, s);
+    if ((st = timed(p, 1, s, [&] { return launch_search(p, batch, 1, s); })) != ACT_OK) return st;
+    if ((st = timed(p, 2, s, [&] { return launch_rescore(p, batch, resid, s); })) != ACT_OK) return st;
+    return timed(p, 3, s, [&] {
+        return launch_select_refine_update(p, batch, k, order, resid, approx, theta, coef, index,
+                                           energy, gap, flags, s);
+    });
+}
+
+extern "C" act_status act_timing_enable(act_plan_t p, int32_t enable) {
+    ACT_REQUIRE(p != nullptr, "act_timing_enable: plan is NULL");
+    p->timing = enable != 0;
+    return ACT_OK;
+}
+
+extern "C" act_status act_timing_read(act_plan_t p, double* ms, int64_t* launches) {
+    ACT_REQUIRE(p != nullptr && ms != nullptr && launches != nullptr, "act_timing_read: NULL argument");
+    for (int i = 0; i < 4; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    for (size_t i = 0; i < p->ev_used; ++i) {
+        ACT_HIP(hipEventSynchronize(p->ev_pool[i].second));
+        float t = 0.0f;
+        ACT_HIP(hipEventElapsedTime(&t, p->ev_pool[i].first, p->ev_pool[i].second));
+        ms[p->ev_phase[i]] += t;
+        launches[p->ev_phase[i]] += 1;
+    }
+    p->ev_used = 0;
+    return ACT_OK;
 }
 
 extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* len_dev,

@@ -165,6 +165,12 @@ struct act_plan_s {
     int chain = 0;                          // FP32 score FMA-chain length (certified margin)
 
     hipStream_t last_stream = nullptr;
+
+    // phase timing (act_timing_enable): event pairs recorded per launch
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    std::vector<int> ev_phase;
+    size_t ev_used = 0;
 };
 
 namespace act {

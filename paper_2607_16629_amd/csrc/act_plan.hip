@@ -134,6 +134,10 @@ static void free_plan(act_plan_s* p) {
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    for (auto& ev : p->ev_pool) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
     delete p;
 }
 
