@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "fp32-1x2048": ("fp32_1x2048", dict(dict_="table", prec="f32"), "hbm", 4),
     "plain-1x512": ("plain_1x512", dict(dict_="synth", prec="f64"), "alu", 0),
+    "bf16-64x2048": ("batched_64x2048", dict(dict_="table", prec="bf16"), "hbm", 2),
 }
 
 
@@ -152,13 +153,18 @@ def main():
     if bound == "hbm":
         algo_bytes = g.size * g.n * elt + B * g.n * elt
         achieved = algo_bytes / (search_ms * 1e-3) / 1e9
-        sha = source_sha("act_search.hip")
+        sha = source_sha({"f32": "act_search_f32t.hip", "bf16": "act_search_bf16.hip"}[plan_kw["prec"]],
+                         "act_emit.h")
         traffic = committed_traffic(wl.name, sha)
+        kern = {"f32": "k_search_f32_table", "bf16": "k_search_bf16_table"}[plan_kw["prec"]]
         line["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                            "traffic": traffic, "kernel": "k_search_f32_table",
+                            "traffic": traffic, "kernel": kern,
                             "algorithmic_bytes_per_launch": algo_bytes,
                             "avg_launch_ms": round(search_ms, 5)}
+        if plan_kw["prec"] == "bf16":
+            flops = 2.0 * g.size * g.n * B
+            line["roofline"]["mfma_frac_of_bf16_peak"] = round(flops / (search_ms * 1e-3) / 2.5e15, 4)
     else:
         # FP64 on-the-fly synthesis: counted as FP64 ALU work per sample
         # (exp + cospi + the dot products ~ 60 FP64 ops); reported against

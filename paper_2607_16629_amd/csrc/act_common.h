@@ -145,6 +145,8 @@ struct act_plan_s {
     double* axis_dev = nullptr;
 
     // dictionary table (ACT_DICT_TABLE)
+    long long atoms_pad = 0;  // table rows (BF16: multiple of the 512-atom MFMA tile)
+    double* inv_norm = nullptr;  // [atoms] 1/|g_i| in FP64 (tables only)
     void* table = nullptr;
     size_t table_bytes = 0;
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
@@ -180,6 +182,7 @@ act_status launch_correlate(act_plan_s* p, int batch, const double* resid, long 
                             long long count, double* out, hipStream_t s);
 // plan-time builders (act_plan.hip)
 act_status build_tables(act_plan_s* p, hipStream_t s);
+act_status write_bf16_table(act_plan_s* p, hipStream_t s);
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
                        int* flags, int order, hipStream_t s);

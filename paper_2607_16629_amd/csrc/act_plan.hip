@@ -48,11 +48,13 @@ __device__ __forceinline__ float d_bf16_to_f32(unsigned short h) {
 }
 
 // One wave per atom: FP64 synthesis of Eq. (1) over the n samples present,
-// unit l2 normalisation (Sec. III-A), rounding to the table type (RNE), and
-// the exact l2 norm of the rounding error, whose maximum over the dictionary
-// enters the certified margin of the search.
-template <typename TOut>
+// unit l2 normalisation (Sec. III-A), the FP64 inverse norm, rounding to the
+// table type (RNE; FP32 rows are written here, BF16 tiles by the swizzled
+// writer), and the exact l2 norm of the rounding error, whose maximum over the
+// dictionary enters the certified margin of the search.
+template <typename TOut, bool WRITE>
 __global__ void __launch_bounds__(256) k_build_table(GridDev g, TOut* __restrict__ table,
+                                                     double* __restrict__ inv_norm,
                                                      unsigned long long* __restrict__ eg_bits) {
     const int lane = threadIdx.x & (kWave - 1);
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -68,20 +70,21 @@ __global__ void __launch_bounds__(256) k_build_table(GridDev g, TOut* __restrict
         }
         q = wave_sum(q);
         const double nrm = sqrt(q);
-        const bool ok = nrm >= 1e-300;
+        const double sc = nrm >= 1e-300 ? 1.0 / nrm : 0.0;
+        if (lane == 0) inv_norm[i] = sc;
         double e2 = 0.0;
         TOut* row = table + (size_t)i * g.n_pad;
         for (int k = lane; k < g.n_pad; k += kWave) {
             double v = 0.0;
-            if (ok && k < g.n) v = atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt) / nrm;
+            if (k < g.n) v = atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt) * sc;
             float f = (float)v;
             double back;
             if constexpr (sizeof(TOut) == 4) {
-                row[k] = f;
+                if (WRITE) row[k] = f;
                 back = (double)f;
             } else {
                 unsigned short h = d_bf16_rne(f);
-                row[k] = h;
+                if (WRITE) row[k] = h;
                 back = (double)d_bf16_to_f32(h);
             }
             double d = back - v;
@@ -110,13 +113,17 @@ act_status build_tables(act_plan_s* p, hipStream_t s) {
     ACT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     long long waves_needed = p->atoms;
     int blocks = (int)std::min<long long>((waves_needed + 3) / 4, (long long)cus * 32);
-    if (p->desc.prec == ACT_PREC_F32)
-        hipLaunchKernelGGL(k_build_table<float>, dim3(blocks), dim3(256), 0, s, p->grid,
-                           (float*)p->table, eg);
-    else
-        hipLaunchKernelGGL(k_build_table<unsigned short>, dim3(blocks), dim3(256), 0, s, p->grid,
-                           (unsigned short*)p->table, eg);
-    ACT_HIP(hipGetLastError());
+    if (p->desc.prec == ACT_PREC_F32) {
+        hipLaunchKernelGGL((k_build_table<float, true>), dim3(blocks), dim3(256), 0, s, p->grid,
+                           (float*)p->table, p->inv_norm, eg);
+        ACT_HIP(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL((k_build_table<unsigned short, false>), dim3(blocks), dim3(256), 0, s, p->grid,
+                           (unsigned short*)nullptr, p->inv_norm, eg);
+        ACT_HIP(hipGetLastError());
+        act_status st = write_bf16_table(p, s);
+        if (st != ACT_OK) return st;
+    }
     unsigned long long bits = 0;
     ACT_HIP(hipMemcpyAsync(&bits, eg, sizeof bits, hipMemcpyDeviceToHost, s));
     ACT_HIP(hipStreamSynchronize(s));
@@ -130,7 +137,7 @@ act_status build_tables(act_plan_s* p, hipStream_t s) {
 static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
-    void* ptrs[] = {p->axis_dev, p->table, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+    void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -167,7 +174,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         set_error("act_plan: ragged plans are not implemented in this build");
         return ACT_ERR_UNSUPPORTED;
     }
-    if (desc->prec == ACT_PREC_BF16 || (desc->prec == ACT_PREC_F32 && desc->dict == ACT_DICT_SYNTH)) {
+    if (desc->dict == ACT_DICT_SYNTH && desc->prec != ACT_PREC_F64) {
         set_error("act_plan: this precision / dictionary pair is not implemented in this build");
         return ACT_ERR_UNSUPPORTED;
     }
@@ -178,7 +185,10 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     p->n = gr.n_samples;
     p->n_pad = (gr.n_samples + 255) / 256 * 256;
     p->max_batch = desc->max_batch;
-    p->chain = f32_chain_length(p->n_pad);
+    // longest FP32 accumulation chain of one search score (certified margin):
+    // the FP32 GEMV's per-lane FMAs plus its reduction tree; the MFMA path is
+    // bounded by one rounding per sample
+    p->chain = desc->prec == ACT_PREC_BF16 ? p->n_pad : f32_chain_length(p->n_pad);
     p->cap = desc->cand_cap > 0 ? desc->cand_cap : 4096;
     const act_axis* ax[4] = {&gr.tc_s, &gr.fc_hz, &gr.c_hz_per_s, &gr.logdt_ln_s};
     long long atoms = 1;
@@ -225,8 +235,9 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
 
     const size_t B = (size_t)p->max_batch, cap = (size_t)p->cap;
     const size_t elt = desc->prec == ACT_PREC_BF16 ? 2 : 4;
+    p->atoms_pad = desc->prec == ACT_PREC_BF16 ? (atoms + 511) / 512 * 512 : atoms;
     if (desc->dict == ACT_DICT_TABLE) {
-        p->table_bytes = (size_t)atoms * p->n_pad * elt;
+        p->table_bytes = (size_t)p->atoms_pad * p->n_pad * elt;
         size_t free_b = 0, total_b = 0;
         PLAN_HIP(hipMemGetInfo(&free_b, &total_b));
         if (p->table_bytes + (64ull << 20) > free_b) {
@@ -235,6 +246,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             return fail(ACT_ERR_NOMEM);
         }
         PLAN_HIP(hipMalloc(&p->table, p->table_bytes));
+        PLAN_HIP(hipMalloc((void**)&p->inv_norm, (size_t)atoms * sizeof(double)));
     }
     PLAN_HIP(hipMalloc(&p->shadow, B * p->n_pad * elt));
     PLAN_HIP(hipMemsetAsync(p->shadow, 0, B * p->n_pad * elt, s));

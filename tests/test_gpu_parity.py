@@ -76,7 +76,10 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label=""):
 # correlation scores
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,dict_,tol", [("f64", "synth", 1e-12), ("f32", "table", 1e-5)])
+# BF16 operands: |p~ - p| <= (|e_g| + |e_r|/|r| + gamma_N) |r| with both
+# rounding terms below 2^-8; 8e-3 |r| is the resulting certified bound.
+@pytest.mark.parametrize("prec,dict_,tol", [("f64", "synth", 1e-12), ("f32", "table", 1e-5),
+                                            ("bf16", "table", 8e-3)])
 def test_correlate_matches_oracle(oracle, prec, dict_, tol):
     wl = W.plain_1x512()
     g = wl.grid
@@ -91,22 +94,26 @@ def test_correlate_matches_oracle(oracle, prec, dict_, tol):
         assert err <= tol, (prec, begin, err)
 
 
-def test_correlate_f32_many_channels_and_ragged_tail(oracle):
-    g = W.eeg_grid(300, 8, 8, 6, 4)   # n not a multiple of 256: padded rows
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16", 8e-3)])
+def test_correlate_many_channels_and_ragged_tail(oracle, prec, tol):
+    g = W.eeg_grid(300, 8, 8, 6, 5)   # n not a multiple of 256, atoms not of 512
     rng = np.random.default_rng(11)
     sig = rng.standard_normal((3, g.n))
-    plan = A().Plan(g, dict_="table", prec="f32", max_batch=3)
+    plan = A().Plan(g, dict_="table", prec=prec, max_batch=3)
     p = plan.act_correlate(sig, 0, g.size).cpu().numpy()
     for b in range(3):
         ref = oracle.correlate(g, sig[b])
-        assert np.max(np.abs(p[b] - ref)) <= 1e-5 * np.linalg.norm(sig[b])
+        assert np.max(np.abs(p[b] - ref)) <= tol * np.linalg.norm(sig[b])
+    # a range that starts and ends inside MFMA tiles
+    q = plan.act_correlate(sig, 700, 411).cpu().numpy()
+    np.testing.assert_array_equal(q, p[:, 700:1111])
 
 
 # --------------------------------------------------------------------------
 # full decompositions
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table")])
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table")])
 def test_decompose_plain_1x512(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, wl.order, refine_steps=30)
@@ -115,7 +122,7 @@ def test_decompose_plain_1x512(oracle, prec, dict_):
     assert n == wl.order
 
 
-@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table")])
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table")])
 def test_decompose_without_refinement_is_exact_mp(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, 8, refine_steps=0)
@@ -131,7 +138,7 @@ def test_decompose_batch_with_edge_channels(oracle):
     sig = wl.signals.copy()
     sig[2] = 0.0
     sig[3, 17] = np.nan
-    for prec, dict_ in [("f64", "synth"), ("f32", "table")]:
+    for prec, dict_ in [("f64", "synth"), ("f32", "table"), ("bf16", "table")]:
         # a coarse grid: the optimum can lie beyond one step, so give the
         # refinement room to converge (parity is judged at convergence)
         gpu = gpu_decompose(g, sig, 4, prec, dict_, refine_steps=60)
@@ -152,13 +159,27 @@ def test_decompose_deterministic():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-def test_small_candidate_capacity_reruns_exactly(oracle):
-    """A capacity of 2 forces the exact-threshold rerun pass; the result must
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_small_candidate_capacity_reruns_exactly(oracle, prec):
+    """A tiny capacity forces the exact-threshold rerun pass; the result must
     not change."""
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, 3, refine_steps=0)
-    gpu = gpu_decompose(wl.grid, wl.signals, 3, "f32", "table", refine_steps=0, cand_cap=2)
+    gpu = gpu_decompose(wl.grid, wl.signals, 3, prec, "table", refine_steps=0,
+                        cand_cap=2 if prec == "f32" else 40)
     assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals)
+
+
+def test_bf16_batch_of_70_channels(oracle):
+    """More than one 64-channel tile, a reduced grid; the oracle checks a
+    few channels from both tiles (channels are independent)."""
+    g = W.eeg_grid(1024, 16, 16, 8, 6)
+    wl = W.batched_64x2048(channels=70, grid=g, order=4)
+    gpu = gpu_decompose(g, wl.signals, 4, "bf16", "table", refine_steps=30)
+    pick = [0, 33, 63, 64, 69]
+    ref = oracle.decompose(g, wl.signals[pick], 4, refine_steps=30)
+    sub = {k: (v[pick] if v is not None else None) for k, v in gpu.items()}
+    assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick]) >= 15
 
 
 def test_fp32_full_size_2m_atoms(oracle):
@@ -191,6 +212,37 @@ def test_fp32_full_size_2m_atoms(oracle):
         assert abs(gpu["energy"][0, k + 1] - float(r @ r)) <= 1e-6 * float(r @ r)
     E = gpu["energy"][0]
     np.testing.assert_allclose(E[1:], E[:-1] - gpu["coef"][0] ** 2, rtol=0, atol=1e-10 * E[0])
+
+
+def test_bf16_full_size_64x2048(oracle):
+    """64 channels x N = 2048 on the 2,097,152-atom grid, BF16 table + FP64
+    rescoring: per order and for sampled channels, the winner's oracle score
+    is not beaten by sampled atoms, the refined parameters equal the oracle's
+    refinement from the same grid point, and the MP identities hold."""
+    wl = W.batched_64x2048()
+    g = wl.grid
+    order = 2
+    gpu = gpu_decompose(g, wl.signals, order, "bf16", "table", refine_steps=30)
+    step, _, _ = oracle.refine_box(g)
+    rng = np.random.default_rng(16)
+    sample = rng.choice(g.size, 1500, replace=False)
+    for b in (0, 31, 63):
+        r = wl.signals[b].copy()
+        for k in range(order):
+            rn = float(np.linalg.norm(r))
+            i = int(gpu["index"][b, k])
+            p_win = oracle.correlate(g, r, i, 1)[0]
+            p_s = np.array([oracle.correlate(g, r, int(j), 1)[0] for j in sample])
+            assert np.all(np.abs(p_s) <= abs(p_win) + 1e-12 * rn)
+            th, J, _ = oracle.refine(g, r, oracle.grid_theta(g, i), 30)
+            dth = np.abs(gpu["theta"][b, k] - th)
+            assert np.all(dth <= 1e-6 * np.maximum(np.abs(th), step)), (b, k, dth)
+            gu, _ = oracle.atom_unit(g.fs, g.n, gpu["theta"][b, k])
+            r = r - gpu["coef"][b, k] * gu
+            assert abs(gpu["energy"][b, k + 1] - float(r @ r)) <= 1e-6 * float(r @ r)
+    E = gpu["energy"]
+    np.testing.assert_allclose(E[:, 1:], E[:, :-1] - gpu["coef"] ** 2, rtol=0, atol=1e-10 * E[:, :1].max())
+    assert np.all(gpu["flags"] & A().FLAG_CAND_OVERFLOW == 0)
 
 
 # --------------------------------------------------------------------------
