@@ -3,20 +3,25 @@
 
 One step = one act_decompose call: every order of the pursuit (search,
 certified FP64 rescoring, refinement, coefficient, update) over one batch of
-seeded synthetic signals that are already resident in HBM.  Prints one JSON
-line: GMAC/s of the dense correlation work (atoms x samples x orders x
-channels per second), MP iterations/s, a roofline object for the search
-kernel measured live with HIP events on the launch stream, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+seeded synthetic signals already resident in HBM.  The default run measures
+the metric "GMAC/s + MP iters/s, BF16+rescore vs plain FP32":
+  * value: the plain FP32 search of one 2048-sample channel against the
+    2,097,152-atom dictionary streamed from an HBM table (10 orders);
+  * companions in the same line: the same workload with the dictionary
+    synthesised on the device, and the BF16 + FP64-rescore search of 64
+    channels (20 orders).
+GMAC/s counts the dense correlation work atoms x samples x orders x channels.
+The roofline object of each leg uses its search kernel's mean launch time,
+measured with HIP events that the library records on the launch stream.  The
+FP64 CPU oracle is timed on a bounded sample of the primary workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-companions]
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import re
 import sys
@@ -27,13 +32,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "residual-chirplet GMAC/s + MP iters/s, BF16+rescore vs plain FP32, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32_mfma": 157.3, "bf16_mfma": 2500.0, "f64_vector": 78.6}
 
-# name -> (workload factory, plan kwargs, bound, element bytes of the streamed table)
+# name -> (workload factory, plan kwargs, roofline kind, table element bytes)
 WORKLOADS = {
     "fp32-1x2048": ("fp32_1x2048", dict(dict_="table", prec="f32"), "hbm", 4),
-    "plain-1x512": ("plain_1x512", dict(dict_="synth", prec="f64"), "alu", 0),
+    "fp32-1x2048-synth": ("fp32_1x2048", dict(dict_="synth", prec="f32"), "mfma_f32", 0),
     "bf16-64x2048": ("batched_64x2048", dict(dict_="table", prec="bf16"), "hbm", 2),
+    "plain-1x512": ("plain_1x512", dict(dict_="synth", prec="f64"), "f64", 0),
 }
+KERNELS = {("table", "f32"): ("k_search_f32_table", "act_search_f32t.hip"),
+           ("table", "bf16"): ("k_search_bf16_table", "act_search_bf16.hip"),
+           ("synth", "f32"): ("k_search_synth_f32", "act_search_synth.hip"),
+           ("synth", "f64"): ("k_search_f64", "act_search_f64.hip")}
 
 
 def source_sha(*names) -> str:
@@ -72,36 +83,21 @@ def cpu_baseline(wl, seconds: float):
     t0 = time.perf_counter()
     oracle.correlate(g, r, 0, count)
     dt = time.perf_counter() - t0
-    return {"value": count * g.n / dt / 1e9, "unit": "GMAC/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"order-1 correlation of channel 0 against atoms [0, {count}) of {g.size} "
-                      f"({dt:.1f} s, FP64, OpenMP over atoms)"}
+    return {"value": round(count * g.n / dt / 1e9, 4), "unit": "GMAC/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"order-1 FP64 correlation of channel 0 of {wl.name} against atoms "
+                      f"[0, {count}) of {g.size} ({dt:.1f} s, OpenMP over atoms)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="fp32-1x2048", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
-        sys.exit(2)
-
+def run_workload(name: str, steps: int, warmup: int):
     import torch
     from paper_2607_16629_amd import act
     from paper_2607_16629_amd import workloads as W
 
-    factory, plan_kw, bound, elt = WORKLOADS[args.workload]
+    factory, plan_kw, kind, elt = WORKLOADS[name]
     wl = getattr(W, factory)()
     g = wl.grid
     B, order = wl.signals.shape[0], wl.order
-    torch.cuda.set_device(0)
     plan = act.Plan(g, max_batch=B, refine_steps=wl.refine_steps, **plan_kw)
     sig = torch.from_numpy(wl.signals).cuda()
     resid = torch.empty_like(sig)
@@ -111,6 +107,113 @@ def main():
         resid.copy_(sig)
         plan.act_decompose(resid, order, out)
 
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.act_timing_enable(True)
+    plan.act_timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = plan.act_timing_read()
+    plan.act_timing_enable(False)
+    flags = out["flags"].cpu().numpy()
+    plan.close()
+
+    s_ms, s_n = phases["search"]
+    search_ms = s_ms / max(s_n, 1)
+    res = {
+        "workload": wl.name, "value": round(g.size * g.n * order * B * steps / wall / 1e9, 3),
+        "unit": "GMAC/s", "ms_per_step": round(wall * 1e3 / steps, 4),
+        "mp_iters_per_s": round(order * steps / wall, 3),
+        "channel_iters_per_s": round(order * B * steps / wall, 3),
+        "search_only_gmac_per_s": round(g.size * g.n * B / (search_ms * 1e-3) / 1e9, 3),
+        "dtype": plan_kw["prec"],
+        "config": {"workload": wl.name, "atoms": g.size, "n_samples": g.n, "channels": B,
+                   "order": order, "dict": plan_kw["dict_"], "refine_steps": wl.refine_steps,
+                   "parallelism": "single-gpu"},
+        "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
+        "candidate_overflow_channels": int(((flags & act.FLAG_CAND_OVERFLOW) != 0).sum()),
+    }
+    kname, ksrc = KERNELS[(plan_kw["dict_"], plan_kw["prec"])]
+    if kind == "hbm":
+        algo_bytes = g.size * g.n * elt + B * g.n * elt
+        achieved = algo_bytes / (search_ms * 1e-3) / 1e9
+        traffic = committed_traffic(wl.name, source_sha(ksrc, "act_emit.h"))
+        res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": traffic, "kernel": kname,
+                           "algorithmic_bytes_per_launch": algo_bytes,
+                           "avg_launch_ms": round(search_ms, 5)}
+        if plan_kw["prec"] == "bf16":
+            flops = 2.0 * g.size * g.n * B
+            res["roofline"]["mfma_frac_of_bf16_peak"] = round(
+                flops / (search_ms * 1e-3) / (PEAK_TFLOPS["bf16_mfma"] * 1e12), 4)
+    elif kind == "mfma_f32":
+        # factored synthesis: the matrix cores execute 2 x (atoms x N x B)
+        # multiply-adds; the roofline counts the dense correlation's flops
+        algo = 2.0 * g.size * g.n * B
+        achieved = algo / (search_ms * 1e-3) / 1e12
+        peak = PEAK_TFLOPS["f32_mfma"]
+        res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                           "kernel": kname, "avg_launch_ms": round(search_ms, 5),
+                           "algorithmic_flops_per_launch": algo,
+                           "executed_mfma_flops_per_launch": 2 * algo}
+    else:
+        # FP64 on-the-fly synthesis, ~60 FP64 operations per atom sample
+        ops = g.size * g.n * B * 60
+        achieved = ops / (search_ms * 1e-3) / 1e12
+        peak = PEAK_TFLOPS["f64_vector"]
+        res["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                           "kernel": kname, "avg_launch_ms": round(search_ms, 5)}
+    return res, wl
+
+
+def run_refine(steps: int, warmup: int):
+    """act_refine on 4096 (residual, start) pairs, 30 L-BFGS iterations each."""
+    import torch
+    from paper_2607_16629_amd import act
+    from paper_2607_16629_amd import workloads as W
+    wl = W.refine_pairs()
+    plan = act.Plan(wl.grid, dict_="synth", prec="f64")
+    r = torch.from_numpy(wl.signals).cuda()
+    th0 = torch.from_numpy(wl.theta0).cuda()
+    for _ in range(warmup):
+        plan.act_refine(r, th0, wl.refine_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.act_refine(r, th0, wl.refine_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"workload": wl.name, "value": round(r.shape[0] * steps / wall, 2),
+            "unit": "refinements/s", "ms_per_step": round(wall * 1e3 / steps, 4),
+            "config": {"workload": wl.name, "pairs": r.shape[0], "n_samples": wl.grid.n,
+                       "lbfgs_steps": wl.refine_steps}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="fp32-1x2048", choices=sorted(WORKLOADS) + ["refine-4096"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-companions", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -118,62 +221,27 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    plan.act_timing_enable(True)
-    plan.act_timing_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    phases = plan.act_timing_read()
-    plan.act_timing_enable(False)
+    if args.workload == "refine-4096":
+        res = run_refine(args.steps, args.warmup)
+        line = {"metric": "refinements/s (4096 pairs x 30 L-BFGS iterations, FP64)", **res,
+                "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64", "data": "synthetic"}
+        print(json.dumps(line), flush=True)
+        return
 
-    macs_per_step = g.size * g.n * order * B
-    ms_step = wall * 1e3 / args.steps
-    value = macs_per_step * args.steps / wall / 1e9
-    s_ms, s_n = phases["search"]
-    search_ms = s_ms / max(s_n, 1)
-    line = {
-        "metric": METRIC, "value": round(value, 3), "unit": "GMAC/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": plan_kw["prec"], "data": "synthetic",
-        "config": {"workload": wl.name, "atoms": g.size, "n_samples": g.n, "channels": B,
-                   "order": order, "dict": plan_kw["dict_"], "refine_steps": wl.refine_steps,
-                   "parallelism": "single-gpu"},
-        "mp_iters_per_s": round(order * args.steps / wall, 3),
-        "channel_iters_per_s": round(order * B * args.steps / wall, 3),
-        "search_only_gmac_per_s": round(g.size * g.n * B / (search_ms * 1e-3) / 1e9, 3),
-        "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
-    }
-    if bound == "hbm":
-        algo_bytes = g.size * g.n * elt + B * g.n * elt
-        achieved = algo_bytes / (search_ms * 1e-3) / 1e9
-        sha = source_sha({"f32": "act_search_f32t.hip", "bf16": "act_search_bf16.hip"}[plan_kw["prec"]],
-                         "act_emit.h")
-        traffic = committed_traffic(wl.name, sha)
-        kern = {"f32": "k_search_f32_table", "bf16": "k_search_bf16_table"}[plan_kw["prec"]]
-        line["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                            "traffic": traffic, "kernel": kern,
-                            "algorithmic_bytes_per_launch": algo_bytes,
-                            "avg_launch_ms": round(search_ms, 5)}
-        if plan_kw["prec"] == "bf16":
-            flops = 2.0 * g.size * g.n * B
-            line["roofline"]["mfma_frac_of_bf16_peak"] = round(flops / (search_ms * 1e-3) / 2.5e15, 4)
-    else:
-        # FP64 on-the-fly synthesis: counted as FP64 ALU work per sample
-        # (exp + cospi + the dot products ~ 60 FP64 ops); reported against
-        # the FP64 vector peak.
-        ops = g.size * g.n * B * 60
-        achieved = ops / (search_ms * 1e-3) / 1e12
-        line["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": 78.6,
-                            "unit": "TFLOP/s", "frac": round(achieved / 78.6, 4), "traffic": None,
-                            "kernel": "k_search_f64", "avg_launch_ms": round(search_ms, 5)}
+    res, wl = run_workload(args.workload, args.steps, args.warmup)
+    line = {"metric": METRIC, "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": res.pop("dtype"), "data": "synthetic", "config": res.pop("config")}
+    line.update(res)
+    if args.workload == "fp32-1x2048" and not args.no_companions:
+        comp = {}
+        for name in ("fp32-1x2048-synth", "bf16-64x2048"):
+            c, _ = run_workload(name, args.steps, args.warmup)
+            comp[name] = c
+        line["companions"] = comp
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -141,7 +141,11 @@ int64_t act_plan_query(act_plan_t plan, int32_t key);
  *   gap_dev     out: [batch][order] lower bound of (|p|_(1)-|p|_(2))/|p|_(1),
  *               the relative margin of the coarse winner, or NULL.
  *   flags_dev   out: [batch] ACT_FLAG_* bits.
- * The whole pass runs on the device; the host enqueues it and returns.
+ * The whole pass runs on the device; the host enqueues it and returns.  The
+ * first call with a given set of (batch, order, pointer) arguments captures
+ * the launch sequence into a HIP graph owned by the plan (at most 4 are kept);
+ * later calls with the same arguments replay it as a single launch on
+ * `stream`.  Phase timing (act_timing_enable) launches the kernels directly.
  * Errors: ACT_ERR_INVALID (batch outside [1, max_batch], order < 1, NULL
  * required pointer, ragged pointers missing or given to a plain plan). */
 act_status act_decompose(act_plan_t plan, int32_t batch, const int32_t* len_dev,

@@ -108,13 +108,62 @@ extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* 
     hipStream_t s = (hipStream_t)stream;
     p->last_stream = s;
     p->search_resid = resid_dev;
-    act_status st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, s);
-    if (st != ACT_OK) return st;
-    for (int k = 0; k < order; ++k) {
-        st = enqueue_order(p, batch, k, order, resid_dev, approx_dev, theta_dev, coef_dev,
-                           (long long*)index_dev, energy_dev, gap_dev, flags_dev, s);
+    auto enqueue_all = [&](hipStream_t q) -> act_status {
+        act_status st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, q);
         if (st != ACT_OK) return st;
+        for (int k = 0; k < order; ++k) {
+            st = enqueue_order(p, batch, k, order, resid_dev, approx_dev, theta_dev, coef_dev,
+                               (long long*)index_dev, energy_dev, gap_dev, flags_dev, q);
+            if (st != ACT_OK) return st;
+        }
+        return ACT_OK;
+    };
+    if (p->timing || !p->use_graphs) return enqueue_all(s);
+
+    // One captured graph per argument signature, replayed on the caller's
+    // stream: the whole pursuit becomes a single launch from the host.
+    std::vector<uintptr_t> key = {(uintptr_t)batch, (uintptr_t)order, (uintptr_t)resid_dev,
+                                  (uintptr_t)approx_dev, (uintptr_t)theta_dev, (uintptr_t)coef_dev,
+                                  (uintptr_t)index_dev, (uintptr_t)energy_dev, (uintptr_t)gap_dev,
+                                  (uintptr_t)flags_dev};
+    for (auto& ge : p->graphs) {
+        if (ge.key == key) {
+            ge.last_use = ++p->graph_clock;
+            ACT_HIP(hipGraphLaunch(ge.exec, s));
+            return ACT_OK;
+        }
     }
+    // capture records without executing; the graph then runs in order on `s`
+    if (!p->cap_stream) ACT_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    ACT_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    act_status st = enqueue_all(p->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(p->cap_stream, &graph);
+    if (st != ACT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ce != hipSuccess) {
+        set_error(std::string("act_decompose: graph capture failed: ") + hipGetErrorString(ce));
+        return ACT_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        set_error(std::string("act_decompose: graph instantiation failed: ") + hipGetErrorString(ie));
+        return ACT_ERR_HIP;
+    }
+    if (p->graphs.size() >= 4) {  // evict the least recently used graph
+        size_t lru = 0;
+        for (size_t i = 1; i < p->graphs.size(); ++i)
+            if (p->graphs[i].last_use < p->graphs[lru].last_use) lru = i;
+        ACT_HIP(hipGraphExecDestroy(p->graphs[lru].exec));
+        ACT_HIP(hipGraphDestroy(p->graphs[lru].graph));
+        p->graphs.erase(p->graphs.begin() + lru);
+    }
+    p->graphs.push_back({key, graph, exec, ++p->graph_clock});
+    ACT_HIP(hipGraphLaunch(exec, s));
     return ACT_OK;
 }
 

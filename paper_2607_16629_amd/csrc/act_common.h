@@ -104,7 +104,10 @@ __device__ __forceinline__ T wave_max(T v) {
 }
 
 // Sum NV doubles over a block of NT threads; every thread receives the totals.
-// `lds` must hold NV * (NT / 64) doubles.  Deterministic: fixed order.
+// `lds` must hold block_sum_lds(NT, NV) doubles.  Deterministic: fixed order
+// (wave butterflies, then thread j adds the wave partials of value j in order).
+constexpr int block_sum_lds(int nt, int nv) { return nv * (nt / kWave + 1); }
+
 template <int NT, int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
     constexpr int NW = NT / kWave;
@@ -117,13 +120,15 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
         for (int j = 0; j < NV; ++j) lds[j * NW + w] = v[j];
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
+    if (threadIdx.x < NV) {
         double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < NW; ++k) s += lds[j * NW + k];
-        v[j] = s;
+#pragma unroll 1
+        for (int k = 0; k < NW; ++k) s += lds[threadIdx.x * NW + k];
+        lds[NV * NW + threadIdx.x] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = lds[NV * NW + j];
     __syncthreads();
 }
 
@@ -149,6 +154,17 @@ struct act_plan_s {
     double* inv_norm = nullptr;  // [atoms] 1/|g_i| in FP64 (tables only)
     void* table = nullptr;
     size_t table_bytes = 0;
+
+    // synthesised dictionary (ACT_DICT_SYNTH with FP32): shift-invariant
+    // factor tables [rows][fac_w], FP32 inverse norms, integer time centres
+    void* fac_u = nullptr;
+    void* fac_v = nullptr;
+    void* fac_c = nullptr;
+    void* fac_s = nullptr;
+    int fac_w = 0, n_cl = 0;
+    float* inv_norm32 = nullptr;
+    int* tc_shift = nullptr;
+    double rho_max = 0.0;     // max over atoms of |envelope|_2 / |g|_2
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
 
     // per-channel workspace [max_batch]
@@ -168,6 +184,18 @@ struct act_plan_s {
 
     hipStream_t last_stream = nullptr;
 
+    // captured act_decompose sequences, keyed by every argument (small LRU)
+    struct GraphEntry {
+        std::vector<uintptr_t> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        unsigned long long last_use = 0;
+    };
+    std::vector<GraphEntry> graphs;
+    unsigned long long graph_clock = 0;
+    hipStream_t cap_stream = nullptr;
+    bool use_graphs = true;
+
     // phase timing (act_timing_enable): event pairs recorded per launch
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -183,6 +211,7 @@ act_status launch_correlate(act_plan_s* p, int batch, const double* resid, long 
 // plan-time builders (act_plan.hip)
 act_status build_tables(act_plan_s* p, hipStream_t s);
 act_status write_bf16_table(act_plan_s* p, hipStream_t s);
+act_status build_synth(act_plan_s* p, hipStream_t s);
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
                        int* flags, int order, hipStream_t s);
@@ -199,6 +228,7 @@ act_status launch_value_and_grad(act_plan_s* p, int m, int dtype, const void* re
                                  hipStream_t s);
 act_status launch_to_shadow(act_plan_s* p, int batch, const double* resid, hipStream_t s);
 int f32_chain_length(int n_pad);
+int synth_chain_length(int n_pad);
 act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double* theta,
                               const double* coef, double* out, hipStream_t s);
 }  // namespace act

@@ -2,6 +2,7 @@
 // dictionary table (FP64 synthesis -> unit norm -> FP32 / BF16 rows), and the
 // per-channel workspace.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -95,6 +96,96 @@ __global__ void __launch_bounds__(256) k_build_table(GridDev g, TOut* __restrict
     }
 }
 
+// Shift-invariant factor tables of the synthesised dictionary, FP64-evaluated
+// and rounded to FP32 (RNE): for column e the lag is d = e - n_pad, tau = d/fs,
+//   U_cl = E cos(2 pi c tau^2), V_cl = E sin(2 pi c tau^2), E = exp(-(tau/dt)^2/2),
+//   C_fc = cos(2 pi f_c tau),   S_fc = sin(2 pi f_c tau).
+__global__ void k_build_factors(GridDev g, int W, float* __restrict__ U, float* __restrict__ V,
+                                float* __restrict__ C, float* __restrict__ S) {
+    const int n_cl = g.cnt[2] * g.cnt[3], n_fc = g.cnt[1];
+    const long long total = (long long)(n_cl + n_fc) * W;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int row = (int)(q / W), e = (int)(q % W);
+        const double tau = (double)(e - g.n_pad) / g.fs;
+        if (row < n_cl) {
+            const int ic = row / g.cnt[3], il = row % g.cnt[3];
+            const double c = g.axis[g.off[2] + ic];
+            const double u = tau / exp(g.axis[g.off[3] + il]);
+            const double env = exp(-0.5 * u * u);
+            double si, co;
+            sincospi(2.0 * (c * tau * tau), &si, &co);
+            U[(size_t)row * W + e] = (float)(env * co);
+            V[(size_t)row * W + e] = (float)(env * si);
+        } else {
+            const int fc = row - n_cl;
+            double si, co;
+            sincospi(2.0 * (g.axis[g.off[1] + fc] * tau), &si, &co);
+            C[(size_t)fc * W + e] = (float)co;
+            S[(size_t)fc * W + e] = (float)si;
+        }
+    }
+}
+
+// One wave per atom: FP64 norms of the atom and of its Gaussian envelope over
+// the samples present; writes 1/|g| (FP64 and FP32) and the largest ratio
+// |envelope| / |g| of the dictionary (it scales the synthesis error bound).
+__global__ void __launch_bounds__(256) k_norms_rho(GridDev g, double* __restrict__ inv_norm,
+                                                   float* __restrict__ inv_norm32,
+                                                   unsigned long long* __restrict__ rho_bits) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const long long nwaves = (long long)gridDim.x * blockDim.x / kWave;
+    for (long long i = wave; i < g.atoms; i += nwaves) {
+        double th[4];
+        grid_theta(g, i, th);
+        const double inv_dt = 1.0 / exp(th[3]);
+        double q = 0.0, qe = 0.0;
+        for (int k = lane; k < g.n; k += kWave) {
+            const double tau = sample_time(k, g.fs) - th[0];
+            const double u = tau * inv_dt;
+            const double e = exp(-0.5 * u * u);
+            const double v = e * cospi(2.0 * (th[2] * tau * tau + th[1] * tau));
+            q += v * v;
+            qe += e * e;
+        }
+        q = wave_sum(q);
+        qe = wave_sum(qe);
+        const double nrm = sqrt(q);
+        const double sc = nrm >= 1e-300 ? 1.0 / nrm : 0.0;
+        if (lane == 0) {
+            inv_norm[i] = sc;
+            inv_norm32[i] = (float)sc;
+            if (nrm >= 1e-300) atomicMax(rho_bits, (unsigned long long)__double_as_longlong(sqrt(qe) / nrm));
+        }
+    }
+}
+
+act_status build_synth(act_plan_s* p, hipStream_t s) {
+    unsigned long long* rb = nullptr;
+    ACT_HIP(hipMalloc((void**)&rb, sizeof(unsigned long long)));
+    ACT_HIP(hipMemsetAsync(rb, 0, sizeof(unsigned long long), s));
+    int dev = 0, cus = 0;
+    ACT_HIP(hipGetDevice(&dev));
+    ACT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const long long total = (long long)(p->n_cl + p->grid.cnt[1]) * p->fac_w;
+    hipLaunchKernelGGL(k_build_factors, dim3((unsigned)std::min<long long>((total + 255) / 256, cus * 64LL)),
+                       dim3(256), 0, s, p->grid, p->fac_w, (float*)p->fac_u, (float*)p->fac_v,
+                       (float*)p->fac_c, (float*)p->fac_s);
+    ACT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_norms_rho, dim3((unsigned)std::min<long long>((p->atoms + 3) / 4, cus * 32LL)),
+                       dim3(256), 0, s, p->grid, p->inv_norm, p->inv_norm32, rb);
+    ACT_HIP(hipGetLastError());
+    unsigned long long bits = 0;
+    ACT_HIP(hipMemcpyAsync(&bits, rb, sizeof bits, hipMemcpyDeviceToHost, s));
+    ACT_HIP(hipStreamSynchronize(s));
+    ACT_HIP(hipFree(rb));
+    double v;
+    memcpy(&v, &bits, sizeof v);
+    p->rho_max = v;
+    return ACT_OK;
+}
+
 static act_status validate_axis(const act_axis& a, const char* name) {
     std::string n(name);
     ACT_REQUIRE(a.count >= 1, n + ": count must be >= 1");
@@ -137,10 +228,16 @@ act_status build_tables(act_plan_s* p, hipStream_t s) {
 static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
-    void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+    void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
+                    p->inv_norm32, p->tc_shift, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    for (auto& ge : p->graphs) {
+        if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+        if (ge.graph) (void)hipGraphDestroy(ge.graph);
+    }
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     for (auto& ev : p->ev_pool) {
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
@@ -174,7 +271,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         set_error("act_plan: ragged plans are not implemented in this build");
         return ACT_ERR_UNSUPPORTED;
     }
-    if (desc->dict == ACT_DICT_SYNTH && desc->prec != ACT_PREC_F64) {
+    if (desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_BF16) {
         set_error("act_plan: this precision / dictionary pair is not implemented in this build");
         return ACT_ERR_UNSUPPORTED;
     }
@@ -185,10 +282,16 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     p->n = gr.n_samples;
     p->n_pad = (gr.n_samples + 255) / 256 * 256;
     p->max_batch = desc->max_batch;
+    {
+        const char* ng = getenv("ACT_NO_GRAPH");
+        p->use_graphs = !(ng && ng[0] == '1');
+    }
     // longest FP32 accumulation chain of one search score (certified margin):
     // the FP32 GEMV's per-lane FMAs plus its reduction tree; the MFMA path is
     // bounded by one rounding per sample
-    p->chain = desc->prec == ACT_PREC_BF16 ? p->n_pad : f32_chain_length(p->n_pad);
+    p->chain = desc->prec == ACT_PREC_BF16 ? p->n_pad
+               : desc->dict == ACT_DICT_SYNTH ? synth_chain_length(p->n_pad)
+                                              : f32_chain_length(p->n_pad);
     p->cap = desc->cand_cap > 0 ? desc->cand_cap : 4096;
     const act_axis* ax[4] = {&gr.tc_s, &gr.fc_hz, &gr.c_hz_per_s, &gr.logdt_ln_s};
     long long atoms = 1;
@@ -248,6 +351,35 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMalloc(&p->table, p->table_bytes));
         PLAN_HIP(hipMalloc((void**)&p->inv_norm, (size_t)atoms * sizeof(double)));
     }
+    const bool synth32 = desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_F32;
+    if (synth32) {
+        // time centres must sit on integer samples that are multiples of 16
+        std::vector<int> shift(ax[0]->count);
+        for (int j = 0; j < ax[0]->count; ++j) {
+            const double mv = vals[p->grid.off[0] + j] * gr.fs_hz;
+            const double mr = std::nearbyint(mv);
+            if (!(std::fabs(mv - mr) <= 1e-6 * std::max(1.0, std::fabs(mv))) || mr < 0 ||
+                mr >= gr.n_samples || ((long long)mr % 16) != 0) {
+                set_error("act_plan: the synthesised FP32 search needs time centres on integer sample "
+                          "offsets that are multiples of 16 inside the signal");
+                return fail(ACT_ERR_UNSUPPORTED);
+            }
+            shift[j] = (int)mr;
+        }
+        p->n_cl = ax[2]->count * ax[3]->count;
+        p->fac_w = 2 * p->n_pad;
+        const size_t ucl = (size_t)p->n_cl * p->fac_w * sizeof(float);
+        const size_t ufc = (size_t)ax[1]->count * p->fac_w * sizeof(float);
+        PLAN_HIP(hipMalloc(&p->fac_u, ucl));
+        PLAN_HIP(hipMalloc(&p->fac_v, ucl));
+        PLAN_HIP(hipMalloc(&p->fac_c, ufc));
+        PLAN_HIP(hipMalloc(&p->fac_s, ufc));
+        PLAN_HIP(hipMalloc((void**)&p->inv_norm, (size_t)atoms * sizeof(double)));
+        PLAN_HIP(hipMalloc((void**)&p->inv_norm32, (size_t)atoms * sizeof(float)));
+        PLAN_HIP(hipMalloc((void**)&p->tc_shift, shift.size() * sizeof(int)));
+        PLAN_HIP(hipMemcpyAsync(p->tc_shift, shift.data(), shift.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        p->table_bytes = 0;
+    }
     PLAN_HIP(hipMalloc(&p->shadow, B * p->n_pad * elt));
     PLAN_HIP(hipMemsetAsync(p->shadow, 0, B * p->n_pad * elt, s));
     PLAN_HIP(hipMalloc((void**)&p->cand_idx, B * cap * sizeof(unsigned)));
@@ -263,6 +395,10 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
 
     act_status bs = build_tables(p, s);
     if (bs != ACT_OK) return fail(bs);
+    if (synth32) {
+        bs = build_synth(p, s);
+        if (bs != ACT_OK) return fail(bs);
+    }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         set_error(std::string("act_plan: ") + hipGetErrorString(e));

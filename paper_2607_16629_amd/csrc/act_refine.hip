@@ -13,8 +13,8 @@ namespace act {
 struct PlanDev {
     GridDev g;
     BoxDev box;
-    int prec, cap, chain;
-    double eg_max;
+    int prec, dict, cap, chain;
+    double eg_max, rho_max;
     void* shadow;
     unsigned* cand_idx;
     float* cand_score;
@@ -31,6 +31,8 @@ static PlanDev view(const act_plan_s* p) {
     v.g = p->grid;
     v.box = p->box;
     v.prec = p->desc.prec;
+    v.dict = p->desc.dict;
+    v.rho_max = p->rho_max;
     v.cap = p->cap;
     v.chain = p->chain;
     v.eg_max = p->eg_max;
@@ -67,15 +69,23 @@ __device__ double score_bound(const PlanDev& P, double rn, double er) {
     const double rt = rn + er;
     const double m = (double)P.chain;
     const double gam = m * u32 / (1.0 - m * u32);
+    if (P.dict == ACT_DICT_SYNTH) {
+        // factored synthesis: each product U (C r) carries <= 5 FP32 roundings
+        // (factors, r, the carrier product, the MFMA product) plus the chain,
+        // against sum_n (|U C| + |V S|)|r_n| <= sqrt(2) |E| |r| = sqrt(2) rho |g| |r|;
+        // the scaling by 1/|g| in FP32 adds 2 u |p|.
+        return 1.01 * ((5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er + 3.0 * u32 * rn);
+    }
     return 1.01 * (P.eg_max * rt + er + gam * (1.0 + P.eg_max) * rt);
 }
 
 // E = |r|^2, the search copy of r (FP32 or BF16, zero padded) and its rounding
 // error; resets the channel's search state.  Block-wide; returns E.
+template <int TB>
 __device__ double refresh_channel(const PlanDev& P, int b, const double* r, double* red,
                                   bool bad) {
     double acc[2] = {0.0, 0.0};
-    for (int k = threadIdx.x; k < P.g.n_pad; k += NT) {
+    for (int k = threadIdx.x; k < P.g.n_pad; k += TB) {
         const double v = k < P.g.n ? r[k] : 0.0;
         double back;
         if (P.prec == ACT_PREC_BF16) {
@@ -91,7 +101,7 @@ __device__ double refresh_channel(const PlanDev& P, int b, const double* r, doub
         const double d = v - back;
         acc[1] += d * d;
     }
-    block_sum<NT, 2>(acc, red);
+    block_sum<TB, 2>(acc, red);
     if (threadIdx.x == 0) {
         const double rn = sqrt(acc[0]);
         P.rnorm[b] = rn;
@@ -107,7 +117,7 @@ __global__ void __launch_bounds__(NT) k_init(PlanDev P, double* __restrict__ res
                                              double* __restrict__ approx,
                                              double* __restrict__ energy, int* __restrict__ flags,
                                              int order) {
-    __shared__ double red[2 * NW];
+    __shared__ double red[block_sum_lds(NT, 2)];
     const int b = blockIdx.x;
     const double* r = resid + (size_t)b * P.g.n;
     int bad = 0;
@@ -116,7 +126,7 @@ __global__ void __launch_bounds__(NT) k_init(PlanDev P, double* __restrict__ res
         if (approx) approx[(size_t)b * P.g.n + k] = 0.0;
     }
     bad = __syncthreads_or(bad);
-    const double E = refresh_channel(P, b, r, red, bad != 0);
+    const double E = refresh_channel<NT>(P, b, r, red, bad != 0);
     if (threadIdx.x == 0) {
         energy[(size_t)b * (order + 1)] = E;
         flags[b] = bad ? ACT_FLAG_NONFINITE : 0;
@@ -183,42 +193,49 @@ __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __rest
 // refinement objective, block-wide
 // --------------------------------------------------------------------------
 
-// J = s^2/q with s = <r,g>, q = <g,g>, and dJ/dtheta (SI units):
-//   dJ/dtheta_j = 2 s <r, d_j g>/q - 2 s^2 <g, d_j g>/q^2, where
+// Per-sample terms of the refinement: g = E C and its partial derivatives
 //   d_tc g = E[(tau/dt^2) C + 2 pi (2 c tau + f_c) S], d_fc g = -2 pi tau E S,
 //   d_c g = -2 pi tau^2 E S, d_logdt g = (tau^2/dt^2) E C.
-__device__ double eval_obj(const double* __restrict__ r, int n, double fs, const double th[4],
-                           double grad[4], double* red) {
-    const double tc = th[0], fc = th[1], c = th[2];
-    const double inv_dt = 1.0 / exp(th[3]);
+__device__ __forceinline__ void atom_terms64(double tau, double fc, double c, double inv_dt,
+                                             double& gk, double d[4]) {
     const double idt2 = inv_dt * inv_dt;
-    double acc[10];
+    const double u = tau * inv_dt;
+    const double e = exp(-0.5 * u * u);
+    double si, co;
+    sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
+    gk = e * co;
+    const double es = e * si;
+    d[0] = e * (tau * idt2 * co) + kTwoPi * (2.0 * c * tau + fc) * es;
+    d[1] = -kTwoPi * tau * es;
+    d[2] = -kTwoPi * tau * tau * es;
+    d[3] = tau * tau * idt2 * gk;
+}
+
+// Sums of the objective: {<r,g>, <g,g>, <r,d_j g> (4), <g,d_j g> (4)}.
+template <int TB>
+__device__ void sums_obj(const double* __restrict__ r, int n, double fs, const double th[4],
+                         double (&acc)[10], double* red) {
+    const double inv_dt = 1.0 / exp(th[3]);
 #pragma unroll
     for (int j = 0; j < 10; ++j) acc[j] = 0.0;
-    for (int k = threadIdx.x; k < n; k += NT) {
-        const double tau = sample_time(k, fs) - tc;
-        const double u = tau * inv_dt;
-        const double e = exp(-0.5 * u * u);
-        double si, co;
-        sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
-        const double gk = e * co, es = e * si;
-        const double d0 = e * (tau * idt2 * co) + kTwoPi * (2.0 * c * tau + fc) * es;
-        const double d1 = -kTwoPi * tau * es;
-        const double d2 = -kTwoPi * tau * tau * es;
-        const double d3 = tau * tau * idt2 * gk;
+#pragma unroll 1
+    for (int k = threadIdx.x; k < n; k += TB) {
+        double gk, d[4];
+        atom_terms64(sample_time(k, fs) - th[0], th[1], th[2], inv_dt, gk, d);
         const double rk = r[k];
         acc[0] += rk * gk;
         acc[1] += gk * gk;
-        acc[2] += rk * d0;
-        acc[3] += rk * d1;
-        acc[4] += rk * d2;
-        acc[5] += rk * d3;
-        acc[6] += gk * d0;
-        acc[7] += gk * d1;
-        acc[8] += gk * d2;
-        acc[9] += gk * d3;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[2 + j] += rk * d[j];
+            acc[6 + j] += gk * d[j];
+        }
     }
-    block_sum<NT, 10>(acc, red);
+    block_sum<TB, 10>(acc, red);
+}
+
+// J = s^2/q and dJ/dtheta_j = 2 s <r, d_j g>/q - 2 s^2 <g, d_j g>/q^2.
+__device__ __forceinline__ double obj_from_sums(const double acc[10], double grad[4]) {
     const double s = acc[0], q = acc[1];
     if (!(q > 0.0)) {
         grad[0] = grad[1] = grad[2] = grad[3] = 0.0;
@@ -229,30 +246,24 @@ __device__ double eval_obj(const double* __restrict__ r, int n, double fs, const
     return s * s / q;
 }
 
-// Coordinate scales of the refinement: the unit atom's resolution along each
-// parameter, s_j = min(step_j, 1/sqrt(G_jj)), G_jj = (|d_j g|^2 - <g,d_j g>^2/q)/q;
-// 0 freezes an axis (single grid value or G_jj <= 0).
-__device__ void eval_scales(const double* __restrict__ r, const GridDev& g, const BoxDev& box,
-                            const double th[4], double h[4], double* red) {
-    (void)r;
-    const double tc = th[0], fc = th[1], c = th[2];
+template <int TB>
+__device__ double eval_obj(const double* __restrict__ r, int n, double fs, const double th[4],
+                           double grad[4], double* red) {
+    double acc[10];
+    sums_obj<TB>(r, n, fs, th, acc, red);
+    return obj_from_sums(acc, grad);
+}
+
+// Sums of the coordinate scales: {<g,g>, <g,d_j g> (4), <d_j g,d_j g> (4)}.
+template <int TB>
+__device__ void sums_scales(int n, double fs, const double th[4], double (&acc)[9], double* red) {
     const double inv_dt = 1.0 / exp(th[3]);
-    const double idt2 = inv_dt * inv_dt;
-    double acc[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) acc[j] = 0.0;
-    for (int k = threadIdx.x; k < g.n; k += NT) {
-        const double tau = sample_time(k, g.fs) - tc;
-        const double u = tau * inv_dt;
-        const double e = exp(-0.5 * u * u);
-        double si, co;
-        sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
-        const double gk = e * co, es = e * si;
-        double d[4];
-        d[0] = e * (tau * idt2 * co) + kTwoPi * (2.0 * c * tau + fc) * es;
-        d[1] = -kTwoPi * tau * es;
-        d[2] = -kTwoPi * tau * tau * es;
-        d[3] = tau * tau * idt2 * gk;
+#pragma unroll 1
+    for (int k = threadIdx.x; k < n; k += TB) {
+        double gk, d[4];
+        atom_terms64(sample_time(k, fs) - th[0], th[1], th[2], inv_dt, gk, d);
         acc[0] += gk * gk;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -260,64 +271,75 @@ __device__ void eval_scales(const double* __restrict__ r, const GridDev& g, cons
             acc[5 + j] += d[j] * d[j];
         }
     }
-    block_sum<NT, 9>(acc, red);
-    const double q = acc[0];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const double G = q > 0.0 ? (acc[5 + j] - acc[1 + j] * acc[1 + j] / q) / q : 0.0;
-        if (!(box.hi[j] > box.lo[j]) || !(G > 0.0)) {
-            h[j] = 0.0;
-        } else {
-            const double rr = 1.0 / sqrt(G);
-            h[j] = rr < box.step[j] ? rr : box.step[j];
-        }
-    }
+    block_sum<TB, 9>(acc, red);
 }
-
-struct LbfgsMem {
-    double S[8][4], Y[8][4], RHO[8];
-};
 
 __device__ __forceinline__ double dot4(const double* a, const double* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
 }
 
-// f(u) = -J(theta0 + h u) and its gradient in u
-__device__ double refine_eval(const double* r, const GridDev& g, const double th0[4],
-                              const double h[4], const double u[4], double gu[4], double* red) {
-    double th[4], gr[4];
+// --------------------------------------------------------------------------
+// Limited-memory BFGS refinement, block-wide.
+//
+// Every thread runs the same scalar iteration on identical block-reduced
+// values (so control flow is uniform and no thread waits for a controller);
+// the pair memory lives in LDS and only thread 0 writes it.  Specification
+// (identical to the oracle): coordinates u_j = (theta_j - theta0_j)/s_j with
+// s_j = min(step_j, 1/sqrt(G_jj)), G_jj the Fisher metric of the unit atom
+// along theta_j (axes with one grid value or G_jj <= 0 are frozen); minimise
+// f(u) = -J on the grid-hull box; memory 8, H0 = gamma I with gamma = s'y/y'y
+// of the newest pair; a pair is kept only if s'y > 1e-12|s||y|;
+// projected-gradient stop max|pg| <= 1e-11 max(1, J); direction components
+// pointing out of the box at active bounds are zeroed, steepest descent if the
+// direction is not a descent direction; first step min(1, 1/max|d|) while the
+// memory is empty, else 1; backtracking (halving, <= 30 trials) accepting a
+// strict-descent trial by Armijo (c1 = 1e-4) or, once FP64 cannot resolve the
+// change of J (f_new <= f + 1e-12|f|), by Hager and Zhang's approximate Wolfe
+// slope test 0.9 dec <= dnew <= -0.8 dec; at most `steps` iterations; the
+// result is kept only if J does not drop.
+// --------------------------------------------------------------------------
+struct RefineLds {
+    double S[8][4], Y[8][4], RHO[8];
+};
+
+template <int TB>
+__device__ __forceinline__ double refine_eval(const double* r, const GridDev& g, const double th0[4],
+                                              const double h[4], const double u[4], double gu[4],
+                                              double* red) {
+    double th[4], gr[4], acc[10];
 #pragma unroll
     for (int j = 0; j < 4; ++j) th[j] = th0[j] + h[j] * u[j];
-    const double J = eval_obj(r, g.n, g.fs, th, gr, red);
+    sums_obj<TB>(r, g.n, g.fs, th, acc, red);
+    const double J = obj_from_sums(acc, gr);
 #pragma unroll
     for (int j = 0; j < 4; ++j) gu[j] = -h[j] * gr[j];
     return -J;
 }
 
-// Limited-memory BFGS maximisation of J from a grid point, block-wide.  Every
-// thread runs the same scalar iteration on identical (block-reduced) values;
-// the pair memory lives in LDS and only thread 0 writes it.  Specification:
-// memory 8, H0 = gamma I with gamma = s'y/y'y of the newest pair; pairs kept
-// only if s'y > 1e-12|s||y|; projected-gradient stop max|pg| <= 1e-11 max(1,J);
-// out-of-box direction components zeroed at active bounds, steepest descent
-// if the direction is not a descent direction; first step min(1, 1/max|d|)
-// while the memory is empty, else 1; backtracking (halving, <= 30 trials) that
-// accepts a strict-descent trial by Armijo (c1 = 1e-4) or, once FP64 cannot
-// resolve the change of J (f_new <= f + 1e-12|f|), by Hager and Zhang's
-// approximate Wolfe slope test 0.9 dec <= dnew <= -0.8 dec; at most `steps`
-// iterations; the result is kept only if J does not drop.
+template <int TB>
 __device__ int refine_block(const double* __restrict__ r, const GridDev& g, const BoxDev& box,
                             const double th0[4], int steps, double th_out[4], double* J_out,
-                            double* red, LbfgsMem* mem) {
+                            double* red, RefineLds& L) {
     double h[4], blo[4], bhi[4], u[4] = {0, 0, 0, 0}, gcur[4];
     int flags = 0;
-    eval_scales(r, g, box, th0, h, red);
+    {
+        double acc[9];
+        sums_scales<TB>(g.n, g.fs, th0, acc, red);
+        const double q = acc[0];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        blo[j] = h[j] == 0.0 ? 0.0 : (box.lo[j] - th0[j]) / h[j];
-        bhi[j] = h[j] == 0.0 ? 0.0 : (box.hi[j] - th0[j]) / h[j];
+        for (int j = 0; j < 4; ++j) {
+            const double G = q > 0.0 ? (acc[5 + j] - acc[1 + j] * acc[1 + j] / q) / q : 0.0;
+            if (!(box.hi[j] > box.lo[j]) || !(G > 0.0)) {
+                h[j] = 0.0;
+            } else {
+                const double rr = 1.0 / sqrt(G);
+                h[j] = rr < box.step[j] ? rr : box.step[j];
+            }
+            blo[j] = h[j] == 0.0 ? 0.0 : (box.lo[j] - th0[j]) / h[j];
+            bhi[j] = h[j] == 0.0 ? 0.0 : (box.hi[j] - th0[j]) / h[j];
+        }
     }
-    double f = refine_eval(r, g, th0, h, u, gcur, red);
+    double f = refine_eval<TB>(r, g, th0, h, u, gcur, red);
     const double f0 = f;
     int nmem = 0, head = 0;
     for (int it = 0; it < steps; ++it) {
@@ -331,28 +353,36 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
         }
         const double Jc = -f;
         if (pgmax <= 1e-11 * (Jc > 1.0 ? Jc : 1.0)) break;
+        // two-loop recursion, newest pair first; the alphas are recomputed in
+        // the second loop's order from a small register array
         double d[4], al[8];
 #pragma unroll
         for (int j = 0; j < 4; ++j) d[j] = -gcur[j];
-        for (int t = 0; t < nmem; ++t) {
-            const int slot = (head - 1 - t + 8) & 7;
-            const double a = mem->RHO[slot] * dot4(mem->S[slot], d);
-            al[t] = a;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) d[j] -= a * mem->Y[slot][j];
+        for (int t = 0; t < 8; ++t) {
+            if (t < nmem) {
+                const int slot = (head - 1 - t + 8) & 7;
+                const double a = L.RHO[slot] * dot4(L.S[slot], d);
+                al[t] = a;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) d[j] -= a * L.Y[slot][j];
+            }
         }
         double gamma = 1.0;
         if (nmem > 0) {
             const int nw = (head - 1 + 8) & 7;
-            gamma = dot4(mem->S[nw], mem->Y[nw]) / dot4(mem->Y[nw], mem->Y[nw]);
+            gamma = dot4(L.S[nw], L.Y[nw]) / dot4(L.Y[nw], L.Y[nw]);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) d[j] *= gamma;
-        for (int t = nmem - 1; t >= 0; --t) {
-            const int slot = (head - 1 - t + 8) & 7;
-            const double bb = mem->RHO[slot] * dot4(mem->Y[slot], d);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) d[j] += (al[t] - bb) * mem->S[slot][j];
+        for (int t = 7; t >= 0; --t) {
+            if (t < nmem) {
+                const int slot = (head - 1 - t + 8) & 7;
+                const double bb = L.RHO[slot] * dot4(L.Y[slot], d);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) d[j] += (al[t] - bb) * L.S[slot][j];
+            }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -378,7 +408,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
                 v = v > bhi[j] ? bhi[j] : v;
                 un[j] = v;
             }
-            fn = refine_eval(r, g, th0, h, un, gn, red);
+            fn = refine_eval<TB>(r, g, th0, h, un, gn, red);
             double dec = 0.0, dnew = 0.0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -402,14 +432,13 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
         }
         const double sy = dot4(sv, yv);
         if (sy > 1e-12 * sqrt(dot4(sv, sv)) * sqrt(dot4(yv, yv))) {
-            __syncthreads();
             if (threadIdx.x == 0) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    mem->S[head][j] = sv[j];
-                    mem->Y[head][j] = yv[j];
+                    L.S[head][j] = sv[j];
+                    L.Y[head][j] = yv[j];
                 }
-                mem->RHO[head] = 1.0 / sy;
+                L.RHO[head] = 1.0 / sy;
             }
             __syncthreads();
             head = (head + 1) & 7;
@@ -438,14 +467,17 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
 // --------------------------------------------------------------------------
 // select -> refine -> coefficient -> update, one block per channel
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(NT) k_select_refine_update(
+constexpr int NTR = 512;            // threads of the refinement kernels
+constexpr int NWR = NTR / kWave;
+
+__global__ void __launch_bounds__(NTR) k_select_refine_update(
     PlanDev P, int k, int order, int steps, double* __restrict__ resid, double* __restrict__ approx,
     double* __restrict__ theta, double* __restrict__ coef, long long* __restrict__ index,
     double* __restrict__ energy, double* __restrict__ gap, int* __restrict__ flags) {
-    __shared__ double red[10 * NW];
-    __shared__ LbfgsMem mem;
-    __shared__ double s_a1[NW], s_a2[NW];
-    __shared__ unsigned s_i1[NW];
+    __shared__ double red[block_sum_lds(NTR, 10)];
+    __shared__ RefineLds L;
+    __shared__ double s_a1[NWR], s_a2[NWR];
+    __shared__ unsigned s_i1[NWR];
     const int b = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     double* r = resid + (size_t)b * P.g.n;
@@ -472,7 +504,7 @@ __global__ void __launch_bounds__(NT) k_select_refine_update(
         const int cnt_raw = P.cand_count[b];
         const int cnt = min(cnt_raw, P.cap);
         if (cnt_raw > P.cap) fl |= ACT_FLAG_CAND_OVERFLOW;
-        for (int j = threadIdx.x; j < cnt; j += NT) {
+        for (int j = threadIdx.x; j < cnt; j += NTR) {
             const double v = P.cand_p64[(size_t)b * P.cap + j];
             if (isnan(v)) continue;
             const double a = fabs(v);
@@ -508,7 +540,7 @@ __global__ void __launch_bounds__(NT) k_select_refine_update(
     a1 = s_a1[0];
     a2 = s_a2[0];
     i1 = s_i1[0];
-    for (int q = 1; q < NW; ++q) {
+    for (int q = 1; q < NWR; ++q) {
         const double oa1 = s_a1[q], oa2 = s_a2[q];
         const unsigned oi1 = s_i1[q];
         if (oa1 > a1 || (oa1 == a1 && oi1 < i1)) {
@@ -520,7 +552,7 @@ __global__ void __launch_bounds__(NT) k_select_refine_update(
         }
     }
     __syncthreads();
-    long long best = (eb >= 0.0 && i1 != 0xffffffffu) ? (long long)i1 : 0;
+    const long long best = (eb >= 0.0 && i1 != 0xffffffffu) ? (long long)i1 : 0;
     double g_gap = 0.0;
     if (eb >= 0.0 && a1 > 0.0) {
         // an atom outside the list has |p| < M - eb (its score was below M - 2 eb)
@@ -532,7 +564,7 @@ __global__ void __launch_bounds__(NT) k_select_refine_update(
     double th0[4], th[4], J = 0.0;
     grid_theta(P.g, best, th0);
     if (steps > 0) {
-        fl |= refine_block(r, P.g, P.box, th0, steps, th, &J, red, &mem);
+        fl |= refine_block<NTR>(r, P.g, P.box, th0, steps, th, &J, red, L);
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) th[j] = th0[j];
@@ -541,27 +573,27 @@ __global__ void __launch_bounds__(NT) k_select_refine_update(
     // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4))
     const double inv_dt = 1.0 / exp(th[3]);
     double acc[1] = {0.0};
-    for (int t = threadIdx.x; t < P.g.n; t += NT) {
+    for (int t = threadIdx.x; t < P.g.n; t += NTR) {
         const double v = atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt);
         acc[0] += v * v;
     }
-    block_sum<NT, 1>(acc, red);
+    block_sum<NTR, 1>(acc, red);
     const double nrm = sqrt(acc[0]);
     const bool ok = nrm >= 1e-300;
     acc[0] = 0.0;
-    for (int t = threadIdx.x; t < P.g.n; t += NT) {
+    for (int t = threadIdx.x; t < P.g.n; t += NTR) {
         const double v = ok ? atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
         acc[0] += v * r[t];
     }
-    block_sum<NT, 1>(acc, red);
+    block_sum<NTR, 1>(acc, red);
     const double ck = acc[0];
-    for (int t = threadIdx.x; t < P.g.n; t += NT) {
+    for (int t = threadIdx.x; t < P.g.n; t += NTR) {
         const double v = ok ? atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
         r[t] = r[t] - ck * v;
         if (approx) approx[(size_t)b * P.g.n + t] = approx[(size_t)b * P.g.n + t] + ck * v;
     }
     __syncthreads();
-    const double E = refresh_channel(P, b, r, red, false);
+    const double E = refresh_channel<NTR>(P, b, r, red, false);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) theta[o * 4 + j] = th[j];
@@ -576,20 +608,20 @@ __global__ void __launch_bounds__(NT) k_select_refine_update(
 // --------------------------------------------------------------------------
 // refinement alone, forward/adjoint alone, reconstruction
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(NT) k_refine_many(GridDev g, BoxDev box,
-                                                    const double* __restrict__ resid,
-                                                    const double* __restrict__ theta0, int steps,
-                                                    double* __restrict__ theta,
-                                                    double* __restrict__ value,
-                                                    int* __restrict__ flags) {
-    __shared__ double red[10 * NW];
-    __shared__ LbfgsMem mem;
+__global__ void __launch_bounds__(NTR) k_refine_many(GridDev g, BoxDev box,
+                                                     const double* __restrict__ resid,
+                                                     const double* __restrict__ theta0, int steps,
+                                                     double* __restrict__ theta,
+                                                     double* __restrict__ value,
+                                                     int* __restrict__ flags) {
+    __shared__ double red[block_sum_lds(NTR, 10)];
+    __shared__ RefineLds L;
     const int p = blockIdx.x;
     const double* r = resid + (size_t)p * g.n;
     double th0[4], th[4], J;
 #pragma unroll
     for (int j = 0; j < 4; ++j) th0[j] = theta0[p * 4 + j];
-    const int fl = refine_block(r, g, box, th0, steps, th, &J, red, &mem);
+    const int fl = refine_block<NTR>(r, g, box, th0, steps, th, &J, red, L);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) theta[p * 4 + j] = th[j];
@@ -602,13 +634,13 @@ __global__ void __launch_bounds__(NT) k_vg_f64(GridDev g, const double* __restri
                                                const double* __restrict__ theta,
                                                double* __restrict__ value,
                                                double* __restrict__ dtheta, double* __restrict__ dr) {
-    __shared__ double red[10 * NW];
+    __shared__ double red[block_sum_lds(NT, 10)];
     const int p = blockIdx.x;
     const double* r = resid + (size_t)p * g.n;
     double th[4], gr[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) th[j] = theta[p * 4 + j];
-    const double J = eval_obj(r, g.n, g.fs, th, gr, red);
+    const double J = eval_obj<NT>(r, g.n, g.fs, th, gr, red);
     if (threadIdx.x == 0) {
         value[p] = J;
 #pragma unroll
@@ -647,7 +679,7 @@ __global__ void __launch_bounds__(NT) k_vg_f32(GridDev g, const float* __restric
                                                const double* __restrict__ theta,
                                                double* __restrict__ value,
                                                double* __restrict__ dtheta, float* __restrict__ dr) {
-    __shared__ double red[10 * NW];
+    __shared__ double red[block_sum_lds(NT, 10)];
     const int p = blockIdx.x;
     const float* r = resid + (size_t)p * g.n;
     const double tc = theta[p * 4 + 0], fc = theta[p * 4 + 1], c = theta[p * 4 + 2];
@@ -714,7 +746,7 @@ __global__ void __launch_bounds__(NT) k_reconstruct(GridDev g, int order,
                                                     const double* __restrict__ theta,
                                                     const double* __restrict__ coef,
                                                     double* __restrict__ out) {
-    __shared__ double red[NW];
+    __shared__ double red[block_sum_lds(NT, 1)];
     const int b = blockIdx.x;
     double* o = out + (size_t)b * g.n;
     for (int t = threadIdx.x; t < g.n; t += NT) o[t] = 0.0;
@@ -768,7 +800,7 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
                                        double* approx, double* theta, double* coef,
                                        long long* index, double* energy, double* gap, int* flags,
                                        hipStream_t s) {
-    hipLaunchKernelGGL(k_select_refine_update, dim3(batch), dim3(NT), 0, s, view(p), k, order,
+    hipLaunchKernelGGL(k_select_refine_update, dim3(batch), dim3(NTR), 0, s, view(p), k, order,
                        p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
@@ -776,7 +808,7 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
 
 act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const double* theta0,
                               int steps, double* theta, double* value, int* flags, hipStream_t s) {
-    hipLaunchKernelGGL(k_refine_many, dim3(m), dim3(NT), 0, s, p->grid, p->box, resid, theta0, steps,
+    hipLaunchKernelGGL(k_refine_many, dim3(m), dim3(NTR), 0, s, p->grid, p->box, resid, theta0, steps,
                        theta, value, flags);
     ACT_HIP(hipGetLastError());
     return ACT_OK;

@@ -79,7 +79,7 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label=""):
 # BF16 operands: |p~ - p| <= (|e_g| + |e_r|/|r| + gamma_N) |r| with both
 # rounding terms below 2^-8; 8e-3 |r| is the resulting certified bound.
 @pytest.mark.parametrize("prec,dict_,tol", [("f64", "synth", 1e-12), ("f32", "table", 1e-5),
-                                            ("bf16", "table", 8e-3)])
+                                            ("bf16", "table", 8e-3), ("f32", "synth", 1e-5)])
 def test_correlate_matches_oracle(oracle, prec, dict_, tol):
     wl = W.plain_1x512()
     g = wl.grid
@@ -113,7 +113,8 @@ def test_correlate_many_channels_and_ragged_tail(oracle, prec, tol):
 # full decompositions
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table")])
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table"),
+                                        ("f32", "synth")])
 def test_decompose_plain_1x512(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, wl.order, refine_steps=30)
@@ -122,7 +123,8 @@ def test_decompose_plain_1x512(oracle, prec, dict_):
     assert n == wl.order
 
 
-@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table")])
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table"),
+                                        ("f32", "synth")])
 def test_decompose_without_refinement_is_exact_mp(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, 8, refine_steps=0)
@@ -151,12 +153,67 @@ def test_decompose_batch_with_edge_channels(oracle):
         np.testing.assert_array_equal(gpu["coef"][2], 0.0)
 
 
+def test_synth_ragged_tail_and_partial_tiles(oracle):
+    """Synthesised FP32 search on a length that is not a multiple of the stage
+    (n = 300), time centres every 16 samples, axis counts that leave partial
+    cl blocks and f_c chunks; several channels."""
+    g = W.Grid(256.0, 300, W.Axis(0.0, 18 * 16 / 256.0, 18, True), W.Axis(2.0, 60.0, 70, False),
+               W.Axis(-15.0, 15.0, 9, False), W.Axis(math.log(0.05), 0.0, 15, False))
+    rng = np.random.default_rng(17)
+    sig = rng.standard_normal((2, g.n))
+    plan = A().Plan(g, dict_="synth", prec="f32", max_batch=2)
+    p = plan.act_correlate(sig, 0, g.size).cpu().numpy()
+    for b in range(2):
+        ref = oracle.correlate(g, sig[b])
+        assert np.max(np.abs(p[b] - ref)) <= 1e-5 * np.linalg.norm(sig[b])
+    ref = oracle.decompose(g, sig, 4, refine_steps=30)
+    gpu = gpu_decompose(g, sig, 4, "f32", "synth", refine_steps=30)
+    assert_decomposition_parity(gpu, ref, g, oracle, sig, "synth")
+
+
+def test_synth_rejects_off_sample_time_centres():
+    act = A()
+    g = W.eeg_grid(300, 8, 8, 6, 4)      # t_c step 37.5 samples
+    with pytest.raises(act.ActError) as e:
+        act.Plan(g, dict_="synth", prec="f32")
+    assert e.value.status == act.ACT_ERR_UNSUPPORTED
+
+
 def test_decompose_deterministic():
     wl = W.plain_1x512()
     a = gpu_decompose(wl.grid, wl.signals, 5, "f32", "table")
     b = gpu_decompose(wl.grid, wl.signals, 5, "f32", "table")
     for k in ("index", "theta", "coef", "energy", "resid"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_graph_replays_match_direct_launches():
+    """act_decompose replays a captured graph for repeated arguments; every
+    replay (with eager host-side work in between) must equal the direct
+    launch sequence bit for bit."""
+    wl = W.plain_1x512()
+    plan = A().Plan(wl.grid, dict_="table", prec="f32", refine_steps=30)
+    sig = torch.from_numpy(wl.signals).cuda()
+    resid = torch.empty_like(sig)
+    out = plan.alloc_outputs(1, 5)
+    plan.act_timing_enable(True)          # direct launches
+    resid.copy_(sig)
+    plan.act_decompose(resid, 5, out)
+    plan.act_timing_read()
+    ref = {k: v.clone() for k, v in out.items() if v is not None}
+    ref_r = resid.clone()
+    plan.act_timing_enable(False)         # graph capture, then replays
+    for rep in range(3):
+        for v in out.values():
+            if v is not None:
+                v.zero_()
+        resid.copy_(sig)
+        plan.act_decompose(resid, 5, out)
+        torch.cuda.synchronize()
+        _ = (resid * 2).sum().item()      # unrelated eager work between replays
+        for k, v in ref.items():
+            assert torch.equal(out[k], v), (rep, k)
+        assert torch.equal(resid, ref_r), rep
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
@@ -182,7 +239,8 @@ def test_bf16_batch_of_70_channels(oracle):
     assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick]) >= 15
 
 
-def test_fp32_full_size_2m_atoms(oracle):
+@pytest.mark.parametrize("dict_", ["table", "synth"])
+def test_fp32_full_size_2m_atoms(oracle, dict_):
     """Single channel at EEG-like scale (N = 2048, 2,097,152 atoms): the
     oracle cannot run the whole pursuit, so each order is checked one by one:
     the winner's oracle score matches, no sampled atom beats it, the refined
@@ -191,7 +249,7 @@ def test_fp32_full_size_2m_atoms(oracle):
     wl = W.fp32_1x2048()
     g = wl.grid
     order = 3
-    gpu = gpu_decompose(g, wl.signals, order, "f32", "table", refine_steps=30)
+    gpu = gpu_decompose(g, wl.signals, order, "f32", dict_, refine_steps=30)
     step, _, _ = oracle.refine_box(g)
     rng = np.random.default_rng(12)
     sample = rng.choice(g.size, 20000, replace=False)
