@@ -467,7 +467,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
 // --------------------------------------------------------------------------
 // select -> refine -> coefficient -> update, one block per channel
 // --------------------------------------------------------------------------
-constexpr int NTR = 512;            // threads of the refinement kernels
+constexpr int NTR = 256;            // threads of the refinement kernels (fastest measured)
 constexpr int NWR = NTR / kWave;
 
 __global__ void __launch_bounds__(NTR) k_select_refine_update(
