@@ -86,7 +86,8 @@ enum {
     ACT_FLAG_CAND_OVERFLOW = 8,   /* more atoms than the candidate capacity lay inside the
                                      certified margin; the search was re-run once with the
                                      exact threshold (set only if even that overflowed) */
-    ACT_FLAG_RAGGED_EMPTY = 16    /* a ragged signal has no time centre (length < divisor) */
+    ACT_FLAG_RAGGED_EMPTY = 16,   /* a ragged signal has no time centre (length < divisor) */
+    ACT_FLAG_BAD_LENGTH = 32      /* a ragged length outside [0, n_samples]: channel skipped */
 };
 
 typedef struct {

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libact.so")
 ACT_OK, ACT_ERR_INVALID, ACT_ERR_NOMEM, ACT_ERR_HIP, ACT_ERR_UNSUPPORTED = range(5)
 ACT_DICT_SYNTH, ACT_DICT_TABLE = 0, 1
 ACT_PREC_F64, ACT_PREC_F32, ACT_PREC_BF16 = 0, 1, 2
-FLAG_NONFINITE, FLAG_REFINE_REJECTED, FLAG_CAND_OVERFLOW, FLAG_RAGGED_EMPTY = 1, 2, 8, 16
+FLAG_NONFINITE, FLAG_REFINE_REJECTED, FLAG_CAND_OVERFLOW, FLAG_RAGGED_EMPTY, FLAG_BAD_LENGTH = 1, 2, 8, 16, 32
 Q_ATOMS, Q_TABLE_BYTES, Q_N_PAD, Q_CAND_CAP, Q_WORKSPACE_BYTES = range(5)
 
 _DICTS = {"synth": ACT_DICT_SYNTH, "table": ACT_DICT_TABLE}
@@ -141,7 +141,8 @@ class Plan:
     """Owns an act_plan_t.  See include/act.h for every call's contract."""
 
     def __init__(self, grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: int = 1,
-                 cand_cap: int = 0, refine_steps: int = 30):
+                 cand_cap: int = 0, refine_steps: int = 30, ragged: bool = False,
+                 ragged_tc_div: int = 32):
         lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("libact needs a ROCm GPU; none is visible")
@@ -150,7 +151,9 @@ class Plan:
         self.prec = prec
         self.max_batch = max_batch
         self.refine_steps = refine_steps
-        self._desc = make_desc(grid, dict_, prec, max_batch, cand_cap, refine_steps)
+        self.ragged = ragged
+        self._desc = make_desc(grid, dict_, prec, max_batch, cand_cap, refine_steps, ragged,
+                               ragged_tc_div)
         h = ctypes.c_void_p()
         _check(lib.act_plan(ctypes.byref(self._desc), _stream(), ctypes.byref(h)))
         self._h = h
@@ -218,6 +221,41 @@ class Plan:
         out = self.alloc_outputs(resid.shape[0], order, approx)
         self.act_decompose(resid, order, out)
         out["resid"] = resid
+        return out
+
+    def act_decompose_ragged(self, resid: torch.Tensor, lengths: torch.Tensor,
+                             offsets: torch.Tensor, order: int, out: dict):
+        """Ragged batch: resid is the packed f64 CUDA signals (in place),
+        lengths int32 and offsets int64 CUDA tensors."""
+        assert resid.is_cuda and resid.dtype == torch.float64 and resid.is_contiguous()
+        assert lengths.dtype == torch.int32 and offsets.dtype == torch.int64
+        B = lengths.shape[0]
+        _check(load().act_decompose(
+            self._h, B, _ptr(lengths), _ptr(offsets), _ptr(resid), _ptr(out["approx"]), int(order),
+            _ptr(out["theta"]), _ptr(out["coef"]), _ptr(out["index"]), _ptr(out["energy"]),
+            _ptr(out["gap"]), _ptr(out["flags"]), _stream()))
+        return out
+
+    def decompose_ragged(self, packed, lengths, offsets, order: int) -> dict:
+        resid = _device_tensor(packed, torch.float64).reshape(-1).clone()
+        lengths = _device_tensor(lengths, torch.int32)
+        offsets = _device_tensor(offsets, torch.int64)
+        B = lengths.shape[0]
+        out = self.alloc_outputs(B, order, approx=False)
+        out["approx"] = torch.empty_like(resid)
+        self.act_decompose_ragged(resid, lengths, offsets, order, out)
+        out["resid"] = resid
+        return out
+
+    def act_reconstruct_ragged(self, theta, coef, lengths, offsets, total: int) -> torch.Tensor:
+        theta = _device_tensor(theta, torch.float64)
+        coef = _device_tensor(coef, torch.float64)
+        lengths = _device_tensor(lengths, torch.int32)
+        offsets = _device_tensor(offsets, torch.int64)
+        B, order = coef.shape
+        out = torch.zeros(total, dtype=torch.float64, device=coef.device)
+        _check(load().act_reconstruct(self._h, B, order, _ptr(theta), _ptr(coef), _ptr(lengths),
+                                      _ptr(offsets), _ptr(out), _stream()))
         return out
 
     def act_refine(self, resid, theta0, steps: int):

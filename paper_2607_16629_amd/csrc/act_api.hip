@@ -108,9 +108,12 @@ extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* 
     hipStream_t s = (hipStream_t)stream;
     p->last_stream = s;
     p->search_resid = resid_dev;
+    p->call_len = len_dev;
+    p->call_off = (const long long*)off_dev;
     auto enqueue_all = [&](hipStream_t q) -> act_status {
         act_status st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, q);
         if (st != ACT_OK) return st;
+        if ((st = launch_ragged_items(p, batch, q)) != ACT_OK) return st;
         for (int k = 0; k < order; ++k) {
             st = enqueue_order(p, batch, k, order, resid_dev, approx_dev, theta_dev, coef_dev,
                                (long long*)index_dev, energy_dev, gap_dev, flags_dev, q);
@@ -122,7 +125,8 @@ extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* 
 
     // One captured graph per argument signature, replayed on the caller's
     // stream: the whole pursuit becomes a single launch from the host.
-    std::vector<uintptr_t> key = {(uintptr_t)batch, (uintptr_t)order, (uintptr_t)resid_dev,
+    std::vector<uintptr_t> key = {(uintptr_t)batch, (uintptr_t)order, (uintptr_t)len_dev,
+                                  (uintptr_t)off_dev, (uintptr_t)resid_dev,
                                   (uintptr_t)approx_dev, (uintptr_t)theta_dev, (uintptr_t)coef_dev,
                                   (uintptr_t)index_dev, (uintptr_t)energy_dev, (uintptr_t)gap_dev,
                                   (uintptr_t)flags_dev};
@@ -200,14 +204,14 @@ extern "C" act_status act_reconstruct(act_plan_t p, int32_t batch, int32_t order
     ACT_REQUIRE(p != nullptr, "act_reconstruct: plan is NULL");
     ACT_REQUIRE(batch >= 1 && order >= 0, "act_reconstruct: batch must be >= 1, order >= 0");
     ACT_REQUIRE(theta_dev && coef_dev && out_dev, "act_reconstruct: NULL pointer");
-    if (p->desc.ragged) {
-        set_error("act_reconstruct: ragged plans are not implemented in this build");
-        return ACT_ERR_UNSUPPORTED;
-    }
-    ACT_REQUIRE(!len_dev && !off_dev, "act_reconstruct: len_dev/off_dev are for ragged plans only");
+    if (p->desc.ragged)
+        ACT_REQUIRE(len_dev && off_dev, "act_reconstruct: ragged plans need len_dev and off_dev");
+    else
+        ACT_REQUIRE(!len_dev && !off_dev, "act_reconstruct: len_dev/off_dev are for ragged plans only");
     hipStream_t s = (hipStream_t)stream;
     p->last_stream = s;
-    return launch_reconstruct(p, batch, order, theta_dev, coef_dev, out_dev, s);
+    return launch_reconstruct(p, batch, order, theta_dev, coef_dev, len_dev, (const long long*)off_dev,
+                              out_dev, s);
 }
 
 extern "C" act_status act_correlate(act_plan_t p, int32_t batch, const double* resid_dev,

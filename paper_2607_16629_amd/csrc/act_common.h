@@ -42,11 +42,13 @@ void set_error(const std::string& msg);
 struct GridDev {
     double fs;            // sampling rate [Hz]
     const double* axis;   // concatenated axis values: tc | fc | c | logdt
-    int n;                // samples per signal
-    int n_pad;            // padded row length (multiple of 256)
+    int n;                // samples per signal (ragged plans: of this channel)
+    int n_pad;            // padded row length (multiple of 256; ragged: of the longest)
     int cnt[4];           // n_tc, n_fc, n_c, n_ld
     int off[4];           // offsets of each axis inside `axis`
     long long atoms;      // n_tc*n_fc*n_c*n_ld
+    int ragged_div;       // ragged plans: samples per time centre (0: plain plan)
+    double tc_step;       // ragged channel: spacing of its time centres [s]
 };
 
 // grid-hull box and grid spacing used by the refinement
@@ -65,7 +67,42 @@ __device__ __forceinline__ void grid_theta(const GridDev& g, long long i, double
         i /= g.cnt[a];
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) th[a] = g.axis[g.off[a] + id[a]];
+    for (int a = 1; a < 4; ++a) th[a] = g.axis[g.off[a] + id[a]];
+    // a ragged channel's time centres form the half-open axis (0, n_tc div/fs,
+    // n_tc): value j = 0 + j * step
+    th[0] = g.ragged_div ? (double)id[0] * g.tc_step : g.axis[g.off[0] + id[0]];
+}
+
+// Geometry of channel b: its samples, offset in the packed residual, and its
+// own dictionary (a ragged channel has floor(len/div) time centres, one every
+// div samples; a plain channel uses the plan grid).
+struct ChanGeom {
+    GridDev g;          // the channel's grid
+    long long off;      // first sample in the packed residual / approximation
+    double box_step0, box_lo0, box_hi0;  // refinement box along t_c
+};
+
+__device__ __forceinline__ ChanGeom chan_geom(const GridDev& g, int b, const int* len,
+                                              const long long* off) {
+    ChanGeom c;
+    c.g = g;
+    if (g.ragged_div) {
+        int n = len[b];
+        if (n < 0 || n > g.n) n = 0;  // out-of-range lengths: no samples (flagged by the init pass)
+        const int ntc = n / g.ragged_div;
+        c.g.n = n;
+        c.g.cnt[0] = ntc;
+        c.g.tc_step = ntc > 0 ? ((double)(ntc * g.ragged_div) / g.fs) / (double)ntc : 1.0;
+        c.g.atoms = (long long)ntc * g.cnt[1] * g.cnt[2] * g.cnt[3];
+        c.off = off[b];
+        c.box_step0 = ntc > 1 ? c.g.tc_step : 1.0;
+        c.box_lo0 = 0.0;
+        c.box_hi0 = ntc > 1 ? (double)(ntc - 1) * c.g.tc_step : 0.0;
+    } else {
+        c.off = (long long)b * g.n;
+        c.box_step0 = c.box_lo0 = c.box_hi0 = 0.0;  // unused: the plan box applies
+    }
+    return c;
 }
 
 // One sample of the real Gaussian chirplet of Eq. (1) without its analytic
@@ -180,6 +217,11 @@ struct act_plan_s {
     size_t workspace_bytes = 0;
 
     const double* search_resid = nullptr;  // FP64 residual the FP64 search reads
+    const int* call_len = nullptr;          // ragged: lengths / offsets of the current call
+    const long long* call_off = nullptr;
+    double* lag_energy = nullptr;           // ragged synthesised: [n_fc][n_cl][fac_w] prefix sums of g^2
+    int* items = nullptr;                   // ragged synthesised: [B + 1] item prefix, [B] order, counters
+    int n_items_max = 0;
     int chain = 0;                          // FP32 score FMA-chain length (certified margin)
 
     hipStream_t last_stream = nullptr;
@@ -212,6 +254,7 @@ act_status launch_correlate(act_plan_s* p, int batch, const double* resid, long 
 act_status build_tables(act_plan_s* p, hipStream_t s);
 act_status write_bf16_table(act_plan_s* p, hipStream_t s);
 act_status build_synth(act_plan_s* p, hipStream_t s);
+act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s);
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
                        int* flags, int order, hipStream_t s);
@@ -230,5 +273,6 @@ act_status launch_to_shadow(act_plan_s* p, int batch, const double* resid, hipSt
 int f32_chain_length(int n_pad);
 int synth_chain_length(int n_pad);
 act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double* theta,
-                              const double* coef, double* out, hipStream_t s);
+                              const double* coef, const int* len, const long long* off, double* out,
+                              hipStream_t s);
 }  // namespace act

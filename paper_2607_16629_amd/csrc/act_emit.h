@@ -17,6 +17,8 @@ struct SearchCtl {
     int pass;           // 0: running-max emission, 1: rerun of overflowed channels
     double* dump;       // act_correlate: scores [batch][dump_count] (no emission)
     long long dump_begin, dump_count;
+    const int* len;         // ragged plans: channel lengths and offsets
+    const long long* off;
 };
 
 // Candidate emission for one lane's score (channel b, atom i).  All lanes of

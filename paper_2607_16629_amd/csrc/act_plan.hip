@@ -161,6 +161,64 @@ __global__ void __launch_bounds__(256) k_norms_rho(GridDev g, double* __restrict
     }
 }
 
+// Ragged synthesised plans: for every (f_c, cl) the inclusive prefix sums
+// over lags d = e - n_pad of the squared atom, q[e] = sum_{e' <= e} g(d')^2,
+// in FP64 and in a fixed order (each thread a contiguous run, then the runs'
+// totals scanned by one thread).  The norm of the atom with time centre m on a
+// channel of n samples is then q[n-1-m+n_pad] - q[-m+n_pad-1].
+// Error-bound ratio: the synthesised score's rounding error scales with
+// |E_w| / |g_w| over the channel's window w of lags.  Every time centre sits at
+// least div samples before the channel's end, so w contains the lags 0..div-1
+// and |g_w|^2 >= sum_{d<div} g(d)^2, while |E_w|^2 <= the envelope's energy
+// over all lags: the ratio of the two bounds every window that occurs.
+__global__ void __launch_bounds__(256) k_lag_energy(GridDev g, int n_cl, int W, int div,
+                                                    double* __restrict__ q,
+                                                    unsigned long long* __restrict__ rho_bits) {
+    __shared__ double tot[256];
+    __shared__ double tot_e[256];
+    __shared__ double tot_h[256];
+    const long long rows = (long long)g.cnt[1] * n_cl;
+    const int per = (W + 255) / 256;
+    for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int fc = (int)(row / n_cl), cl = (int)(row % n_cl);
+        const int ic = cl / g.cnt[3], il = cl % g.cnt[3];
+        const double f = g.axis[g.off[1] + fc], c = g.axis[g.off[2] + ic];
+        const double inv_dt = 1.0 / exp(g.axis[g.off[3] + il]);
+        double* qr = q + (size_t)row * W;
+        const int e0 = threadIdx.x * per, e1 = min(W, e0 + per);
+        double acc = 0.0, acc_e = 0.0, acc_h = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const double tau = (double)(e - g.n_pad) / g.fs;
+            const double u = tau * inv_dt;
+            const double env = exp(-0.5 * u * u);
+            const double v = env * cospi(2.0 * (c * tau * tau + f * tau));
+            acc += v * v;
+            acc_e += env * env;
+            if (e >= g.n_pad && e < g.n_pad + div) acc_h += v * v;
+            qr[e] = acc;
+        }
+        tot[threadIdx.x] = acc;
+        tot_e[threadIdx.x] = acc_e;
+        tot_h[threadIdx.x] = acc_h;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double run = 0.0, run_e = 0.0, head = 0.0;
+            for (int t = 0; t < 256; ++t) {
+                const double x = tot[t];
+                tot[t] = run;
+                run += x;
+                run_e += tot_e[t];
+                head += tot_h[t];
+            }
+            if (head > 0.0) atomicMax(rho_bits, (unsigned long long)__double_as_longlong(sqrt(run_e / head)));
+        }
+        __syncthreads();
+        const double base = tot[threadIdx.x];
+        for (int e = e0; e < e1; ++e) qr[e] += base;
+        __syncthreads();
+    }
+}
+
 act_status build_synth(act_plan_s* p, hipStream_t s) {
     unsigned long long* rb = nullptr;
     ACT_HIP(hipMalloc((void**)&rb, sizeof(unsigned long long)));
@@ -173,8 +231,14 @@ act_status build_synth(act_plan_s* p, hipStream_t s) {
                        dim3(256), 0, s, p->grid, p->fac_w, (float*)p->fac_u, (float*)p->fac_v,
                        (float*)p->fac_c, (float*)p->fac_s);
     ACT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_norms_rho, dim3((unsigned)std::min<long long>((p->atoms + 3) / 4, cus * 32LL)),
-                       dim3(256), 0, s, p->grid, p->inv_norm, p->inv_norm32, rb);
+    if (p->desc.ragged) {
+        const long long rows = (long long)p->grid.cnt[1] * p->n_cl;
+        hipLaunchKernelGGL(k_lag_energy, dim3((unsigned)std::min<long long>(rows, cus * 16LL)), dim3(256), 0, s,
+                           p->grid, p->n_cl, p->fac_w, p->desc.ragged_tc_div, p->lag_energy, rb);
+    } else {
+        hipLaunchKernelGGL(k_norms_rho, dim3((unsigned)std::min<long long>((p->atoms + 3) / 4, cus * 32LL)),
+                           dim3(256), 0, s, p->grid, p->inv_norm, p->inv_norm32, rb);
+    }
     ACT_HIP(hipGetLastError());
     unsigned long long bits = 0;
     ACT_HIP(hipMemcpyAsync(&bits, rb, sizeof bits, hipMemcpyDeviceToHost, s));
@@ -229,7 +293,7 @@ static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
-                    p->inv_norm32, p->tc_shift, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -268,8 +332,15 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     ACT_REQUIRE(desc->max_batch >= 1, "act_plan: max_batch must be >= 1");
     ACT_REQUIRE(desc->cand_cap >= 0 && desc->refine_steps >= 0, "act_plan: negative cand_cap/refine_steps");
     if (desc->ragged) {
-        set_error("act_plan: ragged plans are not implemented in this build");
-        return ACT_ERR_UNSUPPORTED;
+        ACT_REQUIRE(desc->ragged_tc_div >= 1, "act_plan: ragged plans need ragged_tc_div >= 1");
+        if (!(desc->dict == ACT_DICT_SYNTH && (desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32))) {
+            set_error("act_plan: ragged plans support the FP64 and FP32 synthesised searches in this build");
+            return ACT_ERR_UNSUPPORTED;
+        }
+        if (desc->prec == ACT_PREC_F32 && desc->ragged_tc_div % 16 != 0) {
+            set_error("act_plan: the ragged FP32 synthesised search needs ragged_tc_div a multiple of 16");
+            return ACT_ERR_UNSUPPORTED;
+        }
     }
     if (desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_BF16) {
         set_error("act_plan: this precision / dictionary pair is not implemented in this build");
@@ -335,6 +406,14 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     p->grid.n = p->n;
     p->grid.n_pad = p->n_pad;
     p->grid.atoms = atoms;
+    if (desc->ragged) {
+        // a ragged channel has floor(len/div) time centres; the plan grid is the
+        // widest channel's (n_samples long), used for sizing only
+        p->grid.ragged_div = desc->ragged_tc_div;
+        p->grid.cnt[0] = std::max(1, gr.n_samples / desc->ragged_tc_div);
+        p->grid.atoms = (long long)p->grid.cnt[0] * p->grid.cnt[1] * p->grid.cnt[2] * p->grid.cnt[3];
+        p->atoms = p->grid.atoms;
+    }
 
     const size_t B = (size_t)p->max_batch, cap = (size_t)p->cap;
     const size_t elt = desc->prec == ACT_PREC_BF16 ? 2 : 4;
@@ -352,7 +431,32 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMalloc((void**)&p->inv_norm, (size_t)atoms * sizeof(double)));
     }
     const bool synth32 = desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_F32;
-    if (synth32) {
+    if (synth32 && desc->ragged) {
+        p->n_cl = ax[2]->count * ax[3]->count;
+        p->fac_w = 2 * p->n_pad;
+        const size_t ucl = (size_t)p->n_cl * p->fac_w * sizeof(float);
+        const size_t ufc = (size_t)ax[1]->count * p->fac_w * sizeof(float);
+        const size_t qb = (size_t)ax[1]->count * p->n_cl * p->fac_w * sizeof(double);
+        size_t free_b = 0, total_b = 0;
+        PLAN_HIP(hipMemGetInfo(&free_b, &total_b));
+        if (qb + 2 * ucl + 2 * ufc + (64ull << 20) > free_b) {
+            set_error("act_plan: the lag-energy table of " + std::to_string(qb) + " bytes does not fit");
+            return fail(ACT_ERR_NOMEM);
+        }
+        PLAN_HIP(hipMalloc(&p->fac_u, ucl));
+        PLAN_HIP(hipMalloc(&p->fac_v, ucl));
+        PLAN_HIP(hipMalloc(&p->fac_c, ufc));
+        PLAN_HIP(hipMalloc(&p->fac_s, ufc));
+        PLAN_HIP(hipMalloc((void**)&p->lag_energy, qb));
+        PLAN_HIP(hipMalloc((void**)&p->items, ((size_t)p->max_batch + 3) * sizeof(int)));
+        p->table_bytes = 0;
+        const long long tiles = (long long)p->max_batch * (gr.n_samples / desc->ragged_tc_div) *
+                                ((p->n_cl + 127) / 128) * ((ax[1]->count + 63) / 64);
+        if (tiles > 0x7fffffffLL) {
+            set_error("act_plan: a ragged batch of max_batch signals has more than 2^31 search tiles");
+            return fail(ACT_ERR_UNSUPPORTED);
+        }
+    } else if (synth32) {
         // time centres must sit on integer samples that are multiples of 16
         std::vector<int> shift(ax[0]->count);
         for (int j = 0; j < ax[0]->count; ++j) {

@@ -24,6 +24,10 @@ struct PlanDev {
     double* ebound;
     double* rnorm;
     int* need_rerun;
+    const int* len;          // ragged plans: channel lengths and offsets
+    const long long* off;
+    int* items;              // ragged synthesised plans: tile queue (counters after [B])
+    int batch;
 };
 
 static PlanDev view(const act_plan_s* p) {
@@ -45,6 +49,10 @@ static PlanDev view(const act_plan_s* p) {
     v.ebound = p->ebound;
     v.rnorm = p->rnorm;
     v.need_rerun = p->need_rerun;
+    v.len = p->call_len;
+    v.off = p->call_off;
+    v.items = p->items;
+    v.batch = 0;
     return v;
 }
 
@@ -82,11 +90,11 @@ __device__ double score_bound(const PlanDev& P, double rn, double er) {
 // E = |r|^2, the search copy of r (FP32 or BF16, zero padded) and its rounding
 // error; resets the channel's search state.  Block-wide; returns E.
 template <int TB>
-__device__ double refresh_channel(const PlanDev& P, int b, const double* r, double* red,
+__device__ double refresh_channel(const PlanDev& P, int b, const double* r, int n, double* red,
                                   bool bad) {
     double acc[2] = {0.0, 0.0};
     for (int k = threadIdx.x; k < P.g.n_pad; k += TB) {
-        const double v = k < P.g.n ? r[k] : 0.0;
+        const double v = k < n ? r[k] : 0.0;
         double back;
         if (P.prec == ACT_PREC_BF16) {
             unsigned short h = bf16_rne((float)v);
@@ -119,17 +127,22 @@ __global__ void __launch_bounds__(NT) k_init(PlanDev P, double* __restrict__ res
                                              int order) {
     __shared__ double red[block_sum_lds(NT, 2)];
     const int b = blockIdx.x;
-    const double* r = resid + (size_t)b * P.g.n;
+    const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
+    const int n = cg.g.n;
+    const double* r = resid + cg.off;
     int bad = 0;
-    for (int k = threadIdx.x; k < P.g.n; k += NT) {
+    for (int k = threadIdx.x; k < n; k += NT) {
         if (!isfinite(r[k])) bad = 1;
-        if (approx) approx[(size_t)b * P.g.n + k] = 0.0;
+        if (approx) approx[cg.off + k] = 0.0;
     }
     bad = __syncthreads_or(bad);
-    const double E = refresh_channel<NT>(P, b, r, red, bad != 0);
+    const bool empty = cg.g.atoms == 0;
+    const bool bad_len = P.len && (P.len[b] < 0 || P.len[b] > P.g.n);
+    const double E = refresh_channel<NT>(P, b, r, n, red, bad != 0 || empty);
     if (threadIdx.x == 0) {
         energy[(size_t)b * (order + 1)] = E;
-        flags[b] = bad ? ACT_FLAG_NONFINITE : 0;
+        flags[b] = (bad ? ACT_FLAG_NONFINITE : 0) | (empty ? ACT_FLAG_RAGGED_EMPTY : 0) |
+                   (bad_len ? ACT_FLAG_BAD_LENGTH : 0);
     }
 }
 
@@ -148,6 +161,7 @@ __global__ void k_to_shadow(PlanDev P, const double* __restrict__ resid) {
 // the exact final threshold.
 __global__ void k_overflow(PlanDev P, int batch) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0 && P.items) P.items[batch + 2] = 0;  // rerun-pass tile queue
     if (b >= batch) return;
     if (P.cand_count[b] > P.cap) {
         P.need_rerun[b] = 1;
@@ -166,7 +180,8 @@ __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __rest
     const int lane = threadIdx.x & (kWave - 1);
     const int cnt = min(P.cand_count[b], P.cap);
     const double T = (double)bitsf(P.gmax[b]) - 2.0 * eb;
-    const double* r = resid + (size_t)b * P.g.n;
+    const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
+    const double* r = resid + cg.off;
     const int wpb = blockDim.x / kWave;
     for (int j = blockIdx.x * wpb + threadIdx.x / kWave; j < cnt; j += gridDim.x * wpb) {
         const size_t slot = (size_t)b * P.cap + j;
@@ -175,11 +190,11 @@ __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __rest
             continue;
         }
         double th[4];
-        grid_theta(P.g, (long long)P.cand_idx[slot], th);
+        grid_theta(cg.g, (long long)P.cand_idx[slot], th);
         const double inv_dt = 1.0 / exp(th[3]);
         double s = 0.0, q = 0.0;
-        for (int k = lane; k < P.g.n; k += kWave) {
-            const double v = atom_sample64(sample_time(k, P.g.fs), th[0], th[1], th[2], inv_dt);
+        for (int k = lane; k < cg.g.n; k += kWave) {
+            const double v = atom_sample64(sample_time(k, cg.g.fs), th[0], th[1], th[2], inv_dt);
             s += v * r[k];
             q += v * v;
         }
@@ -480,12 +495,16 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
     __shared__ unsigned s_i1[NWR];
     const int b = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    double* r = resid + (size_t)b * P.g.n;
+    const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
+    const GridDev& G = cg.g;
+    double* r = resid + cg.off;
     int fl = flags[b];
     const double eb = P.ebound[b];
     const size_t o = (size_t)b * order + k;
+    // the search of this order has drained its tile queue: reset it for the next
+    if (b == 0 && threadIdx.x == 0 && P.items) P.items[P.batch + 1] = 0;
 
-    if (fl & ACT_FLAG_NONFINITE) {
+    if (fl & (ACT_FLAG_NONFINITE | ACT_FLAG_RAGGED_EMPTY)) {
         if (threadIdx.x == 0) {
             const double nan = __longlong_as_double(0x7ff8000000000000LL);
             for (int j = 0; j < 4; ++j) theta[o * 4 + j] = nan;
@@ -562,9 +581,15 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
     }
 
     double th0[4], th[4], J = 0.0;
-    grid_theta(P.g, best, th0);
+    grid_theta(G, best, th0);
+    BoxDev box = P.box;
+    if (G.ragged_div) {
+        box.step[0] = cg.box_step0;
+        box.lo[0] = cg.box_lo0;
+        box.hi[0] = cg.box_hi0;
+    }
     if (steps > 0) {
-        fl |= refine_block<NTR>(r, P.g, P.box, th0, steps, th, &J, red, L);
+        fl |= refine_block<NTR>(r, G, box, th0, steps, th, &J, red, L);
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) th[j] = th0[j];
@@ -573,27 +598,27 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
     // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4))
     const double inv_dt = 1.0 / exp(th[3]);
     double acc[1] = {0.0};
-    for (int t = threadIdx.x; t < P.g.n; t += NTR) {
-        const double v = atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt);
+    for (int t = threadIdx.x; t < G.n; t += NTR) {
+        const double v = atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt);
         acc[0] += v * v;
     }
     block_sum<NTR, 1>(acc, red);
     const double nrm = sqrt(acc[0]);
     const bool ok = nrm >= 1e-300;
     acc[0] = 0.0;
-    for (int t = threadIdx.x; t < P.g.n; t += NTR) {
-        const double v = ok ? atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
+    for (int t = threadIdx.x; t < G.n; t += NTR) {
+        const double v = ok ? atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
         acc[0] += v * r[t];
     }
     block_sum<NTR, 1>(acc, red);
     const double ck = acc[0];
-    for (int t = threadIdx.x; t < P.g.n; t += NTR) {
-        const double v = ok ? atom_sample64(sample_time(t, P.g.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
+    for (int t = threadIdx.x; t < G.n; t += NTR) {
+        const double v = ok ? atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
         r[t] = r[t] - ck * v;
-        if (approx) approx[(size_t)b * P.g.n + t] = approx[(size_t)b * P.g.n + t] + ck * v;
+        if (approx) approx[cg.off + t] = approx[cg.off + t] + ck * v;
     }
     __syncthreads();
-    const double E = refresh_channel<NTR>(P, b, r, red, false);
+    const double E = refresh_channel<NTR>(P, b, r, G.n, red, false);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) theta[o * 4 + j] = th[j];
@@ -742,13 +767,17 @@ __global__ void __launch_bounds__(NT) k_vg_f32(GridDev g, const float* __restric
     }
 }
 
-__global__ void __launch_bounds__(NT) k_reconstruct(GridDev g, int order,
+__global__ void __launch_bounds__(NT) k_reconstruct(GridDev g0, int order,
                                                     const double* __restrict__ theta,
                                                     const double* __restrict__ coef,
+                                                    const int* __restrict__ len,
+                                                    const long long* __restrict__ off,
                                                     double* __restrict__ out) {
     __shared__ double red[block_sum_lds(NT, 1)];
     const int b = blockIdx.x;
-    double* o = out + (size_t)b * g.n;
+    const ChanGeom cg = chan_geom(g0, b, len, off);
+    const GridDev& g = cg.g;
+    double* o = out + cg.off;
     for (int t = threadIdx.x; t < g.n; t += NT) o[t] = 0.0;
     for (int k = 0; k < order; ++k) {
         const double* th = theta + ((size_t)b * order + k) * 4;
@@ -800,7 +829,9 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
                                        double* approx, double* theta, double* coef,
                                        long long* index, double* energy, double* gap, int* flags,
                                        hipStream_t s) {
-    hipLaunchKernelGGL(k_select_refine_update, dim3(batch), dim3(NTR), 0, s, view(p), k, order,
+    PlanDev v = view(p);
+    v.batch = batch;
+    hipLaunchKernelGGL(k_select_refine_update, dim3(batch), dim3(NTR), 0, s, v, k, order,
                        p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
@@ -828,8 +859,10 @@ act_status launch_value_and_grad(act_plan_s* p, int m, int dtype, const void* re
 }
 
 act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double* theta,
-                              const double* coef, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reconstruct, dim3(batch), dim3(NT), 0, s, p->grid, order, theta, coef, out);
+                              const double* coef, const int* len, const long long* off, double* out,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_reconstruct, dim3(batch), dim3(NT), 0, s, p->grid, order, theta, coef, len, off,
+                       out);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

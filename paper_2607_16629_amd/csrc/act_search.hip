@@ -42,14 +42,14 @@ static act_status dispatch(act_plan_s* p, int batch, hipStream_t s, const Search
 
 act_status launch_search(act_plan_s* p, int batch, int pass, hipStream_t s) {
     SearchCtl ctl{p->cand_idx, p->cand_score, p->cand_count, p->gmax, p->ebound, p->need_rerun,
-                  p->cap, pass, nullptr, 0, 0};
+                  p->cap, pass, nullptr, 0, 0, p->call_len, p->call_off};
     return dispatch(p, batch, s, ctl, p->search_resid);
 }
 
 act_status launch_correlate(act_plan_s* p, int batch, const double* resid, long long begin,
                             long long count, double* out, hipStream_t s) {
     SearchCtl ctl{p->cand_idx, p->cand_score, p->cand_count, p->gmax, p->ebound, p->need_rerun,
-                  p->cap, 0, out, begin, count};
+                  p->cap, 0, out, begin, count, nullptr, nullptr};
     return dispatch(p, batch, s, ctl, resid);
 }
 

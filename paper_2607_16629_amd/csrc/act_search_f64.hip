@@ -9,11 +9,13 @@ namespace act {
 // blockIdx.y = channel.
 // --------------------------------------------------------------------------
 template <bool RERUN>
-__global__ void __launch_bounds__(256) k_search_f64(GridDev g, const double* __restrict__ resid,
+__global__ void __launch_bounds__(256) k_search_f64(GridDev g0, const double* __restrict__ resid,
                                                    SearchCtl ctl) {
     const int b = blockIdx.y;
     if (RERUN && ctl.need_rerun[b] == 0) return;
-    const double* r = resid + (size_t)b * g.n;
+    const ChanGeom cg = chan_geom(g0, b, ctl.len, ctl.off);
+    const GridDev& g = cg.g;
+    const double* r = resid + cg.off;
     const long long total = ctl.dump ? ctl.dump_count : g.atoms;
     const long long base0 = ctl.dump ? ctl.dump_begin : 0;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -42,6 +44,7 @@ __global__ void __launch_bounds__(256) k_search_f64(GridDev g, const double* __r
 
 act_status launch_search_f64(act_plan_s* p, int batch, const SearchCtl& ctl, const double* resid,
                              hipStream_t s) {
+    // ragged plans: every channel's dictionary is at most the widest one
     const long long total = ctl.dump ? ctl.dump_count : p->atoms;
     long long blocks = (total + 255) / 256;
     const long long cap = (long long)device_cus() * 16;

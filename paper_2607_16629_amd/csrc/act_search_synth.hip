@@ -42,33 +42,27 @@ struct SynthDev {
     const float* V;
     const float* C;     // [n_fc][W]
     const float* S;
-    const float* inv_norm;  // [atoms] FP32 copy of 1/|g|
-    const int* tc_shift;    // [n_tc] integer sample of each time centre
+    const float* inv_norm;  // [atoms] FP32 copy of 1/|g| (plain plans)
+    const int* tc_shift;    // [n_tc] integer sample of each time centre (plain plans)
+    const double* lag_energy;  // [n_fc][n_cl][W] prefix sums of g(d)^2 (ragged plans)
     int W, n_cl;
 };
 
-// grid: x = (tc, cl block, fc chunk) tiles, y = channel
-template <bool RERUN, bool DUMP>
-__global__ void __launch_bounds__(256) k_search_synth_f32(GridDev g, SynthDev sy,
-                                                          const float* __restrict__ shadow,
-                                                          SearchCtl ctl, int n_clb, int n_fcc) {
-    // B operand [C|S part][fc][sample]; one f32x4 of padding per column keeps
-    // the 16-byte column reads of 32 lanes on distinct LDS banks
-    __shared__ f32x4 bl[2][SY_COLS][SY_STAGE / 4 + 1];
-    __shared__ float s_red[4];
-    __shared__ float s_M;
+// One workgroup tile: time centre tc (integer shift m) of channel b, 128 cl
+// rows, 64 f_c columns; scores = P * 1/|g| (1/|g| read from inv_norm, or from
+// the prefix sums of g^2 of a ragged channel), fused certified emission.
+struct TileArgs {
+    int b, tc, m, clb, fcc, n, n_pad_ch;  // n: samples of the channel
+};
+
+template <bool RERUN, bool DUMP, bool RAGGED>
+__device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __restrict__ r,
+                           const SearchCtl& ctl, const TileArgs& ta, f32x4 (*bl)[SY_COLS][SY_STAGE / 4 + 1],
+                           float* s_red, float* s_M) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int b = blockIdx.y;
-    if (RERUN && ctl.need_rerun[b] == 0) return;
-    if (!DUMP && ctl.ebound[b] < 0.0) return;
+    const int b = ta.b, tc = ta.tc, m = ta.m, clb = ta.clb, fcc = ta.fcc;
     const int n_fc = g.cnt[1];
-    const long long tiles = (long long)g.cnt[0] * n_clb * n_fcc;
-    const float* r = shadow + (size_t)b * g.n_pad;
-    for (long long t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const int fcc = (int)(t % n_fcc);
-        const int clb = (int)((t / n_fcc) % n_clb);
-        const int tc = (int)(t / ((long long)n_fcc * n_clb));
-        const int m = sy.tc_shift[tc];
+    {
         const int fc0 = fcc * SY_COLS;
         const int cl = clb * SY_ROWS + w * 32 + (lane & 31);   // this lane's A row
         const bool row_ok = cl < sy.n_cl;
@@ -81,14 +75,14 @@ __global__ void __launch_bounds__(256) k_search_synth_f32(GridDev g, SynthDev sy
 #pragma unroll
             for (int v = 0; v < 16; ++v) tot[cb][v] = 0.0f;
 
-        for (int n0 = 0; n0 < g.n_pad; n0 += SY_STAGE) {
+        for (int n0 = 0; n0 < ta.n_pad_ch; n0 += SY_STAGE) {
             __syncthreads();
             // B operand of this stage: C_fc(n-m) r(n) and -S_fc(n-m) r(n)
             for (int q = threadIdx.x; q < SY_COLS * SY_STAGE; q += 256) {
                 const int fcl = q / SY_STAGE, sn = q % SY_STAGE;
                 const int fc = fc0 + fcl, n = n0 + sn;
                 float cv = 0.0f, sv = 0.0f;
-                if (fc < n_fc && n < g.n) {
+                if (fc < n_fc && n < ta.n) {
                     const float rv = r[n];
                     const int e = n - m + g.n_pad;
                     cv = sy.C[(size_t)fc * sy.W + e] * rv;
@@ -142,13 +136,26 @@ __global__ void __launch_bounds__(256) k_search_synth_f32(GridDev g, SynthDev sy
                 const int c2 = clw + mfma32_row_s(v, lane);
                 const bool ok = fc < n_fc && c2 < sy.n_cl;
                 const long long idx = ok ? ((long long)tc * n_fc + fc) * sy.n_cl + c2 : 0;
-                tot[cb][v] = ok ? tot[cb][v] * sy.inv_norm[idx] : 0.0f;
+                float inv = 0.0f;
+                if (ok) {
+                    if (RAGGED) {
+                        // |g|^2 over samples 0..n-1 of the channel = a window of the
+                        // prefix sums of the squared lag atom (lags d = n - m)
+                        const double* q = sy.lag_energy + ((size_t)fc * sy.n_cl + c2) * sy.W;
+                        const int e_lo = g.n_pad - m, e_hi = ta.n - 1 - m + g.n_pad;
+                        const double e2 = q[e_hi] - (e_lo > 0 ? q[e_lo - 1] : 0.0);
+                        inv = e2 > 0.0 ? (float)(1.0 / sqrt(e2)) : 0.0f;
+                    } else {
+                        inv = sy.inv_norm[idx];
+                    }
+                }
+                tot[cb][v] = ok ? tot[cb][v] * inv : 0.0f;
                 lmax = fmaxf(lmax, fabsf(tot[cb][v]));
                 if (DUMP && ok && idx >= ctl.dump_begin && idx < ctl.dump_begin + ctl.dump_count)
                     ctl.dump[(size_t)b * ctl.dump_count + (idx - ctl.dump_begin)] = tot[cb][v];
             }
         }
-        if (DUMP) continue;
+        if (DUMP) return;
         lmax = wave_max(lmax);
         if (lane == 0) s_red[w] = lmax;
         __syncthreads();
@@ -157,10 +164,10 @@ __global__ void __launch_bounds__(256) k_search_synth_f32(GridDev g, SynthDev sy
             const float cur = load_gmax(&ctl.gmax[b]);
             float M = cur;
             if (!RERUN && wm > cur) M = fmaxf(bitsf(atomicMax(&ctl.gmax[b], fbits(wm))), wm);
-            s_M = M;
+            *s_M = M;
         }
         __syncthreads();
-        const double Td = (double)s_M - 2.0 * ctl.ebound[b];
+        const double Td = (double)*s_M - 2.0 * ctl.ebound[b];
         float T = (float)Td;
         if ((double)T > Td) T = nextafterf(T, -INFINITY);
         if (lmax >= T) {
@@ -185,20 +192,113 @@ __global__ void __launch_bounds__(256) k_search_synth_f32(GridDev g, SynthDev sy
     }
 }
 
+// plain plans: grid x = (tc, cl block, f_c chunk) tiles, y = channel
+template <bool RERUN, bool DUMP>
+__global__ void __launch_bounds__(256) k_search_synth_f32(GridDev g, SynthDev sy,
+                                                          const float* __restrict__ shadow,
+                                                          SearchCtl ctl, int n_clb, int n_fcc) {
+    __shared__ f32x4 bl[2][SY_COLS][SY_STAGE / 4 + 1];
+    __shared__ float s_red[4];
+    __shared__ float s_M;
+    const int b = blockIdx.y;
+    if (RERUN && ctl.need_rerun[b] == 0) return;
+    if (!DUMP && ctl.ebound[b] < 0.0) return;
+    const long long tiles = (long long)g.cnt[0] * n_clb * n_fcc;
+    const float* r = shadow + (size_t)b * g.n_pad;
+    for (long long t = blockIdx.x; t < tiles; t += gridDim.x) {
+        TileArgs ta;
+        ta.b = b;
+        ta.fcc = (int)(t % n_fcc);
+        ta.clb = (int)((t / n_fcc) % n_clb);
+        ta.tc = (int)(t / ((long long)n_fcc * n_clb));
+        ta.m = sy.tc_shift[ta.tc];
+        ta.n = g.n;
+        ta.n_pad_ch = g.n_pad;
+        synth_tile<RERUN, DUMP, false>(g, sy, r, ctl, ta, bl, s_red, &s_M);
+    }
+}
+
+// ragged plans: a persistent grid takes (channel, tc, cl block, f_c chunk)
+// tiles from a queue (items[b] = first tile of channel b, items[B] = total,
+// counters after it); every channel has floor(len/div) time centres.
+template <bool RERUN>
+__global__ void __launch_bounds__(256) k_search_synth_f32_ragged(GridDev g, SynthDev sy,
+                                                                 const float* __restrict__ shadow,
+                                                                 SearchCtl ctl, int batch, int n_clb,
+                                                                 int n_fcc, int* __restrict__ items) {
+    __shared__ f32x4 bl[2][SY_COLS][SY_STAGE / 4 + 1];
+    __shared__ float s_red[4];
+    __shared__ float s_M;
+    __shared__ long long s_item;
+    const long long total = items[batch];
+    int* counter = items + batch + 1 + (RERUN ? 1 : 0);
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const long long it = s_item;
+        if (it >= total) break;
+        int lo = 0, hi = batch - 1;  // channel: last b with items[b] <= it
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const int b = lo;
+        if (RERUN && ctl.need_rerun[b] == 0) continue;
+        if (ctl.ebound[b] < 0.0) continue;
+        const long long t = it - items[b];
+        TileArgs ta;
+        ta.b = b;
+        ta.fcc = (int)(t % n_fcc);
+        ta.clb = (int)((t / n_fcc) % n_clb);
+        ta.tc = (int)(t / ((long long)n_fcc * n_clb));
+        ta.m = ta.tc * g.ragged_div;
+        ta.n = ctl.len[b];  // in range: a channel with tiles has 0 < len <= n_samples
+        ta.n_pad_ch = (ta.n + SY_STAGE - 1) / SY_STAGE * SY_STAGE;
+        synth_tile<RERUN, false, true>(g, sy, shadow + (size_t)b * g.n_pad, ctl, ta, bl, s_red, &s_M);
+    }
+}
+
+// Tile prefix of a ragged batch (one thread), and the queue counters reset.
+__global__ void k_ragged_items(const int* __restrict__ len, int batch, int n_max, int div, int n_clb,
+                               int n_fcc, int* __restrict__ items) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int acc = 0;
+    for (int b = 0; b < batch; ++b) {
+        items[b] = acc;
+        const int n = (len[b] < 0 || len[b] > n_max) ? 0 : len[b];
+        acc += (n / div) * n_clb * n_fcc;
+    }
+    items[batch] = acc;
+    items[batch + 1] = 0;
+    items[batch + 2] = 0;
+}
+
 // FP32 accumulation chain of one synthesised score: 2 roundings per MFMA over a
 // stage (2 * SY_STAGE) plus one per stage added to the total.
 int synth_chain_length(int n_pad) { return 2 * SY_STAGE + n_pad / SY_STAGE + 2; }
 
 act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s) {
     SynthDev sy{(const float*)p->fac_u, (const float*)p->fac_v, (const float*)p->fac_c,
-                (const float*)p->fac_s, p->inv_norm32, p->tc_shift, p->fac_w, p->n_cl};
+                (const float*)p->fac_s, p->inv_norm32, p->tc_shift, p->lag_energy, p->fac_w, p->n_cl};
     const int n_clb = (p->n_cl + SY_ROWS - 1) / SY_ROWS;
     const int n_fcc = (p->grid.cnt[1] + SY_COLS - 1) / SY_COLS;
+    const float* sh = (const float*)p->shadow;
+    if (p->desc.ragged) {
+        const unsigned blocks = (unsigned)device_cus() * 2;
+        if (ctl.pass)
+            hipLaunchKernelGGL((k_search_synth_f32_ragged<true>), dim3(blocks), dim3(256), 0, s, p->grid, sy,
+                               sh, ctl, batch, n_clb, n_fcc, p->items);
+        else
+            hipLaunchKernelGGL((k_search_synth_f32_ragged<false>), dim3(blocks), dim3(256), 0, s, p->grid, sy,
+                               sh, ctl, batch, n_clb, n_fcc, p->items);
+        ACT_HIP(hipGetLastError());
+        return ACT_OK;
+    }
     const long long tiles = (long long)p->grid.cnt[0] * n_clb * n_fcc;
     long long blocks = tiles;
     const long long cap = (long long)device_cus() * 4;
     blocks = blocks < cap ? blocks : cap;
-    const float* sh = (const float*)p->shadow;
     if (ctl.dump)
         hipLaunchKernelGGL((k_search_synth_f32<false, true>), dim3((unsigned)blocks, batch), dim3(256), 0, s,
                            p->grid, sy, sh, ctl, n_clb, n_fcc);
@@ -208,6 +308,16 @@ act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ct
     else
         hipLaunchKernelGGL((k_search_synth_f32<false, false>), dim3((unsigned)blocks, batch), dim3(256), 0, s,
                            p->grid, sy, sh, ctl, n_clb, n_fcc);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s) {
+    if (!(p->desc.ragged && p->desc.dict == ACT_DICT_SYNTH && p->desc.prec == ACT_PREC_F32)) return ACT_OK;
+    const int n_clb = (p->n_cl + SY_ROWS - 1) / SY_ROWS;
+    const int n_fcc = (p->grid.cnt[1] + SY_COLS - 1) / SY_COLS;
+    hipLaunchKernelGGL(k_ragged_items, dim3(1), dim3(64), 0, s, p->call_len, batch, p->grid.n,
+                       p->desc.ragged_tc_div, n_clb, n_fcc, p->items);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

@@ -266,17 +266,30 @@ def refine_pairs(seed_cfg: int = 4, pairs: int = 4096,
     return w
 
 
+def ragged_grid(n: int, tc_div: int, n_fc: int, n_c: int, n_ld: int, fs: float = FS_HZ) -> Grid:
+    """Grid of one signal of a ragged batch: floor(n/tc_div) time centres one
+    every tc_div samples (the half-open axis (0, n_tc tc_div/fs, n_tc)), and
+    the EEG-like f_c / c / dt axes."""
+    n_tc = n // tc_div
+    g = eeg_grid(n, max(1, n_tc), n_fc, n_c, n_ld, fs)
+    if n_tc == 0:  # shorter than one time-centre step: no dictionary (flagged
+        # empty by the library); one t_c = 0 keeps the signal model defined
+        return Grid(fs, n, Axis(0.0, 0.0, 1, True), g.fc, g.c, g.logdt)
+    return Grid(fs, n, Axis(0.0, n_tc * tc_div / fs, n_tc, True), g.fc, g.c, g.logdt)
+
+
 def ragged_batch(seed_cfg: int = 5, count: int = 1000, n_min: int = 256,
                  n_max: int = 16384, order: int = 15,
-                 fc_c_ld: Tuple[int, int, int] = (64, 32, 16)) -> Workload:
+                 fc_c_ld: Tuple[int, int, int] = (64, 32, 16), tc_div: int = 32) -> Workload:
     """Uneven batch: lengths log-uniform in [n_min, n_max]; each signal has
-    its own grid with n_tc = floor(N/32) time centres and 64 x 32 x 16
-    (f_c, c, dt) points; 2-16 chirplets, SNR U(-5, 20) dB; order 15."""
+    its own grid with n_tc = floor(N/32) time centres every 32 samples and
+    64 x 32 x 16 (f_c, c, dt) points; 2-16 chirplets, SNR U(-5, 20) dB;
+    order 15."""
     rngs = _streams(seed_cfg, count)
     lens, grids, parts, ths, amps = [], [], [], [], []
     for rng in rngs:
         n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
-        g = eeg_grid(n, max(1, n // 32), *fc_c_ld)
+        g = ragged_grid(n, tc_div, *fc_c_ld)
         k = int(rng.integers(2, 17))
         s, th, a = make_signal(rng, g, k, rng.uniform(-5.0, 20.0))
         lens.append(n)

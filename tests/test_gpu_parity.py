@@ -45,7 +45,44 @@ def gpu_decompose(grid, signals, order, prec, dict_, refine_steps=30, cand_cap=0
     return res
 
 
-def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label=""):
+def hessian_condition(oracle, grid, r, theta0, theta):
+    """Condition number of the Hessian of J at theta in the refinement's
+    scaled coordinates (central differences of the oracle's gradient), over
+    the unfrozen axes; inf when the optimum sits on the grid hull."""
+    step, lo, hi = oracle.refine_box(grid)
+    h = oracle.refine_scales(grid, theta0)
+    free = [j for j in range(4) if h[j] > 0]
+    if any(theta[j] <= lo[j] + 1e-12 * max(1, abs(lo[j])) or theta[j] >= hi[j] - 1e-12 * max(1, abs(hi[j]))
+           for j in free):
+        return np.inf
+    H = np.zeros((len(free), len(free)))
+    for a, j in enumerate(free):
+        e = np.zeros(4)
+        e[j] = 1e-5 * h[j]
+        gp = oracle.objective(grid.fs, theta + e, r)[1] * h
+        gm = oracle.objective(grid.fs, theta - e, r)[1] * h
+        H[a] = (gp - gm)[free] / 2e-5
+    H = 0.5 * (H + H.T)
+    w = np.abs(np.linalg.eigvalsh(H))
+    return w.max() / max(w.min(), 1e-300)
+
+
+def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_steps):
+    """Order by order against the oracle.  Every step of the GPU's pursuit is
+    checked as the oracle's step on the GPU's own residual (rebuilt in FP64 from
+    the GPU's earlier atoms), so that rounding carried along the chain is not
+    mistaken for a wrong step:
+      - the selected atom is the oracle's arg-max on that residual (or ties it
+        within the gap excuse);
+      - the refined parameters equal the oracle's refinement from that grid
+        atom at converged, well-conditioned optima (the oracle's result does
+        not move with 10x the iterations and the Hessian condition in scaled
+        coordinates is < 1e8), else J agrees to 1e-6;
+      - the coefficient and the residual energy follow from those parameters.
+    While the two chains hold the same atoms at tight parameters, the residual
+    energies must also agree with the oracle's own chain to 1e-6; a tie broken
+    the other way or a loosely matched step ends that comparison (the two
+    pursuits then legitimately differ)."""
     step, _, _ = oracle.refine_box(grid)
     B, order = ref["index"].shape
     compared = 0
@@ -53,22 +90,48 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label=""):
         s = signals[b]
         sn = float(np.linalg.norm(s))
         np.testing.assert_allclose(gpu["energy"][b, 0], ref["energy"][b, 0], rtol=1e-12)
+        rg = s.copy()          # the GPU's residual before order k
+        chain = True           # GPU chain still comparable with the oracle's
         for k in range(order):
-            gi, ri = gpu["index"][b, k], ref["index"][b, k]
-            if gi != ri:
-                assert ref["gap"][b, k] <= GAP_EXCUSE, (label, b, k, gi, ri, ref["gap"][b, k])
-                break  # the two pursuits legitimately diverge from here
-            dth = np.abs(gpu["theta"][b, k] - ref["theta"][b, k])
-            tol = 1e-6 * np.maximum(np.abs(ref["theta"][b, k]), step)
-            assert np.all(dth <= tol), (label, b, k, dth / np.maximum(np.abs(ref["theta"][b, k]), step))
-            assert abs(gpu["coef"][b, k] - ref["coef"][b, k]) <= 1e-6 * abs(ref["coef"][b, k]) + 1e-12 * sn, \
-                (label, b, k, gpu["coef"][b, k], ref["coef"][b, k])
-            e_ref = ref["energy"][b, k + 1]
-            assert abs(gpu["energy"][b, k + 1] - e_ref) <= 1e-6 * e_ref + 1e-12 * sn * sn, \
-                (label, b, k, gpu["energy"][b, k + 1], e_ref)
+            gi = int(gpu["index"][b, k])
+            i_o, gap = oracle.argmax(oracle.correlate(grid, rg))
+            if gi != i_o:
+                assert gap <= GAP_EXCUSE, (label, b, k, gi, i_o, gap)
+                p_g = abs(oracle.correlate(grid, rg, gi, 1)[0])
+                p_o = abs(oracle.correlate(grid, rg, i_o, 1)[0])
+                assert p_g >= (1 - 2 * GAP_EXCUSE) * p_o, (label, b, k, p_g, p_o)
+            if chain and gi != int(ref["index"][b, k]):
+                assert ref["gap"][b, k] <= GAP_EXCUSE, (label, b, k, gi, ref["index"][b, k])
+                chain = False
+            th_g = gpu["theta"][b, k]
+            th0 = oracle.grid_theta(grid, gi)
+            th_o, J_o, _ = oracle.refine(grid, rg, th0, refine_steps)
+            scale = np.maximum(np.abs(th_o), step)
+            dth = np.abs(th_g - th_o) / scale
+            J_g = oracle.objective(grid.fs, th_g, rg)[0]
+            if not np.all(dth <= 1e-6):
+                th_long, _, _ = oracle.refine(grid, rg, th0, 10 * max(refine_steps, 1))
+                converged = np.all(np.abs(th_long - th_o) <= 1e-8 * scale)
+                cond = hessian_condition(oracle, grid, rg, th0, th_o)
+                assert not (converged and cond <= 1e8), (label, b, k, "converged", cond, dth)
+                assert abs(J_g - J_o) <= 1e-6 * J_o, (label, b, k, cond, J_g, J_o, dth)
+                chain = False
+            gu, _ = oracle.atom_unit(grid.fs, grid.n, th_g)
+            c_o = float(gu @ rg)
+            assert abs(gpu["coef"][b, k] - c_o) <= 1e-9 * abs(c_o) + 1e-12 * sn, \
+                (label, b, k, gpu["coef"][b, k], c_o)
+            rg = rg - gpu["coef"][b, k] * gu
+            e_own = float(rg @ rg)
+            assert abs(gpu["energy"][b, k + 1] - e_own) <= 1e-9 * e_own + 1e-12 * sn * sn, \
+                (label, b, k, gpu["energy"][b, k + 1], e_own)
+            if chain:
+                e_ref = ref["energy"][b, k + 1]
+                assert abs(gpu["energy"][b, k + 1] - e_ref) <= 1e-6 * e_ref + 1e-12 * sn * sn, \
+                    (label, b, k, gpu["energy"][b, k + 1], e_ref)
             compared += 1
         # decomposition identities on the GPU result itself
         np.testing.assert_allclose(gpu["approx"][b] + gpu["resid"][b], s, rtol=0, atol=1e-12 * np.abs(s).max())
+        np.testing.assert_allclose(gpu["resid"][b], rg, rtol=0, atol=1e-10 * sn)
     return compared
 
 
@@ -119,7 +182,7 @@ def test_decompose_plain_1x512(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, wl.order, refine_steps=30)
     gpu = gpu_decompose(wl.grid, wl.signals, wl.order, prec, dict_, refine_steps=30)
-    n = assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec)
+    n = assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, 30)
     assert n == wl.order
 
 
@@ -129,7 +192,7 @@ def test_decompose_without_refinement_is_exact_mp(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, 8, refine_steps=0)
     gpu = gpu_decompose(wl.grid, wl.signals, 8, prec, dict_, refine_steps=0)
-    assert assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals) == 8
+    assert assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, 0) == 8
 
 
 def test_decompose_batch_with_edge_channels(oracle):
@@ -146,7 +209,7 @@ def test_decompose_batch_with_edge_channels(oracle):
         gpu = gpu_decompose(g, sig, 4, prec, dict_, refine_steps=60)
         ref = oracle.decompose(g, sig[:2], 4, refine_steps=60)
         assert_decomposition_parity({k: (v[:2] if v is not None else None) for k, v in gpu.items()},
-                                    ref, g, oracle, sig[:2], prec)
+                                    ref, g, oracle, sig[:2], prec, 60)
         assert gpu["flags"][3] & A().FLAG_NONFINITE
         assert gpu["flags"][2] == 0
         np.testing.assert_array_equal(gpu["energy"][2], 0.0)
@@ -168,7 +231,7 @@ def test_synth_ragged_tail_and_partial_tiles(oracle):
         assert np.max(np.abs(p[b] - ref)) <= 1e-5 * np.linalg.norm(sig[b])
     ref = oracle.decompose(g, sig, 4, refine_steps=30)
     gpu = gpu_decompose(g, sig, 4, "f32", "synth", refine_steps=30)
-    assert_decomposition_parity(gpu, ref, g, oracle, sig, "synth")
+    assert_decomposition_parity(gpu, ref, g, oracle, sig, "synth", 30)
 
 
 def test_synth_rejects_off_sample_time_centres():
@@ -177,6 +240,91 @@ def test_synth_rejects_off_sample_time_centres():
     with pytest.raises(act.ActError) as e:
         act.Plan(g, dict_="synth", prec="f32")
     assert e.value.status == act.ACT_ERR_UNSUPPORTED
+
+
+def _ragged_case(count, n_min, n_max, fc_c_ld, order, seed=5):
+    wl = W.ragged_batch(seed_cfg=seed, count=count, n_min=n_min, n_max=n_max, order=order,
+                        fc_c_ld=fc_c_ld)
+    return wl
+
+
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "synth")])
+def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_):
+    """Uneven lengths in one call: every signal has its own dictionary
+    (floor(N/32) time centres); each is checked against the oracle run on that
+    signal alone; lengths below 32 samples are flagged empty."""
+    wl = _ragged_case(9, 20, 900, (8, 6, 4), 4)
+    lens = wl.lengths.copy()
+    nmax = int(lens.max())
+    plan = A().Plan(W.ragged_grid(nmax, 32, 8, 6, 4), dict_=dict_, prec=prec, max_batch=len(lens),
+                    refine_steps=200, ragged=True, ragged_tc_div=32)
+    gpu = plan.decompose_ragged(wl.signals, lens, wl.offsets, 4)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in gpu.items() if v is not None}
+    checked = 0
+    for b in range(len(lens)):
+        n, o = int(lens[b]), int(wl.offsets[b])
+        s = wl.signals[o:o + n]
+        if n < 32:
+            assert res["flags"][b] & A().FLAG_RAGGED_EMPTY
+            continue
+        g = wl.grids[b]
+        ref = oracle.decompose(g, s, 4, refine_steps=200)
+        sub = {"index": res["index"][b:b + 1], "theta": res["theta"][b:b + 1],
+               "coef": res["coef"][b:b + 1], "energy": res["energy"][b:b + 1],
+               "gap": res["gap"][b:b + 1], "approx": res["approx"][None, o:o + n],
+               "resid": res["resid"][None, o:o + n]}
+        checked += assert_decomposition_parity(sub, ref, g, oracle, s[None, :], f"ragged{b}", 200)
+    assert checked >= 20
+    rec = plan.act_reconstruct_ragged(gpu["theta"], gpu["coef"], lens, wl.offsets,
+                                      wl.signals.size).cpu().numpy()
+    ok = np.repeat(lens >= 32, lens)
+    np.testing.assert_allclose(rec[ok], res["approx"][ok], rtol=0, atol=1e-12 * np.abs(wl.signals).max())
+
+
+def test_ragged_bad_lengths_are_flagged_and_queue_replays_match():
+    """Lengths outside [0, n_samples] are flagged and skipped without touching
+    the other channels; repeated calls (captured-graph replays of the
+    synthesised search's tile queue) reproduce the direct launches bit for bit."""
+    act = A()
+    wl = _ragged_case(5, 40, 400, (8, 6, 4), 3, seed=9)
+    lens = wl.lengths.copy()
+    plan = act.Plan(W.ragged_grid(int(lens.max()), 32, 8, 6, 4), dict_="synth", prec="f32",
+                    max_batch=len(lens), refine_steps=30, ragged=True, ragged_tc_div=32)
+    good = plan.decompose_ragged(wl.signals, lens, wl.offsets, 3)
+    bad = lens.copy()
+    bad[1] = int(lens.max()) + 1
+    bad[3] = -5
+    plan.act_timing_enable(True)
+    out = plan.decompose_ragged(wl.signals, bad, wl.offsets, 3)
+    plan.act_timing_enable(False)
+    ref = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    ref_resid = out["resid"].cpu().numpy()
+    g = {k: v.cpu().numpy() for k, v in good.items() if v is not None}
+    for b in (1, 3):
+        assert ref["flags"][b] & act.FLAG_BAD_LENGTH
+        assert np.all(ref["index"][b] == -1)
+    for b in (0, 2, 4):
+        assert ref["flags"][b] == g["flags"][b]
+        for k in ("index", "theta", "coef", "energy"):
+            np.testing.assert_array_equal(ref[k][b], g[k][b])
+    # fixed buffers: the second and later calls replay one captured graph
+    sig = torch.from_numpy(wl.signals).cuda()
+    resid = torch.empty_like(sig)
+    lt = torch.from_numpy(bad.astype(np.int32)).cuda()
+    ot = torch.from_numpy(wl.offsets.astype(np.int64)).cuda()
+    o2 = plan.alloc_outputs(len(lens), 3, approx=False)
+    o2["approx"] = torch.empty_like(sig)
+    for rep in range(4):
+        for v in o2.values():
+            v.zero_()
+        resid.copy_(sig)
+        plan.act_decompose_ragged(resid, lt, ot, 3, o2)
+        torch.cuda.synchronize()
+        _ = (resid * 2).sum().item()      # unrelated eager work between replays
+        for k in ("index", "theta", "coef", "energy", "flags"):
+            np.testing.assert_array_equal(o2[k].cpu().numpy(), ref[k], err_msg=f"{rep} {k}")
+        np.testing.assert_array_equal(resid.cpu().numpy(), ref_resid)
 
 
 def test_decompose_deterministic():
@@ -224,7 +372,7 @@ def test_small_candidate_capacity_reruns_exactly(oracle, prec):
     ref = oracle.decompose(wl.grid, wl.signals, 3, refine_steps=0)
     gpu = gpu_decompose(wl.grid, wl.signals, 3, prec, "table", refine_steps=0,
                         cand_cap=2 if prec == "f32" else 40)
-    assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals)
+    assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, 0)
 
 
 def test_bf16_batch_of_70_channels(oracle):
@@ -236,7 +384,7 @@ def test_bf16_batch_of_70_channels(oracle):
     pick = [0, 33, 63, 64, 69]
     ref = oracle.decompose(g, wl.signals[pick], 4, refine_steps=30)
     sub = {k: (v[pick] if v is not None else None) for k, v in gpu.items()}
-    assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick]) >= 15
+    assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick], "bf16", 30) >= 15
 
 
 @pytest.mark.parametrize("dict_", ["table", "synth"])
