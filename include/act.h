@@ -76,7 +76,9 @@ enum {
 enum {
     ACT_PREC_F64 = 0,  /* FP64 correlation (ACT_DICT_SYNTH only) */
     ACT_PREC_F32 = 1,  /* FP32 correlation, certified FP64 rescoring of the candidates */
-    ACT_PREC_BF16 = 2  /* BF16 x BF16 -> FP32 MFMA correlation, certified FP64 rescoring */
+    ACT_PREC_BF16 = 2, /* BF16 x BF16 -> FP32 MFMA correlation, certified FP64 rescoring */
+    ACT_PREC_F16 = 3   /* FP16 x FP16 -> FP32 MFMA correlation over factor tables
+                          (ACT_DICT_SYNTH only), certified FP64 rescoring */
 };
 
 /* Per-channel flags written by act_decompose / act_refine. */

@@ -201,6 +201,9 @@ struct act_plan_s {
     int fac_w = 0, n_cl = 0;
     float* inv_norm32 = nullptr;
     int* tc_shift = nullptr;
+    void* fac_u16 = nullptr;  // ACT_PREC_F16: FP16 copies of fac_u / fac_v
+    void* fac_v16 = nullptr;
+    float* rscale = nullptr;  // ACT_PREC_F16: [B] power-of-two scale of the FP16 operand
     double rho_max = 0.0;     // max over atoms of |envelope|_2 / |g|_2
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
 
@@ -255,6 +258,7 @@ act_status build_tables(act_plan_s* p, hipStream_t s);
 act_status write_bf16_table(act_plan_s* p, hipStream_t s);
 act_status build_synth(act_plan_s* p, hipStream_t s);
 act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s);
+act_status build_h16_factors(act_plan_s* p, hipStream_t s);
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
                        int* flags, int order, hipStream_t s);
@@ -272,6 +276,7 @@ act_status launch_value_and_grad(act_plan_s* p, int m, int dtype, const void* re
 act_status launch_to_shadow(act_plan_s* p, int batch, const double* resid, hipStream_t s);
 int f32_chain_length(int n_pad);
 int synth_chain_length(int n_pad);
+int h16_chain_length(int n_pad);
 act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double* theta,
                               const double* coef, const int* len, const long long* off, double* out,
                               hipStream_t s);

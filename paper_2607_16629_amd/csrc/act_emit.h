@@ -59,5 +59,6 @@ act_status launch_search_f64(act_plan_s* p, int batch, const SearchCtl& ctl, con
 act_status launch_search_f32t(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s);
 act_status launch_search_bf16t(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s);
 act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s);
+act_status launch_search_h16(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s);
 
 }  // namespace act

@@ -293,7 +293,7 @@ static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
-                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->rscale, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -325,20 +325,23 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     if ((st = validate_axis(gr.c_hz_per_s, "c_hz_per_s")) != ACT_OK) return st;
     if ((st = validate_axis(gr.logdt_ln_s, "logdt_ln_s")) != ACT_OK) return st;
     ACT_REQUIRE(desc->dict == ACT_DICT_SYNTH || desc->dict == ACT_DICT_TABLE, "act_plan: unknown dict");
-    ACT_REQUIRE(desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32 || desc->prec == ACT_PREC_BF16,
+    ACT_REQUIRE(desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32 || desc->prec == ACT_PREC_BF16 ||
+                    desc->prec == ACT_PREC_F16,
                 "act_plan: unknown prec");
+    ACT_REQUIRE(!(desc->prec == ACT_PREC_F16 && desc->dict == ACT_DICT_TABLE),
+                "act_plan: ACT_PREC_F16 is the synthesised factor-table search; use ACT_DICT_SYNTH");
     ACT_REQUIRE(!(desc->prec == ACT_PREC_F64 && desc->dict == ACT_DICT_TABLE),
                 "act_plan: ACT_PREC_F64 searches synthesise atoms; use ACT_DICT_SYNTH");
     ACT_REQUIRE(desc->max_batch >= 1, "act_plan: max_batch must be >= 1");
     ACT_REQUIRE(desc->cand_cap >= 0 && desc->refine_steps >= 0, "act_plan: negative cand_cap/refine_steps");
     if (desc->ragged) {
         ACT_REQUIRE(desc->ragged_tc_div >= 1, "act_plan: ragged plans need ragged_tc_div >= 1");
-        if (!(desc->dict == ACT_DICT_SYNTH && (desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32))) {
-            set_error("act_plan: ragged plans support the FP64 and FP32 synthesised searches in this build");
+        if (!(desc->dict == ACT_DICT_SYNTH && desc->prec != ACT_PREC_BF16)) {
+            set_error("act_plan: ragged plans support the synthesised FP64, FP32 and FP16 searches");
             return ACT_ERR_UNSUPPORTED;
         }
-        if (desc->prec == ACT_PREC_F32 && desc->ragged_tc_div % 16 != 0) {
-            set_error("act_plan: the ragged FP32 synthesised search needs ragged_tc_div a multiple of 16");
+        if (desc->prec != ACT_PREC_F64 && desc->ragged_tc_div % 16 != 0) {
+            set_error("act_plan: the ragged MFMA synthesised searches need ragged_tc_div a multiple of 16");
             return ACT_ERR_UNSUPPORTED;
         }
     }
@@ -360,7 +363,8 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     // longest FP32 accumulation chain of one search score (certified margin):
     // the FP32 GEMV's per-lane FMAs plus its reduction tree; the MFMA path is
     // bounded by one rounding per sample
-    p->chain = desc->prec == ACT_PREC_BF16 ? p->n_pad
+    p->chain = desc->prec == ACT_PREC_BF16  ? p->n_pad
+               : desc->prec == ACT_PREC_F16 ? h16_chain_length(p->n_pad)
                : desc->dict == ACT_DICT_SYNTH ? synth_chain_length(p->n_pad)
                                               : f32_chain_length(p->n_pad);
     p->cap = desc->cand_cap > 0 ? desc->cand_cap : 4096;
@@ -430,7 +434,8 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMalloc(&p->table, p->table_bytes));
         PLAN_HIP(hipMalloc((void**)&p->inv_norm, (size_t)atoms * sizeof(double)));
     }
-    const bool synth32 = desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_F32;
+    // MFMA synthesised searches (FP32, FP16) share the FP32 factor tables
+    const bool synth32 = desc->dict == ACT_DICT_SYNTH && (desc->prec == ACT_PREC_F32 || desc->prec == ACT_PREC_F16);
     if (synth32 && desc->ragged) {
         p->n_cl = ax[2]->count * ax[3]->count;
         p->fac_w = 2 * p->n_pad;
@@ -464,7 +469,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             const double mr = std::nearbyint(mv);
             if (!(std::fabs(mv - mr) <= 1e-6 * std::max(1.0, std::fabs(mv))) || mr < 0 ||
                 mr >= gr.n_samples || ((long long)mr % 16) != 0) {
-                set_error("act_plan: the synthesised FP32 search needs time centres on integer sample "
+                set_error("act_plan: the MFMA synthesised searches need time centres on integer sample "
                           "offsets that are multiples of 16 inside the signal");
                 return fail(ACT_ERR_UNSUPPORTED);
             }
@@ -484,6 +489,12 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMemcpyAsync(p->tc_shift, shift.data(), shift.size() * sizeof(int), hipMemcpyHostToDevice, s));
         p->table_bytes = 0;
     }
+    if (synth32 && desc->prec == ACT_PREC_F16) {
+        const size_t u16b = (size_t)p->n_cl * p->fac_w * 2;
+        PLAN_HIP(hipMalloc(&p->fac_u16, u16b));
+        PLAN_HIP(hipMalloc(&p->fac_v16, u16b));
+        PLAN_HIP(hipMalloc((void**)&p->rscale, B * sizeof(float)));
+    }
     PLAN_HIP(hipMalloc(&p->shadow, B * p->n_pad * elt));
     PLAN_HIP(hipMemsetAsync(p->shadow, 0, B * p->n_pad * elt, s));
     PLAN_HIP(hipMalloc((void**)&p->cand_idx, B * cap * sizeof(unsigned)));
@@ -502,6 +513,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     if (synth32) {
         bs = build_synth(p, s);
         if (bs != ACT_OK) return fail(bs);
+        if (desc->prec == ACT_PREC_F16 && (bs = build_h16_factors(p, s)) != ACT_OK) return fail(bs);
     }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

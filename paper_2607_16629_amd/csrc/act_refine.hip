@@ -28,6 +28,7 @@ struct PlanDev {
     const long long* off;
     int* items;              // ragged synthesised plans: tile queue (counters after [B])
     int batch;
+    float* rscale;           // ACT_PREC_F16: [B] power-of-two scale of the FP16 operand
 };
 
 static PlanDev view(const act_plan_s* p) {
@@ -53,6 +54,7 @@ static PlanDev view(const act_plan_s* p) {
     v.off = p->call_off;
     v.items = p->items;
     v.batch = 0;
+    v.rscale = p->rscale;
     return v;
 }
 
@@ -71,12 +73,24 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 //   |sum g~ r~ - p| <= eg_max |r~| + |e_r|
 //   |fl(sum) - sum| <= gamma_m |g~| |r~|, gamma_m = m u / (1 - m u)   (chain m)
 // FP64 searches round the score to FP32 when storing it: u32 |r| + FP64 sums.
-__device__ double score_bound(const PlanDev& P, double rn, double er) {
+__device__ double score_bound(const PlanDev& P, double rn, double er, double scale) {
     const double u32 = 5.9604644775390625e-08;  // 2^-24
     if (P.prec == ACT_PREC_F64) return 1.01 * (u32 + (P.g.n + 16) * 2.220446049250313e-16) * rn;
     const double rt = rn + er;
     const double m = (double)P.chain;
     const double gam = m * u32 / (1.0 - m * u32);
+    if (P.prec == ACT_PREC_F16) {
+        // FP16 factored synthesis: U and the scaled carrier product C r s are
+        // each rounded to FP16 after FP32 steps (<= 2 u16 + 5 u32 per product
+        // against |U C r|), the FP32 chain, and the FP16 subnormal floor 2^-25
+        // on either operand: sum_n 2^-25 (|C| + |S|)|r| <= 2^-25 sqrt(2N) |r| for
+        // A (|g| >= 1: the centre sample is always present) and
+        // 2^-25 / s sqrt(2N) rho for B; 1/|g| and 1/s scaling adds 2 u |p|.
+        const double u16 = 4.8828125e-04;  // 2^-11
+        const double sub = 2.98023223876953125e-08 * sqrt(2.0 * P.g.n_pad);  // 2^-25 sqrt(2N)
+        return 1.01 * ((2.0 * u16 + 5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er +
+                       3.0 * u32 * rn + sub * (rt + P.rho_max / scale));
+    }
     if (P.dict == ACT_DICT_SYNTH) {
         // factored synthesis: each product U (C r) carries <= 5 FP32 roundings
         // (factors, r, the carrier product, the MFMA product) plus the chain,
@@ -85,6 +99,34 @@ __device__ double score_bound(const PlanDev& P, double rn, double er) {
         return 1.01 * ((5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er + 3.0 * u32 * rn);
     }
     return 1.01 * (P.eg_max * rt + er + gam * (1.0 + P.eg_max) * rt);
+}
+
+// Largest |fl32(r_k)| of a channel (block-wide; every thread gets it).
+template <int TB>
+__device__ float block_absmax(const double* r, int n) {
+    __shared__ unsigned s_mx;
+    if (threadIdx.x == 0) s_mx = 0u;
+    __syncthreads();
+    float m = 0.0f;
+    for (int k = threadIdx.x; k < n; k += TB) m = fmaxf(m, fabsf((float)r[k]));
+    m = wave_max(m);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&s_mx, __float_as_uint(m));
+    __syncthreads();
+    const float v = __uint_as_float(s_mx);
+    __syncthreads();
+    return v;
+}
+
+// Power of two s with s max|r| in [2^12, 2^13): the FP16 operand C r s stays
+// below 2^13 and its subnormal floor 2^-25 / s is at most 2^-37 max|r|.
+// Clamped to [2^-100, 2^100] (the error bound uses the actual s).
+__device__ __forceinline__ float f16_operand_scale(float absmax) {
+    if (!(absmax > 0.0f) || !isfinite(absmax)) return 1.0f;
+    int ex;
+    (void)frexpf(absmax, &ex);  // absmax = f 2^ex, f in [0.5, 1)
+    int k = 13 - ex;
+    k = k < -100 ? -100 : (k > 100 ? 100 : k);
+    return ldexpf(1.0f, k);
 }
 
 // E = |r|^2, the search copy of r (FP32 or BF16, zero padded) and its rounding
@@ -110,10 +152,13 @@ __device__ double refresh_channel(const PlanDev& P, int b, const double* r, int 
         acc[1] += d * d;
     }
     block_sum<TB, 2>(acc, red);
+    const float scale = P.prec == ACT_PREC_F16 ? f16_operand_scale(block_absmax<TB>(r, n)) : 1.0f;
     if (threadIdx.x == 0) {
         const double rn = sqrt(acc[0]);
         P.rnorm[b] = rn;
-        P.ebound[b] = (bad || !(acc[0] > 0.0) || !isfinite(acc[0])) ? -1.0 : score_bound(P, rn, sqrt(acc[1]));
+        if (P.rscale) P.rscale[b] = scale;
+        P.ebound[b] = (bad || !(acc[0] > 0.0) || !isfinite(acc[0])) ? -1.0
+                                                                     : score_bound(P, rn, sqrt(acc[1]), scale);
         P.cand_count[b] = 0;
         P.gmax[b] = 0u;
         P.need_rerun[b] = 0;
@@ -146,8 +191,12 @@ __global__ void __launch_bounds__(NT) k_init(PlanDev P, double* __restrict__ res
     }
 }
 
-__global__ void k_to_shadow(PlanDev P, const double* __restrict__ resid) {
+__global__ void __launch_bounds__(256) k_to_shadow(PlanDev P, const double* __restrict__ resid) {
     const int b = blockIdx.x;
+    if (P.prec == ACT_PREC_F16) {
+        const float sc = f16_operand_scale(block_absmax<256>(resid + (size_t)b * P.g.n, P.g.n));
+        if (threadIdx.x == 0) P.rscale[b] = sc;
+    }
     for (int k = threadIdx.x; k < P.g.n_pad; k += blockDim.x) {
         const double v = k < P.g.n ? resid[(size_t)b * P.g.n + k] : 0.0;
         if (P.prec == ACT_PREC_BF16)

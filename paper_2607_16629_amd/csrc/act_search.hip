@@ -36,6 +36,8 @@ static act_status dispatch(act_plan_s* p, int batch, hipStream_t s, const Search
         return launch_search_bf16t(p, batch, ctl, s);
     if (p->desc.prec == ACT_PREC_F32 && p->desc.dict == ACT_DICT_SYNTH)
         return launch_search_synth_f32(p, batch, ctl, s);
+    if (p->desc.prec == ACT_PREC_F16 && p->desc.dict == ACT_DICT_SYNTH)
+        return launch_search_h16(p, batch, ctl, s);
     set_error("search: unsupported precision / dictionary");
     return ACT_ERR_UNSUPPORTED;
 }

@@ -313,9 +313,12 @@ act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ct
 }
 
 act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s) {
-    if (!(p->desc.ragged && p->desc.dict == ACT_DICT_SYNTH && p->desc.prec == ACT_PREC_F32)) return ACT_OK;
-    const int n_clb = (p->n_cl + SY_ROWS - 1) / SY_ROWS;
-    const int n_fcc = (p->grid.cnt[1] + SY_COLS - 1) / SY_COLS;
+    if (!(p->desc.ragged && p->items)) return ACT_OK;
+    // tiles per time centre: cl blocks x f_c chunks of the search kernel in use
+    const bool h16 = p->desc.prec == ACT_PREC_F16;
+    const int rows = h16 ? 256 : SY_ROWS, cols = h16 ? 64 : SY_COLS;
+    const int n_clb = (p->n_cl + rows - 1) / rows;
+    const int n_fcc = (p->grid.cnt[1] + cols - 1) / cols;
     hipLaunchKernelGGL(k_ragged_items, dim3(1), dim3(64), 0, s, p->call_len, batch, p->grid.n,
                        p->desc.ragged_tc_div, n_clb, n_fcc, p->items);
     ACT_HIP(hipGetLastError());

@@ -141,8 +141,11 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_s
 
 # BF16 operands: |p~ - p| <= (|e_g| + |e_r|/|r| + gamma_N) |r| with both
 # rounding terms below 2^-8; 8e-3 |r| is the resulting certified bound.
+# FP16 factored synthesis: (2 u16 + 5 u32 + gamma) sqrt(2) rho |r| with
+# u16 = 2^-11 and rho (|envelope| / |atom|) below 1.5 on these grids: 2.5e-3 |r|.
 @pytest.mark.parametrize("prec,dict_,tol", [("f64", "synth", 1e-12), ("f32", "table", 1e-5),
-                                            ("bf16", "table", 8e-3), ("f32", "synth", 1e-5)])
+                                            ("bf16", "table", 8e-3), ("f32", "synth", 1e-5),
+                                            ("f16", "synth", 2.5e-3)])
 def test_correlate_matches_oracle(oracle, prec, dict_, tol):
     wl = W.plain_1x512()
     g = wl.grid
@@ -177,7 +180,7 @@ def test_correlate_many_channels_and_ragged_tail(oracle, prec, tol):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table"),
-                                        ("f32", "synth")])
+                                        ("f32", "synth"), ("f16", "synth")])
 def test_decompose_plain_1x512(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, wl.order, refine_steps=30)
@@ -187,7 +190,7 @@ def test_decompose_plain_1x512(oracle, prec, dict_):
 
 
 @pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table"),
-                                        ("f32", "synth")])
+                                        ("f32", "synth"), ("f16", "synth")])
 def test_decompose_without_refinement_is_exact_mp(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, 8, refine_steps=0)
@@ -216,22 +219,23 @@ def test_decompose_batch_with_edge_channels(oracle):
         np.testing.assert_array_equal(gpu["coef"][2], 0.0)
 
 
-def test_synth_ragged_tail_and_partial_tiles(oracle):
-    """Synthesised FP32 search on a length that is not a multiple of the stage
-    (n = 300), time centres every 16 samples, axis counts that leave partial
-    cl blocks and f_c chunks; several channels."""
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 2.5e-3)])
+def test_synth_ragged_tail_and_partial_tiles(oracle, prec, tol):
+    """Synthesised MFMA searches on a length that is not a multiple of the
+    stage (n = 300), time centres every 16 samples, axis counts that leave
+    partial cl blocks and f_c chunks; several channels."""
     g = W.Grid(256.0, 300, W.Axis(0.0, 18 * 16 / 256.0, 18, True), W.Axis(2.0, 60.0, 70, False),
                W.Axis(-15.0, 15.0, 9, False), W.Axis(math.log(0.05), 0.0, 15, False))
     rng = np.random.default_rng(17)
     sig = rng.standard_normal((2, g.n))
-    plan = A().Plan(g, dict_="synth", prec="f32", max_batch=2)
+    plan = A().Plan(g, dict_="synth", prec=prec, max_batch=2)
     p = plan.act_correlate(sig, 0, g.size).cpu().numpy()
     for b in range(2):
         ref = oracle.correlate(g, sig[b])
-        assert np.max(np.abs(p[b] - ref)) <= 1e-5 * np.linalg.norm(sig[b])
+        assert np.max(np.abs(p[b] - ref)) <= tol * np.linalg.norm(sig[b])
     ref = oracle.decompose(g, sig, 4, refine_steps=30)
-    gpu = gpu_decompose(g, sig, 4, "f32", "synth", refine_steps=30)
-    assert_decomposition_parity(gpu, ref, g, oracle, sig, "synth", 30)
+    gpu = gpu_decompose(g, sig, 4, prec, "synth", refine_steps=30)
+    assert_decomposition_parity(gpu, ref, g, oracle, sig, "synth-" + prec, 30)
 
 
 def test_synth_rejects_off_sample_time_centres():
@@ -248,7 +252,7 @@ def _ragged_case(count, n_min, n_max, fc_c_ld, order, seed=5):
     return wl
 
 
-@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "synth")])
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "synth"), ("f16", "synth")])
 def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_):
     """Uneven lengths in one call: every signal has its own dictionary
     (floor(N/32) time centres); each is checked against the oracle run on that
@@ -364,27 +368,27 @@ def test_graph_replays_match_direct_launches():
         assert torch.equal(resid, ref_r), rep
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_small_candidate_capacity_reruns_exactly(oracle, prec):
+@pytest.mark.parametrize("prec,dict_,cap", [("f32", "table", 2), ("bf16", "table", 40), ("f16", "synth", 8)])
+def test_small_candidate_capacity_reruns_exactly(oracle, prec, dict_, cap):
     """A tiny capacity forces the exact-threshold rerun pass; the result must
     not change."""
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, 3, refine_steps=0)
-    gpu = gpu_decompose(wl.grid, wl.signals, 3, prec, "table", refine_steps=0,
-                        cand_cap=2 if prec == "f32" else 40)
+    gpu = gpu_decompose(wl.grid, wl.signals, 3, prec, dict_, refine_steps=0, cand_cap=cap)
     assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, 0)
 
 
-def test_bf16_batch_of_70_channels(oracle):
+@pytest.mark.parametrize("prec,dict_", [("bf16", "table"), ("f16", "synth")])
+def test_batch_of_70_channels(oracle, prec, dict_):
     """More than one 64-channel tile, a reduced grid; the oracle checks a
     few channels from both tiles (channels are independent)."""
     g = W.eeg_grid(1024, 16, 16, 8, 6)
     wl = W.batched_64x2048(channels=70, grid=g, order=4)
-    gpu = gpu_decompose(g, wl.signals, 4, "bf16", "table", refine_steps=30)
+    gpu = gpu_decompose(g, wl.signals, 4, prec, dict_, refine_steps=30)
     pick = [0, 33, 63, 64, 69]
     ref = oracle.decompose(g, wl.signals[pick], 4, refine_steps=30)
     sub = {k: (v[pick] if v is not None else None) for k, v in gpu.items()}
-    assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick], "bf16", 30) >= 15
+    assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick], prec, 30) >= 15
 
 
 @pytest.mark.parametrize("dict_", ["table", "synth"])
@@ -420,15 +424,17 @@ def test_fp32_full_size_2m_atoms(oracle, dict_):
     np.testing.assert_allclose(E[1:], E[:-1] - gpu["coef"][0] ** 2, rtol=0, atol=1e-10 * E[0])
 
 
-def test_bf16_full_size_64x2048(oracle):
-    """64 channels x N = 2048 on the 2,097,152-atom grid, BF16 table + FP64
-    rescoring: per order and for sampled channels, the winner's oracle score
-    is not beaten by sampled atoms, the refined parameters equal the oracle's
-    refinement from the same grid point, and the MP identities hold."""
+@pytest.mark.parametrize("prec,dict_", [("bf16", "table"), ("f16", "synth")])
+def test_full_size_64x2048(oracle, prec, dict_):
+    """64 channels x N = 2048 on the 2,097,152-atom grid, BF16 table or FP16
+    synthesis + FP64 rescoring: per order and for sampled channels, the
+    winner's oracle score is not beaten by sampled atoms, the refined
+    parameters equal the oracle's refinement from the same grid point, and the
+    MP identities hold."""
     wl = W.batched_64x2048()
     g = wl.grid
     order = 2
-    gpu = gpu_decompose(g, wl.signals, order, "bf16", "table", refine_steps=30)
+    gpu = gpu_decompose(g, wl.signals, order, prec, dict_, refine_steps=30)
     step, _, _ = oracle.refine_box(g)
     rng = np.random.default_rng(16)
     sample = rng.choice(g.size, 1500, replace=False)
