@@ -8,8 +8,10 @@ the metric "GMAC/s + MP iters/s, BF16+rescore vs plain FP32":
   * value: the plain FP32 search of one 2048-sample channel against the
     2,097,152-atom dictionary streamed from an HBM table (10 orders);
   * companions in the same line: the same workload with the dictionary
-    synthesised on the device, and the BF16 + FP64-rescore search of 64
-    channels (20 orders).
+    synthesised on the device; 64 channels (20 orders) with the BF16 table +
+    FP64 rescoring and with FP16 factor-table synthesis + FP64 rescoring; and
+    the uneven batch of 1000 signals of 256..16384 samples (15 orders, FP16
+    synthesis, one launch per pass over a tile queue).
 GMAC/s counts the dense correlation work atoms x samples x orders x channels.
 The roofline object of each leg uses its search kernel's mean launch time,
 measured with HIP events that the library records on the launch stream.  The
@@ -32,18 +34,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "residual-chirplet GMAC/s + MP iters/s, BF16+rescore vs plain FP32, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"f32_mfma": 157.3, "bf16_mfma": 2500.0, "f64_vector": 78.6}
+PEAK_TFLOPS = {"f32_mfma": 157.3, "bf16_mfma": 2500.0, "f16_mfma": 2500.0, "f64_vector": 78.6}
 
 # name -> (workload factory, plan kwargs, roofline kind, table element bytes)
 WORKLOADS = {
     "fp32-1x2048": ("fp32_1x2048", dict(dict_="table", prec="f32"), "hbm", 4),
     "fp32-1x2048-synth": ("fp32_1x2048", dict(dict_="synth", prec="f32"), "mfma_f32", 0),
     "bf16-64x2048": ("batched_64x2048", dict(dict_="table", prec="bf16"), "hbm", 2),
+    "f16-64x2048-synth": ("batched_64x2048", dict(dict_="synth", prec="f16"), "mfma_f16", 0),
     "plain-1x512": ("plain_1x512", dict(dict_="synth", prec="f64"), "f64", 0),
 }
 KERNELS = {("table", "f32"): ("k_search_f32_table", "act_search_f32t.hip"),
            ("table", "bf16"): ("k_search_bf16_table", "act_search_bf16.hip"),
            ("synth", "f32"): ("k_search_synth_f32", "act_search_synth.hip"),
+           ("synth", "f16"): ("k_search_h16", "act_search_h16.hip"),
            ("synth", "f64"): ("k_search_f64", "act_search_f64.hip")}
 
 
@@ -152,12 +156,12 @@ def run_workload(name: str, steps: int, warmup: int):
             flops = 2.0 * g.size * g.n * B
             res["roofline"]["mfma_frac_of_bf16_peak"] = round(
                 flops / (search_ms * 1e-3) / (PEAK_TFLOPS["bf16_mfma"] * 1e12), 4)
-    elif kind == "mfma_f32":
+    elif kind in ("mfma_f32", "mfma_f16"):
         # factored synthesis: the matrix cores execute 2 x (atoms x N x B)
         # multiply-adds; the roofline counts the dense correlation's flops
         algo = 2.0 * g.size * g.n * B
         achieved = algo / (search_ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS["f32_mfma"]
+        peak = PEAK_TFLOPS[kind[5:] + "_mfma"]
         res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                            "kernel": kname, "avg_launch_ms": round(search_ms, 5),
@@ -172,6 +176,69 @@ def run_workload(name: str, steps: int, warmup: int):
                            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                            "kernel": kname, "avg_launch_ms": round(search_ms, 5)}
     return res, wl
+
+
+def run_ragged(steps: int, warmup: int, prec: str = "f16"):
+    """Uneven batch: 1000 signals of log-uniform length 256..16384 in one
+    act_decompose call, each with its own grid (floor(N/32) time centres,
+    64 f_c x 32 c x 16 dt), 15 orders, synthesised search + FP64 rescoring."""
+    import numpy as np
+    import torch
+    from paper_2607_16629_amd import act
+    from paper_2607_16629_amd import workloads as W
+    wl = W.ragged_batch()
+    lens = wl.lengths
+    B, order = len(lens), wl.order
+    per_tc = 64 * 32 * 16
+    plan = act.Plan(W.ragged_grid(int(lens.max()), 32, 64, 32, 16), dict_="synth", prec=prec, max_batch=B,
+                    refine_steps=wl.refine_steps, ragged=True, ragged_tc_div=32)
+    sig = torch.from_numpy(wl.signals).cuda()
+    resid = torch.empty_like(sig)
+    lt = torch.from_numpy(lens.astype(np.int32)).cuda()
+    ot = torch.from_numpy(wl.offsets.astype(np.int64)).cuda()
+    out = plan.alloc_outputs(B, order, approx=False)
+    out["approx"] = torch.empty_like(sig)
+
+    def step():
+        resid.copy_(sig)
+        plan.act_decompose_ragged(resid, lt, ot, order, out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.act_timing_enable(True)
+    plan.act_timing_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = plan.act_timing_read()
+    plan.act_timing_enable(False)
+    flags = out["flags"].cpu().numpy()
+    plan.close()
+    macs = float(sum((int(n) // 32) * per_tc * int(n) for n in lens))  # dense MACs of one order
+    s_ms, s_n = phases["search"]
+    search_ms = s_ms / max(s_n, 1)
+    algo = 2.0 * macs
+    achieved = algo / (search_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec + "_mfma"]
+    kname, _ = KERNELS[("synth", prec)]
+    return {"workload": wl.name + "-" + prec, "value": round(macs * order * steps / wall / 1e9, 3),
+            "unit": "GMAC/s", "ms_per_step": round(wall * 1e3 / steps, 3),
+            "mp_iters_per_s": round(order * steps / wall, 3),
+            "channel_iters_per_s": round(order * B * steps / wall, 3),
+            "search_only_gmac_per_s": round(macs / (search_ms * 1e-3) / 1e9, 3),
+            "dtype": prec,
+            "config": {"workload": wl.name, "signals": B, "n_min": int(lens.min()), "n_max": int(lens.max()),
+                       "dense_macs_per_order": macs, "order": order, "dict": "synth",
+                       "refine_steps": wl.refine_steps, "parallelism": "single-gpu"},
+            "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
+            "candidate_overflow_channels": int(((flags & act.FLAG_CAND_OVERFLOW) != 0).sum()),
+            "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                         "frac": round(achieved / peak, 4), "traffic": None,
+                         "kernel": kname + "_ragged", "avg_launch_ms": round(search_ms, 5),
+                         "algorithmic_flops_per_launch": algo, "executed_mfma_flops_per_launch": 2 * algo}}
 
 
 def run_refine(steps: int, warmup: int):
@@ -202,7 +269,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="fp32-1x2048", choices=sorted(WORKLOADS) + ["refine-4096"])
+    ap.add_argument("--workload", default="fp32-1x2048",
+                    choices=sorted(WORKLOADS) + ["refine-4096", "ragged-1000-f16", "ragged-1000-f32"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
@@ -230,6 +298,16 @@ def main():
         print(json.dumps(line), flush=True)
         return
 
+    if args.workload.startswith("ragged-1000"):
+        res = run_ragged(args.steps, args.warmup, args.workload.rsplit("-", 1)[1])
+        line = {"metric": METRIC, "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": res.pop("dtype"), "data": "synthetic", "config": res.pop("config")}
+        line.update(res)
+        print(json.dumps(line), flush=True)
+        return
+
     res, wl = run_workload(args.workload, args.steps, args.warmup)
     line = {"metric": METRIC, "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
@@ -238,9 +316,12 @@ def main():
     line.update(res)
     if args.workload == "fp32-1x2048" and not args.no_companions:
         comp = {}
-        for name in ("fp32-1x2048-synth", "bf16-64x2048"):
+        for name in ("fp32-1x2048-synth", "bf16-64x2048", "f16-64x2048-synth"):
             c, _ = run_workload(name, args.steps, args.warmup)
             comp[name] = c
+        # the uneven batch (15 orders of 1000 signals, ~3.3e13 MACs per order)
+        # takes seconds per step: one timed step after one warm-up
+        comp["ragged-1000-f16"] = run_ragged(1, 1, "f16")
         line["companions"] = comp
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

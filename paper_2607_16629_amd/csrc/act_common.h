@@ -201,9 +201,15 @@ struct act_plan_s {
     int fac_w = 0, n_cl = 0;
     float* inv_norm32 = nullptr;
     int* tc_shift = nullptr;
-    void* fac_u16 = nullptr;  // ACT_PREC_F16: FP16 copies of fac_u / fac_v
+    void* fac_u16 = nullptr;  // ACT_PREC_F16: FP16 copies of the four factor tables
     void* fac_v16 = nullptr;
-    float* rscale = nullptr;  // ACT_PREC_F16: [B] power-of-two scale of the FP16 operand
+    void* fac_c16 = nullptr;
+    void* fac_s16 = nullptr;
+    double* env_q = nullptr;  // ACT_PREC_F16: [n_ld][fac_w] prefix sums of the squared envelope
+    float* rscale = nullptr;  // ACT_PREC_F16: [B] power-of-two scale of the FP16 search copy
+    double* ebmul = nullptr;  // ACT_PREC_F16: [B] per-atom bound factor (times |E_w| / |g_w|)
+    int* perm = nullptr;      // ACT_PREC_F16 ragged: [B] channels by decreasing length
+    unsigned* tmax = nullptr; // ACT_PREC_F16: [B][n_tc] largest pass-0 upper bound per time centre
     double rho_max = 0.0;     // max over atoms of |envelope|_2 / |g|_2
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
 
@@ -259,6 +265,7 @@ act_status write_bf16_table(act_plan_s* p, hipStream_t s);
 act_status build_synth(act_plan_s* p, hipStream_t s);
 act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s);
 act_status build_h16_factors(act_plan_s* p, hipStream_t s);
+act_status launch_h16_ragged_prep(act_plan_s* p, int batch, hipStream_t s);
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
                        int* flags, int order, hipStream_t s);

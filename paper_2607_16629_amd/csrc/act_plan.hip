@@ -293,7 +293,7 @@ static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
-                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->rscale, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -367,7 +367,10 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
                : desc->prec == ACT_PREC_F16 ? h16_chain_length(p->n_pad)
                : desc->dict == ACT_DICT_SYNTH ? synth_chain_length(p->n_pad)
                                               : f32_chain_length(p->n_pad);
-    p->cap = desc->cand_cap > 0 ? desc->cand_cap : 4096;
+    // ragged batches hold long, densely sampled signals: a strong chirplet has
+    // many grid neighbours inside the certified margin, and rescoring them
+    // costs far less than a rerun of the search
+    p->cap = desc->cand_cap > 0 ? desc->cand_cap : (desc->ragged ? 32768 : 4096);
     const act_axis* ax[4] = {&gr.tc_s, &gr.fc_hz, &gr.c_hz_per_s, &gr.logdt_ln_s};
     long long atoms = 1;
     int total = 0;
@@ -420,7 +423,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     }
 
     const size_t B = (size_t)p->max_batch, cap = (size_t)p->cap;
-    const size_t elt = desc->prec == ACT_PREC_BF16 ? 2 : 4;
+    const size_t elt = (desc->prec == ACT_PREC_BF16 || desc->prec == ACT_PREC_F16) ? 2 : 4;
     p->atoms_pad = desc->prec == ACT_PREC_BF16 ? (atoms + 511) / 512 * 512 : atoms;
     if (desc->dict == ACT_DICT_TABLE) {
         p->table_bytes = (size_t)p->atoms_pad * p->n_pad * elt;
@@ -453,7 +456,8 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMalloc(&p->fac_c, ufc));
         PLAN_HIP(hipMalloc(&p->fac_s, ufc));
         PLAN_HIP(hipMalloc((void**)&p->lag_energy, qb));
-        PLAN_HIP(hipMalloc((void**)&p->items, ((size_t)p->max_batch + 3) * sizeof(int)));
+        // tile prefix [B + 1], pass-0 / pass-1 queue counters, any-rerun flag
+        PLAN_HIP(hipMalloc((void**)&p->items, ((size_t)p->max_batch + 4) * sizeof(int)));
         p->table_bytes = 0;
         const long long tiles = (long long)p->max_batch * (gr.n_samples / desc->ragged_tc_div) *
                                 ((p->n_cl + 127) / 128) * ((ax[1]->count + 63) / 64);
@@ -491,9 +495,16 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     }
     if (synth32 && desc->prec == ACT_PREC_F16) {
         const size_t u16b = (size_t)p->n_cl * p->fac_w * 2;
+        const size_t c16b = (size_t)ax[1]->count * p->fac_w * 2;
         PLAN_HIP(hipMalloc(&p->fac_u16, u16b));
         PLAN_HIP(hipMalloc(&p->fac_v16, u16b));
+        PLAN_HIP(hipMalloc(&p->fac_c16, c16b));
+        PLAN_HIP(hipMalloc(&p->fac_s16, c16b));
+        PLAN_HIP(hipMalloc((void**)&p->env_q, (size_t)ax[3]->count * p->fac_w * sizeof(double)));
         PLAN_HIP(hipMalloc((void**)&p->rscale, B * sizeof(float)));
+        PLAN_HIP(hipMalloc((void**)&p->ebmul, B * sizeof(double)));
+        if (desc->ragged) PLAN_HIP(hipMalloc((void**)&p->perm, B * sizeof(int)));
+        PLAN_HIP(hipMalloc((void**)&p->tmax, B * p->grid.cnt[0] * sizeof(unsigned)));
     }
     PLAN_HIP(hipMalloc(&p->shadow, B * p->n_pad * elt));
     PLAN_HIP(hipMemsetAsync(p->shadow, 0, B * p->n_pad * elt, s));

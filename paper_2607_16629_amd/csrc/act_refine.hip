@@ -28,7 +28,10 @@ struct PlanDev {
     const long long* off;
     int* items;              // ragged synthesised plans: tile queue (counters after [B])
     int batch;
-    float* rscale;           // ACT_PREC_F16: [B] power-of-two scale of the FP16 operand
+    float* rscale;           // ACT_PREC_F16: [B] power-of-two scale of the FP16 search copy
+    double* ebmul;           // ACT_PREC_F16: [B] per-atom bound factor
+    unsigned* tmax;          // ACT_PREC_F16: [B][n_tc] pass-0 upper bound per time centre
+    bool per_atom;           // gmax holds the max lower bound, cand_score upper bounds
 };
 
 static PlanDev view(const act_plan_s* p) {
@@ -55,6 +58,9 @@ static PlanDev view(const act_plan_s* p) {
     v.items = p->items;
     v.batch = 0;
     v.rscale = p->rscale;
+    v.ebmul = p->ebmul;
+    v.tmax = p->tmax;
+    v.per_atom = p->desc.prec == ACT_PREC_F16;
     return v;
 }
 
@@ -73,23 +79,22 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 //   |sum g~ r~ - p| <= eg_max |r~| + |e_r|
 //   |fl(sum) - sum| <= gamma_m |g~| |r~|, gamma_m = m u / (1 - m u)   (chain m)
 // FP64 searches round the score to FP32 when storing it: u32 |r| + FP64 sums.
-__device__ double score_bound(const PlanDev& P, double rn, double er, double scale) {
+__device__ double score_bound(const PlanDev& P, double rn, double er, double scale, int n) {
     const double u32 = 5.9604644775390625e-08;  // 2^-24
     if (P.prec == ACT_PREC_F64) return 1.01 * (u32 + (P.g.n + 16) * 2.220446049250313e-16) * rn;
     const double rt = rn + er;
     const double m = (double)P.chain;
     const double gam = m * u32 / (1.0 - m * u32);
     if (P.prec == ACT_PREC_F16) {
-        // FP16 factored synthesis: U and the scaled carrier product C r s are
-        // each rounded to FP16 after FP32 steps (<= 2 u16 + 5 u32 per product
-        // against |U C r|), the FP32 chain, and the FP16 subnormal floor 2^-25
-        // on either operand: sum_n 2^-25 (|C| + |S|)|r| <= 2^-25 sqrt(2N) |r| for
-        // A (|g| >= 1: the centre sample is always present) and
-        // 2^-25 / s sqrt(2N) rho for B; 1/|g| and 1/s scaling adds 2 u |p|.
-        const double u16 = 4.8828125e-04;  // 2^-11
-        const double sub = 2.98023223876953125e-08 * sqrt(2.0 * P.g.n_pad);  // 2^-25 sqrt(2N)
-        return 1.01 * ((2.0 * u16 + 5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er +
-                       3.0 * u32 * rn + sub * (rt + P.rho_max / scale));
+        // additive part of the per-atom bound (the part that scales with
+        // |E_w| / |g_w| is h16_bound_mul): the FP16 search copy's own error
+        // |r - r~| (Cauchy-Schwarz), the FP32 1/|g| (<= 2.5 u when computed
+        // from the prefix sums) and the scalings by 1/|g| and 1/s, and the FP16
+        // subnormal floor 2^-25 of the A operand: sum_n 2^-25 |B_n|
+        // <= 2^-25 sqrt(2N) |r~|, with |g_w| >= 1 (the centre sample is present).
+        const double sub = 2.98023223876953125e-08 * sqrt(2.0 * n);  // 2^-25 sqrt(2N)
+        (void)scale;
+        return 1.01 * (er + 6.0 * u32 * rt + sub * rt);
     }
     if (P.dict == ACT_DICT_SYNTH) {
         // factored synthesis: each product U (C r) carries <= 5 FP32 roundings
@@ -99,6 +104,24 @@ __device__ double score_bound(const PlanDev& P, double rn, double er, double sca
         return 1.01 * ((5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er + 3.0 * u32 * rn);
     }
     return 1.01 * (P.eg_max * rt + er + gam * (1.0 + P.eg_max) * rt);
+}
+
+// Factor of |E_w| / |g_w| in the per-atom bound of the FP16 synthesised search.
+// Each product U (C r~ s) carries FP16 roundings of U and C (each after an
+// FP32 one) and of the packed product: <= 3.01 u16 + 2 u32 relative, against
+// sum_n (|U C| + |V S|)|r~_n| <= |E_w| |r~| (|cos a cos b| + |sin a sin b| is
+// |cos(a - b)| or |cos(a + b)|, at most 1); plus the FP32 chain, the
+// subnormal floor 2^-25 of C (times |r~ s| <= 2^13, i.e. 2^-25 max|r~| after
+// 1/s) and of the product (2^-25 / s), each summed against |E_w| sqrt(2N).
+__device__ double h16_bound_mul(double rn, double er, double scale, int n) {
+    const double u32 = 5.9604644775390625e-08, u16 = 4.8828125e-04;
+    // the channel's own chain: its 2N products (the zero samples past its end
+    // add exactly), plus the final scalings
+    const double m = 2.0 * n + 2.0;
+    const double gam = m * u32 / (1.0 - m * u32);
+    const double rt = rn + er;
+    const double sub = 2.98023223876953125e-08 * sqrt(2.0 * n);
+    return 1.01 * ((3.01 * u16 + 2.0 * u32 + gam) * rt + sub * (rt + 1.0 / scale));
 }
 
 // Largest |fl32(r_k)| of a channel (block-wide; every thread gets it).
@@ -135,10 +158,16 @@ template <int TB>
 __device__ double refresh_channel(const PlanDev& P, int b, const double* r, int n, double* red,
                                   bool bad) {
     double acc[2] = {0.0, 0.0};
+    const float scale = P.prec == ACT_PREC_F16 ? f16_operand_scale(block_absmax<TB>(r, n)) : 1.0f;
     for (int k = threadIdx.x; k < P.g.n_pad; k += TB) {
         const double v = k < n ? r[k] : 0.0;
         double back;
-        if (P.prec == ACT_PREC_BF16) {
+        if (P.prec == ACT_PREC_F16) {
+            // search copy r~ = fl16(fl32(r) s) / s, stored scaled
+            const _Float16 h = (_Float16)((float)v * scale);
+            ((_Float16*)P.shadow)[(size_t)b * P.g.n_pad + k] = h;
+            back = (double)(float)h / (double)scale;
+        } else if (P.prec == ACT_PREC_BF16) {
             unsigned short h = bf16_rne((float)v);
             ((unsigned short*)P.shadow)[(size_t)b * P.g.n_pad + k] = h;
             back = (double)__uint_as_float(((unsigned)h) << 16);
@@ -151,14 +180,16 @@ __device__ double refresh_channel(const PlanDev& P, int b, const double* r, int 
         const double d = v - back;
         acc[1] += d * d;
     }
+    if (P.tmax)
+        for (int k = threadIdx.x; k < P.g.cnt[0]; k += TB) P.tmax[(size_t)b * P.g.cnt[0] + k] = 0u;
     block_sum<TB, 2>(acc, red);
-    const float scale = P.prec == ACT_PREC_F16 ? f16_operand_scale(block_absmax<TB>(r, n)) : 1.0f;
     if (threadIdx.x == 0) {
         const double rn = sqrt(acc[0]);
         P.rnorm[b] = rn;
         if (P.rscale) P.rscale[b] = scale;
+        if (P.ebmul) P.ebmul[b] = h16_bound_mul(rn, sqrt(acc[1]), scale, n);
         P.ebound[b] = (bad || !(acc[0] > 0.0) || !isfinite(acc[0])) ? -1.0
-                                                                     : score_bound(P, rn, sqrt(acc[1]), scale);
+                                                                     : score_bound(P, rn, sqrt(acc[1]), scale, n);
         P.cand_count[b] = 0;
         P.gmax[b] = 0u;
         P.need_rerun[b] = 0;
@@ -196,6 +227,11 @@ __global__ void __launch_bounds__(256) k_to_shadow(PlanDev P, const double* __re
     if (P.prec == ACT_PREC_F16) {
         const float sc = f16_operand_scale(block_absmax<256>(resid + (size_t)b * P.g.n, P.g.n));
         if (threadIdx.x == 0) P.rscale[b] = sc;
+        for (int k = threadIdx.x; k < P.g.n_pad; k += blockDim.x) {
+            const double v = k < P.g.n ? resid[(size_t)b * P.g.n + k] : 0.0;
+            ((_Float16*)P.shadow)[(size_t)b * P.g.n_pad + k] = (_Float16)((float)v * sc);
+        }
+        return;
     }
     for (int k = threadIdx.x; k < P.g.n_pad; k += blockDim.x) {
         const double v = k < P.g.n ? resid[(size_t)b * P.g.n + k] : 0.0;
@@ -215,6 +251,7 @@ __global__ void k_overflow(PlanDev P, int batch) {
     if (P.cand_count[b] > P.cap) {
         P.need_rerun[b] = 1;
         P.cand_count[b] = 0;
+        if (P.items) atomicOr(&P.items[batch + 3], 1);  // the rerun queue has work
     } else {
         P.need_rerun[b] = 0;
     }
@@ -228,7 +265,8 @@ __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __rest
     if (eb < 0.0) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int cnt = min(P.cand_count[b], P.cap);
-    const double T = (double)bitsf(P.gmax[b]) - 2.0 * eb;
+    // per-atom bounds: candidates carry upper bounds, gmax the largest lower bound
+    const double T = P.per_atom ? (double)bitsf(P.gmax[b]) : (double)bitsf(P.gmax[b]) - 2.0 * eb;
     const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
     const double* r = resid + cg.off;
     const int wpb = blockDim.x / kWave;
@@ -551,7 +589,10 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
     const double eb = P.ebound[b];
     const size_t o = (size_t)b * order + k;
     // the search of this order has drained its tile queue: reset it for the next
-    if (b == 0 && threadIdx.x == 0 && P.items) P.items[P.batch + 1] = 0;
+    if (b == 0 && threadIdx.x == 0 && P.items) {
+        P.items[P.batch + 1] = 0;
+        P.items[P.batch + 3] = 0;
+    }
 
     if (fl & (ACT_FLAG_NONFINITE | ACT_FLAG_RAGGED_EMPTY)) {
         if (threadIdx.x == 0) {
@@ -623,8 +664,9 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
     const long long best = (eb >= 0.0 && i1 != 0xffffffffu) ? (long long)i1 : 0;
     double g_gap = 0.0;
     if (eb >= 0.0 && a1 > 0.0) {
-        // an atom outside the list has |p| < M - eb (its score was below M - 2 eb)
-        const double outside = (double)bitsf(P.gmax[b]) - eb;
+        // an atom outside the list has |p| < M - eb (its score was below M - 2 eb);
+        // with per-atom bounds, |p| < L (its upper bound was below L)
+        const double outside = P.per_atom ? (double)bitsf(P.gmax[b]) : (double)bitsf(P.gmax[b]) - eb;
         const double runner = fmax(a2, outside);
         g_gap = fmax(0.0, (a1 - runner) / a1);
     }

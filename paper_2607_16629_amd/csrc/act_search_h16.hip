@@ -5,271 +5,373 @@
 // Same factorisation as the FP32 synthesised search (angle-sum identity on the
 // real part of Eq. (1), time centres on integer samples m):
 //   P[cl][(fc,b)] = sum_n U_cl(n-m) [C_fc(n-m) r_b(n)] - V_cl(n-m) [S_fc(n-m) r_b(n)]
-// A = [U | V]: FP16 copies of the FP64-evaluated envelope-chirp factors, rows cl.
-// B = the carrier-modulated residuals, formed per stage in FP32, scaled by a
-//     power of two per channel (exact) and rounded to FP16.
-// Columns are (f_c, channel) pairs, so a batch of channels shares every A
-// fragment; P is never written to memory (fused certified emission).
+// A = [U | V]: FP16 copies of the FP64-evaluated envelope-chirp factors (rows cl).
+// B = the carrier-modulated residuals: the FP16 carrier table times the FP16
+//     search copy of the residual (scaled by a power of two per channel), one
+//     packed FP16 multiply per two samples, formed per stage in LDS.
+// Columns are (f_c, channel) pairs, so up to 64 channels share every A
+// fragment.  P is never written to memory.
 //
-// Workgroup = 4 waves, each 64 rows x 64 columns (2 x 2 MFMA tiles):
-//   WGC = 1: 256 cl rows x 64 columns  (64 f_c of one channel)
-//   WGC = 2: 128 cl rows x 128 columns (cpf channels for each of 128/cpf f_c)
+// Workgroup = 4 waves stacked along the rows, each 32*WRB rows x 32*WCB columns:
+//   WRB = 2, WCB = 4: 256 cl rows x 128 columns (channel groups of up to 64)
+//   WRB = 2, WCB = 2: 256 cl rows x 64 columns (one channel, 64 f_c)
 // The B operand of a 128-sample stage sits in LDS in MFMA operand order (each
 // k-step and column block is one contiguous KiB: 16-byte conflict-free reads);
-// A fragments stream from L2 with one k-step of prefetch.  Every stage
-// accumulates into fresh registers that are then added to the total, so the
-// FP32 chain of one score is at most 2*128 + N/128 + 2 roundings.
+// A fragments stream from L2 in blocks of two k-steps, one block ahead.
+//
+// Certified emission with per-atom error bounds: every score p~_a carries a
+// bound E_a = rho_a * mul_b + add_b on |p~_a - p_a|, where rho_a is the ratio
+// |envelope| / |atom| over the atom's own window of samples.  The running
+// maximum L of the lower bounds |p~| - E over the channel never exceeds the
+// true maximum, so every atom with |p~_a| + E_a >= L is emitted (with its upper
+// bound); the FP64 rescoring then decides among them exactly.
 #include "act_emit.h"
 
 namespace act {
 
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int H_KS = 128;             // samples per LDS stage
 constexpr int H_KSTEPS = H_KS / 16;   // MFMA k-steps per stage
+constexpr int H_WRB = 2;              // 32-row blocks per wave
+constexpr int H_RW = 4 * 32 * H_WRB;  // rows per workgroup
 
 __device__ __forceinline__ int h_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 
 struct H16Dev {
-    const _Float16* U;      // [n_cl][W] FP16 factor tables, column e = lag + n_pad
+    const _Float16* U;       // [n_cl][W] envelope-chirp factors, column e = lag + n_pad
     const _Float16* V;
-    const float* C;         // [n_fc][W] FP32 carrier tables
-    const float* S;
-    const float* inv_norm;  // plain plans: [atoms] FP32 1/|g|
-    const int* tc_shift;    // plain plans: [n_tc] integer sample of each time centre
+    const _Float16* C;       // [n_fc][W] carrier factors
+    const _Float16* S;
+    const float* inv_norm;   // plain plans: [atoms] FP32 1/|g|
+    const int* tc_shift;     // plain plans: [n_tc] integer sample of each time centre
     const double* lag_energy;  // ragged plans: [n_fc][n_cl][W] prefix sums of g(d)^2
-    const float* rscale;    // [B] power-of-two scale of each channel's FP16 operand
-    int W, n_cl;
+    const double* env_q;     // [n_ld][W] prefix sums of E(d)^2
+    const _Float16* shadow;  // [B][n_pad] fl16(fl32(r) s_b), zero past each length
+    const float* rscale;     // [B] s_b
+    const double* ebmul;     // [B] per-atom bound factor (times rho_a)
+    const int* perm;         // ragged plans: channels in order of decreasing length
+    unsigned* tmax;          // [B][n_tc] largest upper bound of the pass-0 tiles (float bits)
+    int W, n_cl, n_ld, n_tc;
 };
 
 struct H16Tile {
-    int tc, m;        // time centre index and its integer sample
-    int row0;         // first cl row
-    int fc0, b0, cpf; // first f_c, first channel, channels per f_c
-    int nb;           // channels present in this tile's channel group
-    int n_ch;         // samples of the channel (ragged) or of the plan
-    int n_pad_ch;     // samples covered by the stages (multiple of H_KS)
+    int tc, m;         // time centre index and its integer sample
+    int row0;          // first cl row
+    int fc0, cpf;      // first f_c; channels per f_c in the column set
+    int slot0, nslot;  // first channel slot of the group, slots in the batch
+    int n_pad_ch;      // samples covered by the stages (multiple of H_KS)
 };
 
-template <int WGC>
+constexpr int H_NLD = 32;  // log-durations tabulated per tile for the ragged bounds
+
+template <int WCB>
 struct H16Lds {
-    f16x8 bc[H_KSTEPS * 2 * WGC * 64];  // C-part of B, [k-step][col block][lane]
-    f16x8 bs[H_KSTEPS * 2 * WGC * 64];  // (-S)-part of B
-    unsigned cm[64 * WGC];              // column maxima (float bits)
-    float M[64];                        // per-channel running max used for emission
+    f16x8 bc[H_KSTEPS * WCB * 64];  // C-part of B, [k-step][column block][lane]
+    f16x8 bs[H_KSTEPS * WCB * 64];  // (-S)-part of B
+    unsigned cm[32 * WCB];          // column maxima of the lower bounds (float bits)
+    unsigned cu[32 * WCB];          // column maxima of the upper bounds (float bits)
+    float M[64];                    // per-slot running maximum used for emission
+    float env[64 * H_NLD];          // |E_w| of the tile: per row (plain) or per (slot, ld) (ragged)
 };
 
-template <int WGC, bool RERUN, bool DUMP, bool RAGGED>
-__device__ void h16_tile(const GridDev& g, const H16Dev& hd, const float* __restrict__ shadow,
-                         const SearchCtl& ctl, const H16Tile& t, H16Lds<WGC>& L) {
-    constexpr int TC = 64 * WGC;   // columns per workgroup
-    constexpr int NCB = TC / 32;   // column blocks
+__device__ __forceinline__ double window_sum(const double* q, int e_lo, int e_hi) {
+    return q[e_hi] - (e_lo > 0 ? q[e_lo - 1] : 0.0);
+}
+
+// Column c of a tile: its f_c and channel, the channel's length, and whether
+// it takes part (exists, has this time centre, is searched in this pass).
+struct H16Col {
+    int fc, b, n;
+    bool ok;
+};
+
+template <bool RERUN, bool DUMP, bool RAGGED>
+__device__ __forceinline__ H16Col h16_col(const GridDev& g, const H16Dev& hd, const SearchCtl& ctl,
+                                          const H16Tile& t, int c) {
+    H16Col col;
+    col.fc = t.fc0 + c / t.cpf;
+    const int slot = t.slot0 + c % t.cpf;
+    col.ok = col.fc < g.cnt[1] && slot < t.nslot;
+    col.b = 0;
+    col.n = g.n;
+    if (col.ok) {
+        col.b = RAGGED ? hd.perm[slot] : slot;
+        if (RAGGED) {
+            col.n = ctl.len[col.b];
+            col.ok = col.n >= 0 && col.n <= g.n && t.tc < col.n / g.ragged_div;  // has this time centre
+        }
+        col.ok = col.ok && (DUMP || (ctl.ebound[col.b] >= 0.0 && (!RERUN || ctl.need_rerun[col.b])));
+    }
+    return col;
+}
+
+template <int WCB, bool RERUN, bool DUMP, bool RAGGED>
+__device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ctl, const H16Tile& t,
+                         H16Lds<WCB>& L) {
+    constexpr int TC = 32 * WCB;   // columns per workgroup
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wr = w / WGC, wc = w % WGC;
     const int n_fc = g.cnt[1];
     const int W = hd.W;
 
-    // A rows of this lane (two 32-row blocks)
-    int arow[2];
-    bool aok[2];
+    // A rows of this lane
+    int arow[H_WRB];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-        const int cl = t.row0 + wr * 64 + rb * 32 + (lane & 31);
-        aok[rb] = cl < hd.n_cl;
-        arow[rb] = aok[rb] ? cl : 0;
+    for (int rb = 0; rb < H_WRB; ++rb) {
+        const int cl = t.row0 + w * 32 * H_WRB + rb * 32 + (lane & 31);
+        arow[rb] = cl < hd.n_cl ? cl : 0;
     }
-    f32x16 tot[2][2];
+    f32x16 acc[H_WRB][WCB];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < H_WRB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < WCB; ++cb)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) tot[rb][cb][v] = 0.0f;
+            for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.0f;
 
     for (int n0 = 0; n0 < t.n_pad_ch; n0 += H_KS) {
         __syncthreads();
-        // ---- B stage: chunk q = 8 samples of one column, column fastest
-        for (int q = threadIdx.x; q < TC * H_KSTEPS * 2; q += 256) {
-            const int c = q % TC, sh = q / TC, s = sh >> 1, h = sh & 1;
-            const int fc = t.fc0 + c / t.cpf, bl = c % t.cpf;
-            f16x8 cv, sv;
+        // ---- B stage: each thread forms 8-sample chunks of one column; k-slot
+        // order: in each 32-sample block, half h and k-step s' of a lane hold
+        // samples 16 h + 8 s' + (0..7), so a lane's A operands of two k-steps
+        // are 32 contiguous bytes (a lane pair reads 64 contiguous bytes)
+        {
+            constexpr int NQ = TC * H_KSTEPS * 2 / 256;  // chunks per thread
+            constexpr int HALF = NQ / 2;
+            const int c = threadIdx.x % TC;
+            const int fc = t.fc0 + c / t.cpf, slot = t.slot0 + c % t.cpf;
+            const bool ok = fc < n_fc && slot < t.nslot;
+            const int b = ok ? (RAGGED ? hd.perm[slot] : slot) : 0;
+            const _Float16* rp = hd.shadow + (size_t)b * g.n_pad + n0;
+            const _Float16* cp = hd.C + (size_t)(ok ? fc : 0) * W + (n0 - t.m + g.n_pad);
+            const _Float16* sp = hd.S + (size_t)(ok ? fc : 0) * W + (n0 - t.m + g.n_pad);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                cv[j] = (_Float16)0.0f;
-                sv[j] = (_Float16)0.0f;
-            }
-            if (fc < n_fc && bl < t.nb) {
-                const int b = t.b0 + bl;
-                const int n = n0 + 16 * s + 8 * h;
-                const float sc = hd.rscale[b];
-                const float* rp = shadow + (size_t)b * g.n_pad + n;
-                const size_t e = (size_t)fc * W + (n - t.m + g.n_pad);
-                const f32x4 r0 = *reinterpret_cast<const f32x4*>(rp);
-                const f32x4 r1 = *reinterpret_cast<const f32x4*>(rp + 4);
-                const f32x4 c0 = *reinterpret_cast<const f32x4*>(hd.C + e);
-                const f32x4 c1 = *reinterpret_cast<const f32x4*>(hd.C + e + 4);
-                const f32x4 s0 = *reinterpret_cast<const f32x4*>(hd.S + e);
-                const f32x4 s1 = *reinterpret_cast<const f32x4*>(hd.S + e + 4);
+            for (int hf = 0; hf < 2; ++hf) {
+                f16x8 r8[HALF], c8[HALF], s8[HALF];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    cv[j] = (_Float16)((c0[j] * r0[j]) * sc);
-                    cv[4 + j] = (_Float16)((c1[j] * r1[j]) * sc);
-                    sv[j] = (_Float16)(-((s0[j] * r0[j]) * sc));
-                    sv[4 + j] = (_Float16)(-((s1[j] * r1[j]) * sc));
+                for (int i = 0; i < HALF; ++i) {  // loads first, then the products
+                    const int no = 8 * ((hf * HALF + i) * (256 / TC) + threadIdx.x / TC);
+                    r8[i] = *reinterpret_cast<const f16x8*>(rp + no);
+                    c8[i] = *reinterpret_cast<const f16x8*>(cp + no);
+                    s8[i] = *reinterpret_cast<const f16x8*>(sp + no);
+                }
+#pragma unroll
+                for (int i = 0; i < HALF; ++i) {
+                    const int no = 8 * ((hf * HALF + i) * (256 / TC) + threadIdx.x / TC);
+                    const int s = 2 * (no >> 5) + ((no & 15) >> 3), h = (no >> 4) & 1;
+                    f16x8 cv = c8[i] * r8[i], sv = -s8[i] * r8[i];
+                    if (!ok) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            cv[j] = (_Float16)0.0f;
+                            sv[j] = (_Float16)0.0f;
+                        }
+                    }
+                    const int slot_lds = (s * WCB + (c >> 5)) * 64 + (c & 31) + 32 * h;
+                    L.bc[slot_lds] = cv;
+                    L.bs[slot_lds] = sv;
                 }
             }
-            const int slot = (s * NCB + (c >> 5)) * 64 + (c & 31) + 32 * h;
-            L.bc[slot] = cv;
-            L.bs[slot] = sv;
         }
         __syncthreads();
 
-        // ---- MFMA over the stage
-        f32x16 acc[2][2];
+        // ---- MFMA over the stage: blocks of two k-steps, the next block's A
+        // fragments loaded while the current block runs
+        {
+            constexpr int KB = 2, NB = H_KSTEPS / KB;
+            f16x8 ua[2][H_WRB][KB], va[2][H_WRB][KB];
+            auto load_blk = [&](int blk, int buf) {
+                const int eb = n0 + 16 * KB * blk - t.m + g.n_pad + 8 * KB * (lane >> 5);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+                for (int rb = 0; rb < H_WRB; ++rb) {
+                    const f16x8* up = reinterpret_cast<const f16x8*>(hd.U + (size_t)arow[rb] * W + eb);
+                    const f16x8* vp = reinterpret_cast<const f16x8*>(hd.V + (size_t)arow[rb] * W + eb);
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.0f;
-        const int ebase = n0 - t.m + g.n_pad + 8 * (lane >> 5);
-        f16x8 ua[2], va[2], un[2], vn[2];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-            const size_t o = (size_t)arow[rb] * W + ebase;
-            ua[rb] = *reinterpret_cast<const f16x8*>(hd.U + o);
-            va[rb] = *reinterpret_cast<const f16x8*>(hd.V + o);
-        }
-#pragma unroll 2
-        for (int s = 0; s < H_KSTEPS; ++s) {
-            if (s + 1 < H_KSTEPS) {
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    const size_t o = (size_t)arow[rb] * W + ebase + 16 * (s + 1);
-                    un[rb] = *reinterpret_cast<const f16x8*>(hd.U + o);
-                    vn[rb] = *reinterpret_cast<const f16x8*>(hd.V + o);
-                }
-            }
-            f16x8 bC[2], bS[2];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                bC[cb] = L.bc[(s * NCB + wc * 2 + cb) * 64 + lane];
-                bS[cb] = L.bs[(s * NCB + wc * 2 + cb) * 64 + lane];
-            }
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ua[rb], bC[cb], acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(va[rb], bS[cb], acc[rb][cb], 0, 0, 0);
-                }
-            if (s + 1 < H_KSTEPS) {
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    ua[rb] = un[rb];
-                    va[rb] = vn[rb];
-                }
-            }
-        }
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) tot[rb][cb][v] += acc[rb][cb][v];
-    }
-
-    // ---- epilogue: scale to scores (1/|g| and the channel's 1/scale)
-    int col_b[2], col_fc[2];
-    bool col_ok[2];
-    float col_rinv[2];
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-        const int c = wc * 64 + cb * 32 + (lane & 31);
-        col_fc[cb] = t.fc0 + c / t.cpf;
-        const int bl = c % t.cpf;
-        col_b[cb] = t.b0 + bl;
-        col_ok[cb] = col_fc[cb] < n_fc && bl < t.nb;
-        col_rinv[cb] = col_ok[cb] ? 1.0f / hd.rscale[col_b[cb]] : 0.0f;
-    }
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int cl = t.row0 + wr * 64 + rb * 32 + h_row(v, lane);
-                const bool ok = col_ok[cb] && cl < hd.n_cl;
-                float inv = 0.0f;
-                if (ok) {
-                    if (RAGGED) {
-                        const double* qr = hd.lag_energy + ((size_t)col_fc[cb] * hd.n_cl + cl) * W;
-                        const int e_lo = g.n_pad - t.m, e_hi = t.n_ch - 1 - t.m + g.n_pad;
-                        const double e2 = qr[e_hi] - (e_lo > 0 ? qr[e_lo - 1] : 0.0);
-                        inv = e2 > 0.0 ? (float)(1.0 / sqrt(e2)) : 0.0f;
-                    } else {
-                        inv = hd.inv_norm[((size_t)t.tc * n_fc + col_fc[cb]) * hd.n_cl + cl];
+                    for (int j = 0; j < KB; ++j) {
+                        ua[buf][rb][j] = up[j];
+                        va[buf][rb][j] = vp[j];
                     }
                 }
-                tot[rb][cb][v] = ok ? (tot[rb][cb][v] * inv) * col_rinv[cb] : 0.0f;
-                if (DUMP && ok) {
-                    const long long idx = ((long long)t.tc * n_fc + col_fc[cb]) * hd.n_cl + cl;
-                    if (idx >= ctl.dump_begin && idx < ctl.dump_begin + ctl.dump_count)
-                        ctl.dump[(size_t)col_b[cb] * ctl.dump_count + (idx - ctl.dump_begin)] = tot[rb][cb][v];
+            };
+            load_blk(0, 0);
+#pragma unroll
+            for (int blk = 0; blk < NB; ++blk) {
+                const int cur = blk & 1;
+                if (blk + 1 < NB) load_blk(blk + 1, cur ^ 1);
+#pragma unroll
+                for (int sp = 0; sp < KB; ++sp) {
+                    const int s = KB * blk + sp;
+#pragma unroll
+                    for (int cb = 0; cb < WCB; ++cb) {
+                        const f16x8 bC = L.bc[(s * WCB + cb) * 64 + lane];
+                        const f16x8 bS = L.bs[(s * WCB + cb) * 64 + lane];
+#pragma unroll
+                        for (int rb = 0; rb < H_WRB; ++rb) {
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ua[cur][rb][sp], bC, acc[rb][cb], 0, 0, 0);
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(va[cur][rb][sp], bS, acc[rb][cb], 0, 0, 0);
+                        }
+                    }
                 }
             }
-    if (DUMP) return;
-
-    // ---- certified emission: column maxima -> channel maxima -> threshold
-    if (threadIdx.x < TC) L.cm[threadIdx.x] = 0u;
-    __syncthreads();
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-        float m = 0.0f;
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) m = fmaxf(m, fabsf(tot[rb][cb][v]));
-        m = fmaxf(m, __shfl_xor(m, 32, 64));
-        if (lane < 32) atomicMax(&L.cm[wc * 64 + cb * 32 + lane], fbits(m));
-    }
-    __syncthreads();
-    const int nchan = t.cpf < t.nb ? t.cpf : t.nb;
-    if (threadIdx.x < nchan) {
-        const int bl = threadIdx.x, b = t.b0 + bl;
-        float M = INFINITY;
-        if (ctl.ebound[b] >= 0.0 && (!RERUN || ctl.need_rerun[b])) {
-            float wm = 0.0f;
-            for (int c = bl; c < TC; c += t.cpf) wm = fmaxf(wm, bitsf(L.cm[c]));
-            const float cur = load_gmax(&ctl.gmax[b]);
-            M = cur;
-            if (!RERUN && wm > cur) M = fmaxf(bitsf(atomicMax(&ctl.gmax[b], fbits(wm))), wm);
         }
-        L.M[bl] = M;
+    }
+
+    // ---- epilogue: scores and per-atom bounds, one column block at a time
+    const int e_lo = g.n_pad - t.m;
+    // |E_w| (rounded up) of the envelope over each window of the tile: the
+    // window depends on the log-duration and, for ragged plans, on the
+    // signal's length (one entry per (slot, ld)); plain plans index by row.
+    const bool env_tab = !DUMP && (!RAGGED || hd.n_ld <= H_NLD);
+    if (env_tab) {
+        if (RAGGED) {
+            for (int q = threadIdx.x; q < t.cpf * hd.n_ld; q += 256) {
+                const int sl = q / hd.n_ld, ld = q % hd.n_ld;
+                float v = 0.0f;
+                if (t.slot0 + sl < t.nslot) {
+                    int n = ctl.len[hd.perm[t.slot0 + sl]];
+                    n = (n < 0 || n > g.n) ? 0 : n;
+                    if (t.tc < n / g.ragged_div)
+                        v = (float)(sqrt(window_sum(hd.env_q + (size_t)ld * W, e_lo, n - 1 - t.m + g.n_pad)) *
+                                    (1.0 + 1e-6));
+                }
+                L.env[sl * H_NLD + ld] = v;
+            }
+        } else {
+            const int cl = t.row0 + threadIdx.x;
+            float v = 0.0f;
+            if (cl < hd.n_cl)
+                v = (float)(sqrt(window_sum(hd.env_q + (size_t)(cl % hd.n_ld) * W, e_lo, g.n - 1 - t.m + g.n_pad)) *
+                            (1.0 + 1e-6));
+            L.env[threadIdx.x] = v;
+        }
     }
     __syncthreads();
+    float emax[WCB];  // largest bound of this lane's atoms, per column block
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-        if (!col_ok[cb]) continue;
-        const int b = col_b[cb];
-        const float Mc = L.M[b - t.b0];
-        if (Mc == INFINITY) continue;
-        const double Td = (double)Mc - 2.0 * ctl.ebound[b];
-        float T = (float)Td;
-        if ((double)T > Td) T = nextafterf(T, -INFINITY);  // keep the test inclusive
+    for (int cb = 0; cb < WCB; ++cb) {
+        const H16Col col = h16_col<RERUN, DUMP, RAGGED>(g, hd, ctl, t, cb * 32 + (lane & 31));
+        const float rinv = col.ok ? 1.0f / hd.rscale[col.b] : 0.0f;
+        // per-channel bound parts as FP32, rounded up
+        const float mul = col.ok && !DUMP ? (float)(hd.ebmul[col.b] * (1.0 + 1e-6)) : 0.0f;
+        const float add = col.ok && !DUMP ? (float)(ctl.ebound[col.b] * (1.0 + 1e-6)) : 0.0f;
+        const int e_hi = col.n - 1 - t.m + g.n_pad;
+        const int slot_l = (cb * 32 + (lane & 31)) % t.cpf;
+        float em = 0.0f;
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < H_WRB; ++rb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int cl = t.row0 + wr * 64 + rb * 32 + h_row(v, lane);
-                if (cl < hd.n_cl && fabsf(tot[rb][cb][v]) >= T) {
+                const int rl = w * 32 * H_WRB + rb * 32 + h_row(v, lane);  // row in the tile
+                const int cl = t.row0 + rl;
+                float p = 0.0f;
+                if (col.ok && cl < hd.n_cl) {
+                    float inv;
+                    if (RAGGED) {
+                        // FP64 window of the prefix sums, then FP32 (correctly
+                        // rounded) square root and division: <= 2.5 u relative
+                        const double e2 = window_sum(hd.lag_energy + ((size_t)col.fc * hd.n_cl + cl) * W,
+                                                     e_lo, e_hi);
+                        inv = e2 > 0.0 ? 1.0f / sqrtf((float)e2) : 0.0f;
+                    } else {
+                        inv = hd.inv_norm[((size_t)t.tc * n_fc + col.fc) * hd.n_cl + cl];
+                    }
+                    p = (acc[rb][cb][v] * inv) * rinv;
+                    if (DUMP) {
+                        const long long idx = ((long long)t.tc * n_fc + col.fc) * hd.n_cl + cl;
+                        if (idx >= ctl.dump_begin && idx < ctl.dump_begin + ctl.dump_count)
+                            ctl.dump[(size_t)col.b * ctl.dump_count + (idx - ctl.dump_begin)] = p;
+                    } else {
+                        float envn;
+                        if (!RAGGED) {
+                            envn = L.env[rl];
+                        } else if (env_tab) {
+                            envn = L.env[slot_l * H_NLD + cl % hd.n_ld];
+                        } else {
+                            envn = (float)(sqrt(window_sum(hd.env_q + (size_t)(cl % hd.n_ld) * W, e_lo, e_hi)) *
+                                           (1.0 + 1e-6));
+                        }
+                        // rho_a = |E_w| / |g_w| and E_a, rounded up (1 + 2^-20 covers
+                        // the FP32 products), plus room for the rounding of |p| -+ E
+                        const float ef = (envn * inv * mul + add) * 1.00000095f + 2.4e-7f * fabsf(p);
+                        em = fmaxf(em, ef);
+                    }
+                }
+                acc[rb][cb][v] = p;
+                // bound the loads in flight (register pressure of the unrolled epilogue)
+                if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+        emax[cb] = em;
+    }
+    if (DUMP) return;
+
+    // column maxima of |p~| - E (E of the lane's atoms bounded by emax, which
+    // only lowers the lower bounds: still valid)
+    if (threadIdx.x < TC) {
+        L.cm[threadIdx.x] = 0u;
+        L.cu[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < WCB; ++cb) {
+        float m = 0.0f;
+#pragma unroll
+        for (int rb = 0; rb < H_WRB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) m = fmaxf(m, fabsf(acc[rb][cb][v]));
+        float mu = m + emax[cb];
+        m = fmaxf(m - emax[cb], 0.0f);
+        m = fmaxf(m, __shfl_xor(m, 32, 64));
+        mu = fmaxf(mu, __shfl_xor(mu, 32, 64));
+        if (lane < 32) {
+            atomicMax(&L.cm[cb * 32 + lane], fbits(m));
+            atomicMax(&L.cu[cb * 32 + lane], fbits(mu));
+        }
+    }
+    __syncthreads();
+    const int nslots = min(t.cpf, t.nslot - t.slot0);
+    if (threadIdx.x < nslots) {
+        const int sl = threadIdx.x;
+        const int b = RAGGED ? hd.perm[t.slot0 + sl] : t.slot0 + sl;
+        float M = INFINITY;
+        if (ctl.ebound[b] >= 0.0 && (!RERUN || ctl.need_rerun[b])) {
+            float wm = 0.0f, wu = 0.0f;
+            for (int c = sl; c < TC; c += t.cpf) {
+                wm = fmaxf(wm, bitsf(L.cm[c]));
+                wu = fmaxf(wu, bitsf(L.cu[c]));
+            }
+            const float cur = load_gmax(&ctl.gmax[b]);
+            M = cur;
+            if (!RERUN) {
+                if (wm > cur) M = fmaxf(bitsf(atomicMax(&ctl.gmax[b], fbits(wm))), wm);
+                // this time centre's largest upper bound: the rerun pass skips
+                // time centres that cannot hold a candidate
+                atomicMax(&hd.tmax[(size_t)b * hd.n_tc + t.tc], fbits(wu));
+            }
+        }
+        L.M[sl] = M;
+    }
+    __syncthreads();
+    // emission: every atom whose upper bound reaches the running maximum lower bound
+#pragma unroll
+    for (int cb = 0; cb < WCB; ++cb) {
+        const H16Col col = h16_col<RERUN, DUMP, RAGGED>(g, hd, ctl, t, cb * 32 + (lane & 31));
+        if (!col.ok) continue;
+        const int b = col.b;
+        const float T = L.M[(cb * 32 + (lane & 31)) % t.cpf];
+        if (T == INFINITY) continue;
+#pragma unroll
+        for (int rb = 0; rb < H_WRB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int cl = t.row0 + w * 32 * H_WRB + rb * 32 + h_row(v, lane);
+                const float up = fabsf(acc[rb][cb][v]) + emax[cb];
+                if (cl < hd.n_cl && up >= T) {
                     const int j = atomicAdd(&ctl.cand_count[b], 1);
                     if (j < ctl.cap) {
                         ctl.cand_idx[(size_t)b * ctl.cap + j] =
-                            (unsigned)(((long long)t.tc * n_fc + col_fc[cb]) * hd.n_cl + cl);
-                        ctl.cand_score[(size_t)b * ctl.cap + j] = tot[rb][cb][v];
+                            (unsigned)(((long long)t.tc * n_fc + col.fc) * hd.n_cl + cl);
+                        ctl.cand_score[(size_t)b * ctl.cap + j] = up;
                     }
                 }
             }
@@ -277,16 +379,16 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const float* __rest
     __syncthreads();  // L.M / L.cm are rewritten by the next tile
 }
 
-// Plain plans: tiles (tc, row block, f_c group, channel group), channel group
-// fastest so that concurrently running tiles share the A window of one time
-// centre; tile ids are dealt to the 8 XCDs in contiguous ranges (workgroup x
-// runs on XCD x % 8) so that those tiles also share one L2.
-template <int WGC, bool RERUN, bool DUMP>
-__global__ void __launch_bounds__(256, 2) k_search_h16(GridDev g, H16Dev hd, const float* __restrict__ shadow,
-                                                        SearchCtl ctl, int batch, int cpf, int n_rb, int n_fg,
-                                                        int n_bg) {
-    __shared__ H16Lds<WGC> L;
-    constexpr int TC = 64 * WGC, RW = (4 / WGC) * 64;
+// Plain plans: tiles (row block, tc, f_c group, channel group), channel group
+// fastest, so that concurrently running tiles read the A rows of one row block
+// over overlapping windows (adjacent time centres); tile ids are dealt to the
+// 8 XCDs in contiguous ranges (workgroup x runs on XCD x % 8, the grid is a
+// multiple of 8) so those tiles share an L2.
+template <int WCB, bool RERUN, bool DUMP>
+__global__ void __launch_bounds__(256, 2) k_search_h16(GridDev g, H16Dev hd, SearchCtl ctl, int batch, int cpf,
+                                                        int n_rb, int n_fg, int n_bg) {
+    __shared__ H16Lds<WCB> L;
+    constexpr int TC = 32 * WCB;
     const long long tiles = (long long)g.cnt[0] * n_rb * n_fg * n_bg;
     const long long chunk = (tiles + 7) / 8;
     for (long long x = blockIdx.x; x < 8 * chunk; x += gridDim.x) {
@@ -297,36 +399,39 @@ __global__ void __launch_bounds__(256, 2) k_search_h16(GridDev g, H16Dev hd, con
         long long r = tid / n_bg;
         const int fg = (int)(r % n_fg);
         r /= n_fg;
-        const int rb = (int)(r % n_rb);
-        t.tc = (int)(r / n_rb);
+        t.tc = (int)(r % g.cnt[0]);
+        const int rb = (int)(r / g.cnt[0]);
         t.m = hd.tc_shift[t.tc];
-        t.row0 = rb * RW;
+        t.row0 = rb * H_RW;
         t.cpf = cpf;
         t.fc0 = fg * (TC / cpf);
-        t.b0 = bg * cpf;
-        t.nb = min(cpf, batch - t.b0);
-        t.n_ch = g.n;
+        t.slot0 = bg * cpf;
+        t.nslot = batch;
         t.n_pad_ch = g.n_pad;
-        // skip tiles none of whose channels take part
-        int live = 0;
-        if (threadIdx.x < t.nb) {
-            const int b = t.b0 + threadIdx.x;
-            live = DUMP || (ctl.ebound[b] >= 0.0 && (!RERUN || ctl.need_rerun[b]));
+        int live = 0;  // skip tiles none of whose channels take part
+        if (threadIdx.x < cpf && t.slot0 + threadIdx.x < batch) {
+            const int b = t.slot0 + threadIdx.x;
+            live = DUMP || (ctl.ebound[b] >= 0.0 &&
+                            (!RERUN || (ctl.need_rerun[b] && bitsf(hd.tmax[(size_t)b * hd.n_tc + t.tc]) >=
+                                                                  bitsf(ctl.gmax[b]))));
         }
         if (!__syncthreads_or(live)) continue;
-        h16_tile<WGC, RERUN, DUMP, false>(g, hd, shadow, ctl, t, L);
+        h16_tile<WCB, RERUN, DUMP, false>(g, hd, ctl, t, L);
     }
 }
 
-// Ragged plans: a persistent grid takes single-channel tiles (channel, tc, row
-// block, f_c group) from a queue (items[b] = first tile of channel b,
-// items[B] = total, the two pass counters after it).
+// Ragged plans: channels sorted by decreasing length form groups of 64 (the
+// columns of a tile: 2 f_c x 64 signals); a persistent grid takes (group, tc,
+// row block, f_c group) tiles from a queue.  A group's stages cover its
+// longest signal; shorter signals are zero past their end and their columns
+// are masked for time centres they do not have.
 template <bool RERUN>
-__global__ void __launch_bounds__(256, 2) k_search_h16_ragged(GridDev g, H16Dev hd, const float* __restrict__ shadow,
-                                                               SearchCtl ctl, int batch, int n_rb, int n_fg,
-                                                               int* __restrict__ items) {
-    __shared__ H16Lds<1> L;
+__global__ void __launch_bounds__(256, 2) k_search_h16_ragged(GridDev g, H16Dev hd, SearchCtl ctl, int batch,
+                                                               int n_rb, int n_fg, int* __restrict__ items) {
+    __shared__ H16Lds<4> L;
     __shared__ int s_item;
+    if (RERUN && items[batch + 3] == 0) return;  // no channel overflowed
+    const int ng = (batch + 63) / 64;
     const int total = items[batch];
     int* counter = items + batch + 1 + (RERUN ? 1 : 0);
     while (true) {
@@ -335,61 +440,116 @@ __global__ void __launch_bounds__(256, 2) k_search_h16_ragged(GridDev g, H16Dev 
         __syncthreads();
         const int it = s_item;
         if (it >= total) break;
-        int lo = 0, hi = batch - 1;  // channel: last b with items[b] <= it
+        int lo = 0, hi = ng - 1;  // group: last j with items[j] <= it
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (items[mid] <= it) lo = mid; else hi = mid - 1;
         }
-        const int b = lo;
-        if (RERUN && ctl.need_rerun[b] == 0) continue;
-        if (ctl.ebound[b] < 0.0) continue;
-        const int q = it - items[b];
+        const int grp = lo;
+        const int q = it - items[grp];
         H16Tile t;
+        t.slot0 = grp * 64;
+        int nmax = ctl.len[hd.perm[t.slot0]];  // the group's longest signal comes first
+        nmax = (nmax < 0 || nmax > g.n) ? 0 : nmax;
+        const int n_tc = nmax / g.ragged_div;  // > 0: the group has tiles
+        // row block outermost: concurrent tiles read one row block over
+        // overlapping windows (adjacent time centres)
         const int fg = q % n_fg;
-        const int rb = (q / n_fg) % n_rb;
-        t.tc = q / (n_fg * n_rb);
+        t.tc = (q / n_fg) % n_tc;
+        const int rb = q / (n_fg * n_tc);
         t.m = t.tc * g.ragged_div;
-        t.row0 = rb * 256;
-        t.cpf = 1;
-        t.fc0 = fg * 64;
-        t.b0 = b;
-        t.nb = 1;
-        t.n_ch = ctl.len[b];  // in range: a channel with tiles has 0 < len <= n_samples
-        t.n_pad_ch = (t.n_ch + H_KS - 1) / H_KS * H_KS;
-        h16_tile<1, RERUN, false, true>(g, hd, shadow, ctl, t, L);
+        t.row0 = rb * H_RW;
+        t.cpf = 64;
+        t.fc0 = fg * 2;
+        t.nslot = batch;
+        t.n_pad_ch = (nmax + H_KS - 1) / H_KS * H_KS;
+        int live = 0;
+        if (threadIdx.x < 64 && t.slot0 + threadIdx.x < batch) {
+            const int b = hd.perm[t.slot0 + threadIdx.x];
+            const int n = ctl.len[b];
+            live = n >= 0 && n <= g.n && t.tc < n / g.ragged_div && ctl.ebound[b] >= 0.0 &&
+                   (!RERUN || (ctl.need_rerun[b] &&
+                               bitsf(hd.tmax[(size_t)b * hd.n_tc + t.tc]) >= bitsf(ctl.gmax[b])));
+        }
+        if (!__syncthreads_or(live)) continue;
+        h16_tile<4, RERUN, false, true>(g, hd, ctl, t, L);
     }
 }
 
-int h16_chain_length(int n_pad) { return 2 * H_KS + n_pad / H_KS + 2; }
+// Ragged preparation, once per call: channels ranked by decreasing length
+// (ties by index; out-of-range lengths count as 0), then the tile prefix of
+// the groups of 64 (one thread) and the queue counters.
+__global__ void __launch_bounds__(1024) k_h16_ragged_prep(const int* __restrict__ len, int batch, int n_max,
+                                                          int div, int n_rb, int n_fg, int* __restrict__ perm,
+                                                          int* __restrict__ items) {
+    for (int b = threadIdx.x; b < batch; b += blockDim.x) {
+        int nb = len[b];
+        nb = (nb < 0 || nb > n_max) ? 0 : nb;
+        int rank = 0;
+        for (int j = 0; j < batch; ++j) {
+            int nj = len[j];
+            nj = (nj < 0 || nj > n_max) ? 0 : nj;
+            rank += (nj > nb || (nj == nb && j < b)) ? 1 : 0;
+        }
+        perm[rank] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int ng = (batch + 63) / 64;
+        int acc = 0;
+        for (int j = 0; j < ng; ++j) {
+            items[j] = acc;
+            int n = len[perm[j * 64]];
+            n = (n < 0 || n > n_max) ? 0 : n;
+            acc += (n / div) * n_rb * n_fg;
+        }
+        for (int j = ng; j <= batch; ++j) items[j] = acc;
+        items[batch + 1] = 0;
+        items[batch + 2] = 0;
+        items[batch + 3] = 0;
+    }
+}
+
+// FP32 accumulation chain of one score: one rounding per product (2 per
+// sample) plus the final scaling.
+int h16_chain_length(int n_pad) { return 2 * n_pad + 2; }
 
 static H16Dev h16_dev(act_plan_s* p) {
-    return H16Dev{(const _Float16*)p->fac_u16, (const _Float16*)p->fac_v16, (const float*)p->fac_c,
-                  (const float*)p->fac_s, p->inv_norm32, p->tc_shift, p->lag_energy, p->rscale,
-                  p->fac_w, p->n_cl};
+    return H16Dev{(const _Float16*)p->fac_u16, (const _Float16*)p->fac_v16, (const _Float16*)p->fac_c16,
+                  (const _Float16*)p->fac_s16, p->inv_norm32, p->tc_shift, p->lag_energy, p->env_q,
+                  (const _Float16*)p->shadow, p->rscale, p->ebmul, p->perm, p->tmax, p->fac_w, p->n_cl,
+                  p->grid.cnt[3], p->grid.cnt[0]};
+}
+
+act_status launch_h16_ragged_prep(act_plan_s* p, int batch, hipStream_t s) {
+    const int n_rb = (p->n_cl + H_RW - 1) / H_RW, n_fg = (p->grid.cnt[1] + 1) / 2;
+    hipLaunchKernelGGL(k_h16_ragged_prep, dim3(1), dim3(1024), 0, s, p->call_len, batch, p->grid.n,
+                       p->desc.ragged_tc_div, n_rb, n_fg, p->perm, p->items);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
 }
 
 act_status launch_search_h16(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s) {
     const H16Dev hd = h16_dev(p);
-    const float* sh = (const float*)p->shadow;
     const int n_fc = p->grid.cnt[1];
+    const int n_rb = (p->n_cl + H_RW - 1) / H_RW;
     if (p->desc.ragged) {
-        const int n_rb = (p->n_cl + 255) / 256, n_fg = (n_fc + 63) / 64;
+        const int n_fg = (n_fc + 1) / 2;
         const unsigned blocks = (unsigned)device_cus() * 2;
         if (ctl.pass)
-            hipLaunchKernelGGL((k_search_h16_ragged<true>), dim3(blocks), dim3(256), 0, s, p->grid, hd, sh, ctl,
-                               batch, n_rb, n_fg, p->items);
+            hipLaunchKernelGGL((k_search_h16_ragged<true>), dim3(blocks), dim3(256), 0, s, p->grid, hd, ctl, batch,
+                               n_rb, n_fg, p->items);
         else
-            hipLaunchKernelGGL((k_search_h16_ragged<false>), dim3(blocks), dim3(256), 0, s, p->grid, hd, sh, ctl,
-                               batch, n_rb, n_fg, p->items);
+            hipLaunchKernelGGL((k_search_h16_ragged<false>), dim3(blocks), dim3(256), 0, s, p->grid, hd, ctl, batch,
+                               n_rb, n_fg, p->items);
         ACT_HIP(hipGetLastError());
         return ACT_OK;
     }
-    // one channel: 256 rows x 64 f_c tiles; several: 128 rows x (cpf channels x 128/cpf f_c)
+    // one channel: 64 f_c columns; several: cpf channels x 128/cpf f_c
     const bool multi = batch > 1;
     int cpf = 1;
     while (multi && cpf < batch && cpf < 64) cpf *= 2;
-    const int TC = multi ? 128 : 64, RW = multi ? 128 : 256;
-    const int n_rb = (p->n_cl + RW - 1) / RW;
+    const int TC = multi ? 128 : 64;
     const int n_fg = (n_fc + TC / cpf - 1) / (TC / cpf);
     const int n_bg = (batch + cpf - 1) / cpf;
     const long long tiles = (long long)p->grid.cnt[0] * n_rb * n_fg * n_bg;
@@ -397,38 +557,74 @@ act_status launch_search_h16(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     const long long cap = (long long)device_cus() * 2;
     blocks = blocks < cap ? blocks : cap;
     const dim3 grid((unsigned)blocks), blk(256);
-#define H16_LAUNCH(WGC, RR, DD)                                                                        \
-    hipLaunchKernelGGL((k_search_h16<WGC, RR, DD>), grid, blk, 0, s, p->grid, hd, sh, ctl, batch, cpf, n_rb, \
+#define H16_LAUNCH(WCB, RR, DD)                                                                      \
+    hipLaunchKernelGGL((k_search_h16<WCB, RR, DD>), grid, blk, 0, s, p->grid, hd, ctl, batch, cpf, n_rb, \
                        n_fg, n_bg)
     if (multi) {
+        if (ctl.dump) H16_LAUNCH(4, false, true);
+        else if (ctl.pass) H16_LAUNCH(4, true, false);
+        else H16_LAUNCH(4, false, false);
+    } else {
         if (ctl.dump) H16_LAUNCH(2, false, true);
         else if (ctl.pass) H16_LAUNCH(2, true, false);
         else H16_LAUNCH(2, false, false);
-    } else {
-        if (ctl.dump) H16_LAUNCH(1, false, true);
-        else if (ctl.pass) H16_LAUNCH(1, true, false);
-        else H16_LAUNCH(1, false, false);
     }
 #undef H16_LAUNCH
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }
 
-// FP16 copies of the FP32 envelope-chirp factors (RNE).
-__global__ void k_factors_to_f16(const float* __restrict__ U, const float* __restrict__ V, long long count,
-                                 _Float16* __restrict__ U16, _Float16* __restrict__ V16) {
+// FP16 copies (RNE) of the FP32 factor tables, and the FP64 prefix sums of the
+// squared Gaussian envelope over lags (one block per log-duration).
+__global__ void k_factors_to_f16(const float* __restrict__ src, long long count, _Float16* __restrict__ dst) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (long long)gridDim.x * blockDim.x) {
-        U16[i] = (_Float16)U[i];
-        V16[i] = (_Float16)V[i];
+         i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (_Float16)src[i];
+}
+
+__global__ void __launch_bounds__(256) k_env_prefix(GridDev g, int W, double* __restrict__ q) {
+    __shared__ double tot[256];
+    const int il = blockIdx.x;
+    const double inv_dt = 1.0 / exp(g.axis[g.off[3] + il]);
+    double* qr = q + (size_t)il * W;
+    const int per = (W + 255) / 256;
+    const int e0 = threadIdx.x * per, e1 = min(W, e0 + per);
+    double acc = 0.0;
+    for (int e = e0; e < e1; ++e) {
+        const double u = (double)(e - g.n_pad) / g.fs * inv_dt;
+        acc += exp(-u * u);  // E(d)^2
+        qr[e] = acc;
     }
+    tot[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double run = 0.0;
+        for (int t = 0; t < 256; ++t) {
+            const double x = tot[t];
+            tot[t] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    const double base = tot[threadIdx.x];
+    for (int e = e0; e < e1; ++e) qr[e] += base;
 }
 
 act_status build_h16_factors(act_plan_s* p, hipStream_t s) {
-    const long long count = (long long)p->n_cl * p->fac_w;
-    const long long blocks = std::min<long long>((count + 255) / 256, (long long)device_cus() * 64);
-    hipLaunchKernelGGL(k_factors_to_f16, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)p->fac_u,
-                       (const float*)p->fac_v, count, (_Float16*)p->fac_u16, (_Float16*)p->fac_v16);
+    const long long cl_count = (long long)p->n_cl * p->fac_w;
+    const long long fc_count = (long long)p->grid.cnt[1] * p->fac_w;
+    const long long cap = (long long)device_cus() * 64;
+    const unsigned b1 = (unsigned)std::min<long long>((cl_count + 255) / 256, cap);
+    const unsigned b2 = (unsigned)std::min<long long>((fc_count + 255) / 256, cap);
+    hipLaunchKernelGGL(k_factors_to_f16, dim3(b1), dim3(256), 0, s, (const float*)p->fac_u, cl_count,
+                       (_Float16*)p->fac_u16);
+    hipLaunchKernelGGL(k_factors_to_f16, dim3(b1), dim3(256), 0, s, (const float*)p->fac_v, cl_count,
+                       (_Float16*)p->fac_v16);
+    hipLaunchKernelGGL(k_factors_to_f16, dim3(b2), dim3(256), 0, s, (const float*)p->fac_c, fc_count,
+                       (_Float16*)p->fac_c16);
+    hipLaunchKernelGGL(k_factors_to_f16, dim3(b2), dim3(256), 0, s, (const float*)p->fac_s, fc_count,
+                       (_Float16*)p->fac_s16);
+    hipLaunchKernelGGL(k_env_prefix, dim3(p->grid.cnt[3]), dim3(256), 0, s, p->grid, p->fac_w, p->env_q);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

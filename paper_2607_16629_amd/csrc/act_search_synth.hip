@@ -230,6 +230,7 @@ __global__ void __launch_bounds__(256) k_search_synth_f32_ragged(GridDev g, Synt
     __shared__ float s_red[4];
     __shared__ float s_M;
     __shared__ long long s_item;
+    if (RERUN && items[batch + 3] == 0) return;  // no channel overflowed
     const long long total = items[batch];
     int* counter = items + batch + 1 + (RERUN ? 1 : 0);
     while (true) {
@@ -272,6 +273,7 @@ __global__ void k_ragged_items(const int* __restrict__ len, int batch, int n_max
     items[batch] = acc;
     items[batch + 1] = 0;
     items[batch + 2] = 0;
+    items[batch + 3] = 0;
 }
 
 // FP32 accumulation chain of one synthesised score: 2 roundings per MFMA over a
@@ -314,11 +316,9 @@ act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ct
 
 act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s) {
     if (!(p->desc.ragged && p->items)) return ACT_OK;
-    // tiles per time centre: cl blocks x f_c chunks of the search kernel in use
-    const bool h16 = p->desc.prec == ACT_PREC_F16;
-    const int rows = h16 ? 256 : SY_ROWS, cols = h16 ? 64 : SY_COLS;
-    const int n_clb = (p->n_cl + rows - 1) / rows;
-    const int n_fcc = (p->grid.cnt[1] + cols - 1) / cols;
+    if (p->desc.prec == ACT_PREC_F16) return launch_h16_ragged_prep(p, batch, s);
+    const int n_clb = (p->n_cl + SY_ROWS - 1) / SY_ROWS;
+    const int n_fcc = (p->grid.cnt[1] + SY_COLS - 1) / SY_COLS;
     hipLaunchKernelGGL(k_ragged_items, dim3(1), dim3(64), 0, s, p->call_len, batch, p->grid.n,
                        p->desc.ragged_tc_div, n_clb, n_fcc, p->items);
     ACT_HIP(hipGetLastError());
