@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
+    ap.add_argument("--companions", default="fp32-1x2048-synth,bf16-64x2048,f16-64x2048-synth,ragged-1000-f16",
+                    help="comma-separated companion workloads of the default run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -316,12 +318,13 @@ def main():
     line.update(res)
     if args.workload == "fp32-1x2048" and not args.no_companions:
         comp = {}
-        for name in ("fp32-1x2048-synth", "bf16-64x2048", "f16-64x2048-synth"):
-            c, _ = run_workload(name, args.steps, args.warmup)
-            comp[name] = c
-        # the uneven batch (15 orders of 1000 signals, ~3.3e13 MACs per order)
-        # takes seconds per step: one timed step after one warm-up
-        comp["ragged-1000-f16"] = run_ragged(1, 1, "f16")
+        for name in [c for c in args.companions.split(",") if c]:
+            if name.startswith("ragged-1000"):
+                # the uneven batch (15 orders of 1000 signals, ~3.3e13 MACs per
+                # order) takes seconds per step: one timed step after one warm-up
+                comp[name] = run_ragged(1, 1, name.rsplit("-", 1)[1])
+            else:
+                comp[name], _ = run_workload(name, args.steps, args.warmup)
         line["companions"] = comp
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
