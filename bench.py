@@ -42,6 +42,8 @@ WORKLOADS = {
     "fp32-1x2048-synth": ("fp32_1x2048", dict(dict_="synth", prec="f32"), "mfma_f32", 0),
     "bf16-64x2048": ("batched_64x2048", dict(dict_="table", prec="bf16"), "hbm", 2),
     "f16-64x2048-synth": ("batched_64x2048", dict(dict_="synth", prec="f16"), "mfma_f16", 0),
+    # support-truncated: GMAC/s still counts the dense work (dense-equivalent rate)
+    "f16-64x2048-synth-cut": ("batched_64x2048", dict(dict_="synth", prec="f16", support_cut=True), "mfma_f16", 0),
     "plain-1x512": ("plain_1x512", dict(dict_="synth", prec="f64"), "f64", 0),
 }
 KERNELS = {("table", "f32"): ("k_search_f32_table", "act_search_f32t.hip"),
@@ -130,7 +132,7 @@ def run_workload(name: str, steps: int, warmup: int):
     s_ms, s_n = phases["search"]
     search_ms = s_ms / max(s_n, 1)
     res = {
-        "workload": wl.name, "value": round(g.size * g.n * order * B * steps / wall / 1e9, 3),
+        "workload": name, "value": round(g.size * g.n * order * B * steps / wall / 1e9, 3),
         "unit": "GMAC/s", "ms_per_step": round(wall * 1e3 / steps, 4),
         "mp_iters_per_s": round(order * steps / wall, 3),
         "channel_iters_per_s": round(order * B * steps / wall, 3),
@@ -138,7 +140,7 @@ def run_workload(name: str, steps: int, warmup: int):
         "dtype": plan_kw["prec"],
         "config": {"workload": wl.name, "atoms": g.size, "n_samples": g.n, "channels": B,
                    "order": order, "dict": plan_kw["dict_"], "refine_steps": wl.refine_steps,
-                   "parallelism": "single-gpu"},
+                   "support_cut": bool(plan_kw.get("support_cut", False)), "parallelism": "single-gpu"},
         "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
         "candidate_overflow_channels": int(((flags & act.FLAG_CAND_OVERFLOW) != 0).sum()),
     }
@@ -178,7 +180,7 @@ def run_workload(name: str, steps: int, warmup: int):
     return res, wl
 
 
-def run_ragged(steps: int, warmup: int, prec: str = "f16"):
+def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False):
     """Uneven batch: 1000 signals of log-uniform length 256..16384 in one
     act_decompose call, each with its own grid (floor(N/32) time centres,
     64 f_c x 32 c x 16 dt), 15 orders, synthesised search + FP64 rescoring."""
@@ -191,7 +193,7 @@ def run_ragged(steps: int, warmup: int, prec: str = "f16"):
     B, order = len(lens), wl.order
     per_tc = 64 * 32 * 16
     plan = act.Plan(W.ragged_grid(int(lens.max()), 32, 64, 32, 16), dict_="synth", prec=prec, max_batch=B,
-                    refine_steps=wl.refine_steps, ragged=True, ragged_tc_div=32)
+                    refine_steps=wl.refine_steps, ragged=True, ragged_tc_div=32, support_cut=cut)
     sig = torch.from_numpy(wl.signals).cuda()
     resid = torch.empty_like(sig)
     lt = torch.from_numpy(lens.astype(np.int32)).cuda()
@@ -224,14 +226,15 @@ def run_ragged(steps: int, warmup: int, prec: str = "f16"):
     achieved = algo / (search_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec + "_mfma"]
     kname, _ = KERNELS[("synth", prec)]
-    return {"workload": wl.name + "-" + prec, "value": round(macs * order * steps / wall / 1e9, 3),
+    return {"workload": wl.name + "-" + prec + ("-cut" if cut else ""),
+            "value": round(macs * order * steps / wall / 1e9, 3),
             "unit": "GMAC/s", "ms_per_step": round(wall * 1e3 / steps, 3),
             "mp_iters_per_s": round(order * steps / wall, 3),
             "channel_iters_per_s": round(order * B * steps / wall, 3),
             "search_only_gmac_per_s": round(macs / (search_ms * 1e-3) / 1e9, 3),
             "dtype": prec,
             "config": {"workload": wl.name, "signals": B, "n_min": int(lens.min()), "n_max": int(lens.max()),
-                       "dense_macs_per_order": macs, "order": order, "dict": "synth",
+                       "dense_macs_per_order": macs, "order": order, "dict": "synth", "support_cut": cut,
                        "refine_steps": wl.refine_steps, "parallelism": "single-gpu"},
             "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
             "candidate_overflow_channels": int(((flags & act.FLAG_CAND_OVERFLOW) != 0).sum()),
@@ -270,11 +273,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp32-1x2048",
-                    choices=sorted(WORKLOADS) + ["refine-4096", "ragged-1000-f16", "ragged-1000-f32"])
+                    choices=sorted(WORKLOADS) + ["refine-4096", "ragged-1000-f16", "ragged-1000-f32",
+                                                 "ragged-1000-f16-cut"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
-    ap.add_argument("--companions", default="fp32-1x2048-synth,bf16-64x2048,f16-64x2048-synth,ragged-1000-f16",
+    ap.add_argument("--companions", default="fp32-1x2048-synth,bf16-64x2048,f16-64x2048-synth,"
+                                            "f16-64x2048-synth-cut,ragged-1000-f16,ragged-1000-f16-cut",
                     help="comma-separated companion workloads of the default run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -301,7 +306,8 @@ def main():
         return
 
     if args.workload.startswith("ragged-1000"):
-        res = run_ragged(args.steps, args.warmup, args.workload.rsplit("-", 1)[1])
+        parts = args.workload.split("-")
+        res = run_ragged(args.steps, args.warmup, parts[2], parts[-1] == "cut")
         line = {"metric": METRIC, "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
                 "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -322,7 +328,8 @@ def main():
             if name.startswith("ragged-1000"):
                 # the uneven batch (15 orders of 1000 signals, ~3.3e13 MACs per
                 # order) takes seconds per step: one timed step after one warm-up
-                comp[name] = run_ragged(1, 1, name.rsplit("-", 1)[1])
+                parts = name.split("-")
+                comp[name] = run_ragged(1, 1, parts[2], parts[-1] == "cut")
             else:
                 comp[name], _ = run_workload(name, args.steps, args.warmup)
         line["companions"] = comp

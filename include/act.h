@@ -102,7 +102,12 @@ typedef struct {
     int32_t ragged;         /* 1: channels have their own lengths (len_dev/off_dev) and
                                grids with floor(len/ragged_tc_div) time centres */
     int32_t ragged_tc_div;  /* samples per time centre of a ragged plan (e.g. 32) */
-    int32_t reserved;
+    int32_t support_cut;    /* ACT_PREC_F16 synthesis only. 0: dense correlation over every
+                               sample. 1: each block of atoms skips the samples where the
+                               Gaussian envelope of all its log-durations has tail energy
+                               below 2^-48 (relative bound 2^-24 on the score, added to the
+                               certified margin; the FP64 rescoring is unchanged, so the
+                               selected atoms are the same) */
 } act_plan_desc;
 
 typedef struct act_plan_s* act_plan_t;

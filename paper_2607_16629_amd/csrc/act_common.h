@@ -210,6 +210,9 @@ struct act_plan_s {
     double* ebmul = nullptr;  // ACT_PREC_F16: [B] per-atom bound factor (times |E_w| / |g_w|)
     int* perm = nullptr;      // ACT_PREC_F16 ragged: [B] channels by decreasing length
     unsigned* tmax = nullptr; // ACT_PREC_F16: [B][n_tc] largest pass-0 upper bound per time centre
+    int* ld_half = nullptr;   // ACT_PREC_F16: [n_ld] half-support in samples of each log-duration
+    float* inv_full32 = nullptr;  // ACT_PREC_F16 ragged: [n_fc][n_cl] 1/|g| over all lags
+    double trunc_tail = 0.0;  // largest sqrt(envelope tail energy) outside the supports
     double rho_max = 0.0;     // max over atoms of |envelope|_2 / |g|_2
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
 
@@ -265,6 +268,7 @@ act_status write_bf16_table(act_plan_s* p, hipStream_t s);
 act_status build_synth(act_plan_s* p, hipStream_t s);
 act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s);
 act_status build_h16_factors(act_plan_s* p, hipStream_t s);
+act_status build_supports(act_plan_s* p, hipStream_t s);
 act_status launch_h16_ragged_prep(act_plan_s* p, int batch, hipStream_t s);
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,

@@ -219,6 +219,16 @@ __global__ void __launch_bounds__(256) k_lag_energy(GridDev g, int n_cl, int W, 
     }
 }
 
+// 1/|g| over every lag of the table, per (f_c, cl) row: the norm of an atom
+// whose support lies inside its signal.
+__global__ void k_inv_full(const double* __restrict__ q, long long rows, int W, float* __restrict__ inv) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < rows) {
+        const double e2 = q[(size_t)r * W + (W - 1)];
+        inv[r] = e2 > 0.0 ? (float)(1.0 / sqrt(e2)) : 0.0f;
+    }
+}
+
 act_status build_synth(act_plan_s* p, hipStream_t s) {
     unsigned long long* rb = nullptr;
     ACT_HIP(hipMalloc((void**)&rb, sizeof(unsigned long long)));
@@ -235,6 +245,9 @@ act_status build_synth(act_plan_s* p, hipStream_t s) {
         const long long rows = (long long)p->grid.cnt[1] * p->n_cl;
         hipLaunchKernelGGL(k_lag_energy, dim3((unsigned)std::min<long long>(rows, cus * 16LL)), dim3(256), 0, s,
                            p->grid, p->n_cl, p->fac_w, p->desc.ragged_tc_div, p->lag_energy, rb);
+        if (p->inv_full32)
+            hipLaunchKernelGGL(k_inv_full, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, p->lag_energy, rows,
+                               p->fac_w, p->inv_full32);
     } else {
         hipLaunchKernelGGL(k_norms_rho, dim3((unsigned)std::min<long long>((p->atoms + 3) / 4, cus * 32LL)),
                            dim3(256), 0, s, p->grid, p->inv_norm, p->inv_norm32, rb);
@@ -247,6 +260,47 @@ act_status build_synth(act_plan_s* p, hipStream_t s) {
     double v;
     memcpy(&v, &bits, sizeof v);
     p->rho_max = v;
+    return ACT_OK;
+}
+
+// Half-supports of the FP16 search's envelopes: for each log-duration the
+// smallest D (in samples) whose envelope tail energy over lags |d| > D (inside
+// the table's lag range) is at most 2^-48, from the FP64 prefix sums.  They
+// mark the atoms whose support lies inside their signal (full-window norm),
+// and with support_cut the samples each block of atoms may skip (the tail then
+// enters the certified bound).
+act_status build_supports(act_plan_s* p, hipStream_t s) {
+    const int n_ld = p->grid.cnt[3], W = p->fac_w, np = p->n_pad;
+    std::vector<int> half(n_ld, np);
+    double tail_max = 0.0;
+    {
+        std::vector<double> q((size_t)n_ld * W);
+        ACT_HIP(hipMemcpyAsync(q.data(), p->env_q, q.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        ACT_HIP(hipStreamSynchronize(s));
+        const double lim = 3.552713678800501e-15;  // 2^-48
+        for (int il = 0; il < n_ld; ++il) {
+            const double* qr = q.data() + (size_t)il * W;
+            const double total = qr[W - 1];
+            int D = np;
+            double t_at = 0.0;
+            for (int d = 0; d < np; ++d) {
+                // lags <= -(d+1): columns [0, np-d-1); lags >= d+1: columns [np+d+1, W)
+                const double left = np - d - 1 >= 0 ? qr[np - d - 1] : 0.0;
+                const double right = total - qr[np + d];
+                const double tail = left + right;
+                if (tail <= lim) {
+                    D = d;
+                    t_at = tail > 0.0 ? tail : 0.0;
+                    break;
+                }
+            }
+            half[il] = D;
+            tail_max = std::max(tail_max, std::sqrt(t_at) * (1.0 + 1e-9));
+        }
+    }
+    ACT_HIP(hipMemcpyAsync(p->ld_half, half.data(), half.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    ACT_HIP(hipStreamSynchronize(s));
+    p->trunc_tail = p->desc.support_cut ? tail_max : 0.0;
     return ACT_OK;
 }
 
@@ -293,7 +347,7 @@ static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
-                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -330,6 +384,11 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
                 "act_plan: unknown prec");
     ACT_REQUIRE(!(desc->prec == ACT_PREC_F16 && desc->dict == ACT_DICT_TABLE),
                 "act_plan: ACT_PREC_F16 is the synthesised factor-table search; use ACT_DICT_SYNTH");
+    ACT_REQUIRE(desc->support_cut == 0 || desc->support_cut == 1, "act_plan: support_cut must be 0 or 1");
+    if (desc->support_cut && !(desc->prec == ACT_PREC_F16 && desc->dict == ACT_DICT_SYNTH)) {
+        set_error("act_plan: support_cut applies to the FP16 synthesised search only");
+        return ACT_ERR_UNSUPPORTED;
+    }
     ACT_REQUIRE(!(desc->prec == ACT_PREC_F64 && desc->dict == ACT_DICT_TABLE),
                 "act_plan: ACT_PREC_F64 searches synthesise atoms; use ACT_DICT_SYNTH");
     ACT_REQUIRE(desc->max_batch >= 1, "act_plan: max_batch must be >= 1");
@@ -505,6 +564,9 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMalloc((void**)&p->ebmul, B * sizeof(double)));
         if (desc->ragged) PLAN_HIP(hipMalloc((void**)&p->perm, B * sizeof(int)));
         PLAN_HIP(hipMalloc((void**)&p->tmax, B * p->grid.cnt[0] * sizeof(unsigned)));
+        PLAN_HIP(hipMalloc((void**)&p->ld_half, ax[3]->count * sizeof(int)));
+        if (desc->ragged)
+            PLAN_HIP(hipMalloc((void**)&p->inv_full32, (size_t)ax[1]->count * p->n_cl * sizeof(float)));
     }
     PLAN_HIP(hipMalloc(&p->shadow, B * p->n_pad * elt));
     PLAN_HIP(hipMemsetAsync(p->shadow, 0, B * p->n_pad * elt, s));
@@ -525,6 +587,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         bs = build_synth(p, s);
         if (bs != ACT_OK) return fail(bs);
         if (desc->prec == ACT_PREC_F16 && (bs = build_h16_factors(p, s)) != ACT_OK) return fail(bs);
+        if (desc->prec == ACT_PREC_F16 && (bs = build_supports(p, s)) != ACT_OK) return fail(bs);
     }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

@@ -31,6 +31,7 @@ struct PlanDev {
     float* rscale;           // ACT_PREC_F16: [B] power-of-two scale of the FP16 search copy
     double* ebmul;           // ACT_PREC_F16: [B] per-atom bound factor
     unsigned* tmax;          // ACT_PREC_F16: [B][n_tc] pass-0 upper bound per time centre
+    double trunc_tail;       // ACT_PREC_F16 with support_cut: skipped envelope tail (relative)
     bool per_atom;           // gmax holds the max lower bound, cand_score upper bounds
 };
 
@@ -60,6 +61,7 @@ static PlanDev view(const act_plan_s* p) {
     v.rscale = p->rscale;
     v.ebmul = p->ebmul;
     v.tmax = p->tmax;
+    v.trunc_tail = p->trunc_tail;
     v.per_atom = p->desc.prec == ACT_PREC_F16;
     return v;
 }
@@ -94,7 +96,9 @@ __device__ double score_bound(const PlanDev& P, double rn, double er, double sca
         // <= 2^-25 sqrt(2N) |r~|, with |g_w| >= 1 (the centre sample is present).
         const double sub = 2.98023223876953125e-08 * sqrt(2.0 * n);  // 2^-25 sqrt(2N)
         (void)scale;
-        return 1.01 * (er + 6.0 * u32 * rt + sub * rt);
+        // support cut: the skipped products sum to at most sqrt(tail) |r| / |g_w|
+        // (|g| <= E and Cauchy-Schwarz), and |g_w| >= 1
+        return 1.01 * (er + 6.0 * u32 * rt + sub * rt + P.trunc_tail * rt);
     }
     if (P.dict == ACT_DICT_SYNTH) {
         // factored synthesis: each product U (C r) carries <= 5 FP32 roundings

@@ -25,6 +25,8 @@
 // maximum L of the lower bounds |p~| - E over the channel never exceeds the
 // true maximum, so every atom with |p~_a| + E_a >= L is emitted (with its upper
 // bound); the FP64 rescoring then decides among them exactly.
+#include <type_traits>
+
 #include "act_emit.h"
 
 namespace act {
@@ -53,8 +55,25 @@ struct H16Dev {
     const double* ebmul;     // [B] per-atom bound factor (times rho_a)
     const int* perm;         // ragged plans: channels in order of decreasing length
     unsigned* tmax;          // [B][n_tc] largest upper bound of the pass-0 tiles (float bits)
+    const int* ld_half;      // [n_ld] half-support (samples) of each log-duration's envelope
+    const float* inv_full;   // ragged plans: [n_fc][n_cl] 1/|g| over all lags (interior atoms)
     int W, n_cl, n_ld, n_tc;
+    int cut;                 // 1: skip samples outside the supports
 };
+
+// Rows are ordered log-duration major (row = il * n_c + ic), so a block of
+// rows spans few envelope widths and can skip samples outside their support;
+// the atom index keeps cl = ic * n_ld + il.
+__device__ __forceinline__ int h_cl(int row, int n_c, int n_ld) { return (row % n_c) * n_ld + row / n_c; }
+
+// Largest half-support over the rows [r0, r1] (clipped to the dictionary); -1 if none.
+__device__ __forceinline__ int h_support(const H16Dev& hd, int n_c, int r0, int r1) {
+    r1 = min(r1, hd.n_cl - 1);
+    if (r0 > r1) return -1;
+    int D = 0;
+    for (int il = r0 / n_c; il <= r1 / n_c; ++il) D = max(D, hd.ld_half[il]);
+    return D;
+}
 
 struct H16Tile {
     int tc, m;         // time centre index and its integer sample
@@ -74,6 +93,8 @@ struct H16Lds {
     unsigned cu[32 * WCB];          // column maxima of the upper bounds (float bits)
     float M[64];                    // per-slot running maximum used for emission
     float env[64 * H_NLD];          // |E_w| of the tile: per row (plain) or per (slot, ld) (ragged)
+    int rowcl[H_RW];                // atom row cl of each tile row (-1 past the dictionary)
+    int rowld[H_RW];                // log-duration index of each tile row
 };
 
 __device__ __forceinline__ double window_sum(const double* q, int e_lo, int e_hi) {
@@ -108,20 +129,40 @@ __device__ __forceinline__ H16Col h16_col(const GridDev& g, const H16Dev& hd, co
 }
 
 template <int WCB, bool RERUN, bool DUMP, bool RAGGED>
-__device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ctl, const H16Tile& t,
+__device__ __forceinline__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ctl, const H16Tile& t,
                          H16Lds<WCB>& L) {
     constexpr int TC = 32 * WCB;   // columns per workgroup
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // wave-uniform values live in scalar registers
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n_fc = g.cnt[1];
     const int W = hd.W;
 
+    const int n_c = g.cnt[2];
+    // row -> (cl, log-duration) of the tile, read by the epilogue; the previous
+    // tile ended with a barrier and the first stage starts with one
+    {
+        const int row = t.row0 + (int)threadIdx.x;
+        L.rowcl[threadIdx.x] = row < hd.n_cl ? h_cl(row, n_c, hd.n_ld) : -1;
+        L.rowld[threadIdx.x] = row < hd.n_cl ? row / n_c : 0;
+    }
     // A rows of this lane
     int arow[H_WRB];
 #pragma unroll
     for (int rb = 0; rb < H_WRB; ++rb) {
-        const int cl = t.row0 + w * 32 * H_WRB + rb * 32 + (lane & 31);
-        arow[rb] = cl < hd.n_cl ? cl : 0;
+        const int row = t.row0 + w * 32 * H_WRB + rb * 32 + (lane & 31);
+        arow[rb] = row < hd.n_cl ? h_cl(row, n_c, hd.n_ld) : 0;
     }
+    // samples that can matter: lags within the widest half-support of the
+    // workgroup's rows (stages) and of this wave's rows (32-sample blocks)
+    const int D_full = g.n_pad;  // dense: every lag
+    int D_wg = h_support(hd, n_c, t.row0, t.row0 + H_RW - 1);
+    int D_w = h_support(hd, n_c, t.row0 + w * 32 * H_WRB, t.row0 + (w + 1) * 32 * H_WRB - 1);
+    if (!hd.cut) {
+        D_wg = D_wg < 0 ? -1 : D_full;
+        D_w = D_w < 0 ? -1 : D_full;
+    }
+    const int n_first = max(0, t.m - D_wg) / H_KS * H_KS;
+    const int n_end = D_wg < 0 ? 0 : min(t.n_pad_ch, t.m + D_wg + 1);
     f32x16 acc[H_WRB][WCB];
 #pragma unroll
     for (int rb = 0; rb < H_WRB; ++rb)
@@ -130,7 +171,7 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.0f;
 
-    for (int n0 = 0; n0 < t.n_pad_ch; n0 += H_KS) {
+    for (int n0 = n_first; n0 < n_end; n0 += H_KS) {
         __syncthreads();
         // ---- B stage: each thread forms 8-sample chunks of one column; k-slot
         // order: in each 32-sample block, half h and k-step s' of a lane hold
@@ -176,12 +217,14 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
         }
         __syncthreads();
 
-        // ---- MFMA over the stage: blocks of two k-steps, the next block's A
-        // fragments loaded while the current block runs
-        {
-            constexpr int KB = 2, NB = H_KSTEPS / KB;
-            f16x8 ua[2][H_WRB][KB], va[2][H_WRB][KB];
-            auto load_blk = [&](int blk, int buf) {
+        // ---- MFMA over the stage: four blocks of two k-steps in two register
+        // buffers, each block's A fragments loaded while the previous block
+        // runs; a wave whose rows' supports miss the stage skips it
+        if (n0 + H_KS - 1 >= t.m - D_w && n0 <= t.m + D_w) {
+            constexpr int KB = 2;
+            static_assert(H_KSTEPS == 4 * KB, "four blocks per stage");
+            f16x8 ua0[H_WRB][KB], va0[H_WRB][KB], ua1[H_WRB][KB], va1[H_WRB][KB];
+            auto load_blk = [&](f16x8 (&ua)[H_WRB][KB], f16x8 (&va)[H_WRB][KB], int blk) {
                 const int eb = n0 + 16 * KB * blk - t.m + g.n_pad + 8 * KB * (lane >> 5);
 #pragma unroll
                 for (int rb = 0; rb < H_WRB; ++rb) {
@@ -189,16 +232,12 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
                     const f16x8* vp = reinterpret_cast<const f16x8*>(hd.V + (size_t)arow[rb] * W + eb);
 #pragma unroll
                     for (int j = 0; j < KB; ++j) {
-                        ua[buf][rb][j] = up[j];
-                        va[buf][rb][j] = vp[j];
+                        ua[rb][j] = up[j];
+                        va[rb][j] = vp[j];
                     }
                 }
             };
-            load_blk(0, 0);
-#pragma unroll
-            for (int blk = 0; blk < NB; ++blk) {
-                const int cur = blk & 1;
-                if (blk + 1 < NB) load_blk(blk + 1, cur ^ 1);
+            auto run_blk = [&](const f16x8 (&ua)[H_WRB][KB], const f16x8 (&va)[H_WRB][KB], int blk) {
 #pragma unroll
                 for (int sp = 0; sp < KB; ++sp) {
                     const int s = KB * blk + sp;
@@ -208,12 +247,20 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
                         const f16x8 bS = L.bs[(s * WCB + cb) * 64 + lane];
 #pragma unroll
                         for (int rb = 0; rb < H_WRB; ++rb) {
-                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ua[cur][rb][sp], bC, acc[rb][cb], 0, 0, 0);
-                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(va[cur][rb][sp], bS, acc[rb][cb], 0, 0, 0);
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ua[rb][sp], bC, acc[rb][cb], 0, 0, 0);
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(va[rb][sp], bS, acc[rb][cb], 0, 0, 0);
                         }
                     }
                 }
-            }
+            };
+            load_blk(ua0, va0, 0);
+            load_blk(ua1, va1, 1);
+            run_blk(ua0, va0, 0);
+            load_blk(ua0, va0, 2);
+            run_blk(ua1, va1, 1);
+            load_blk(ua1, va1, 3);
+            run_blk(ua0, va0, 2);
+            run_blk(ua1, va1, 3);
         }
     }
 
@@ -238,18 +285,28 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
                 L.env[sl * H_NLD + ld] = v;
             }
         } else {
-            const int cl = t.row0 + threadIdx.x;
+            const int row = t.row0 + threadIdx.x;
             float v = 0.0f;
-            if (cl < hd.n_cl)
-                v = (float)(sqrt(window_sum(hd.env_q + (size_t)(cl % hd.n_ld) * W, e_lo, g.n - 1 - t.m + g.n_pad)) *
+            if (row < hd.n_cl)
+                v = (float)(sqrt(window_sum(hd.env_q + (size_t)(row / n_c) * W, e_lo, g.n - 1 - t.m + g.n_pad)) *
                             (1.0 + 1e-6));
             L.env[threadIdx.x] = v;
         }
     }
     __syncthreads();
     float emax[WCB];  // largest bound of this lane's atoms, per column block
-#pragma unroll
-    for (int cb = 0; cb < WCB; ++cb) {
+    // column blocks unrolled by hand (compile-time cb): a rolled loop would
+    // index the accumulators dynamically and move them to scratch memory
+    auto for_cb = [&](auto f) {
+        f(std::integral_constant<int, 0>{});
+        f(std::integral_constant<int, 1>{});
+        if constexpr (WCB > 2) {
+            f(std::integral_constant<int, 2>{});
+            f(std::integral_constant<int, 3>{});
+        }
+    };
+    for_cb([&](auto cbc) {
+        constexpr int cb = decltype(cbc)::value;
         const H16Col col = h16_col<RERUN, DUMP, RAGGED>(g, hd, ctl, t, cb * 32 + (lane & 31));
         const float rinv = col.ok ? 1.0f / hd.rscale[col.b] : 0.0f;
         // per-channel bound parts as FP32, rounded up
@@ -263,16 +320,23 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int rl = w * 32 * H_WRB + rb * 32 + h_row(v, lane);  // row in the tile
-                const int cl = t.row0 + rl;
+                const int cl = L.rowcl[rl];
                 float p = 0.0f;
-                if (col.ok && cl < hd.n_cl) {
+                if (col.ok && cl >= 0) {
                     float inv;
                     if (RAGGED) {
-                        // FP64 window of the prefix sums, then FP32 (correctly
-                        // rounded) square root and division: <= 2.5 u relative
-                        const double e2 = window_sum(hd.lag_energy + ((size_t)col.fc * hd.n_cl + cl) * W,
-                                                     e_lo, e_hi);
-                        inv = e2 > 0.0 ? 1.0f / sqrtf((float)e2) : 0.0f;
+                        const int Dr = hd.ld_half[L.rowld[rl]];
+                        if (t.m >= Dr && t.m + Dr <= col.n - 1) {
+                            // the support lies inside the signal: the window misses
+                            // at most 2^-48 of |g|^2 (>= 1), far inside the bound's slack
+                            inv = hd.inv_full[(size_t)col.fc * hd.n_cl + cl];
+                        } else {
+                            // FP64 window of the prefix sums, then FP32 (correctly
+                            // rounded) square root and division: <= 2.5 u relative
+                            const double e2 = window_sum(hd.lag_energy + ((size_t)col.fc * hd.n_cl + cl) * W,
+                                                         e_lo, e_hi);
+                            inv = e2 > 0.0 ? 1.0f / sqrtf((float)e2) : 0.0f;
+                        }
                     } else {
                         inv = hd.inv_norm[((size_t)t.tc * n_fc + col.fc) * hd.n_cl + cl];
                     }
@@ -286,9 +350,9 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
                         if (!RAGGED) {
                             envn = L.env[rl];
                         } else if (env_tab) {
-                            envn = L.env[slot_l * H_NLD + cl % hd.n_ld];
+                            envn = L.env[slot_l * H_NLD + L.rowld[rl]];
                         } else {
-                            envn = (float)(sqrt(window_sum(hd.env_q + (size_t)(cl % hd.n_ld) * W, e_lo, e_hi)) *
+                            envn = (float)(sqrt(window_sum(hd.env_q + (size_t)L.rowld[rl] * W, e_lo, e_hi)) *
                                            (1.0 + 1e-6));
                         }
                         // rho_a = |E_w| / |g_w| and E_a, rounded up (1 + 2^-20 covers
@@ -302,7 +366,7 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
                 if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
             }
         emax[cb] = em;
-    }
+    });
     if (DUMP) return;
 
     // column maxima of |p~| - E (E of the lane's atoms bounded by emax, which
@@ -312,8 +376,8 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
         L.cu[threadIdx.x] = 0u;
     }
     __syncthreads();
-#pragma unroll
-    for (int cb = 0; cb < WCB; ++cb) {
+    for_cb([&](auto cbc) {
+        constexpr int cb = decltype(cbc)::value;
         float m = 0.0f;
 #pragma unroll
         for (int rb = 0; rb < H_WRB; ++rb)
@@ -327,7 +391,7 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
             atomicMax(&L.cm[cb * 32 + lane], fbits(m));
             atomicMax(&L.cu[cb * 32 + lane], fbits(mu));
         }
-    }
+    });
     __syncthreads();
     const int nslots = min(t.cpf, t.nslot - t.slot0);
     if (threadIdx.x < nslots) {
@@ -353,20 +417,20 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
     }
     __syncthreads();
     // emission: every atom whose upper bound reaches the running maximum lower bound
-#pragma unroll
-    for (int cb = 0; cb < WCB; ++cb) {
+    for_cb([&](auto cbc) {
+        constexpr int cb = decltype(cbc)::value;
         const H16Col col = h16_col<RERUN, DUMP, RAGGED>(g, hd, ctl, t, cb * 32 + (lane & 31));
-        if (!col.ok) continue;
+        if (!col.ok) return;
         const int b = col.b;
         const float T = L.M[(cb * 32 + (lane & 31)) % t.cpf];
-        if (T == INFINITY) continue;
+        if (T == INFINITY) return;
 #pragma unroll
         for (int rb = 0; rb < H_WRB; ++rb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int cl = t.row0 + w * 32 * H_WRB + rb * 32 + h_row(v, lane);
+                const int cl = L.rowcl[w * 32 * H_WRB + rb * 32 + h_row(v, lane)];
                 const float up = fabsf(acc[rb][cb][v]) + emax[cb];
-                if (cl < hd.n_cl && up >= T) {
+                if (cl >= 0 && up >= T) {
                     const int j = atomicAdd(&ctl.cand_count[b], 1);
                     if (j < ctl.cap) {
                         ctl.cand_idx[(size_t)b * ctl.cap + j] =
@@ -375,7 +439,7 @@ __device__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ct
                     }
                 }
             }
-    }
+    });
     __syncthreads();  // L.M / L.cm are rewritten by the next tile
 }
 
@@ -438,7 +502,7 @@ __global__ void __launch_bounds__(256, 2) k_search_h16_ragged(GridDev g, H16Dev 
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar registers
         if (it >= total) break;
         int lo = 0, hi = ng - 1;  // group: last j with items[j] <= it
         while (lo < hi) {
@@ -517,8 +581,8 @@ int h16_chain_length(int n_pad) { return 2 * n_pad + 2; }
 static H16Dev h16_dev(act_plan_s* p) {
     return H16Dev{(const _Float16*)p->fac_u16, (const _Float16*)p->fac_v16, (const _Float16*)p->fac_c16,
                   (const _Float16*)p->fac_s16, p->inv_norm32, p->tc_shift, p->lag_energy, p->env_q,
-                  (const _Float16*)p->shadow, p->rscale, p->ebmul, p->perm, p->tmax, p->fac_w, p->n_cl,
-                  p->grid.cnt[3], p->grid.cnt[0]};
+                  (const _Float16*)p->shadow, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32,
+                  p->fac_w, p->n_cl, p->grid.cnt[3], p->grid.cnt[0], p->desc.support_cut};
 }
 
 act_status launch_h16_ragged_prep(act_plan_s* p, int batch, hipStream_t s) {

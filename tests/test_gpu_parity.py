@@ -35,9 +35,9 @@ def A():
     return act
 
 
-def gpu_decompose(grid, signals, order, prec, dict_, refine_steps=30, cand_cap=0):
+def gpu_decompose(grid, signals, order, prec, dict_, refine_steps=30, cand_cap=0, support_cut=False):
     plan = A().Plan(grid, dict_=dict_, prec=prec, max_batch=signals.shape[0], cand_cap=cand_cap,
-                    refine_steps=refine_steps)
+                    refine_steps=refine_steps, support_cut=support_cut)
     out = plan.decompose(torch.from_numpy(signals), order)
     torch.cuda.synchronize()
     res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
@@ -179,12 +179,13 @@ def test_correlate_many_channels_and_ragged_tail(oracle, prec, tol):
 # full decompositions
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table"),
-                                        ("f32", "synth"), ("f16", "synth")])
-def test_decompose_plain_1x512(oracle, prec, dict_):
+@pytest.mark.parametrize("prec,dict_,cut", [("f64", "synth", False), ("f32", "table", False),
+                                            ("bf16", "table", False), ("f32", "synth", False),
+                                            ("f16", "synth", False), ("f16", "synth", True)])
+def test_decompose_plain_1x512(oracle, prec, dict_, cut):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, wl.order, refine_steps=30)
-    gpu = gpu_decompose(wl.grid, wl.signals, wl.order, prec, dict_, refine_steps=30)
+    gpu = gpu_decompose(wl.grid, wl.signals, wl.order, prec, dict_, refine_steps=30, support_cut=cut)
     n = assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, 30)
     assert n == wl.order
 
@@ -238,6 +239,21 @@ def test_synth_ragged_tail_and_partial_tiles(oracle, prec, tol):
     assert_decomposition_parity(gpu, ref, g, oracle, sig, "synth-" + prec, 30)
 
 
+def test_support_cut_correlation_within_bound(oracle):
+    """Support-truncated FP16 correlation: every score within the FP16 bound
+    plus the 2^-24 truncation term; the cut plan skips work on narrow atoms
+    of a long signal and still decomposes like the oracle."""
+    g = W.eeg_grid(2048, 16, 16, 8, 8)
+    rng = np.random.default_rng(23)
+    sig = rng.standard_normal((1, g.n))
+    plan = A().Plan(g, dict_="synth", prec="f16", support_cut=True)
+    p = plan.act_correlate(sig, 0, g.size).cpu().numpy()[0]
+    ref = oracle.correlate(g, sig[0])
+    assert np.max(np.abs(p - ref)) <= 2.5e-3 * np.linalg.norm(sig[0])
+    with pytest.raises(A().ActError):
+        A().Plan(g, dict_="synth", prec="f32", support_cut=True)
+
+
 def test_synth_rejects_off_sample_time_centres():
     act = A()
     g = W.eeg_grid(300, 8, 8, 6, 4)      # t_c step 37.5 samples
@@ -252,8 +268,9 @@ def _ragged_case(count, n_min, n_max, fc_c_ld, order, seed=5):
     return wl
 
 
-@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "synth"), ("f16", "synth")])
-def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_):
+@pytest.mark.parametrize("prec,dict_,cut", [("f64", "synth", False), ("f32", "synth", False),
+                                            ("f16", "synth", False), ("f16", "synth", True)])
+def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_, cut):
     """Uneven lengths in one call: every signal has its own dictionary
     (floor(N/32) time centres); each is checked against the oracle run on that
     signal alone; lengths below 32 samples are flagged empty."""
@@ -261,7 +278,7 @@ def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_):
     lens = wl.lengths.copy()
     nmax = int(lens.max())
     plan = A().Plan(W.ragged_grid(nmax, 32, 8, 6, 4), dict_=dict_, prec=prec, max_batch=len(lens),
-                    refine_steps=200, ragged=True, ragged_tc_div=32)
+                    refine_steps=200, ragged=True, ragged_tc_div=32, support_cut=cut)
     gpu = plan.decompose_ragged(wl.signals, lens, wl.offsets, 4)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in gpu.items() if v is not None}
@@ -424,8 +441,9 @@ def test_fp32_full_size_2m_atoms(oracle, dict_):
     np.testing.assert_allclose(E[1:], E[:-1] - gpu["coef"][0] ** 2, rtol=0, atol=1e-10 * E[0])
 
 
-@pytest.mark.parametrize("prec,dict_", [("bf16", "table"), ("f16", "synth")])
-def test_full_size_64x2048(oracle, prec, dict_):
+@pytest.mark.parametrize("prec,dict_,cut", [("bf16", "table", False), ("f16", "synth", False),
+                                            ("f16", "synth", True)])
+def test_full_size_64x2048(oracle, prec, dict_, cut):
     """64 channels x N = 2048 on the 2,097,152-atom grid, BF16 table or FP16
     synthesis + FP64 rescoring: per order and for sampled channels, the
     winner's oracle score is not beaten by sampled atoms, the refined
@@ -434,7 +452,7 @@ def test_full_size_64x2048(oracle, prec, dict_):
     wl = W.batched_64x2048()
     g = wl.grid
     order = 2
-    gpu = gpu_decompose(g, wl.signals, order, prec, dict_, refine_steps=30)
+    gpu = gpu_decompose(g, wl.signals, order, prec, dict_, refine_steps=30, support_cut=cut)
     step, _, _ = oracle.refine_box(g)
     rng = np.random.default_rng(16)
     sample = rng.choice(g.size, 1500, replace=False)
