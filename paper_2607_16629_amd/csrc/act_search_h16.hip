@@ -171,22 +171,32 @@ __device__ __forceinline__ void h16_tile(const GridDev& g, const H16Dev& hd, con
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.0f;
 
+    // this thread's B column for the whole tile (f_c, channel, row pointers)
+    const int fm_c = threadIdx.x % TC;
+    const _Float16 *fm_r, *fm_cs, *fm_ss;
+    bool fm_ok;
+    {
+        const int fc = t.fc0 + fm_c / t.cpf, slot = t.slot0 + fm_c % t.cpf;
+        fm_ok = fc < n_fc && slot < t.nslot;
+        const int b = fm_ok ? (RAGGED ? hd.perm[slot] : slot) : 0;
+        fm_r = hd.shadow + (size_t)b * g.n_pad;
+        fm_cs = hd.C + (size_t)(fm_ok ? fc : 0) * W + (g.n_pad - t.m);
+        fm_ss = hd.S + (size_t)(fm_ok ? fc : 0) * W + (g.n_pad - t.m);
+    }
     for (int n0 = n_first; n0 < n_end; n0 += H_KS) {
         __syncthreads();
-        // ---- B stage: each thread forms 8-sample chunks of one column; k-slot
+        // ---- B stage: each thread forms 8-sample chunks of its column; k-slot
         // order: in each 32-sample block, half h and k-step s' of a lane hold
         // samples 16 h + 8 s' + (0..7), so a lane's A operands of two k-steps
         // are 32 contiguous bytes (a lane pair reads 64 contiguous bytes)
         {
             constexpr int NQ = TC * H_KSTEPS * 2 / 256;  // chunks per thread
             constexpr int HALF = NQ / 2;
-            const int c = threadIdx.x % TC;
-            const int fc = t.fc0 + c / t.cpf, slot = t.slot0 + c % t.cpf;
-            const bool ok = fc < n_fc && slot < t.nslot;
-            const int b = ok ? (RAGGED ? hd.perm[slot] : slot) : 0;
-            const _Float16* rp = hd.shadow + (size_t)b * g.n_pad + n0;
-            const _Float16* cp = hd.C + (size_t)(ok ? fc : 0) * W + (n0 - t.m + g.n_pad);
-            const _Float16* sp = hd.S + (size_t)(ok ? fc : 0) * W + (n0 - t.m + g.n_pad);
+            const int c = fm_c;
+            const bool ok = fm_ok;
+            const _Float16* rp = fm_r + n0;
+            const _Float16* cp = fm_cs + n0;
+            const _Float16* sp = fm_ss + n0;
 #pragma unroll
             for (int hf = 0; hf < 2; ++hf) {
                 f16x8 r8[HALF], c8[HALF], s8[HALF];
