@@ -108,6 +108,14 @@ typedef struct {
                                below 2^-48 (relative bound 2^-24 on the score, added to the
                                certified margin; the FP64 rescoring is unchanged, so the
                                selected atoms are the same) */
+    int32_t prior_act;      /* 1: the prior ACT that Sec. III-A contrasts with (its table of
+                               algorithmic properties), for stability comparisons: atoms keep
+                               Eq. (1)'s prefactor (sqrt(pi) dt)^-1/2 instead of unit norm; the
+                               exact FP64 search, the refinement of <s, g>^2 and the coefficient
+                               <g*, s> all use the original signal s, repeated each order
+                               (r_{k+1} = r_k - c g*). ACT_DICT_SYNTH + ACT_PREC_F64, not ragged;
+                               coef_dev then multiplies these atoms (act_reconstruct uses them);
+                               gap_dev is 0 */
 } act_plan_desc;
 
 typedef struct act_plan_s* act_plan_t;

@@ -20,6 +20,10 @@ Parity status per function (the pins are in tests/test_oracle_pins.py):
   refine               pinned: off-grid recovery, scipy optimum, monotone J
   decompose            pinned: MP identities, one-iteration recovery, brute force
   reconstruct          pinned: a_P + r_P = s
+  prior ACT (contrast) pinned: continuous-time norm of Eq. (1)'s prefactor,
+                       numpy brute force of the un-normalised dictionary,
+                       central differences of its objective, the closed form
+                       of the repeated update, normalised residue above 1
 """
 from __future__ import annotations
 
@@ -96,6 +100,13 @@ def _load():
         lib.oracle_refine_many.argtypes = [pg, i32, pd, pd, i32, pd, pd, pi32]
         lib.oracle_decompose.argtypes = [pg, i32, pd, i32, i32, pd, pd, pd, pd, pi64, pd, pd, pi32]
         lib.oracle_reconstruct.argtypes = [d, i32, i32, pd, pd, pd]
+        lib.oracle_atom_prior.argtypes = [d, i32, pd, pd]
+        lib.oracle_correlate_prior.argtypes = [pg, pd, i64, i64, pd]
+        lib.oracle_objective_prior.argtypes = [d, i32, pd, pd, pd]
+        lib.oracle_objective_prior.restype = d
+        lib.oracle_refine_prior.argtypes = [d, i32, pd, pd, pd, pd, pd, i32, pd, pd]
+        lib.oracle_refine_prior.restype = ctypes.c_int
+        lib.oracle_decompose_prior.argtypes = [pg, i32, pd, i32, i32, pd, pd, pd, pd, pi64, pd, pi32]
         _lib = lib
     return _lib
 
@@ -255,4 +266,59 @@ def reconstruct(fs: float, n: int, theta, coef) -> np.ndarray:
     coef = _f64(coef).reshape(-1)
     out = np.zeros(n)
     _load().oracle_reconstruct(float(fs), int(n), theta.shape[0], _p(theta), _p(coef), _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The prior ACT (Sec. III-A, Table "Comparison of algorithmic properties"):
+# un-normalised atoms with Eq. (1)'s prefactor; search, refinement and
+# coefficient against the original signal.
+# ---------------------------------------------------------------------------
+
+def atom_prior(fs: float, n: int, theta) -> np.ndarray:
+    out = np.zeros(n)
+    _load().oracle_atom_prior(float(fs), int(n), _p(_f64(theta)), _p(out))
+    return out
+
+
+def correlate_prior(grid, s, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+    s = _f64(s)
+    K = grid_size(grid)
+    count = K - begin if count is None else count
+    out = np.zeros(count)
+    g = make_grid(grid)
+    _load().oracle_correlate_prior(ctypes.byref(g), _p(s), int(begin), int(count), _p(out))
+    return out
+
+
+def objective_prior(fs: float, theta, s):
+    """(J, dJ/dtheta) of J = <s, g(theta)>^2 with the un-normalised atom."""
+    s = _f64(s)
+    grad = np.zeros(4)
+    J = _load().oracle_objective_prior(float(fs), s.size, _p(_f64(theta)), _p(s), _p(grad))
+    return float(J), grad
+
+
+def refine_prior(grid, s, theta0, steps: int = 30):
+    step, lo, hi = refine_box(grid)
+    th = np.zeros(4)
+    J = ctypes.c_double(0.0)
+    fl = _load().oracle_refine_prior(float(grid.fs), int(grid.n), _p(_f64(s)), _p(_f64(theta0)),
+                                     _p(step), _p(lo), _p(hi), int(steps), _p(th), ctypes.byref(J))
+    return th, float(J.value), int(fl)
+
+
+def decompose_prior(grid, signals, order: int, refine_steps: int = 30):
+    """The prior ACT over `order` orders for each row of ``signals``."""
+    s = _f64(np.atleast_2d(signals))
+    B, n = s.shape
+    assert n == grid.n
+    g = make_grid(grid)
+    out = dict(resid=np.zeros((B, n)), approx=np.zeros((B, n)), theta=np.zeros((B, order, 4)),
+               coef=np.zeros((B, order)), index=np.zeros((B, order), dtype=np.int64),
+               energy=np.zeros((B, order + 1)), flags=np.zeros(B, dtype=np.int32))
+    _load().oracle_decompose_prior(ctypes.byref(g), B, _p(s), int(order), int(refine_steps),
+                                   _p(out["resid"]), _p(out["approx"]), _p(out["theta"]), _p(out["coef"]),
+                                   _p(out["index"], ctypes.c_int64), _p(out["energy"]),
+                                   _p(out["flags"], ctypes.c_int32))
     return out

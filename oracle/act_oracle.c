@@ -41,6 +41,7 @@
 #endif
 
 #define TWO_PI 6.283185307179586476925286766559
+#define ORACLE_PI 3.141592653589793238462643383280
 
 typedef struct {
     double lo, hi;
@@ -264,11 +265,15 @@ double oracle_objective(double fs, int32_t n, const double theta[4], const doubl
  * ------------------------------------------------------------------------- */
 #define LBFGS_M 8
 
+double oracle_objective_prior(double fs, int32_t n, const double theta[4], const double* s,
+                              double grad[4]);
+
+/* mode 0: J of the residue-based ACT; mode 1: the prior ACT's objective. */
 static double refine_eval(double fs, int32_t n, const double* r, const double th0[4],
-                          const double h[4], const double u[4], double gu[4]) {
+                          const double h[4], const double u[4], double gu[4], int mode) {
     double th[4], gr[4];
     for (int j = 0; j < 4; ++j) th[j] = th0[j] + h[j] * u[j];
-    double J = oracle_objective(fs, n, th, r, gr, NULL);
+    double J = mode ? oracle_objective_prior(fs, n, th, r, gr) : oracle_objective(fs, n, th, r, gr, NULL);
     for (int j = 0; j < 4; ++j) gu[j] = -h[j] * gr[j];
     return -J;
 }
@@ -308,9 +313,9 @@ void oracle_refine_scales(double fs, int32_t n, const double theta0[4], const do
     }
 }
 
-int oracle_refine(double fs, int32_t n, const double* r, const double theta0[4],
-                  const double step[4], const double lo[4], const double hi[4], int32_t steps,
-                  double theta_out[4], double* j_out) {
+static int refine_core(double fs, int32_t n, const double* r, const double theta0[4],
+                       const double step[4], const double lo[4], const double hi[4], int32_t steps,
+                       double theta_out[4], double* j_out, int mode) {
     double h[4], blo[4], bhi[4], u[4] = {0, 0, 0, 0}, g[4];
     int flags = 0;
     oracle_refine_scales(fs, n, theta0, step, lo, hi, h);
@@ -318,7 +323,7 @@ int oracle_refine(double fs, int32_t n, const double* r, const double theta0[4],
         blo[j] = h[j] == 0.0 ? 0.0 : (lo[j] - theta0[j]) / h[j];
         bhi[j] = h[j] == 0.0 ? 0.0 : (hi[j] - theta0[j]) / h[j];
     }
-    double f = refine_eval(fs, n, r, theta0, h, u, g);
+    double f = refine_eval(fs, n, r, theta0, h, u, g, mode);
     double f0 = f;
     double S[LBFGS_M][4], Y[LBFGS_M][4], RHO[LBFGS_M];
     int mem = 0, head = 0; /* head = slot of the next insertion */
@@ -372,7 +377,7 @@ int oracle_refine(double fs, int32_t n, const double* r, const double theta0[4],
                 if (v > bhi[j]) v = bhi[j];
                 un[j] = v;
             }
-            fn = refine_eval(fs, n, r, theta0, h, un, gn);
+            fn = refine_eval(fs, n, r, theta0, h, un, gn, mode);
             double dec = 0.0, dnew = 0.0;
             for (int j = 0; j < 4; ++j) {
                 dec += g[j] * (un[j] - u[j]);
@@ -420,6 +425,12 @@ int oracle_refine(double fs, int32_t n, const double* r, const double theta0[4],
         flags |= ORACLE_FLAG_REFINE_REJECTED;
     }
     return flags;
+}
+
+int oracle_refine(double fs, int32_t n, const double* r, const double theta0[4],
+                  const double step[4], const double lo[4], const double hi[4], int32_t steps,
+                  double theta_out[4], double* j_out) {
+    return refine_core(fs, n, r, theta0, step, lo, hi, steps, theta_out, j_out, 0);
 }
 
 /* Grid-hull box and spacing used by the refinement. */
@@ -489,6 +500,123 @@ void oracle_decompose(const oracle_grid* grid, int32_t batch, const double* s, i
             coef[o] = ck;
             index[o] = best;
             gap[o] = gp;
+            energy[(size_t)b * (order + 1) + k + 1] = dot(r, r, n);
+        }
+        flags[b] = fl & ~ORACLE_FLAG_LINESEARCH;
+    }
+    free(gs);
+    free(p);
+}
+
+/* ---------------------------------------------------------------------------
+ * The prior ACT that Sec. III-A contrasts with (Table "Comparison of
+ * algorithmic properties"): atoms are not normalised to unit l2 norm (the
+ * sampled real part of Eq. (1) keeps its analytic prefactor
+ * (sqrt(pi) dt)^(-1/2)); the coarse search, the refinement and the
+ * coefficient all use the original signal s rather than the residual; the
+ * process repeats for each order, r_{k+1} = r_k - c g*, a_{k+1} = a_k + c g*.
+ * ------------------------------------------------------------------------- */
+
+/* (sqrt(pi) dt)^(-1/2) * real part of Eq. (1), sampled at t_k = k/fs. */
+void oracle_atom_prior(double fs, int32_t n, const double theta[4], double* g) {
+    oracle_atom_raw(fs, n, theta, g);
+    double pref = 1.0 / sqrt(sqrt(ORACLE_PI) * exp(theta[3]));
+    for (int32_t k = 0; k < n; ++k) g[k] = pref * g[k];
+}
+
+/* p_i = <g_i, s> with the prior ACT's (un-normalised) atoms. */
+void oracle_correlate_prior(const oracle_grid* grid, const double* s, int64_t begin, int64_t count,
+                            double* p) {
+    int32_t n = grid->n;
+#pragma omp parallel
+    {
+        double* g = (double*)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < count; ++j) {
+            double th[4];
+            oracle_grid_theta(grid, begin + j, th);
+            oracle_atom_prior(grid->fs, n, th, g);
+            p[j] = dot(g, s, n);
+        }
+        free(g);
+    }
+}
+
+/* J(theta) = <s, g(theta)>^2 with the un-normalised atom, and its gradient:
+ * with w = raw atom and P^2 = 1/(sqrt(pi) dt), J = P^2 <s,w>^2 and
+ * dJ/dtheta_j = 2 P^2 <s,w> <s, d_j w>, plus -J for theta_3 = ln dt. */
+double oracle_objective_prior(double fs, int32_t n, const double theta[4], const double* s,
+                              double grad[4]) {
+    double tc = theta[0], fc = theta[1], c = theta[2];
+    double dt = exp(theta[3]);
+    double p2 = 1.0 / (sqrt(ORACLE_PI) * dt);
+    double sw = 0.0, sd[4] = {0, 0, 0, 0};
+    for (int32_t k = 0; k < n; ++k) {
+        double tau = (double)k / fs - tc;
+        double u = tau / dt;
+        double e = exp(-0.5 * u * u);
+        double ph = TWO_PI * (c * tau * tau + fc * tau);
+        double co = cos(ph), si = sin(ph);
+        double d[4];
+        d[0] = e * ((tau / (dt * dt)) * co + TWO_PI * (2.0 * c * tau + fc) * si);
+        d[1] = -TWO_PI * tau * e * si;
+        d[2] = -TWO_PI * tau * tau * e * si;
+        d[3] = (tau * tau / (dt * dt)) * e * co;
+        sw += s[k] * e * co;
+        for (int j = 0; j < 4; ++j) sd[j] += s[k] * d[j];
+    }
+    double J = p2 * sw * sw;
+    if (grad) {
+        for (int j = 0; j < 4; ++j) grad[j] = 2.0 * p2 * sw * sd[j];
+        grad[3] -= J;
+    }
+    return J;
+}
+
+int oracle_refine_prior(double fs, int32_t n, const double* s, const double theta0[4],
+                        const double step[4], const double lo[4], const double hi[4], int32_t steps,
+                        double theta_out[4], double* j_out) {
+    return refine_core(fs, n, s, theta0, step, lo, hi, steps, theta_out, j_out, 1);
+}
+
+/* The prior ACT over P orders (arguments as oracle_decompose; gap unused). */
+void oracle_decompose_prior(const oracle_grid* grid, int32_t batch, const double* s, int32_t order,
+                            int32_t refine_steps, double* resid, double* approx, double* theta,
+                            double* coef, int64_t* index, double* energy, int32_t* flags) {
+    int32_t n = grid->n;
+    int64_t K = oracle_grid_size(grid);
+    double step[4], lo[4], hi[4];
+    oracle_refine_box(grid, step, lo, hi);
+    double* p = (double*)malloc(sizeof(double) * (size_t)K);
+    double* gs = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int32_t b = 0; b < batch; ++b) {
+        const double* sb = s + (size_t)b * n;
+        double* r = resid + (size_t)b * n;
+        double* a = approx ? approx + (size_t)b * n : NULL;
+        memcpy(r, sb, sizeof(double) * (size_t)n);
+        if (a) memset(a, 0, sizeof(double) * (size_t)n);
+        int fl = 0;
+        for (int32_t k = 0; k < n; ++k)
+            if (!isfinite(r[k])) fl |= ORACLE_FLAG_NONFINITE;
+        energy[(size_t)b * (order + 1)] = dot(r, r, n);
+        for (int32_t k = 0; k < order; ++k) {
+            size_t o = (size_t)b * order + k;
+            oracle_correlate_prior(grid, sb, 0, K, p);
+            int64_t best = oracle_argmax(p, K, NULL);
+            double th0[4], th[4], J;
+            oracle_grid_theta(grid, best, th0);
+            if (refine_steps > 0)
+                fl |= oracle_refine_prior(grid->fs, n, sb, th0, step, lo, hi, refine_steps, th, &J);
+            else
+                memcpy(th, th0, sizeof th);
+            oracle_atom_prior(grid->fs, n, th, gs);
+            double ck = dot(gs, sb, n);
+            for (int32_t t = 0; t < n; ++t) r[t] = r[t] - ck * gs[t];
+            if (a)
+                for (int32_t t = 0; t < n; ++t) a[t] = a[t] + ck * gs[t];
+            memcpy(theta + 4 * o, th, sizeof th);
+            coef[o] = ck;
+            index[o] = best;
             energy[(size_t)b * (order + 1) + k + 1] = dot(r, r, n);
         }
         flags[b] = fl & ~ORACLE_FLAG_LINESEARCH;

@@ -48,7 +48,8 @@ class _PlanDesc(ctypes.Structure):
     _fields_ = [("grid", _Grid), ("dict", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("ragged", ctypes.c_int32),
-                ("ragged_tc_div", ctypes.c_int32), ("support_cut", ctypes.c_int32)]
+                ("ragged_tc_div", ctypes.c_int32), ("support_cut", ctypes.c_int32),
+                ("prior_act", ctypes.c_int32)]
 
 
 EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_decompose", "act_refine",
@@ -119,7 +120,7 @@ def _device_tensor(x, dtype) -> torch.Tensor:
 
 def make_desc(grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: int = 1,
               cand_cap: int = 0, refine_steps: int = 30, ragged: bool = False,
-              ragged_tc_div: int = 32, support_cut: bool = False) -> _PlanDesc:
+              ragged_tc_div: int = 32, support_cut: bool = False, prior_act: bool = False) -> _PlanDesc:
     g = _Grid()
     g.fs_hz = float(grid.fs)
     g.n_samples = int(grid.n)
@@ -135,6 +136,7 @@ def make_desc(grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: in
     desc.ragged = int(bool(ragged))
     desc.ragged_tc_div = int(ragged_tc_div)
     desc.support_cut = int(bool(support_cut))
+    desc.prior_act = int(bool(prior_act))
     return desc
 
 
@@ -143,7 +145,7 @@ class Plan:
 
     def __init__(self, grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: int = 1,
                  cand_cap: int = 0, refine_steps: int = 30, ragged: bool = False,
-                 ragged_tc_div: int = 32, support_cut: bool = False):
+                 ragged_tc_div: int = 32, support_cut: bool = False, prior_act: bool = False):
         lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("libact needs a ROCm GPU; none is visible")
@@ -154,8 +156,9 @@ class Plan:
         self.refine_steps = refine_steps
         self.ragged = ragged
         self.support_cut = support_cut
+        self.prior_act = prior_act
         self._desc = make_desc(grid, dict_, prec, max_batch, cand_cap, refine_steps, ragged,
-                               ragged_tc_div, support_cut)
+                               ragged_tc_div, support_cut, prior_act)
         h = ctypes.c_void_p()
         _check(lib.act_plan(ctypes.byref(self._desc), _stream(), ctypes.byref(h)))
         self._h = h

@@ -113,6 +113,17 @@ extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* 
     auto enqueue_all = [&](hipStream_t q) -> act_status {
         act_status st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, q);
         if (st != ACT_OK) return st;
+        if (p->desc.prior_act) {  // contrast mode: every order works on the original signal
+            if ((st = launch_prior_init(p, batch, resid_dev, q)) != ACT_OK) return st;
+            for (int k = 0; k < order; ++k) {
+                st = timed(p, 3, q, [&] {
+                    return launch_prior_order(p, batch, k, order, resid_dev, approx_dev, theta_dev, coef_dev,
+                                              (long long*)index_dev, energy_dev, gap_dev, flags_dev, q);
+                });
+                if (st != ACT_OK) return st;
+            }
+            return ACT_OK;
+        }
         if ((st = launch_ragged_items(p, batch, q)) != ACT_OK) return st;
         for (int k = 0; k < order; ++k) {
             st = enqueue_order(p, batch, k, order, resid_dev, approx_dev, theta_dev, coef_dev,

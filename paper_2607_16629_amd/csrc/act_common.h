@@ -212,6 +212,9 @@ struct act_plan_s {
     unsigned* tmax = nullptr; // ACT_PREC_F16: [B][n_tc] largest pass-0 upper bound per time centre
     int* ld_half = nullptr;   // ACT_PREC_F16: [n_ld] half-support in samples of each log-duration
     float* inv_full32 = nullptr;  // ACT_PREC_F16 ragged: [n_fc][n_cl] 1/|g| over all lags
+    double* prior_s = nullptr;       // prior ACT: [B][n] original signals
+    double* prior_part = nullptr;    // prior ACT: [B][search blocks] best |score| per block
+    long long* prior_pidx = nullptr; // prior ACT: [B][search blocks] its atom index
     double trunc_tail = 0.0;  // largest sqrt(envelope tail energy) outside the supports
     double rho_max = 0.0;     // max over atoms of |envelope|_2 / |g|_2
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
@@ -270,6 +273,11 @@ act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s);
 act_status build_h16_factors(act_plan_s* p, hipStream_t s);
 act_status build_supports(act_plan_s* p, hipStream_t s);
 act_status launch_h16_ragged_prep(act_plan_s* p, int batch, hipStream_t s);
+act_status launch_prior_init(act_plan_s* p, int batch, const double* resid, hipStream_t s);
+act_status launch_prior_order(act_plan_s* p, int batch, int k, int order, double* resid, double* approx,
+                              double* theta, double* coef, long long* index, double* energy, double* gap,
+                              int* flags, hipStream_t s);
+size_t prior_workspace_blocks();
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
                        int* flags, int order, hipStream_t s);

@@ -347,7 +347,7 @@ static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
-                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -385,6 +385,11 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     ACT_REQUIRE(!(desc->prec == ACT_PREC_F16 && desc->dict == ACT_DICT_TABLE),
                 "act_plan: ACT_PREC_F16 is the synthesised factor-table search; use ACT_DICT_SYNTH");
     ACT_REQUIRE(desc->support_cut == 0 || desc->support_cut == 1, "act_plan: support_cut must be 0 or 1");
+    ACT_REQUIRE(desc->prior_act == 0 || desc->prior_act == 1, "act_plan: prior_act must be 0 or 1");
+    if (desc->prior_act && !(desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_F64 && !desc->ragged)) {
+        set_error("act_plan: prior_act needs a plain ACT_DICT_SYNTH + ACT_PREC_F64 plan");
+        return ACT_ERR_UNSUPPORTED;
+    }
     if (desc->support_cut && !(desc->prec == ACT_PREC_F16 && desc->dict == ACT_DICT_SYNTH)) {
         set_error("act_plan: support_cut applies to the FP16 synthesised search only");
         return ACT_ERR_UNSUPPORTED;
@@ -567,6 +572,11 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMalloc((void**)&p->ld_half, ax[3]->count * sizeof(int)));
         if (desc->ragged)
             PLAN_HIP(hipMalloc((void**)&p->inv_full32, (size_t)ax[1]->count * p->n_cl * sizeof(float)));
+    }
+    if (desc->prior_act) {
+        PLAN_HIP(hipMalloc((void**)&p->prior_s, B * p->n * sizeof(double)));
+        PLAN_HIP(hipMalloc((void**)&p->prior_part, B * prior_workspace_blocks() * sizeof(double)));
+        PLAN_HIP(hipMalloc((void**)&p->prior_pidx, B * prior_workspace_blocks() * sizeof(long long)));
     }
     PLAN_HIP(hipMalloc(&p->shadow, B * p->n_pad * elt));
     PLAN_HIP(hipMemsetAsync(p->shadow, 0, B * p->n_pad * elt, s));

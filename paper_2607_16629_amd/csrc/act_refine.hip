@@ -408,7 +408,20 @@ struct RefineLds {
     double S[8][4], Y[8][4], RHO[8];
 };
 
-template <int TB>
+// The prior ACT's objective (contrast mode): J = <s, g>^2 with the
+// un-normalised atom P w (P^2 = 1/(sqrt(pi) dt), w the raw atom), so
+// dJ/dtheta_j = 2 P^2 <s,w> <s, d_j w>, plus -J along ln dt.
+__device__ __forceinline__ double obj_prior_from_sums(const double acc[10], double inv_dt, double grad[4]) {
+    const double p2 = inv_dt * 0.56418958354775628694807945156077;  // 1/sqrt(pi)
+    const double s = acc[0];
+    const double J = p2 * s * s;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) grad[j] = 2.0 * p2 * s * acc[2 + j];
+    grad[3] -= J;
+    return J;
+}
+
+template <int TB, bool PRIOR = false>
 __device__ __forceinline__ double refine_eval(const double* r, const GridDev& g, const double th0[4],
                                               const double h[4], const double u[4], double gu[4],
                                               double* red) {
@@ -416,13 +429,13 @@ __device__ __forceinline__ double refine_eval(const double* r, const GridDev& g,
 #pragma unroll
     for (int j = 0; j < 4; ++j) th[j] = th0[j] + h[j] * u[j];
     sums_obj<TB>(r, g.n, g.fs, th, acc, red);
-    const double J = obj_from_sums(acc, gr);
+    const double J = PRIOR ? obj_prior_from_sums(acc, 1.0 / exp(th[3]), gr) : obj_from_sums(acc, gr);
 #pragma unroll
     for (int j = 0; j < 4; ++j) gu[j] = -h[j] * gr[j];
     return -J;
 }
 
-template <int TB>
+template <int TB, bool PRIOR = false>
 __device__ int refine_block(const double* __restrict__ r, const GridDev& g, const BoxDev& box,
                             const double th0[4], int steps, double th_out[4], double* J_out,
                             double* red, RefineLds& L) {
@@ -445,7 +458,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
             bhi[j] = h[j] == 0.0 ? 0.0 : (box.hi[j] - th0[j]) / h[j];
         }
     }
-    double f = refine_eval<TB>(r, g, th0, h, u, gcur, red);
+    double f = refine_eval<TB, PRIOR>(r, g, th0, h, u, gcur, red);
     const double f0 = f;
     int nmem = 0, head = 0;
     for (int it = 0; it < steps; ++it) {
@@ -514,7 +527,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
                 v = v > bhi[j] ? bhi[j] : v;
                 un[j] = v;
             }
-            fn = refine_eval<TB>(r, g, th0, h, un, gn, red);
+            fn = refine_eval<TB, PRIOR>(r, g, th0, h, un, gn, red);
             double dec = 0.0, dnew = 0.0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -867,7 +880,7 @@ __global__ void __launch_bounds__(NT) k_reconstruct(GridDev g0, int order,
                                                     const double* __restrict__ coef,
                                                     const int* __restrict__ len,
                                                     const long long* __restrict__ off,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, int prior) {
     __shared__ double red[block_sum_lds(NT, 1)];
     const int b = blockIdx.x;
     const ChanGeom cg = chan_geom(g0, b, len, off);
@@ -885,7 +898,8 @@ __global__ void __launch_bounds__(NT) k_reconstruct(GridDev g0, int order,
             acc[0] += v * v;
         }
         block_sum<NT, 1>(acc, red);
-        const double nrm = sqrt(acc[0]);
+        // unit atoms; the prior ACT's atoms keep Eq. (1)'s prefactor instead
+        const double nrm = prior ? 1.0 / sqrt(inv_dt * 0.56418958354775628694807945156077) : sqrt(acc[0]);
         if (!(nrm >= 1e-300)) continue;
         for (int t = threadIdx.x; t < g.n; t += NT)
             o[t] = o[t] + ck * (atom_sample64(sample_time(t, g.fs), th[0], th[1], th[2], inv_dt) / nrm);
@@ -957,9 +971,191 @@ act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double*
                               const double* coef, const int* len, const long long* off, double* out,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_reconstruct, dim3(batch), dim3(NT), 0, s, p->grid, order, theta, coef, len, off,
-                       out);
+                       out, p->desc.prior_act);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }
+
+// --------------------------------------------------------------------------
+// The prior ACT (contrast mode, Sec. III-A and Table "Comparison of
+// algorithmic properties"): atoms keep Eq. (1)'s prefactor (no unit-norm
+// scaling); the search, the refinement and the coefficient all use the
+// original signal, and each order repeats them: r_{k+1} = r_k - c g*.
+// --------------------------------------------------------------------------
+constexpr int kPriorBlocks = 512;  // search blocks per channel
+
+// Exact FP64 scores |<g_i, s>| of every atom (one thread per atom, grid
+// stride), arg-max per block with the lowest index on ties.
+__global__ void __launch_bounds__(256) k_prior_search(GridDev g, const double* __restrict__ sorig,
+                                                      double* __restrict__ part_score,
+                                                      long long* __restrict__ part_idx) {
+    __shared__ double bs[4];
+    __shared__ long long bi[4];
+    const int b = blockIdx.y;
+    const double* sv = sorig + (size_t)b * g.n;
+    double best = -1.0;
+    long long bidx = -1;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < g.atoms; i += (long long)gridDim.x * 256) {
+        double th[4];
+        grid_theta(g, i, th);
+        const double inv_dt = 1.0 / exp(th[3]);
+        double acc = 0.0;
+        for (int k = 0; k < g.n; ++k) acc += atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt) * sv[k];
+        const double p = fabs(acc) * sqrt(inv_dt * 0.56418958354775628694807945156077);
+        if (p > best) {  // i grows along the thread's sequence: ties keep the lowest
+            best = p;
+            bidx = i;
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const long long oi = __shfl_xor(bidx, o, 64);
+        if (ob > best || (ob == best && oi >= 0 && (bidx < 0 || oi < bidx))) {
+            best = ob;
+            bidx = oi;
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        bs[w] = best;
+        bi[w] = bidx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 4; ++q)
+            if (bs[q] > bs[0] || (bs[q] == bs[0] && bi[q] >= 0 && (bi[0] < 0 || bi[q] < bi[0]))) {
+                bs[0] = bs[q];
+                bi[0] = bi[q];
+            }
+        part_score[(size_t)b * gridDim.x + blockIdx.x] = bs[0];
+        part_idx[(size_t)b * gridDim.x + blockIdx.x] = bi[0];
+    }
+}
+
+__global__ void k_prior_copy(const double* __restrict__ src, double* __restrict__ dst, long long count) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// Winner of the search blocks, refinement of J = <s, g>^2 on the original
+// signal, c = <g*, s>, and the update of the residual and approximation.
+__global__ void __launch_bounds__(NTR) k_prior_select_update(
+    PlanDev P, int k, int order, int steps, const double* __restrict__ sorig, int nblk,
+    const double* __restrict__ part_score, const long long* __restrict__ part_idx, double* __restrict__ resid,
+    double* __restrict__ approx, double* __restrict__ theta, double* __restrict__ coef,
+    long long* __restrict__ index, double* __restrict__ energy, double* __restrict__ gap,
+    int* __restrict__ flags) {
+    __shared__ double red[block_sum_lds(NTR, 10)];
+    __shared__ RefineLds L;
+    __shared__ double s_best[NWR];
+    __shared__ long long s_idx[NWR];
+    const int b = blockIdx.x;
+    const GridDev& G = P.g;
+    const double* sv = sorig + (size_t)b * G.n;
+    double* r = resid + (size_t)b * G.n;
+    const size_t o = (size_t)b * order + k;
+    int fl = flags[b];
+    if (fl & ACT_FLAG_NONFINITE) {
+        if (threadIdx.x == 0) {
+            const double nan = __longlong_as_double(0x7ff8000000000000LL);
+            for (int j = 0; j < 4; ++j) theta[o * 4 + j] = nan;
+            coef[o] = 0.0;
+            index[o] = -1;
+            if (gap) gap[o] = 0.0;
+            energy[(size_t)b * (order + 1) + k + 1] = energy[(size_t)b * (order + 1) + k];
+        }
+        return;
+    }
+    double best = -1.0;
+    long long bidx = -1;
+    for (int j = threadIdx.x; j < nblk; j += NTR) {
+        const double v = part_score[(size_t)b * nblk + j];
+        const long long id = part_idx[(size_t)b * nblk + j];
+        if (id >= 0 && (v > best || (v == best && id < bidx))) {
+            best = v;
+            bidx = id;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, kWave);
+        const long long oi = __shfl_xor(bidx, off, kWave);
+        if (oi >= 0 && (ob > best || (ob == best && (bidx < 0 || oi < bidx)))) {
+            best = ob;
+            bidx = oi;
+        }
+    }
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        s_best[w] = best;
+        s_idx[w] = bidx;
+    }
+    __syncthreads();
+    best = s_best[0];
+    bidx = s_idx[0];
+    for (int q = 1; q < NWR; ++q)
+        if (s_idx[q] >= 0 && (s_best[q] > best || (s_best[q] == best && (bidx < 0 || s_idx[q] < bidx)))) {
+            best = s_best[q];
+            bidx = s_idx[q];
+        }
+    __syncthreads();
+    if (bidx < 0) bidx = 0;
+
+    double th0[4], th[4], J = 0.0;
+    grid_theta(G, bidx, th0);
+    if (steps > 0) {
+        fl |= refine_block<NTR, true>(sv, G, P.box, th0, steps, th, &J, red, L);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) th[j] = th0[j];
+    }
+    const double inv_dt = 1.0 / exp(th[3]);
+    const double pref = sqrt(inv_dt * 0.56418958354775628694807945156077);
+    double acc[1] = {0.0};
+    for (int t = threadIdx.x; t < G.n; t += NTR)
+        acc[0] += pref * atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) * sv[t];
+    block_sum<NTR, 1>(acc, red);
+    const double ck = acc[0];
+    acc[0] = 0.0;
+    for (int t = threadIdx.x; t < G.n; t += NTR) {
+        const double v = pref * atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt);
+        const double rn = r[t] - ck * v;
+        r[t] = rn;
+        if (approx) approx[(size_t)b * G.n + t] += ck * v;
+        acc[0] += rn * rn;
+    }
+    block_sum<NTR, 1>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) theta[o * 4 + j] = th[j];
+        coef[o] = ck;
+        index[o] = bidx;
+        if (gap) gap[o] = 0.0;
+        energy[(size_t)b * (order + 1) + k + 1] = acc[0];
+        flags[b] = fl;
+    }
+}
+
+act_status launch_prior_init(act_plan_s* p, int batch, const double* resid, hipStream_t s) {
+    const long long count = (long long)batch * p->n;
+    hipLaunchKernelGGL(k_prior_copy, dim3((unsigned)std::min<long long>((count + 255) / 256, 4096)), dim3(256), 0,
+                       s, resid, p->prior_s, count);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_prior_order(act_plan_s* p, int batch, int k, int order, double* resid, double* approx,
+                              double* theta, double* coef, long long* index, double* energy, double* gap,
+                              int* flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_prior_search, dim3(kPriorBlocks, batch), dim3(256), 0, s, p->grid, p->prior_s,
+                       p->prior_part, p->prior_pidx);
+    ACT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_prior_select_update, dim3(batch), dim3(NTR), 0, s, view(p), k, order,
+                       p->desc.refine_steps, p->prior_s, kPriorBlocks, p->prior_part, p->prior_pidx, resid, approx,
+                       theta, coef, index, energy, gap, flags);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+size_t prior_workspace_blocks() { return kPriorBlocks; }
 
 }  // namespace act

@@ -2,8 +2,9 @@
 that include/act.h declares, and rejects bad arguments on the host with
 ACT_ERR_INVALID before any device work."""
 import ctypes
-import math
 import os
+import subprocess
+import math
 import re
 
 import pytest
@@ -41,11 +42,27 @@ def test_library_exports_every_declared_symbol(lib):
     assert set(A.EXPORTS) <= set(declared_functions())
 
 
-def test_struct_layout_matches_header():
-    # act_axis: 2 doubles + 2 int32; act_grid: double, 2 int32, 4 axes
-    assert ctypes.sizeof(A._Axis) == 24
-    assert ctypes.sizeof(A._Grid) == 16 + 4 * 24
-    assert ctypes.sizeof(A._PlanDesc) == ctypes.sizeof(A._Grid) + 8 * 4
+def test_struct_layout_matches_header(tmp_path):
+    """Sizes and field offsets of the binding's structs equal the C header's,
+    as compiled by gcc from include/act.h."""
+    fields = {"act_axis": A._Axis, "act_grid": A._Grid, "act_plan_desc": A._PlanDesc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "act.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for cname, py in fields.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
 
 
 def _plan_status(lib, desc):

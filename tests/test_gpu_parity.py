@@ -77,12 +77,15 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_s
       - the refined parameters equal the oracle's refinement from that grid
         atom at converged, well-conditioned optima (the oracle's result does
         not move with 10x the iterations and the Hessian condition in scaled
-        coordinates is < 1e8), else J agrees to 1e-6;
+        coordinates is < 1e8), else J agrees to 1e-6 (floored at 1e-9 |s|^2);
       - the coefficient and the residual energy follow from those parameters.
-    While the two chains hold the same atoms at tight parameters, the residual
-    energies must also agree with the oracle's own chain to 1e-6; a tie broken
-    the other way or a loosely matched step ends that comparison (the two
-    pursuits then legitimately differ)."""
+    While the two chains hold the same atoms at tight parameters, their
+    normalised residues E_k / |s|^2 (Sec. III-C) must agree to 1e-6.  The
+    chains may pick different atoms only where the oracle's top-2 gap (in
+    absolute score) is within the gap excuse or within twice the distance
+    between the two residuals (unit-atom scores move by at most that
+    distance); that, or a loosely matched step, ends the chain comparison (the
+    two pursuits then legitimately differ)."""
     step, _, _ = oracle.refine_box(grid)
     B, order = ref["index"].shape
     compared = 0
@@ -91,6 +94,7 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_s
         sn = float(np.linalg.norm(s))
         np.testing.assert_allclose(gpu["energy"][b, 0], ref["energy"][b, 0], rtol=1e-12)
         rg = s.copy()          # the GPU's residual before order k
+        rr = s.copy()          # the oracle chain's residual before order k
         chain = True           # GPU chain still comparable with the oracle's
         for k in range(order):
             gi = int(gpu["index"][b, k])
@@ -101,7 +105,11 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_s
                 p_o = abs(oracle.correlate(grid, rg, i_o, 1)[0])
                 assert p_g >= (1 - 2 * GAP_EXCUSE) * p_o, (label, b, k, p_g, p_o)
             if chain and gi != int(ref["index"][b, k]):
-                assert ref["gap"][b, k] <= GAP_EXCUSE, (label, b, k, gi, ref["index"][b, k])
+                ri = int(ref["index"][b, k])
+                p1 = abs(oracle.correlate(grid, rr, ri, 1)[0])
+                drift = float(np.linalg.norm(rg - rr))
+                assert ref["gap"][b, k] <= GAP_EXCUSE or ref["gap"][b, k] * p1 <= 2.0 * drift, \
+                    (label, b, k, gi, ri, ref["gap"][b, k], p1, drift)
                 chain = False
             th_g = gpu["theta"][b, k]
             th0 = oracle.grid_theta(grid, gi)
@@ -114,19 +122,25 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_s
                 converged = np.all(np.abs(th_long - th_o) <= 1e-8 * scale)
                 cond = hessian_condition(oracle, grid, rg, th0, th_o)
                 assert not (converged and cond <= 1e8), (label, b, k, "converged", cond, dth)
-                assert abs(J_g - J_o) <= 1e-6 * J_o, (label, b, k, cond, J_g, J_o, dth)
+                # captured energy: 1e-6 relative, floored at 1e-9 of |s|^2 for
+                # the tiny atoms of deep orders (below the stopping rule's reach)
+                assert abs(J_g - J_o) <= 1e-6 * J_o + 1e-9 * sn * sn, (label, b, k, cond, J_g, J_o, dth)
                 chain = False
             gu, _ = oracle.atom_unit(grid.fs, grid.n, th_g)
             c_o = float(gu @ rg)
             assert abs(gpu["coef"][b, k] - c_o) <= 1e-9 * abs(c_o) + 1e-12 * sn, \
                 (label, b, k, gpu["coef"][b, k], c_o)
             rg = rg - gpu["coef"][b, k] * gu
+            if chain:
+                gr_, _ = oracle.atom_unit(grid.fs, grid.n, ref["theta"][b, k])
+                rr = rr - ref["coef"][b, k] * gr_
             e_own = float(rg @ rg)
             assert abs(gpu["energy"][b, k + 1] - e_own) <= 1e-9 * e_own + 1e-12 * sn * sn, \
                 (label, b, k, gpu["energy"][b, k + 1], e_own)
             if chain:
+                # the chain's normalised residue E_k / |s|^2 (Sec. III-C) within 1e-6
                 e_ref = ref["energy"][b, k + 1]
-                assert abs(gpu["energy"][b, k + 1] - e_ref) <= 1e-6 * e_ref + 1e-12 * sn * sn, \
+                assert abs(gpu["energy"][b, k + 1] - e_ref) <= 1e-6 * sn * sn, \
                     (label, b, k, gpu["energy"][b, k + 1], e_ref)
             compared += 1
         # decomposition identities on the GPU result itself
@@ -562,3 +576,66 @@ def test_invalid_calls_raise():
     assert e.value.status == act.ACT_ERR_INVALID
     with pytest.raises(act.ActError):
         plan.act_correlate(np.zeros(g.n), g.size - 1, 5)
+
+
+# --------------------------------------------------------------------------
+# the prior ACT (contrast mode) and the order-200 convergence sweep
+# --------------------------------------------------------------------------
+
+def test_prior_act_matches_oracle(oracle):
+    """Contrast mode against the oracle's prior ACT: the same atom every order
+    (search and refinement on the original signal), c = <g*, s> with the
+    un-normalised atom, the repeated update, and reconstruction with those
+    atoms."""
+    wl = W.plain_1x512()
+    g = wl.grid
+    ref = oracle.decompose_prior(g, wl.signals, 5, refine_steps=30)
+    plan = A().Plan(g, dict_="synth", prec="f64", refine_steps=30, prior_act=True)
+    out = plan.decompose(torch.from_numpy(wl.signals), 5)
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    step, _, _ = oracle.refine_box(g)
+    np.testing.assert_array_equal(gpu["index"], ref["index"])
+    dth = np.abs(gpu["theta"] - ref["theta"]) / np.maximum(np.abs(ref["theta"]), step)
+    assert np.all(dth <= 1e-6), dth
+    np.testing.assert_allclose(gpu["coef"], ref["coef"], rtol=1e-9)
+    np.testing.assert_allclose(gpu["energy"], ref["energy"], rtol=1e-9)
+    s = wl.signals[0]
+    np.testing.assert_allclose(gpu["approx"][0] + gpu["resid"][0], s, atol=1e-12 * np.abs(s).max() * 1e3)
+    rec = plan.act_reconstruct(out["theta"], out["coef"]).cpu().numpy()
+    np.testing.assert_allclose(rec, gpu["approx"], rtol=0, atol=1e-9 * np.abs(gpu["approx"]).max())
+
+
+def test_prior_act_stability_contrast_on_gpu():
+    """The paper's stability contrast on a synthetic EEG-like epoch: the prior
+    ACT's normalised residue exceeds 1 within 10 orders; the residue-based
+    ACT's stays below 1 and never increases."""
+    g = W.eeg_grid(256, 16, 16, 8, 6)
+    rng = np.random.default_rng(34)
+    s, _, _ = W.make_signal(rng, g, 3, 10.0)
+    res = {}
+    for prior in (True, False):
+        plan = A().Plan(g, dict_="synth", prec="f64", refine_steps=30, prior_act=prior)
+        out = plan.decompose(torch.from_numpy(s[None, :]), 10)
+        torch.cuda.synchronize()
+        e = out["energy"].cpu().numpy()[0]
+        res[prior] = e / e[0]
+    assert res[True].max() > 1.0
+    assert np.all(res[False] <= 1.0) and np.all(np.diff(res[False]) <= 1e-12)
+
+
+def test_convergence_sweep_order_200(oracle):
+    """Order-200 decomposition of a 1 s EEG-like epoch (Sec. III-C's
+    convergence study on synthetic input): every order checked against the
+    oracle's step on the GPU's residual, energies monotone, and the
+    normalised residue falls by orders of magnitude."""
+    g = W.eeg_grid(256, 16, 16, 8, 6)
+    rng = np.random.default_rng(35)
+    s, _, _ = W.make_signal(rng, g, 6, 15.0)
+    order = 200
+    ref = oracle.decompose(g, s, order, refine_steps=30)
+    gpu = gpu_decompose(g, s[None, :], order, "f64", "synth", refine_steps=30)
+    assert assert_decomposition_parity(gpu, ref, g, oracle, s[None, :], "sweep", 30) >= 50
+    e = gpu["energy"][0] / gpu["energy"][0, 0]
+    assert np.all(np.diff(e) <= 1e-12)
+    assert e[-1] < 1e-2
