@@ -304,3 +304,28 @@ def ragged_batch(seed_cfg: int = 5, count: int = 1000, n_min: int = 256,
                  order, 30, ths, amps)
     w.lengths, w.offsets, w.grids = lens, offs, grids
     return w
+
+
+def paper_eeg_grid() -> Grid:
+    """The paper's EEG parameter grid (Sec. III-B, Table "Parameter ranges":
+    t_c 0..256 step 16 samples, f_c 0.5..15 step 0.5 Hz, c -10..10 step 0.5,
+    logDt -4..1 step 0.5; 185,600 atoms) on 1 s windows at 256 Hz, t_c in
+    seconds."""
+    _, fc, c, ld = paper_table_grids()["EEG"]
+    return Grid(FS_HZ, 256, Axis(0.0, 1.0, 16, True), fc, c, ld)
+
+
+def eeg_sweep(seed_cfg: int = 6, windows: int = 50, order: int = 200) -> Workload:
+    """Synthetic stand-in for the paper's convergence and old-vs-new study
+    (Sec. III-B/III-C: 50 consecutive 1 s EEG windows, orders up to 200):
+    per window 3-8 chirplets over the grid hull plus pink noise at
+    SNR U(5, 20) dB."""
+    g = paper_eeg_grid()
+    sig = np.zeros((windows, g.n))
+    ths, amps = [], []
+    for b, rng in enumerate(_streams(seed_cfg, windows)):
+        s, th, a = make_signal(rng, g, int(rng.integers(3, 9)), rng.uniform(5.0, 20.0), pink=True)
+        sig[b] = s
+        ths.append(th)
+        amps.append(a)
+    return Workload("eeg-sweep", g, sig, order, 30, ths, amps)
