@@ -20,6 +20,8 @@ Parity status per function (the pins are in tests/test_oracle_pins.py):
   refine               pinned: off-grid recovery, scipy optimum, monotone J
   decompose            pinned: MP identities, one-iteration recovery, brute force
   reconstruct          pinned: a_P + r_P = s
+  LEM search           pinned: exhaustive search when the families cover the
+                       grid (numpy brute force), MP identities
   prior ACT (contrast) pinned: continuous-time norm of Eq. (1)'s prefactor,
                        numpy brute force of the un-normalised dictionary,
                        central differences of its objective, the closed form
@@ -66,6 +68,11 @@ class _Grid(ctypes.Structure):
 _lib = None
 
 
+class _Lem(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32), ("levels", ctypes.c_int32), ("topk", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("radius", ctypes.c_int32 * 4), ("step", (ctypes.c_double * 4) * 8)]
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -107,6 +114,7 @@ def _load():
         lib.oracle_refine_prior.argtypes = [d, i32, pd, pd, pd, pd, pd, i32, pd, pd]
         lib.oracle_refine_prior.restype = ctypes.c_int
         lib.oracle_decompose_prior.argtypes = [pg, i32, pd, i32, i32, pd, pd, pd, pd, pi64, pd, pi32]
+        lib.oracle_lem_decompose.argtypes = [pg, P(_Lem), i32, pd, pd, i32, i32, pd, pd, pd, pd, pd, pi32]
         _lib = lib
     return _lib
 
@@ -321,4 +329,37 @@ def decompose_prior(grid, signals, order: int, refine_steps: int = 30):
                                    _p(out["resid"]), _p(out["approx"]), _p(out["theta"]), _p(out["coef"]),
                                    _p(out["index"], ctypes.c_int64), _p(out["energy"]),
                                    _p(out["flags"], ctypes.c_int32))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# LEM-inspired hierarchical coarse-to-fine search (Sec. VII)
+# ---------------------------------------------------------------------------
+
+def make_lem(cfg) -> _Lem:
+    """cfg: samples, levels, topk, radius[4], steps[levels+1][4] (axes t_c s,
+    f_c Hz, c Hz/s, ln dt)."""
+    L = _Lem()
+    L.samples, L.levels, L.topk = int(cfg.samples), int(cfg.levels), int(cfg.topk)
+    for d in range(4):
+        L.radius[d] = int(cfg.radius[d])
+    for lv, row in enumerate(cfg.steps):
+        for d in range(4):
+            L.step[lv][d] = float(row[d])
+    return L
+
+
+def lem_decompose(grid, signals, lhs, cfg, order: int, refine_steps: int = 30):
+    """Hierarchical search + refinement per order; lhs [B][order][samples][4]."""
+    s = _f64(np.atleast_2d(signals))
+    B, n = s.shape
+    lhs = _f64(lhs)
+    assert lhs.shape == (B, order, cfg.samples, 4)
+    g = make_grid(grid)
+    L = make_lem(cfg)
+    out = dict(resid=np.zeros((B, n)), approx=np.zeros((B, n)), theta=np.zeros((B, order, 4)),
+               coef=np.zeros((B, order)), energy=np.zeros((B, order + 1)), flags=np.zeros(B, dtype=np.int32))
+    _load().oracle_lem_decompose(ctypes.byref(g), ctypes.byref(L), B, _p(s), _p(lhs), int(order),
+                                 int(refine_steps), _p(out["resid"]), _p(out["approx"]), _p(out["theta"]),
+                                 _p(out["coef"]), _p(out["energy"]), _p(out["flags"], ctypes.c_int32))
     return out

@@ -625,6 +625,146 @@ void oracle_decompose_prior(const oracle_grid* grid, int32_t batch, const double
     free(p);
 }
 
+/* ---------------------------------------------------------------------------
+ * LEM-inspired hierarchical coarse-to-fine search (Sec. VII, Fig.
+ * "Hierarchical LEM-inspired coarse-to-fine search"), per order on the
+ * current residual:
+ *   1. Latin-hypercube samples u (drawn by the caller, [samples][4] in [0,1))
+ *      map to the parameter hull and snap to the coarsest step grid (level 0);
+ *      each is projected (unit atom) onto the residual and the top-k distinct
+ *      candidates by |<g, r>| are kept (ties: earlier candidate).
+ *   2. For each refinement level l = 1..L, every kept candidate spawns the
+ *      local family candidate + i * step_l, i_d in [-radius_d, radius_d]
+ *      (members outside the hull dropped); all families are pooled and the
+ *      top-k distinct are kept again.
+ *   3. The best final candidate initialises the refinement (scales capped by
+ *      the finest step), then c_k = <g*, r_k> and the residual update.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t samples, levels, topk, pad;
+    int32_t radius[4];
+    double step[8][4]; /* per level 0..levels, axes (t_c s, f_c Hz, c Hz/s, ln dt) */
+} oracle_lem;
+
+static double lem_snap(double x, double lo, double hi, double st) {
+    if (!(hi > lo) || !(st > 0.0)) return lo;
+    double v = lo + floor((x - lo) / st + 0.5) * st;
+    if (v > hi) v = lo + floor((hi - lo) / st) * st;
+    return v < lo ? lo : v;
+}
+
+/* top-k distinct candidates by |p| (ties: the earlier one); returns count */
+static int lem_topk(const double* cand, const double* p, int m, int k, double* kept) {
+    int nk = 0;
+    char* used = (char*)calloc((size_t)(m > 0 ? m : 1), 1);
+    while (nk < k) {
+        int best = -1;
+        for (int j = 0; j < m; ++j)
+            if (!used[j] && (best < 0 || fabs(p[j]) > fabs(p[best]))) best = j;
+        if (best < 0) break;
+        used[best] = 1;
+        int dup = 0;
+        for (int a = 0; a < nk; ++a)
+            if (kept[4 * a] == cand[4 * best] && kept[4 * a + 1] == cand[4 * best + 1] &&
+                kept[4 * a + 2] == cand[4 * best + 2] && kept[4 * a + 3] == cand[4 * best + 3])
+                dup = 1;
+        if (dup) continue;
+        memcpy(kept + 4 * nk, cand + 4 * best, 4 * sizeof(double));
+        ++nk;
+    }
+    free(used);
+    return nk;
+}
+
+static void lem_scores(double fs, int32_t n, const double* cand, int m, const double* r, double* p) {
+#pragma omp parallel
+    {
+        double* g = (double*)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int j = 0; j < m; ++j) {
+            oracle_atom_unit(fs, n, cand + 4 * j, g);
+            p[j] = dot(g, r, n);
+        }
+        free(g);
+    }
+}
+
+/* lhs: [batch][order][samples][4]; outputs as oracle_decompose (no index/gap). */
+void oracle_lem_decompose(const oracle_grid* grid, const oracle_lem* cfg, int32_t batch, const double* s,
+                          const double* lhs, int32_t order, int32_t refine_steps, double* resid,
+                          double* approx, double* theta, double* coef, double* energy, int32_t* flags) {
+    int32_t n = grid->n;
+    double gstep[4], lo[4], hi[4];
+    oracle_refine_box(grid, gstep, lo, hi);
+    int fam = 1;
+    for (int d = 0; d < 4; ++d) fam *= 2 * cfg->radius[d] + 1;
+    int cap = cfg->samples > cfg->topk * fam ? cfg->samples : cfg->topk * fam;
+    double* cand = (double*)malloc(sizeof(double) * 4 * (size_t)cap);
+    double* p = (double*)malloc(sizeof(double) * (size_t)cap);
+    double* kept = (double*)malloc(sizeof(double) * 4 * (size_t)cfg->topk);
+    double* gs = (double*)malloc(sizeof(double) * (size_t)n);
+    const double* fin = cfg->step[cfg->levels];
+    for (int32_t b = 0; b < batch; ++b) {
+        double* r = resid + (size_t)b * n;
+        double* a = approx ? approx + (size_t)b * n : NULL;
+        memcpy(r, s + (size_t)b * n, sizeof(double) * (size_t)n);
+        if (a) memset(a, 0, sizeof(double) * (size_t)n);
+        int fl = 0;
+        for (int32_t k = 0; k < n; ++k)
+            if (!isfinite(r[k])) fl |= ORACLE_FLAG_NONFINITE;
+        energy[(size_t)b * (order + 1)] = dot(r, r, n);
+        for (int32_t k = 0; k < order; ++k) {
+            size_t o = (size_t)b * order + k;
+            const double* u = lhs + (((size_t)b * order + k) * cfg->samples) * 4;
+            for (int j = 0; j < cfg->samples; ++j)
+                for (int d = 0; d < 4; ++d)
+                    cand[4 * j + d] = lem_snap(lo[d] + u[4 * j + d] * (hi[d] - lo[d]), lo[d], hi[d], cfg->step[0][d]);
+            lem_scores(grid->fs, n, cand, cfg->samples, r, p);
+            int nk = lem_topk(cand, p, cfg->samples, cfg->topk, kept);
+            for (int lv = 1; lv <= cfg->levels; ++lv) {
+                const double* st = cfg->step[lv];
+                int m = 0;
+                for (int q = 0; q < nk; ++q)
+                    for (int i0 = -cfg->radius[0]; i0 <= cfg->radius[0]; ++i0)
+                        for (int i1 = -cfg->radius[1]; i1 <= cfg->radius[1]; ++i1)
+                            for (int i2 = -cfg->radius[2]; i2 <= cfg->radius[2]; ++i2)
+                                for (int i3 = -cfg->radius[3]; i3 <= cfg->radius[3]; ++i3) {
+                                    const int ii[4] = {i0, i1, i2, i3};
+                                    double th[4];
+                                    int in = 1;
+                                    for (int d = 0; d < 4; ++d) {
+                                        th[d] = kept[4 * q + d] + (double)ii[d] * st[d];
+                                        if (th[d] < lo[d] || th[d] > hi[d]) in = 0;
+                                    }
+                                    if (!in) continue;
+                                    memcpy(cand + 4 * m, th, sizeof th);
+                                    ++m;
+                                }
+                lem_scores(grid->fs, n, cand, m, r, p);
+                nk = lem_topk(cand, p, m, cfg->topk, kept);
+            }
+            double th[4], J;
+            if (refine_steps > 0)
+                fl |= oracle_refine(grid->fs, n, r, kept, fin, lo, hi, refine_steps, th, &J);
+            else
+                memcpy(th, kept, sizeof th);
+            oracle_atom_unit(grid->fs, n, th, gs);
+            double ck = dot(gs, r, n);
+            for (int32_t t = 0; t < n; ++t) r[t] = r[t] - ck * gs[t];
+            if (a)
+                for (int32_t t = 0; t < n; ++t) a[t] = a[t] + ck * gs[t];
+            memcpy(theta + 4 * o, th, sizeof th);
+            coef[o] = ck;
+            energy[(size_t)b * (order + 1) + k + 1] = dot(r, r, n);
+        }
+        flags[b] = fl & ~ORACLE_FLAG_LINESEARCH;
+    }
+    free(gs);
+    free(kept);
+    free(p);
+    free(cand);
+}
+
 /* sum_k coef_k * unit_atom(theta_k) for one channel (Eq. (3)). */
 void oracle_reconstruct(double fs, int32_t n, int32_t order, const double* theta,
                         const double* coef, double* out) {

@@ -329,3 +329,37 @@ def eeg_sweep(seed_cfg: int = 6, windows: int = 50, order: int = 200) -> Workloa
         ths.append(th)
         amps.append(a)
     return Workload("eeg-sweep", g, sig, order, 30, ths, amps)
+
+
+
+@dataclass
+class LemConfig:
+    """Hierarchical search settings: LHS samples, refinement levels, top-k,
+    neighbourhood radius per axis (in steps) and the step per level and axis
+    (axes t_c [s], f_c [Hz], c [Hz/s], ln dt)."""
+    samples: int
+    levels: int
+    topk: int
+    radius: Tuple[int, int, int, int]
+    steps: Tuple[Tuple[float, float, float, float], ...]
+
+
+def paper_lem_config(fs: float = FS_HZ, samples: int = 512) -> LemConfig:
+    """The paper's LEM settings (Sec. VII-A): 2 refinement levels, top-4,
+    step schedule (t_c, f_c, logDt, c) = (64, 2.0, 2.0, 5.0), (32, 1.0, 1.0,
+    2.5), (16, 0.5, 0.5, 0.5) with t_c in samples, radius 2 steps for t_c, f_c
+    and c and 1 for logDt; the LHS sample count is not given (512 here)."""
+    sched = [(64, 2.0, 2.0, 5.0), (32, 1.0, 1.0, 2.5), (16, 0.5, 0.5, 0.5)]
+    steps = tuple((tc / fs, f, c, ld) for tc, f, ld, c in sched)
+    return LemConfig(samples, 2, 4, (2, 2, 2, 1), steps)
+
+
+def lem_lhs(seed_cfg: int, batch: int, order: int, samples: int) -> np.ndarray:
+    """Latin-hypercube uniforms [batch][order][samples][4]: per axis a random
+    permutation of the strata plus a uniform jitter inside each stratum."""
+    out = np.zeros((batch, order, samples, 4))
+    for b, rng in enumerate(_streams(seed_cfg, batch)):
+        for k in range(order):
+            for d in range(4):
+                out[b, k, :, d] = (rng.permutation(samples) + rng.uniform(size=samples)) / samples
+    return out

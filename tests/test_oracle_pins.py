@@ -463,3 +463,48 @@ def test_prior_act_normalised_residue_exceeds_one(oracle):
     e_new = new["energy"][0] / new["energy"][0, 0]
     assert e_old.max() > 1.0
     assert np.all(e_new <= 1.0) and np.all(np.diff(e_new) <= 1e-12)
+
+
+# --------------------------------------------------------------------------
+# LEM-inspired hierarchical search
+# --------------------------------------------------------------------------
+
+def _covering_lem(g, samples=16):
+    """Level-0 and level-1 steps equal the grid spacing and the radius spans
+    the whole grid, so one family already holds every grid atom."""
+    sp = tuple(a.spacing() if a.count > 1 else 1.0 for a in g.axes)
+    return W.LemConfig(samples, 1, 2, tuple(a.count - 1 for a in g.axes), (sp, sp))
+
+
+def test_lem_with_covering_families_is_exhaustive_mp(oracle):
+    """When the neighbourhood families cover the grid, the hierarchical search
+    must select the exhaustive arg-max: without refinement it reproduces
+    numpy's brute-force matching pursuit order by order."""
+    from oracle import brute
+    g = _tiny_grid()
+    cfg = _covering_lem(g)
+    D = brute.dictionary(g.fs, g.n, *[brute.axis(a.lo, a.hi, a.count, a.half_open) for a in g.axes])
+    rng = np.random.default_rng(41)
+    for trial in range(4):
+        s = rng.standard_normal(g.n)
+        lhs = W.lem_lhs(100 + trial, 1, 6, cfg.samples)
+        out = oracle.lem_decompose(g, s, lhs, cfg, 6, refine_steps=0)
+        idx, coef, energy, r = brute.mp(D, s, 6)
+        th = np.array([g.theta(int(i)) for i in idx])
+        np.testing.assert_allclose(out["theta"][0], th, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(out["coef"][0], coef, rtol=0, atol=1e-12 * np.linalg.norm(s))
+        np.testing.assert_allclose(out["energy"][0], energy, rtol=1e-11, atol=1e-13)
+
+
+def test_lem_mp_identities(oracle):
+    """E_{k+1} = E_k - c_k^2 with unit atoms, monotone energy, a_P + r_P = s,
+    on the paper's LEM settings."""
+    wl = W.plain_1x512()
+    cfg = W.paper_lem_config(samples=128)
+    lhs = W.lem_lhs(42, 1, 6, cfg.samples)
+    out = oracle.lem_decompose(wl.grid, wl.signals, lhs, cfg, 6, refine_steps=30)
+    E, c = out["energy"][0], out["coef"][0]
+    np.testing.assert_allclose(E[1:], E[:-1] - c ** 2, rtol=0, atol=1e-11 * E[0])
+    assert np.all(np.diff(E) <= 1e-12 * E[0])
+    s = wl.signals[0]
+    np.testing.assert_allclose(out["approx"][0] + out["resid"][0], s, atol=1e-12 * np.abs(s).max())
