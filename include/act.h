@@ -169,6 +169,40 @@ act_status act_decompose(act_plan_t plan, int32_t batch, const int32_t* len_dev,
                          int32_t order, double* theta_dev, double* coef_dev, int64_t* index_dev,
                          double* energy_dev, double* gap_dev, int32_t* flags_dev, void* stream);
 
+/* LEM-inspired hierarchical coarse-to-fine search (Sec. VII, Fig.
+ * "Hierarchical LEM-inspired coarse-to-fine search"): per order, Latin
+ * hypercube samples of the parameter hull snapped to the level-0 steps, the
+ * top-k distinct candidates by |<g_hat, r_k>|, then for each refinement level
+ * the local families candidate + i * step_l (|i_d| <= radius_d, members
+ * outside the hull dropped) pooled and re-ranked to the top-k; the best
+ * candidate initialises the plan's refinement (scales capped by the finest
+ * step), then c_k and the update.  No dictionary is evaluated beyond these
+ * candidates. */
+typedef struct {
+    int32_t samples;        /* LHS samples per order (>= 1) */
+    int32_t levels;         /* refinement levels, 0..7 */
+    int32_t topk;           /* candidates kept per stage, 1..16 */
+    int32_t reserved;
+    int32_t radius[4];      /* neighbourhood half-width in steps (t_c, f_c, c, ln dt), >= 0 */
+    double step[8][4];      /* step of level 0..levels per axis (t_c s, f_c Hz, c Hz/s, ln dt), > 0 */
+} act_lem_desc;
+
+/* Hierarchical decomposition of `batch` channels of a plain ACT_DICT_SYNTH +
+ * ACT_PREC_F64 plan (the grid gives the parameter hull and the refinement box).
+ *   lhs_dev   in: [batch][order][samples][4] Latin-hypercube uniforms in [0,1)
+ *             (the random draws are the caller's, so runs are reproducible).
+ *   resid_dev in/out as act_decompose; approx_dev optional.
+ *   theta_dev [batch][order][4], coef_dev [batch][order],
+ *   energy_dev [batch][order+1], flags_dev [batch] as act_decompose.
+ * Candidates per stage: max(samples, topk * prod(2 radius_d + 1)) <= 8192;
+ * the plan keeps a workspace of that many candidates per channel (allocated
+ * on first use).  Errors: ACT_ERR_INVALID (bad settings or pointers),
+ * ACT_ERR_UNSUPPORTED (plan not plain FP64 synthesised). */
+act_status act_lem_decompose(act_plan_t plan, const act_lem_desc* cfg, int32_t batch,
+                             const double* lhs_dev, double* resid_dev, double* approx_dev,
+                             int32_t order, double* theta_dev, double* coef_dev, double* energy_dev,
+                             int32_t* flags_dev, void* stream);
+
 /* Continuous refinement alone (Sec. III-A "BFGS refinement"), for m
  * independent problems: from theta0 maximise J(theta) = <r, g(theta)>^2 /
  * <g(theta), g(theta)> with the plan's L-BFGS (box = the plan grid's hull,

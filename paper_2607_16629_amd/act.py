@@ -52,12 +52,30 @@ class _PlanDesc(ctypes.Structure):
                 ("prior_act", ctypes.c_int32)]
 
 
-EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_decompose", "act_refine",
-           "act_value_and_grad", "act_reconstruct", "act_correlate", "act_timing_enable",
+EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_decompose", "act_lem_decompose",
+           "act_refine", "act_value_and_grad", "act_reconstruct", "act_correlate", "act_timing_enable",
            "act_timing_read", "act_status_string", "act_last_error")
 PHASES = ("search", "rerun", "rescore", "select_refine_update")
 
 _lib = None
+
+
+class _LemDesc(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32), ("levels", ctypes.c_int32), ("topk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("radius", ctypes.c_int32 * 4),
+                ("step", (ctypes.c_double * 4) * 8)]
+
+
+def make_lem_desc(cfg) -> _LemDesc:
+    """cfg: samples, levels, topk, radius[4], steps[levels+1][4]."""
+    d = _LemDesc()
+    d.samples, d.levels, d.topk = int(cfg.samples), int(cfg.levels), int(cfg.topk)
+    for a in range(4):
+        d.radius[a] = int(cfg.radius[a])
+    for lv, row in enumerate(cfg.steps):
+        for a in range(4):
+            d.step[lv][a] = float(row[a])
+    return d
 
 
 def load() -> ctypes.CDLL:
@@ -70,6 +88,8 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.act_plan.argtypes = [ctypes.POINTER(_PlanDesc), vp, ctypes.POINTER(vp)]
+    lib.act_lem_decompose.argtypes = [vp, ctypes.POINTER(_LemDesc), i32, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.act_lem_decompose.restype = ctypes.c_int
     lib.act_plan.restype = ctypes.c_int
     lib.act_plan_destroy.argtypes = [vp]
     lib.act_plan_destroy.restype = None
@@ -239,6 +259,27 @@ class Plan:
             self._h, B, _ptr(lengths), _ptr(offsets), _ptr(resid), _ptr(out["approx"]), int(order),
             _ptr(out["theta"]), _ptr(out["coef"]), _ptr(out["index"]), _ptr(out["energy"]),
             _ptr(out["gap"]), _ptr(out["flags"]), _stream()))
+        return out
+
+    def act_lem_decompose(self, resid: torch.Tensor, lhs: torch.Tensor, cfg, order: int, out: dict):
+        """Hierarchical (LEM-inspired) decomposition in place on `resid` ([B, N]
+        f64 CUDA); lhs [B, order, samples, 4] f64 CUDA uniforms."""
+        assert resid.is_cuda and resid.dtype == torch.float64 and resid.is_contiguous()
+        assert lhs.is_cuda and lhs.dtype == torch.float64 and lhs.is_contiguous()
+        B = resid.shape[0]
+        assert tuple(lhs.shape) == (B, order, cfg.samples, 4)
+        desc = make_lem_desc(cfg)
+        _check(load().act_lem_decompose(
+            self._h, ctypes.byref(desc), B, _ptr(lhs), _ptr(resid), _ptr(out["approx"]), int(order),
+            _ptr(out["theta"]), _ptr(out["coef"]), _ptr(out["energy"]), _ptr(out["flags"]), _stream()))
+        return out
+
+    def lem_decompose(self, signals, lhs, cfg, order: int) -> dict:
+        resid = _device_tensor(signals, torch.float64).reshape(-1, self.grid.n).clone()
+        lhs = _device_tensor(lhs, torch.float64).contiguous()
+        out = self.alloc_outputs(resid.shape[0], order)
+        self.act_lem_decompose(resid, lhs, cfg, order, out)
+        out["resid"] = resid
         return out
 
     def decompose_ragged(self, packed, lengths, offsets, order: int) -> dict:

@@ -1,5 +1,7 @@
 // act_api.hip -- C ABI entry points: argument checks on the host, then the
 // stream-ordered launch sequence of the matching pursuit.
+#include <algorithm>
+#include <cmath>
 #include <string>
 
 #include "act_common.h"
@@ -179,6 +181,56 @@ extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* 
     }
     p->graphs.push_back({key, graph, exec, ++p->graph_clock});
     ACT_HIP(hipGraphLaunch(exec, s));
+    return ACT_OK;
+}
+
+extern "C" act_status act_lem_decompose(act_plan_t p, const act_lem_desc* cfg, int32_t batch,
+                                        const double* lhs_dev, double* resid_dev, double* approx_dev,
+                                        int32_t order, double* theta_dev, double* coef_dev, double* energy_dev,
+                                        int32_t* flags_dev, void* stream) {
+    ACT_REQUIRE(p != nullptr && cfg != nullptr, "act_lem_decompose: plan or settings NULL");
+    if (!(p->desc.dict == ACT_DICT_SYNTH && p->desc.prec == ACT_PREC_F64 && !p->desc.ragged && !p->desc.prior_act)) {
+        set_error("act_lem_decompose: needs a plain ACT_DICT_SYNTH + ACT_PREC_F64 plan");
+        return ACT_ERR_UNSUPPORTED;
+    }
+    ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, "act_lem_decompose: batch outside [1, max_batch]");
+    ACT_REQUIRE(order >= 1, "act_lem_decompose: order must be >= 1");
+    ACT_REQUIRE(cfg->samples >= 1 && cfg->levels >= 0 && cfg->levels <= 7 && cfg->topk >= 1 && cfg->topk <= 16,
+                "act_lem_decompose: samples >= 1, levels in [0, 7], topk in [1, 16]");
+    long long fam = 1;
+    for (int d = 0; d < 4; ++d) {
+        ACT_REQUIRE(cfg->radius[d] >= 0 && cfg->radius[d] <= 64, "act_lem_decompose: radius outside [0, 64]");
+        fam *= 2 * cfg->radius[d] + 1;
+    }
+    for (int l = 0; l <= cfg->levels; ++l)
+        for (int d = 0; d < 4; ++d)
+            ACT_REQUIRE(std::isfinite(cfg->step[l][d]) && cfg->step[l][d] > 0.0, "act_lem_decompose: steps must be > 0");
+    const long long cap = std::max<long long>(cfg->samples, cfg->topk * fam);
+    ACT_REQUIRE(cap <= 8192, "act_lem_decompose: more than 8192 candidates per stage");
+    ACT_REQUIRE(lhs_dev && resid_dev && theta_dev && coef_dev && energy_dev && flags_dev,
+                "act_lem_decompose: NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    p->last_stream = s;
+    if (p->lem_cap < cap) {  // workspace: candidates, scores and marks per channel
+        ACT_HIP(hipStreamSynchronize(s));
+        if (p->lem_cand) ACT_HIP(hipFree(p->lem_cand));
+        if (p->lem_score) ACT_HIP(hipFree(p->lem_score));
+        p->lem_cand = nullptr;
+        p->lem_score = nullptr;
+        p->lem_cap = 0;
+        ACT_HIP(hipMalloc((void**)&p->lem_cand, (size_t)p->max_batch * cap * 4 * sizeof(double)));
+        ACT_HIP(hipMalloc((void**)&p->lem_score, (size_t)p->max_batch * cap * (sizeof(double) + 1)));
+        p->lem_cap = (int)cap;
+    }
+    act_status st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, s);
+    if (st != ACT_OK) return st;
+    for (int k = 0; k < order; ++k) {
+        st = timed(p, 3, s, [&] {
+            return launch_lem_order(p, cfg, p->lem_cap, batch, k, order, lhs_dev, resid_dev, approx_dev, theta_dev,
+                                    coef_dev, energy_dev, flags_dev, s);
+        });
+        if (st != ACT_OK) return st;
+    }
     return ACT_OK;
 }
 

@@ -215,6 +215,9 @@ struct act_plan_s {
     double* prior_s = nullptr;       // prior ACT: [B][n] original signals
     double* prior_part = nullptr;    // prior ACT: [B][search blocks] best |score| per block
     long long* prior_pidx = nullptr; // prior ACT: [B][search blocks] its atom index
+    double* lem_cand = nullptr;      // LEM: [B][lem_cap][4] candidate parameters
+    double* lem_score = nullptr;     // LEM: [B][lem_cap] candidate scores
+    int lem_cap = 0;
     double trunc_tail = 0.0;  // largest sqrt(envelope tail energy) outside the supports
     double rho_max = 0.0;     // max over atoms of |envelope|_2 / |g|_2
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
@@ -278,6 +281,9 @@ act_status launch_prior_order(act_plan_s* p, int batch, int k, int order, double
                               double* theta, double* coef, long long* index, double* energy, double* gap,
                               int* flags, hipStream_t s);
 size_t prior_workspace_blocks();
+act_status launch_lem_order(act_plan_s* p, const act_lem_desc* cfg, int cap, int batch, int k, int order,
+                            const double* lhs, double* resid, double* approx, double* theta, double* coef,
+                            double* energy, int* flags, hipStream_t s);
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
                        int* flags, int order, hipStream_t s);

@@ -347,7 +347,7 @@ static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
-                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->lem_cand, p->lem_score, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);

@@ -1158,4 +1158,196 @@ act_status launch_prior_order(act_plan_s* p, int batch, int k, int order, double
 
 size_t prior_workspace_blocks() { return kPriorBlocks; }
 
+// --------------------------------------------------------------------------
+// LEM-inspired hierarchical coarse-to-fine search (Sec. VII): one workgroup
+// per channel runs every stage of one order on the device (LHS candidates,
+// pooled top-k, local families per level, refinement, coefficient, update).
+// --------------------------------------------------------------------------
+struct LemDev {
+    int samples, levels, topk, cap;
+    int radius[4];
+    double step[8][4];
+};
+
+// LHS sample x snapped to the level-0 grid anchored at lo (RN products and
+// sums, no contraction, so candidates are bit-identical to a plain FP64 run)
+__device__ __forceinline__ double lem_snap(double x, double lo, double hi, double st) {
+    if (!(hi > lo) || !(st > 0.0)) return lo;
+    double v = __dadd_rn(lo, __dmul_rn(floor(__dadd_rn(__ddiv_rn(__dadd_rn(x, -lo), st), 0.5)), st));
+    if (v > hi) v = __dadd_rn(lo, __dmul_rn(floor(__ddiv_rn(__dadd_rn(hi, -lo), st)), st));
+    return v < lo ? lo : v;
+}
+
+// Scores <g/|g|, r> of candidates [0, m) (one thread per candidate); a
+// candidate marked invalid (first parameter NaN) scores NaN.
+__device__ void lem_score_all(const GridDev& g, const double* r, const double* cand, double* sc, int m) {
+    for (int j = threadIdx.x; j < m; j += NTR) {
+        const double* th = cand + 4 * (size_t)j;
+        if (isnan(th[0])) {
+            sc[j] = __longlong_as_double(0x7ff8000000000000LL);
+            continue;
+        }
+        const double inv_dt = 1.0 / exp(th[3]);
+        double s = 0.0, q = 0.0;
+        for (int k = 0; k < g.n; ++k) {
+            const double v = atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt);
+            s += v * r[k];
+            q += v * v;
+        }
+        sc[j] = q > 0.0 ? s / sqrt(q) : 0.0;
+    }
+}
+
+// Top-k distinct candidates by |score| (ties: the earlier candidate), by one
+// thread into kept[topk][4]; returns the count.
+__device__ int lem_topk(const double* cand, const double* sc, int m, int k, double (*kept)[4], char* used) {
+    for (int j = 0; j < m; ++j) used[j] = 0;
+    int nk = 0;
+    while (nk < k) {
+        int best = -1;
+        for (int j = 0; j < m; ++j)
+            if (!used[j] && !isnan(sc[j]) && (best < 0 || fabs(sc[j]) > fabs(sc[best]))) best = j;
+        if (best < 0) break;
+        used[best] = 1;
+        const double* c = cand + 4 * (size_t)best;
+        bool dup = false;
+        for (int a = 0; a < nk; ++a)
+            if (kept[a][0] == c[0] && kept[a][1] == c[1] && kept[a][2] == c[2] && kept[a][3] == c[3]) dup = true;
+        if (dup) continue;
+        for (int d = 0; d < 4; ++d) kept[nk][d] = c[d];
+        ++nk;
+    }
+    return nk;
+}
+
+__global__ void __launch_bounds__(NTR) k_lem_order(PlanDev P, LemDev cfg, int k, int order, int steps,
+                                                   const double* __restrict__ lhs, double* __restrict__ cand_ws,
+                                                   double* __restrict__ score_ws, char* __restrict__ used_ws,
+                                                   double* __restrict__ resid, double* __restrict__ approx,
+                                                   double* __restrict__ theta, double* __restrict__ coef,
+                                                   double* __restrict__ energy, int* __restrict__ flags) {
+    __shared__ double red[block_sum_lds(NTR, 10)];
+    __shared__ RefineLds L;
+    __shared__ double kept[16][4];
+    __shared__ int s_nk;
+    const int b = blockIdx.x;
+    const GridDev& G = P.g;
+    double* r = resid + (size_t)b * G.n;
+    const size_t o = (size_t)b * order + k;
+    int fl = flags[b];
+    if (fl & ACT_FLAG_NONFINITE) {
+        if (threadIdx.x == 0) {
+            const double nan = __longlong_as_double(0x7ff8000000000000LL);
+            for (int j = 0; j < 4; ++j) theta[o * 4 + j] = nan;
+            coef[o] = 0.0;
+            energy[(size_t)b * (order + 1) + k + 1] = energy[(size_t)b * (order + 1) + k];
+        }
+        return;
+    }
+    double* cand = cand_ws + (size_t)b * cfg.cap * 4;
+    double* sc = score_ws + (size_t)b * cfg.cap;
+    char* used = used_ws + (size_t)b * cfg.cap;
+    const double* lo = P.box.lo;
+    const double* hi = P.box.hi;
+    // level 0: Latin-hypercube samples snapped to the coarsest steps
+    const double* u = lhs + ((size_t)b * order + k) * cfg.samples * 4;
+    for (int j = threadIdx.x; j < cfg.samples; j += NTR)
+        for (int d = 0; d < 4; ++d)
+            cand[4 * (size_t)j + d] =
+                lem_snap(__dadd_rn(lo[d], __dmul_rn(u[4 * (size_t)j + d], __dadd_rn(hi[d], -lo[d]))), lo[d], hi[d],
+                         cfg.step[0][d]);
+    __syncthreads();
+    lem_score_all(G, r, cand, sc, cfg.samples);
+    __syncthreads();
+    if (threadIdx.x == 0) s_nk = lem_topk(cand, sc, cfg.samples, cfg.topk, kept, used);
+    __syncthreads();
+    int fam = 1;
+    for (int d = 0; d < 4; ++d) fam *= 2 * cfg.radius[d] + 1;
+    for (int lv = 1; lv <= cfg.levels; ++lv) {
+        const int nk = s_nk, m = nk * fam;
+        // families in parent order, offsets lexicographic (ln dt fastest)
+        for (int q = threadIdx.x; q < m; q += NTR) {
+            const int a = q / fam;
+            int f = q % fam;
+            int ii[4];
+            for (int d = 3; d >= 0; --d) {
+                const int w = 2 * cfg.radius[d] + 1;
+                ii[d] = f % w - cfg.radius[d];
+                f /= w;
+            }
+            double* c = cand + 4 * (size_t)q;
+            bool in = true;
+            for (int d = 0; d < 4; ++d) {
+                c[d] = __dadd_rn(kept[a][d], __dmul_rn((double)ii[d], cfg.step[lv][d]));
+                if (c[d] < lo[d] || c[d] > hi[d]) in = false;
+            }
+            if (!in) c[0] = __longlong_as_double(0x7ff8000000000000LL);
+        }
+        __syncthreads();
+        lem_score_all(G, r, cand, sc, m);
+        __syncthreads();
+        if (threadIdx.x == 0) s_nk = lem_topk(cand, sc, m, cfg.topk, kept, used);
+        __syncthreads();
+    }
+    double th0[4], th[4], J = 0.0;
+    for (int d = 0; d < 4; ++d) th0[d] = kept[0][d];
+    BoxDev box = P.box;
+    for (int d = 0; d < 4; ++d) box.step[d] = cfg.step[cfg.levels][d];
+    if (steps > 0) {
+        fl |= refine_block<NTR>(r, G, box, th0, steps, th, &J, red, L);
+    } else {
+        for (int d = 0; d < 4; ++d) th[d] = th0[d];
+    }
+    // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4))
+    const double inv_dt = 1.0 / exp(th[3]);
+    double acc[1] = {0.0};
+    for (int t = threadIdx.x; t < G.n; t += NTR) {
+        const double v = atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt);
+        acc[0] += v * v;
+    }
+    block_sum<NTR, 1>(acc, red);
+    const double nrm = sqrt(acc[0]);
+    const bool ok = nrm >= 1e-300;
+    acc[0] = 0.0;
+    for (int t = threadIdx.x; t < G.n; t += NTR) {
+        const double v = ok ? atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
+        acc[0] += v * r[t];
+    }
+    block_sum<NTR, 1>(acc, red);
+    const double ck = acc[0];
+    acc[0] = 0.0;
+    for (int t = threadIdx.x; t < G.n; t += NTR) {
+        const double v = ok ? atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
+        const double rn = r[t] - ck * v;
+        r[t] = rn;
+        if (approx) approx[(size_t)b * G.n + t] += ck * v;
+        acc[0] += rn * rn;
+    }
+    block_sum<NTR, 1>(acc, red);
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 4; ++d) theta[o * 4 + d] = th[d];
+        coef[o] = ck;
+        energy[(size_t)b * (order + 1) + k + 1] = acc[0];
+        flags[b] = fl;
+    }
+}
+
+act_status launch_lem_order(act_plan_s* p, const act_lem_desc* cfg, int cap, int batch, int k, int order,
+                            const double* lhs, double* resid, double* approx, double* theta, double* coef,
+                            double* energy, int* flags, hipStream_t s) {
+    LemDev d;
+    d.samples = cfg->samples;
+    d.levels = cfg->levels;
+    d.topk = cfg->topk;
+    d.cap = cap;
+    for (int a = 0; a < 4; ++a) d.radius[a] = cfg->radius[a];
+    for (int l = 0; l < 8; ++l)
+        for (int a = 0; a < 4; ++a) d.step[l][a] = cfg->step[l][a];
+    hipLaunchKernelGGL(k_lem_order, dim3(batch), dim3(NTR), 0, s, view(p), d, k, order, p->desc.refine_steps, lhs,
+                       p->lem_cand, p->lem_score, (char*)(p->lem_score + (size_t)p->max_batch * cap), resid,
+                       approx, theta, coef, energy, flags);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
 }  // namespace act

@@ -639,3 +639,53 @@ def test_convergence_sweep_order_200(oracle):
     e = gpu["energy"][0] / gpu["energy"][0, 0]
     assert np.all(np.diff(e) <= 1e-12)
     assert e[-1] < 1e-2
+
+
+# --------------------------------------------------------------------------
+# LEM-inspired hierarchical search
+# --------------------------------------------------------------------------
+
+def _lem_run(g, signals, lhs, cfg, order, steps):
+    plan = A().Plan(g, dict_="synth", prec="f64", max_batch=signals.shape[0], refine_steps=steps)
+    out = plan.lem_decompose(torch.from_numpy(signals), torch.from_numpy(lhs), cfg, order)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    plan.close()
+    return res
+
+
+def test_lem_matches_oracle(oracle):
+    """The device-resident hierarchical search against the oracle on the same
+    Latin-hypercube draws: parameters, coefficients and normalised residues
+    order by order, MP identities on the device result."""
+    wl = W.batched_64x2048(channels=3, grid=W.eeg_grid(512, 32, 16, 16, 8), order=5)
+    g = wl.grid
+    cfg = W.paper_lem_config(samples=256)
+    lhs = W.lem_lhs(43, 3, 5, cfg.samples)
+    ref = oracle.lem_decompose(g, wl.signals, lhs, cfg, 5, refine_steps=30)
+    gpu = _lem_run(g, wl.signals, lhs, cfg, 5, 30)
+    step = np.array(cfg.steps[-1])
+    dth = np.abs(gpu["theta"] - ref["theta"]) / np.maximum(np.abs(ref["theta"]), step)
+    assert np.all(dth <= 1e-6), dth.max()
+    np.testing.assert_allclose(gpu["coef"], ref["coef"], rtol=1e-6, atol=1e-9)
+    e0 = ref["energy"][:, :1]
+    assert np.all(np.abs(gpu["energy"] - ref["energy"]) <= 1e-6 * e0)
+    E, c = gpu["energy"], gpu["coef"]
+    assert np.all(np.abs(E[:, 1:] - (E[:, :-1] - c ** 2)) <= 1e-10 * e0)
+    np.testing.assert_allclose(gpu["approx"] + gpu["resid"], wl.signals, atol=1e-12 * np.abs(wl.signals).max())
+
+
+def test_lem_covering_families_is_exhaustive_on_gpu(oracle):
+    """With families that cover the grid the device search is exhaustive MP."""
+    g = W.Grid(64.0, 64, W.Axis(0.0, 1.0, 3, True), W.Axis(2.0, 12.0, 4, False),
+               W.Axis(-4.0, 4.0, 3, False), W.Axis(math.log(0.1), math.log(0.4), 2, False))
+    sp = tuple(a.spacing() for a in g.axes)
+    cfg = W.LemConfig(16, 1, 2, tuple(a.count - 1 for a in g.axes), (sp, sp))
+    rng = np.random.default_rng(44)
+    sig = rng.standard_normal((2, g.n))
+    lhs = W.lem_lhs(45, 2, 6, cfg.samples)
+    ref = oracle.decompose(g, sig, 6, refine_steps=0)
+    gpu = _lem_run(g, sig, lhs, cfg, 6, 0)
+    th = np.array([[g.theta(int(i)) for i in row] for row in ref["index"]])
+    np.testing.assert_allclose(gpu["theta"], th, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(gpu["energy"], ref["energy"], rtol=1e-11, atol=1e-13)
