@@ -363,3 +363,16 @@ def lem_lhs(seed_cfg: int, batch: int, order: int, samples: int) -> np.ndarray:
             for d in range(4):
                 out[b, k, :, d] = (rng.permutation(samples) + rng.uniform(size=samples)) / samples
     return out
+
+
+def lem_eeg(seed_cfg: int = 7, windows: int = 19, order: int = 10) -> Workload:
+    """Synthetic stand-in for the paper's LEM study (Sec. VII-A: 2 s EEG
+    epochs of 512 samples, the EEG parameter ranges of its table, order 10,
+    19 measured epochs): 3-8 chirplets over the grid hull plus pink noise at
+    SNR U(5, 20) dB per window."""
+    _, fc, c, ld = paper_table_grids()["EEG"]
+    g = Grid(FS_HZ, 512, Axis(0.0, 1.0, 16, True), fc, c, ld)
+    sig = np.zeros((windows, g.n))
+    for b, rng in enumerate(_streams(seed_cfg, windows)):
+        sig[b], _, _ = make_signal(rng, g, int(rng.integers(3, 9)), rng.uniform(5.0, 20.0), pink=True)
+    return Workload("lem-eeg", g, sig, order, 30)
