@@ -22,6 +22,8 @@ Parity status per function (the pins are in tests/test_oracle_pins.py):
   reconstruct          pinned: a_P + r_P = s
   LEM search           pinned: exhaustive search when the families cover the
                        grid (numpy brute force), MP identities
+  complex atoms        pinned: FFT magnitude special case, central differences,
+                       one-order recovery at any phase, projection identities
   prior ACT (contrast) pinned: continuous-time norm of Eq. (1)'s prefactor,
                        numpy brute force of the un-normalised dictionary,
                        central differences of its objective, the closed form
@@ -115,6 +117,12 @@ def _load():
         lib.oracle_refine_prior.restype = ctypes.c_int
         lib.oracle_decompose_prior.argtypes = [pg, i32, pd, i32, i32, pd, pd, pd, pd, pi64, pd, pi32]
         lib.oracle_lem_decompose.argtypes = [pg, P(_Lem), i32, pd, pd, i32, i32, pd, pd, pd, pd, pd, pi32]
+        lib.oracle_correlate_complex.argtypes = [pg, pd, i64, i64, pd]
+        lib.oracle_objective_complex.argtypes = [d, i32, pd, pd, pd]
+        lib.oracle_objective_complex.restype = d
+        lib.oracle_refine_complex.argtypes = [d, i32, pd, pd, pd, pd, pd, i32, pd, pd]
+        lib.oracle_refine_complex.restype = ctypes.c_int
+        lib.oracle_decompose_complex.argtypes = [pg, i32, pd, i32, i32, pd, pd, pd, pd, pd, pi64, pd, pd, pi32]
         _lib = lib
     return _lib
 
@@ -362,4 +370,51 @@ def lem_decompose(grid, signals, lhs, cfg, order: int, refine_steps: int = 30):
     _load().oracle_lem_decompose(ctypes.byref(g), ctypes.byref(L), B, _p(s), _p(lhs), int(order),
                                  int(refine_steps), _p(out["resid"]), _p(out["approx"]), _p(out["theta"]),
                                  _p(out["coef"]), _p(out["energy"]), _p(out["flags"], ctypes.c_int32))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Complex (analytic) atoms: Eq. (1) literally, |<g_hat, r>| selection,
+# amplitude-and-phase least-squares update of the real residual.
+# ---------------------------------------------------------------------------
+
+def correlate_complex(grid, r, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+    r = _f64(r)
+    K = grid_size(grid)
+    count = K - begin if count is None else count
+    out = np.zeros(count)
+    g = make_grid(grid)
+    _load().oracle_correlate_complex(ctypes.byref(g), _p(r), int(begin), int(count), _p(out))
+    return out
+
+
+def objective_complex(fs: float, theta, r):
+    r = _f64(r)
+    grad = np.zeros(4)
+    J = _load().oracle_objective_complex(float(fs), r.size, _p(_f64(theta)), _p(r), _p(grad))
+    return float(J), grad
+
+
+def refine_complex(grid, r, theta0, steps: int = 30):
+    step, lo, hi = refine_box(grid)
+    th = np.zeros(4)
+    J = ctypes.c_double(0.0)
+    fl = _load().oracle_refine_complex(float(grid.fs), int(grid.n), _p(_f64(r)), _p(_f64(theta0)),
+                                       _p(step), _p(lo), _p(hi), int(steps), _p(th), ctypes.byref(J))
+    return th, float(J.value), int(fl)
+
+
+def decompose_complex(grid, signals, order: int, refine_steps: int = 30):
+    s = _f64(np.atleast_2d(signals))
+    B, n = s.shape
+    assert n == grid.n
+    g = make_grid(grid)
+    out = dict(resid=np.zeros((B, n)), approx=np.zeros((B, n)), theta=np.zeros((B, order, 4)),
+               coef_re=np.zeros((B, order)), coef_im=np.zeros((B, order)),
+               index=np.zeros((B, order), dtype=np.int64), energy=np.zeros((B, order + 1)),
+               gap=np.zeros((B, order)), flags=np.zeros(B, dtype=np.int32))
+    _load().oracle_decompose_complex(ctypes.byref(g), B, _p(s), int(order), int(refine_steps),
+                                     _p(out["resid"]), _p(out["approx"]), _p(out["theta"]), _p(out["coef_re"]),
+                                     _p(out["coef_im"]), _p(out["index"], ctypes.c_int64), _p(out["energy"]),
+                                     _p(out["gap"]), _p(out["flags"], ctypes.c_int32))
     return out

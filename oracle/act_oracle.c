@@ -268,12 +268,16 @@ double oracle_objective(double fs, int32_t n, const double theta[4], const doubl
 double oracle_objective_prior(double fs, int32_t n, const double theta[4], const double* s,
                               double grad[4]);
 
-/* mode 0: J of the residue-based ACT; mode 1: the prior ACT's objective. */
+double oracle_objective_complex(double fs, int32_t n, const double theta[4], const double* r, double grad[4]);
+
+/* mode 0: J of the residue-based ACT; 1: the prior ACT's objective; 2: complex atoms. */
 static double refine_eval(double fs, int32_t n, const double* r, const double th0[4],
                           const double h[4], const double u[4], double gu[4], int mode) {
     double th[4], gr[4];
     for (int j = 0; j < 4; ++j) th[j] = th0[j] + h[j] * u[j];
-    double J = mode ? oracle_objective_prior(fs, n, th, r, gr) : oracle_objective(fs, n, th, r, gr, NULL);
+    double J = mode == 1   ? oracle_objective_prior(fs, n, th, r, gr)
+               : mode == 2 ? oracle_objective_complex(fs, n, th, r, gr)
+                           : oracle_objective(fs, n, th, r, gr, NULL);
     for (int j = 0; j < 4; ++j) gu[j] = -h[j] * gr[j];
     return -J;
 }
@@ -573,6 +577,11 @@ double oracle_objective_prior(double fs, int32_t n, const double theta[4], const
     return J;
 }
 
+int oracle_refine_complex(double fs, int32_t n, const double* r, const double theta0[4], const double step[4],
+                          const double lo[4], const double hi[4], int32_t steps, double theta_out[4], double* j_out) {
+    return refine_core(fs, n, r, theta0, step, lo, hi, steps, theta_out, j_out, 2);
+}
+
 int oracle_refine_prior(double fs, int32_t n, const double* s, const double theta0[4],
                         const double step[4], const double lo[4], const double hi[4], int32_t steps,
                         double theta_out[4], double* j_out) {
@@ -763,6 +772,155 @@ void oracle_lem_decompose(const oracle_grid* grid, const oracle_lem* cfg, int32_
     free(kept);
     free(p);
     free(cand);
+}
+
+/* ---------------------------------------------------------------------------
+ * Complex (analytic) atoms, Eq. (1) literally: g = E e^{i phi}, phi =
+ * 2 pi (c tau^2 + f_c tau), normalised over the samples present (|g|^2 = sum
+ * E^2).  Selection and refinement use |<g_hat, r>|^2 = (a^2 + b^2) / sum E^2,
+ * a = sum r E cos(phi), b = sum r E sin(phi).  A real signal is updated by its
+ * orthogonal projection onto the real span of {Re g, Im g} (amplitude and
+ * phase fitted by least squares), so the residual energy never increases.
+ * ------------------------------------------------------------------------- */
+
+/* |<g_hat, r>| for dictionary atoms [begin, begin+count). */
+void oracle_correlate_complex(const oracle_grid* grid, const double* r, int64_t begin, int64_t count,
+                              double* p) {
+    int32_t n = grid->n;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < count; ++j) {
+        double th[4];
+        oracle_grid_theta(grid, begin + j, th);
+        double dt = exp(th[3]), a = 0.0, b = 0.0, q = 0.0;
+        for (int32_t k = 0; k < n; ++k) {
+            double tau = (double)k / grid->fs - th[0];
+            double u = tau / dt;
+            double e = exp(-0.5 * u * u);
+            double ph = TWO_PI * (th[2] * tau * tau + th[1] * tau);
+            a += r[k] * e * cos(ph);
+            b += r[k] * e * sin(ph);
+            q += e * e;
+        }
+        p[j] = q > 0.0 ? sqrt((a * a + b * b) / q) : 0.0;
+    }
+}
+
+/* J = (a^2 + b^2) / q and its gradient in theta (SI units). */
+double oracle_objective_complex(double fs, int32_t n, const double theta[4], const double* r, double grad[4]) {
+    double tc = theta[0], fc = theta[1], c = theta[2];
+    double dt = exp(theta[3]);
+    double a = 0.0, b = 0.0, q = 0.0, da[4] = {0, 0, 0, 0}, db[4] = {0, 0, 0, 0}, dq[4] = {0, 0, 0, 0};
+    for (int32_t k = 0; k < n; ++k) {
+        double tau = (double)k / fs - tc;
+        double u = tau / dt;
+        double e = exp(-0.5 * u * u);
+        double ph = TWO_PI * (c * tau * tau + fc * tau);
+        double co = cos(ph), si = sin(ph);
+        /* dE/dtheta and dphi/dtheta */
+        double de[4] = {e * tau / (dt * dt), 0.0, 0.0, e * tau * tau / (dt * dt)};
+        double dp[4] = {-TWO_PI * (2.0 * c * tau + fc), TWO_PI * tau, TWO_PI * tau * tau, 0.0};
+        a += r[k] * e * co;
+        b += r[k] * e * si;
+        q += e * e;
+        for (int j = 0; j < 4; ++j) {
+            da[j] += r[k] * (co * de[j] - e * si * dp[j]);
+            db[j] += r[k] * (si * de[j] + e * co * dp[j]);
+            dq[j] += 2.0 * e * de[j];
+        }
+    }
+    if (!(q > 0.0)) {
+        if (grad) grad[0] = grad[1] = grad[2] = grad[3] = 0.0;
+        return 0.0;
+    }
+    double J = (a * a + b * b) / q;
+    if (grad)
+        for (int j = 0; j < 4; ++j) grad[j] = (2.0 * a * da[j] + 2.0 * b * db[j]) / q - J * dq[j] / q;
+    return J;
+}
+
+/* Re and Im of the complex atom at theta (no normalisation). */
+static void atom_complex(double fs, int32_t n, const double th[4], double* u, double* v) {
+    double dt = exp(th[3]);
+    for (int32_t k = 0; k < n; ++k) {
+        double tau = (double)k / fs - th[0];
+        double x = tau / dt;
+        double e = exp(-0.5 * x * x);
+        double ph = TWO_PI * (th[2] * tau * tau + th[1] * tau);
+        u[k] = e * cos(ph);
+        v[k] = e * sin(ph);
+    }
+}
+
+/* least-squares amplitudes (alpha, beta) of r on {u, v}; 0 when singular */
+static void fit2(const double* u, const double* v, const double* r, int32_t n, double* alpha, double* beta) {
+    double uu = dot(u, u, n), vv = dot(v, v, n), uv = dot(u, v, n), ur = dot(u, r, n), vr = dot(v, r, n);
+    double det = uu * vv - uv * uv;
+    if (!(det > 1e-300 * (uu * vv > 0.0 ? uu * vv : 1.0)) || !(uu > 0.0)) {
+        /* degenerate (e.g. f_c = c = 0 at t_c: v = 0): one-dimensional fit on u */
+        *alpha = uu > 0.0 ? ur / uu : 0.0;
+        *beta = 0.0;
+        return;
+    }
+    *alpha = (vv * ur - uv * vr) / det;
+    *beta = (uu * vr - uv * ur) / det;
+}
+
+int oracle_refine_complex(double fs, int32_t n, const double* r, const double theta0[4], const double step[4],
+                          const double lo[4], const double hi[4], int32_t steps, double theta_out[4], double* j_out);
+
+/* Complex-atom MP; coef_re/coef_im [batch][order] are the amplitudes of Re g
+ * and Im g of the raw atom; index/gap as oracle_decompose. */
+void oracle_decompose_complex(const oracle_grid* grid, int32_t batch, const double* s, int32_t order,
+                              int32_t refine_steps, double* resid, double* approx, double* theta,
+                              double* coef_re, double* coef_im, int64_t* index, double* energy, double* gap,
+                              int32_t* flags) {
+    int32_t n = grid->n;
+    int64_t K = oracle_grid_size(grid);
+    double step[4], lo[4], hi[4];
+    oracle_refine_box(grid, step, lo, hi);
+    double* p = (double*)malloc(sizeof(double) * (size_t)K);
+    double* u = (double*)malloc(sizeof(double) * (size_t)n);
+    double* v = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int32_t b = 0; b < batch; ++b) {
+        double* r = resid + (size_t)b * n;
+        double* a = approx ? approx + (size_t)b * n : NULL;
+        memcpy(r, s + (size_t)b * n, sizeof(double) * (size_t)n);
+        if (a) memset(a, 0, sizeof(double) * (size_t)n);
+        int fl = 0;
+        for (int32_t k = 0; k < n; ++k)
+            if (!isfinite(r[k])) fl |= ORACLE_FLAG_NONFINITE;
+        energy[(size_t)b * (order + 1)] = dot(r, r, n);
+        for (int32_t k = 0; k < order; ++k) {
+            size_t o = (size_t)b * order + k;
+            oracle_correlate_complex(grid, r, 0, K, p);
+            double gp;
+            int64_t best = oracle_argmax(p, K, &gp);
+            double th0[4], th[4], J;
+            oracle_grid_theta(grid, best, th0);
+            if (refine_steps > 0)
+                fl |= oracle_refine_complex(grid->fs, n, r, th0, step, lo, hi, refine_steps, th, &J);
+            else
+                memcpy(th, th0, sizeof th);
+            atom_complex(grid->fs, n, th, u, v);
+            double al, be;
+            fit2(u, v, r, n, &al, &be);
+            for (int32_t t = 0; t < n; ++t) {
+                double w = al * u[t] + be * v[t];
+                r[t] = r[t] - w;
+                if (a) a[t] = a[t] + w;
+            }
+            memcpy(theta + 4 * o, th, sizeof th);
+            coef_re[o] = al;
+            coef_im[o] = be;
+            index[o] = best;
+            gap[o] = gp;
+            energy[(size_t)b * (order + 1) + k + 1] = dot(r, r, n);
+        }
+        flags[b] = fl & ~ORACLE_FLAG_LINESEARCH;
+    }
+    free(v);
+    free(u);
+    free(p);
 }
 
 /* sum_k coef_k * unit_atom(theta_k) for one channel (Eq. (3)). */

@@ -508,3 +508,87 @@ def test_lem_mp_identities(oracle):
     assert np.all(np.diff(E) <= 1e-12 * E[0])
     s = wl.signals[0]
     np.testing.assert_allclose(out["approx"][0] + out["resid"][0], s, atol=1e-12 * np.abs(s).max())
+
+
+# --------------------------------------------------------------------------
+# complex (analytic) atoms
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shift", [0, 5])
+def test_complex_score_is_fft_magnitude(oracle, shift):
+    """c = 0, flat envelope, f_c on FFT bins: the unit complex atom is a
+    Fourier vector, so |<g_hat, r>| = |FFT(r)[m]| / sqrt(N) for every phase
+    (t_c shifts only rotate the phase)."""
+    n, fs = 64, 64.0
+    g = W.Grid(fs, n, W.Axis(shift / fs, shift / fs, 1, False), W.Axis(1.0, 31.0, 31, False),
+               W.Axis(0.0, 0.0, 1, False), W.Axis(15.0, 15.0, 1, False))
+    rng = np.random.default_rng(51)
+    r = rng.standard_normal(n)
+    p = oracle.correlate_complex(g, r)
+    F = np.abs(np.fft.fft(r))[1:32] / math.sqrt(n)
+    np.testing.assert_allclose(p, F, rtol=1e-11)
+
+
+def test_complex_objective_gradient_central_differences(oracle):
+    g = W.eeg_grid(512, 32, 16, 16, 8)
+    rng = np.random.default_rng(52)
+    for trial in range(5):
+        th = np.array([rng.uniform(0.3, 1.7), rng.uniform(3, 50), rng.uniform(-15, 15),
+                       rng.uniform(math.log(0.05), 0)])
+        r = oracle.atom_raw(g.fs, g.n, th + np.array([0.01, 0.4, 0.6, 0.05])) + 0.1 * rng.standard_normal(g.n)
+        J, grad = oracle.objective_complex(g.fs, th, r)
+        fd = np.zeros(4)
+        for j in range(4):
+            e = np.zeros(4)
+            e[j] = 1e-6
+            fd[j] = (oracle.objective_complex(g.fs, th + e, r)[0] - oracle.objective_complex(g.fs, th - e, r)[0]) / 2e-6
+        assert np.max(np.abs(grad - fd)) <= 1e-6 * max(np.max(np.abs(fd)), 1e-8 * J)
+
+
+def test_complex_atoms_recover_any_phase(oracle):
+    """An on-grid chirplet at an arbitrary carrier phase psi, s = A E cos(phi +
+    psi): the complex search selects it and the amplitude-and-phase fit leaves
+    no residual after one order, whatever psi (the real atom, fixed at phase
+    0, cannot do this).  |<g_hat, r>| of a real signal carries the
+    negative-frequency image <g_hat, conj(g)>, of relative size about
+    exp(-(2 pi f_c dt)^2): the atoms here have f_c dt >= 2 and sit inside the
+    signal, where it is far below rounding."""
+    g = W.eeg_grid(512, 32, 16, 16, 8)
+    rng = np.random.default_rng(53)
+    for psi in (0.0, 0.7, math.pi / 2, 2.5):
+        while True:
+            j = int(rng.integers(g.size))
+            th = g.theta(j)
+            dt = math.exp(th[3])
+            if th[1] * dt >= 2.0 and 8 * dt <= th[0] <= g.n / g.fs - 8 * dt:
+                break
+        t = np.arange(g.n) / g.fs - th[0]
+        env = np.exp(-0.5 * (t / math.exp(th[3])) ** 2)
+        s = 1.7 * env * np.cos(2 * math.pi * (th[2] * t * t + th[1] * t) + psi)
+        out = oracle.decompose_complex(g, s, 1, refine_steps=30)
+        assert out["index"][0, 0] == j
+        assert out["energy"][0, 1] <= 1e-20 * out["energy"][0, 0]
+
+
+def test_complex_projection_identities(oracle):
+    """After each order the residual is orthogonal to Re g and Im g of the
+    selected atom, the energy drops by exactly the fitted part's energy, and
+    a_P + r_P = s."""
+    wl = W.plain_1x512()
+    out = oracle.decompose_complex(wl.grid, wl.signals, 5, refine_steps=30)
+    s = wl.signals[0]
+    r = s.copy()
+    for k in range(5):
+        th = out["theta"][0, k]
+        t = np.arange(wl.grid.n) / wl.grid.fs - th[0]
+        env = np.exp(-0.5 * (t / math.exp(th[3])) ** 2)
+        ph = 2 * math.pi * (th[2] * t * t + th[1] * t)
+        u, v = env * np.cos(ph), env * np.sin(ph)
+        w = out["coef_re"][0, k] * u + out["coef_im"][0, k] * v
+        r_new = r - w
+        assert abs(float(u @ r_new)) <= 1e-11 * np.linalg.norm(r) * np.linalg.norm(u)
+        assert abs(float(v @ r_new)) <= 1e-11 * np.linalg.norm(r) * np.linalg.norm(v)
+        np.testing.assert_allclose(out["energy"][0, k + 1], float(r_new @ r_new), rtol=1e-10)
+        np.testing.assert_allclose(float(r @ r) - float(r_new @ r_new), float(w @ w), rtol=1e-8, atol=1e-12)
+        r = r_new
+    np.testing.assert_allclose(out["approx"][0] + out["resid"][0], s, atol=1e-12 * np.abs(s).max())
