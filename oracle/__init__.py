@@ -106,6 +106,7 @@ def _load():
         lib.oracle_refine.restype = ctypes.c_int
         lib.oracle_refine_box.argtypes = [pg, pd, pd, pd]
         lib.oracle_refine_scales.argtypes = [d, i32, pd, pd, pd, pd, pd]
+        lib.oracle_refine_scales_complex.argtypes = [d, i32, pd, pd, pd, pd, pd]
         lib.oracle_refine_many.argtypes = [pg, i32, pd, pd, i32, pd, pd, pi32]
         lib.oracle_decompose.argtypes = [pg, i32, pd, i32, i32, pd, pd, pd, pd, pi64, pd, pd, pi32]
         lib.oracle_reconstruct.argtypes = [d, i32, i32, pd, pd, pd]
@@ -123,6 +124,8 @@ def _load():
         lib.oracle_refine_complex.argtypes = [d, i32, pd, pd, pd, pd, pd, i32, pd, pd]
         lib.oracle_refine_complex.restype = ctypes.c_int
         lib.oracle_decompose_complex.argtypes = [pg, i32, pd, i32, i32, pd, pd, pd, pd, pd, pi64, pd, pd, pi32]
+        lib.oracle_atom_complex.argtypes = [d, i32, pd, pd, pd]
+        lib.oracle_fit_complex.argtypes = [d, i32, pd, pd, pd]
         _lib = lib
     return _lib
 
@@ -228,11 +231,11 @@ def refine_box(grid):
     return step, lo, hi
 
 
-def refine_scales(grid, theta0) -> np.ndarray:
+def refine_scales(grid, theta0, complex_atoms: bool = False) -> np.ndarray:
     step, lo, hi = refine_box(grid)
     h = np.zeros(4)
-    _load().oracle_refine_scales(float(grid.fs), int(grid.n), _p(_f64(theta0)), _p(step), _p(lo),
-                                 _p(hi), _p(h))
+    fn = _load().oracle_refine_scales_complex if complex_atoms else _load().oracle_refine_scales
+    fn(float(grid.fs), int(grid.n), _p(_f64(theta0)), _p(step), _p(lo), _p(hi), _p(h))
     return h
 
 
@@ -402,6 +405,21 @@ def refine_complex(grid, r, theta0, steps: int = 30):
     fl = _load().oracle_refine_complex(float(grid.fs), int(grid.n), _p(_f64(r)), _p(_f64(theta0)),
                                        _p(step), _p(lo), _p(hi), int(steps), _p(th), ctypes.byref(J))
     return th, float(J.value), int(fl)
+
+
+def atom_complex(fs: float, n: int, theta) -> Tuple[np.ndarray, np.ndarray]:
+    """(E cos phi, E sin phi) of the raw complex atom at theta."""
+    u, v = np.zeros(n), np.zeros(n)
+    _load().oracle_atom_complex(float(fs), int(n), _p(_f64(theta)), _p(u), _p(v))
+    return u, v
+
+
+def fit_complex(fs: float, theta, r) -> np.ndarray:
+    """Least-squares amplitudes (alpha, beta) of r on the atom's two parts."""
+    r = _f64(r)
+    ab = np.zeros(2)
+    _load().oracle_fit_complex(float(fs), r.size, _p(_f64(theta)), _p(r), _p(ab))
+    return ab
 
 
 def decompose_complex(grid, signals, order: int, refine_steps: int = 30):

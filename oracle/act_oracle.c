@@ -317,12 +317,50 @@ void oracle_refine_scales(double fs, int32_t n, const double theta0[4], const do
     }
 }
 
+/* Scales for complex atoms g = E exp(i phi): the metric of the unit complex
+ * atom modulo a global phase (the objective |<g_hat, r>|^2 does not see one),
+ *   G_jj = (|d_j g|^2 - |<g, d_j g>|^2 / q) / q,  q = <E, E>,
+ * with d_j g = (dE_j + i E dphi_j) exp(i phi):
+ *   |d_j g|^2 = sum dE_j^2 + E^2 dphi_j^2,
+ *   <g, d_j g> = sum E dE_j + i sum E^2 dphi_j. */
+void oracle_refine_scales_complex(double fs, int32_t n, const double theta0[4], const double step[4],
+                                  const double lo[4], const double hi[4], double h[4]) {
+    double tc = theta0[0], fc = theta0[1], c = theta0[2];
+    double dt = exp(theta0[3]);
+    double q = 0.0, nrm[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+    for (int32_t k = 0; k < n; ++k) {
+        double tau = (double)k / fs - tc;
+        double u = tau / dt;
+        double e = exp(-0.5 * u * u);
+        double de[4] = {e * tau / (dt * dt), 0.0, 0.0, e * tau * tau / (dt * dt)};
+        double dp[4] = {-TWO_PI * (2.0 * c * tau + fc), TWO_PI * tau, TWO_PI * tau * tau, 0.0};
+        q += e * e;
+        for (int j = 0; j < 4; ++j) {
+            nrm[j] += de[j] * de[j] + e * e * dp[j] * dp[j];
+            re[j] += e * de[j];
+            im[j] += e * e * dp[j];
+        }
+    }
+    for (int j = 0; j < 4; ++j) {
+        double G = q > 0.0 ? (nrm[j] - (re[j] * re[j] + im[j] * im[j]) / q) / q : 0.0;
+        if (!(hi[j] > lo[j]) || !(G > 0.0)) {
+            h[j] = 0.0;
+            continue;
+        }
+        double r = 1.0 / sqrt(G);
+        h[j] = r < step[j] ? r : step[j];
+    }
+}
+
 static int refine_core(double fs, int32_t n, const double* r, const double theta0[4],
                        const double step[4], const double lo[4], const double hi[4], int32_t steps,
                        double theta_out[4], double* j_out, int mode) {
     double h[4], blo[4], bhi[4], u[4] = {0, 0, 0, 0}, g[4];
     int flags = 0;
-    oracle_refine_scales(fs, n, theta0, step, lo, hi, h);
+    if (mode == 2)
+        oracle_refine_scales_complex(fs, n, theta0, step, lo, hi, h);
+    else
+        oracle_refine_scales(fs, n, theta0, step, lo, hi, h);
     for (int j = 0; j < 4; ++j) {
         blo[j] = h[j] == 0.0 ? 0.0 : (lo[j] - theta0[j]) / h[j];
         bhi[j] = h[j] == 0.0 ? 0.0 : (hi[j] - theta0[j]) / h[j];
@@ -867,6 +905,21 @@ static void fit2(const double* u, const double* v, const double* r, int32_t n, d
 
 int oracle_refine_complex(double fs, int32_t n, const double* r, const double theta0[4], const double step[4],
                           const double lo[4], const double hi[4], int32_t steps, double theta_out[4], double* j_out);
+
+/* Re and Im of the raw complex atom, for callers. */
+void oracle_atom_complex(double fs, int32_t n, const double theta[4], double* u, double* v) {
+    atom_complex(fs, n, theta, u, v);
+}
+
+/* Amplitudes (ab[0], ab[1]) of the least-squares fit of r on the atom's parts. */
+void oracle_fit_complex(double fs, int32_t n, const double theta[4], const double* r, double ab[2]) {
+    double* u = (double*)malloc(sizeof(double) * (size_t)n);
+    double* v = (double*)malloc(sizeof(double) * (size_t)n);
+    atom_complex(fs, n, theta, u, v);
+    fit2(u, v, r, n, &ab[0], &ab[1]);
+    free(v);
+    free(u);
+}
 
 /* Complex-atom MP; coef_re/coef_im [batch][order] are the amplitudes of Re g
  * and Im g of the raw atom; index/gap as oracle_decompose. */

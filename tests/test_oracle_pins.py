@@ -584,6 +584,11 @@ def test_complex_projection_identities(oracle):
         env = np.exp(-0.5 * (t / math.exp(th[3])) ** 2)
         ph = 2 * math.pi * (th[2] * t * t + th[1] * t)
         u, v = env * np.cos(ph), env * np.sin(ph)
+        uo, vo = oracle.atom_complex(wl.grid.fs, wl.grid.n, th)
+        np.testing.assert_allclose(uo, u, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(vo, v, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(oracle.fit_complex(wl.grid.fs, th, r), [out["coef_re"][0, k], out["coef_im"][0, k]],
+                                   rtol=1e-12)
         w = out["coef_re"][0, k] * u + out["coef_im"][0, k] * v
         r_new = r - w
         assert abs(float(u @ r_new)) <= 1e-11 * np.linalg.norm(r) * np.linalg.norm(u)
@@ -592,3 +597,23 @@ def test_complex_projection_identities(oracle):
         np.testing.assert_allclose(float(r @ r) - float(r_new @ r_new), float(w @ w), rtol=1e-8, atol=1e-12)
         r = r_new
     np.testing.assert_allclose(out["approx"][0] + out["resid"][0], s, atol=1e-12 * np.abs(s).max())
+
+
+def test_complex_refine_scales_gaussian_closed_forms(oracle):
+    """Metric of the unit complex atom modulo a global phase, for a chirp-free
+    atom well inside a densely sampled signal (sums = Gaussian integrals to
+    rounding): G_tc = 1/(2 dt^2), G_fc = 2 pi^2 dt^2, G_c = 2 pi^2 dt^4,
+    G_logdt = 1/2, independent of f_c (the carrier is a global phase along
+    t_c).  The grid steps are made large so the scales are 1/sqrt(G)."""
+    fs, n = 4096.0, 8192
+    big = W.Axis(-1e6, 1e6, 3, False)
+    g = W.Grid(fs, n, W.Axis(0.0, 2.0, 3, False), W.Axis(-1e6, 1e6, 3, False), big, W.Axis(-30.0, 30.0, 3, False))
+    for dt, fc in [(0.05, 0.0), (0.1, 37.0), (0.2, 3.5)]:
+        th = np.array([1.0, fc, 0.0, math.log(dt)])
+        h = oracle.refine_scales(g, th, complex_atoms=True)
+        expect = [math.sqrt(2.0) * dt, 1.0 / (math.sqrt(2.0) * math.pi * dt),
+                  1.0 / (math.sqrt(2.0) * math.pi * dt * dt), math.sqrt(2.0)]
+        np.testing.assert_allclose(h, expect, rtol=1e-9)
+        # the real atom's metric along t_c carries the carrier: much finer at f_c = 37
+        if fc > 10:
+            assert oracle.refine_scales(g, th)[0] < 0.1 * h[0]
