@@ -116,6 +116,19 @@ typedef struct {
                                (r_{k+1} = r_k - c g*). ACT_DICT_SYNTH + ACT_PREC_F64, not ragged;
                                coef_dev then multiplies these atoms (act_reconstruct uses them);
                                gap_dev is 0 */
+    int32_t complex_atoms;  /* 1: complex (analytic) atoms g = E exp(i phi) of Eq. (1), E the
+                               Gaussian envelope and phi = 2 pi (c tau^2 + f_c tau), scored by
+                               |<g_hat, r>| = sqrt(<r, E cos phi>^2 + <r, E sin phi>^2) / |E|
+                               (unit norm over the samples present), refined on its square,
+                               and removed from the real residual by the least-squares fit of
+                               amplitude and phase: r -= alpha E cos phi + beta E sin phi.
+                               coef_dev then holds the pair (alpha, beta) per order
+                               ([batch][order][2], amplitudes of the un-normalised parts), which
+                               act_reconstruct takes in the same layout.  act_correlate returns
+                               |<g_hat, r>|, act_refine maximises |<g_hat, r>|^2.
+                               ACT_DICT_SYNTH with ACT_PREC_F64 or ACT_PREC_F32, not ragged,
+                               not with prior_act or support_cut; act_value_and_grad and
+                               act_lem_decompose return ACT_ERR_UNSUPPORTED */
 } act_plan_desc;
 
 typedef struct act_plan_s* act_plan_t;
@@ -150,7 +163,8 @@ int64_t act_plan_query(act_plan_t plan, int32_t key);
  *   approx_dev  out: a_P (same layout), or NULL.
  *   len_dev, off_dev  ragged plans only (int32 lengths, int64 offsets); NULL otherwise.
  *   theta_dev   out: [batch][order][4] refined parameters.
- *   coef_dev    out: [batch][order] coefficients c_k = <g*, r_k>.
+ *   coef_dev    out: [batch][order] coefficients c_k = <g*, r_k> ([batch][order][2]
+ *               amplitude pairs for complex_atoms plans).
  *   index_dev   out: [batch][order] flat grid index of the coarse winner.
  *   energy_dev  out: [batch][order+1] |r_k|^2 (k = 0 is |s|^2); the normalised
  *               residue of Eq. (5) is energy[k]/energy[0].

@@ -49,7 +49,7 @@ class _PlanDesc(ctypes.Structure):
                 ("max_batch", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("ragged", ctypes.c_int32),
                 ("ragged_tc_div", ctypes.c_int32), ("support_cut", ctypes.c_int32),
-                ("prior_act", ctypes.c_int32)]
+                ("prior_act", ctypes.c_int32), ("complex_atoms", ctypes.c_int32)]
 
 
 EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_decompose", "act_lem_decompose",
@@ -140,7 +140,8 @@ def _device_tensor(x, dtype) -> torch.Tensor:
 
 def make_desc(grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: int = 1,
               cand_cap: int = 0, refine_steps: int = 30, ragged: bool = False,
-              ragged_tc_div: int = 32, support_cut: bool = False, prior_act: bool = False) -> _PlanDesc:
+              ragged_tc_div: int = 32, support_cut: bool = False, prior_act: bool = False,
+              complex_atoms: bool = False) -> _PlanDesc:
     g = _Grid()
     g.fs_hz = float(grid.fs)
     g.n_samples = int(grid.n)
@@ -157,6 +158,7 @@ def make_desc(grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: in
     desc.ragged_tc_div = int(ragged_tc_div)
     desc.support_cut = int(bool(support_cut))
     desc.prior_act = int(bool(prior_act))
+    desc.complex_atoms = int(bool(complex_atoms))
     return desc
 
 
@@ -165,7 +167,8 @@ class Plan:
 
     def __init__(self, grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: int = 1,
                  cand_cap: int = 0, refine_steps: int = 30, ragged: bool = False,
-                 ragged_tc_div: int = 32, support_cut: bool = False, prior_act: bool = False):
+                 ragged_tc_div: int = 32, support_cut: bool = False, prior_act: bool = False,
+                 complex_atoms: bool = False):
         lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("libact needs a ROCm GPU; none is visible")
@@ -177,8 +180,9 @@ class Plan:
         self.ragged = ragged
         self.support_cut = support_cut
         self.prior_act = prior_act
+        self.complex_atoms = complex_atoms
         self._desc = make_desc(grid, dict_, prec, max_batch, cand_cap, refine_steps, ragged,
-                               ragged_tc_div, support_cut, prior_act)
+                               ragged_tc_div, support_cut, prior_act, complex_atoms)
         h = ctypes.c_void_p()
         _check(lib.act_plan(ctypes.byref(self._desc), _stream(), ctypes.byref(h)))
         self._h = h
@@ -225,7 +229,9 @@ class Plan:
         return dict(
             approx=torch.empty(batch, n, dtype=torch.float64, device=dev) if approx else None,
             theta=torch.empty(batch, order, 4, dtype=torch.float64, device=dev),
-            coef=torch.empty(batch, order, dtype=torch.float64, device=dev),
+            # complex atoms: an amplitude pair per order
+            coef=torch.empty((batch, order, 2) if self.complex_atoms else (batch, order), dtype=torch.float64,
+                             device=dev),
             index=torch.empty(batch, order, dtype=torch.int64, device=dev),
             energy=torch.empty(batch, order + 1, dtype=torch.float64, device=dev),
             gap=torch.empty(batch, order, dtype=torch.float64, device=dev),
@@ -331,7 +337,8 @@ class Plan:
     def act_reconstruct(self, theta, coef) -> torch.Tensor:
         theta = _device_tensor(theta, torch.float64)
         coef = _device_tensor(coef, torch.float64)
-        B, order = coef.shape
+        B, order = coef.shape[:2]
+        assert coef.dim() == (3 if self.complex_atoms else 2)
         out = torch.empty(B, self.grid.n, dtype=torch.float64, device=coef.device)
         _check(load().act_reconstruct(self._h, B, order, _ptr(theta), _ptr(coef), None, None,
                                       _ptr(out), _stream()))

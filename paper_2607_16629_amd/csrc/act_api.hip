@@ -189,8 +189,9 @@ extern "C" act_status act_lem_decompose(act_plan_t p, const act_lem_desc* cfg, i
                                         int32_t order, double* theta_dev, double* coef_dev, double* energy_dev,
                                         int32_t* flags_dev, void* stream) {
     ACT_REQUIRE(p != nullptr && cfg != nullptr, "act_lem_decompose: plan or settings NULL");
-    if (!(p->desc.dict == ACT_DICT_SYNTH && p->desc.prec == ACT_PREC_F64 && !p->desc.ragged && !p->desc.prior_act)) {
-        set_error("act_lem_decompose: needs a plain ACT_DICT_SYNTH + ACT_PREC_F64 plan");
+    if (!(p->desc.dict == ACT_DICT_SYNTH && p->desc.prec == ACT_PREC_F64 && !p->desc.ragged && !p->desc.prior_act &&
+          !p->desc.complex_atoms)) {
+        set_error("act_lem_decompose: needs a plain ACT_DICT_SYNTH + ACT_PREC_F64 plan of real atoms");
         return ACT_ERR_UNSUPPORTED;
     }
     ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, "act_lem_decompose: batch outside [1, max_batch]");
@@ -255,6 +256,10 @@ extern "C" act_status act_value_and_grad(act_plan_t p, int32_t m, int32_t dtype,
     ACT_REQUIRE(m >= 1, "act_value_and_grad: m must be >= 1");
     ACT_REQUIRE(dtype == ACT_PREC_F64 || dtype == ACT_PREC_F32, "act_value_and_grad: dtype must be F64 or F32");
     ACT_REQUIRE(resid_dev && theta_dev && value_dev && dtheta_dev, "act_value_and_grad: NULL pointer");
+    if (p->desc.complex_atoms) {
+        set_error("act_value_and_grad: the forward/adjoint is for real atoms; complex plans refine with act_refine");
+        return ACT_ERR_UNSUPPORTED;
+    }
     hipStream_t s = (hipStream_t)stream;
     p->last_stream = s;
     return launch_value_and_grad(p, m, dtype, resid_dev, theta_dev, value_dev, dtheta_dev, dr_dev, s);

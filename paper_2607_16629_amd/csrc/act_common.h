@@ -117,6 +117,19 @@ __device__ __forceinline__ double atom_sample64(double t, double tc, double fc, 
     return e * cospi(2.0 * cyc);
 }
 
+// One sample of the complex chirplet E exp(i phi) (no prefactor): its real
+// and imaginary parts and the envelope E.
+__device__ __forceinline__ void atom_parts64(double t, double tc, double fc, double c, double inv_dt,
+                                             double& re, double& im, double& env) {
+    const double tau = t - tc;
+    const double u = tau * inv_dt;
+    env = exp(-0.5 * u * u);
+    double si, co;
+    sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
+    re = env * co;
+    im = env * si;
+}
+
 // sample time of index k
 __device__ __forceinline__ double sample_time(int k, double fs) { return (double)k / fs; }
 

@@ -130,9 +130,10 @@ __global__ void k_build_factors(GridDev g, int W, float* __restrict__ U, float* 
 // One wave per atom: FP64 norms of the atom and of its Gaussian envelope over
 // the samples present; writes 1/|g| (FP64 and FP32) and the largest ratio
 // |envelope| / |g| of the dictionary (it scales the synthesis error bound).
+// Complex atoms E exp(i phi) have |g| = |E|: ratio 1.
 __global__ void __launch_bounds__(256) k_norms_rho(GridDev g, double* __restrict__ inv_norm,
                                                    float* __restrict__ inv_norm32,
-                                                   unsigned long long* __restrict__ rho_bits) {
+                                                   unsigned long long* __restrict__ rho_bits, int cplx) {
     const int lane = threadIdx.x & (kWave - 1);
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const long long nwaves = (long long)gridDim.x * blockDim.x / kWave;
@@ -151,6 +152,7 @@ __global__ void __launch_bounds__(256) k_norms_rho(GridDev g, double* __restrict
         }
         q = wave_sum(q);
         qe = wave_sum(qe);
+        if (cplx) q = qe;
         const double nrm = sqrt(q);
         const double sc = nrm >= 1e-300 ? 1.0 / nrm : 0.0;
         if (lane == 0) {
@@ -250,7 +252,7 @@ act_status build_synth(act_plan_s* p, hipStream_t s) {
                                p->fac_w, p->inv_full32);
     } else {
         hipLaunchKernelGGL(k_norms_rho, dim3((unsigned)std::min<long long>((p->atoms + 3) / 4, cus * 32LL)),
-                           dim3(256), 0, s, p->grid, p->inv_norm, p->inv_norm32, rb);
+                           dim3(256), 0, s, p->grid, p->inv_norm, p->inv_norm32, rb, p->desc.complex_atoms);
     }
     ACT_HIP(hipGetLastError());
     unsigned long long bits = 0;
@@ -392,6 +394,13 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     }
     if (desc->support_cut && !(desc->prec == ACT_PREC_F16 && desc->dict == ACT_DICT_SYNTH)) {
         set_error("act_plan: support_cut applies to the FP16 synthesised search only");
+        return ACT_ERR_UNSUPPORTED;
+    }
+    ACT_REQUIRE(desc->complex_atoms == 0 || desc->complex_atoms == 1, "act_plan: complex_atoms must be 0 or 1");
+    if (desc->complex_atoms &&
+        !(desc->dict == ACT_DICT_SYNTH && (desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32) &&
+          !desc->ragged && !desc->prior_act && !desc->support_cut)) {
+        set_error("act_plan: complex_atoms needs a plain ACT_DICT_SYNTH plan with ACT_PREC_F64 or ACT_PREC_F32");
         return ACT_ERR_UNSUPPORTED;
     }
     ACT_REQUIRE(!(desc->prec == ACT_PREC_F64 && desc->dict == ACT_DICT_TABLE),

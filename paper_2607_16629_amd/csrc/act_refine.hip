@@ -33,6 +33,7 @@ struct PlanDev {
     unsigned* tmax;          // ACT_PREC_F16: [B][n_tc] pass-0 upper bound per time centre
     double trunc_tail;       // ACT_PREC_F16 with support_cut: skipped envelope tail (relative)
     bool per_atom;           // gmax holds the max lower bound, cand_score upper bounds
+    bool cplx;               // complex atoms: scores |<g_hat, r>|, two-part update
 };
 
 static PlanDev view(const act_plan_s* p) {
@@ -63,6 +64,7 @@ static PlanDev view(const act_plan_s* p) {
     v.tmax = p->tmax;
     v.trunc_tail = p->trunc_tail;
     v.per_atom = p->desc.prec == ACT_PREC_F16;
+    v.cplx = p->desc.complex_atoms != 0;
     return v;
 }
 
@@ -81,9 +83,17 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 //   |sum g~ r~ - p| <= eg_max |r~| + |e_r|
 //   |fl(sum) - sum| <= gamma_m |g~| |r~|, gamma_m = m u / (1 - m u)   (chain m)
 // FP64 searches round the score to FP32 when storing it: u32 |r| + FP64 sums.
+//
+// Complex atoms: a = <r, Re g_hat> and b = <r, Im g_hat> each obey the bound of
+// the real score (|Re g_hat|, |Im g_hat| <= 1, and each factored product pair
+// sums to at most |E| |r|), so |sqrt(a~^2 + b~^2) - sqrt(a^2 + b^2)| <= sqrt(2)
+// times it; squaring, summing, the square root, the FP32 1/|E| and the scaling
+// add <= 6 u |r~| (the score is at most |r~|).  FP64: two sums of n terms and
+// the norm sum, <= 3 (n + 16) u64 |r| before the FP32 store.
 __device__ double score_bound(const PlanDev& P, double rn, double er, double scale, int n) {
     const double u32 = 5.9604644775390625e-08;  // 2^-24
-    if (P.prec == ACT_PREC_F64) return 1.01 * (u32 + (P.g.n + 16) * 2.220446049250313e-16) * rn;
+    if (P.prec == ACT_PREC_F64)
+        return 1.01 * (u32 + (P.cplx ? 3.0 : 1.0) * (P.g.n + 16) * 2.220446049250313e-16) * rn;
     const double rt = rn + er;
     const double m = (double)P.chain;
     const double gam = m * u32 / (1.0 - m * u32);
@@ -99,6 +109,10 @@ __device__ double score_bound(const PlanDev& P, double rn, double er, double sca
         // support cut: the skipped products sum to at most sqrt(tail) |r| / |g_w|
         // (|g| <= E and Cauchy-Schwarz), and |g_w| >= 1
         return 1.01 * (er + 6.0 * u32 * rt + sub * rt + P.trunc_tail * rt);
+    }
+    if (P.dict == ACT_DICT_SYNTH && P.cplx) {
+        const double part = (5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er;
+        return 1.01 * (1.4142135623730951 * part + 6.0 * u32 * rt);
     }
     if (P.dict == ACT_DICT_SYNTH) {
         // factored synthesis: each product U (C r) carries <= 5 FP32 roundings
@@ -283,14 +297,26 @@ __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __rest
         double th[4];
         grid_theta(cg.g, (long long)P.cand_idx[slot], th);
         const double inv_dt = 1.0 / exp(th[3]);
-        double s = 0.0, q = 0.0;
-        for (int k = lane; k < cg.g.n; k += kWave) {
-            const double v = atom_sample64(sample_time(k, cg.g.fs), th[0], th[1], th[2], inv_dt);
-            s += v * r[k];
-            q += v * v;
+        double s = 0.0, q = 0.0, sb = 0.0;
+        if (P.cplx) {
+            for (int k = lane; k < cg.g.n; k += kWave) {
+                double re, im, e;
+                atom_parts64(sample_time(k, cg.g.fs), th[0], th[1], th[2], inv_dt, re, im, e);
+                s += re * r[k];
+                sb += im * r[k];
+                q += e * e;
+            }
+            sb = wave_sum(sb);
+        } else {
+            for (int k = lane; k < cg.g.n; k += kWave) {
+                const double v = atom_sample64(sample_time(k, cg.g.fs), th[0], th[1], th[2], inv_dt);
+                s += v * r[k];
+                q += v * v;
+            }
         }
         s = wave_sum(s);
         q = wave_sum(q);
+        if (P.cplx) s = sqrt(s * s + sb * sb);
         if (lane == 0) P.cand_p64[slot] = q > 0.0 ? s / sqrt(q) : 0.0;
     }
 }
@@ -384,6 +410,90 @@ __device__ __forceinline__ double dot4(const double* a, const double* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
 }
 
+// Complex atoms: J = (a^2 + b^2) / q with a = <r, E cos phi>, b = <r, E sin phi>,
+// q = <E, E>.  With dE/dtheta = E (tau/dt^2, 0, 0, tau^2/dt^2) and dphi/dtheta =
+// 2 pi (-(2 c tau + f_c), tau, tau^2, 0):
+//   da_j = <r, cos phi dE_j - E sin phi dphi_j>, db_j = <r, sin phi dE_j + E cos phi dphi_j>,
+//   dq_j = 2 <E, dE_j>,  dJ_j = (2 a da_j + 2 b db_j) / q - J dq_j / q.
+// Sums: {a, b, q, da (4), db (4), dq_tc, dq_logdt}.
+template <int TB>
+__device__ void sums_obj_cplx(const double* __restrict__ r, int n, double fs, const double th[4],
+                              double (&acc)[13], double* red) {
+    const double inv_dt = 1.0 / exp(th[3]);
+    const double idt2 = inv_dt * inv_dt;
+    const double fc = th[1], c = th[2];
+#pragma unroll
+    for (int j = 0; j < 13; ++j) acc[j] = 0.0;
+#pragma unroll 1
+    for (int k = threadIdx.x; k < n; k += TB) {
+        const double tau = sample_time(k, fs) - th[0];
+        const double u = tau * inv_dt;
+        const double e = exp(-0.5 * u * u);
+        double si, co;
+        sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
+        const double rk = r[k];
+        const double de0 = e * tau * idt2, de3 = e * tau * tau * idt2;
+        const double dp0 = -kTwoPi * (2.0 * c * tau + fc), dp1 = kTwoPi * tau, dp2 = kTwoPi * tau * tau;
+        const double ec = e * co, es = e * si;
+        acc[0] += rk * ec;
+        acc[1] += rk * es;
+        acc[2] += e * e;
+        acc[3] += rk * (co * de0 - es * dp0);
+        acc[4] += rk * (-es * dp1);
+        acc[5] += rk * (-es * dp2);
+        acc[6] += rk * (co * de3);
+        acc[7] += rk * (si * de0 + ec * dp0);
+        acc[8] += rk * (ec * dp1);
+        acc[9] += rk * (ec * dp2);
+        acc[10] += rk * (si * de3);
+        acc[11] += 2.0 * e * de0;
+        acc[12] += 2.0 * e * de3;
+    }
+    block_sum<TB, 13>(acc, red);
+}
+
+// Coordinate scales for complex atoms: the metric of the unit complex atom
+// modulo a global phase, G_jj = (|d_j g|^2 - |<g, d_j g>|^2 / q) / q with
+// d_j g = (dE_j + i E dphi_j) exp(i phi).  Sums: {q, |d_j g|^2 (4),
+// sum E dE_j (4), sum E^2 dphi_j (4)}.
+template <int TB>
+__device__ void sums_scales_cplx(int n, double fs, const double th[4], double (&acc)[13], double* red) {
+    const double inv_dt = 1.0 / exp(th[3]);
+    const double idt2 = inv_dt * inv_dt;
+    const double fc = th[1], c = th[2];
+#pragma unroll
+    for (int j = 0; j < 13; ++j) acc[j] = 0.0;
+#pragma unroll 1
+    for (int k = threadIdx.x; k < n; k += TB) {
+        const double tau = sample_time(k, fs) - th[0];
+        const double u = tau * inv_dt;
+        const double e = exp(-0.5 * u * u);
+        const double de[4] = {e * tau * idt2, 0.0, 0.0, e * tau * tau * idt2};
+        const double dp[4] = {-kTwoPi * (2.0 * c * tau + fc), kTwoPi * tau, kTwoPi * tau * tau, 0.0};
+        acc[0] += e * e;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[1 + j] += de[j] * de[j] + e * e * dp[j] * dp[j];
+            acc[5 + j] += e * de[j];
+            acc[9 + j] += e * e * dp[j];
+        }
+    }
+    block_sum<TB, 13>(acc, red);
+}
+
+__device__ __forceinline__ double obj_cplx_from_sums(const double acc[13], double grad[4]) {
+    const double a = acc[0], b = acc[1], q = acc[2];
+    if (!(q > 0.0)) {
+        grad[0] = grad[1] = grad[2] = grad[3] = 0.0;
+        return 0.0;
+    }
+    const double J = (a * a + b * b) / q;
+    const double dq[4] = {acc[11], 0.0, 0.0, acc[12]};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) grad[j] = (2.0 * a * acc[3 + j] + 2.0 * b * acc[7 + j]) / q - J * dq[j] / q;
+    return J;
+}
+
 // --------------------------------------------------------------------------
 // Limited-memory BFGS refinement, block-wide.
 //
@@ -421,33 +531,57 @@ __device__ __forceinline__ double obj_prior_from_sums(const double acc[10], doub
     return J;
 }
 
-template <int TB, bool PRIOR = false>
+// objective of the refinement: 0 = the residue-based ACT's J, 1 = the prior
+// ACT's, 2 = complex atoms' |<g_hat, r>|^2 (the red buffer then holds 13 sums)
+enum { kObjReal = 0, kObjPrior = 1, kObjComplex = 2 };
+
+template <int TB, int MODE = kObjReal>
 __device__ __forceinline__ double refine_eval(const double* r, const GridDev& g, const double th0[4],
                                               const double h[4], const double u[4], double gu[4],
                                               double* red) {
-    double th[4], gr[4], acc[10];
+    double th[4], gr[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) th[j] = th0[j] + h[j] * u[j];
-    sums_obj<TB>(r, g.n, g.fs, th, acc, red);
-    const double J = PRIOR ? obj_prior_from_sums(acc, 1.0 / exp(th[3]), gr) : obj_from_sums(acc, gr);
+    double J;
+    if constexpr (MODE == kObjComplex) {
+        double acc[13];
+        sums_obj_cplx<TB>(r, g.n, g.fs, th, acc, red);
+        J = obj_cplx_from_sums(acc, gr);
+    } else {
+        double acc[10];
+        sums_obj<TB>(r, g.n, g.fs, th, acc, red);
+        J = MODE == kObjPrior ? obj_prior_from_sums(acc, 1.0 / exp(th[3]), gr) : obj_from_sums(acc, gr);
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) gu[j] = -h[j] * gr[j];
     return -J;
 }
 
-template <int TB, bool PRIOR = false>
+template <int TB, int MODE = kObjReal>
 __device__ int refine_block(const double* __restrict__ r, const GridDev& g, const BoxDev& box,
                             const double th0[4], int steps, double th_out[4], double* J_out,
                             double* red, RefineLds& L) {
     double h[4], blo[4], bhi[4], u[4] = {0, 0, 0, 0}, gcur[4];
     int flags = 0;
     {
-        double acc[9];
-        sums_scales<TB>(g.n, g.fs, th0, acc, red);
-        const double q = acc[0];
+        double Gd[4];
+        if constexpr (MODE == kObjComplex) {
+            double acc[13];
+            sums_scales_cplx<TB>(g.n, g.fs, th0, acc, red);
+            const double q = acc[0];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                Gd[j] = q > 0.0 ? (acc[1 + j] - (acc[5 + j] * acc[5 + j] + acc[9 + j] * acc[9 + j]) / q) / q : 0.0;
+        } else {
+            double acc[9];
+            sums_scales<TB>(g.n, g.fs, th0, acc, red);
+            const double q = acc[0];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Gd[j] = q > 0.0 ? (acc[5 + j] - acc[1 + j] * acc[1 + j] / q) / q : 0.0;
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const double G = q > 0.0 ? (acc[5 + j] - acc[1 + j] * acc[1 + j] / q) / q : 0.0;
+            const double G = Gd[j];
             if (!(box.hi[j] > box.lo[j]) || !(G > 0.0)) {
                 h[j] = 0.0;
             } else {
@@ -458,7 +592,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
             bhi[j] = h[j] == 0.0 ? 0.0 : (box.hi[j] - th0[j]) / h[j];
         }
     }
-    double f = refine_eval<TB, PRIOR>(r, g, th0, h, u, gcur, red);
+    double f = refine_eval<TB, MODE>(r, g, th0, h, u, gcur, red);
     const double f0 = f;
     int nmem = 0, head = 0;
     for (int it = 0; it < steps; ++it) {
@@ -527,7 +661,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
                 v = v > bhi[j] ? bhi[j] : v;
                 un[j] = v;
             }
-            fn = refine_eval<TB, PRIOR>(r, g, th0, h, un, gn, red);
+            fn = refine_eval<TB, MODE>(r, g, th0, h, un, gn, red);
             double dec = 0.0, dnew = 0.0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -593,7 +727,7 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
     PlanDev P, int k, int order, int steps, double* __restrict__ resid, double* __restrict__ approx,
     double* __restrict__ theta, double* __restrict__ coef, long long* __restrict__ index,
     double* __restrict__ energy, double* __restrict__ gap, int* __restrict__ flags) {
-    __shared__ double red[block_sum_lds(NTR, 10)];
+    __shared__ double red[block_sum_lds(NTR, 13)];
     __shared__ RefineLds L;
     __shared__ double s_a1[NWR], s_a2[NWR];
     __shared__ unsigned s_i1[NWR];
@@ -615,7 +749,12 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
         if (threadIdx.x == 0) {
             const double nan = __longlong_as_double(0x7ff8000000000000LL);
             for (int j = 0; j < 4; ++j) theta[o * 4 + j] = nan;
-            coef[o] = 0.0;
+            if (P.cplx) {
+                coef[2 * o] = 0.0;
+                coef[2 * o + 1] = 0.0;
+            } else {
+                coef[o] = 0.0;
+            }
             index[o] = -1;
             if (gap) gap[o] = 0.0;
             energy[(size_t)b * (order + 1) + k + 1] = energy[(size_t)b * (order + 1) + k];
@@ -697,14 +836,64 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
         box.hi[0] = cg.box_hi0;
     }
     if (steps > 0) {
-        fl |= refine_block<NTR>(r, G, box, th0, steps, th, &J, red, L);
+        if (P.cplx)
+            fl |= refine_block<NTR, kObjComplex>(r, G, box, th0, steps, th, &J, red, L);
+        else
+            fl |= refine_block<NTR>(r, G, box, th0, steps, th, &J, red, L);
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) th[j] = th0[j];
     }
 
-    // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4))
     const double inv_dt = 1.0 / exp(th[3]);
+    if (P.cplx) {
+        // complex atom: amplitudes (alpha, beta) of u = E cos phi and v = E sin
+        // phi by least squares, r -= alpha u + beta v (a pair that is singular
+        // to working precision falls back to the fit on u alone)
+        double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int t = threadIdx.x; t < G.n; t += NTR) {
+            double re, im, e;
+            atom_parts64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt, re, im, e);
+            acc5[0] += re * re;
+            acc5[1] += im * im;
+            acc5[2] += re * im;
+            acc5[3] += re * r[t];
+            acc5[4] += im * r[t];
+        }
+        block_sum<NTR, 5>(acc5, red);
+        const double uu = acc5[0], vv = acc5[1], uv = acc5[2], ur = acc5[3], vr = acc5[4];
+        const double det = uu * vv - uv * uv;
+        double al, be;
+        if (!(det > 1e-300 * (uu * vv > 0.0 ? uu * vv : 1.0)) || !(uu > 0.0)) {
+            al = uu > 0.0 ? ur / uu : 0.0;
+            be = 0.0;
+        } else {
+            al = (vv * ur - uv * vr) / det;
+            be = (uu * vr - uv * ur) / det;
+        }
+        for (int t = threadIdx.x; t < G.n; t += NTR) {
+            double re, im, e;
+            atom_parts64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt, re, im, e);
+            const double w = al * re + be * im;
+            r[t] = r[t] - w;
+            if (approx) approx[cg.off + t] = approx[cg.off + t] + w;
+        }
+        __syncthreads();
+        const double E = refresh_channel<NTR>(P, b, r, G.n, red, false);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) theta[o * 4 + j] = th[j];
+            coef[2 * o] = al;
+            coef[2 * o + 1] = be;
+            index[o] = best;
+            if (gap) gap[o] = g_gap;
+            energy[(size_t)b * (order + 1) + k + 1] = E;
+            flags[b] = fl;
+        }
+        return;
+    }
+
+    // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4))
     double acc[1] = {0.0};
     for (int t = threadIdx.x; t < G.n; t += NTR) {
         const double v = atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt);
@@ -741,20 +930,21 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
 // --------------------------------------------------------------------------
 // refinement alone, forward/adjoint alone, reconstruction
 // --------------------------------------------------------------------------
+template <int MODE>
 __global__ void __launch_bounds__(NTR) k_refine_many(GridDev g, BoxDev box,
                                                      const double* __restrict__ resid,
                                                      const double* __restrict__ theta0, int steps,
                                                      double* __restrict__ theta,
                                                      double* __restrict__ value,
                                                      int* __restrict__ flags) {
-    __shared__ double red[block_sum_lds(NTR, 10)];
+    __shared__ double red[block_sum_lds(NTR, 13)];
     __shared__ RefineLds L;
     const int p = blockIdx.x;
     const double* r = resid + (size_t)p * g.n;
     double th0[4], th[4], J;
 #pragma unroll
     for (int j = 0; j < 4; ++j) th0[j] = theta0[p * 4 + j];
-    const int fl = refine_block<NTR>(r, g, box, th0, steps, th, &J, red, L);
+    const int fl = refine_block<NTR, MODE>(r, g, box, th0, steps, th, &J, red, L);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) theta[p * 4 + j] = th[j];
@@ -880,7 +1070,7 @@ __global__ void __launch_bounds__(NT) k_reconstruct(GridDev g0, int order,
                                                     const double* __restrict__ coef,
                                                     const int* __restrict__ len,
                                                     const long long* __restrict__ off,
-                                                    double* __restrict__ out, int prior) {
+                                                    double* __restrict__ out, int prior, int cplx) {
     __shared__ double red[block_sum_lds(NT, 1)];
     const int b = blockIdx.x;
     const ChanGeom cg = chan_geom(g0, b, len, off);
@@ -889,9 +1079,18 @@ __global__ void __launch_bounds__(NT) k_reconstruct(GridDev g0, int order,
     for (int t = threadIdx.x; t < g.n; t += NT) o[t] = 0.0;
     for (int k = 0; k < order; ++k) {
         const double* th = theta + ((size_t)b * order + k) * 4;
-        const double ck = coef[(size_t)b * order + k];
         if (isnan(th[0])) continue;
         const double inv_dt = 1.0 / exp(th[3]);
+        if (cplx) {  // amplitude pair of the raw parts E cos phi, E sin phi
+            const double al = coef[2 * ((size_t)b * order + k)], be = coef[2 * ((size_t)b * order + k) + 1];
+            for (int t = threadIdx.x; t < g.n; t += NT) {
+                double re, im, e;
+                atom_parts64(sample_time(t, g.fs), th[0], th[1], th[2], inv_dt, re, im, e);
+                o[t] = o[t] + (al * re + be * im);
+            }
+            continue;
+        }
+        const double ck = coef[(size_t)b * order + k];
         double acc[1] = {0.0};
         for (int t = threadIdx.x; t < g.n; t += NT) {
             const double v = atom_sample64(sample_time(t, g.fs), th[0], th[1], th[2], inv_dt);
@@ -948,8 +1147,8 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
 
 act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const double* theta0,
                               int steps, double* theta, double* value, int* flags, hipStream_t s) {
-    hipLaunchKernelGGL(k_refine_many, dim3(m), dim3(NTR), 0, s, p->grid, p->box, resid, theta0, steps,
-                       theta, value, flags);
+    hipLaunchKernelGGL((p->desc.complex_atoms ? k_refine_many<kObjComplex> : k_refine_many<kObjReal>), dim3(m),
+                       dim3(NTR), 0, s, p->grid, p->box, resid, theta0, steps, theta, value, flags);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }
@@ -971,7 +1170,7 @@ act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double*
                               const double* coef, const int* len, const long long* off, double* out,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_reconstruct, dim3(batch), dim3(NT), 0, s, p->grid, order, theta, coef, len, off,
-                       out, p->desc.prior_act);
+                       out, p->desc.prior_act, p->desc.complex_atoms);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }
@@ -1103,7 +1302,7 @@ __global__ void __launch_bounds__(NTR) k_prior_select_update(
     double th0[4], th[4], J = 0.0;
     grid_theta(G, bidx, th0);
     if (steps > 0) {
-        fl |= refine_block<NTR, true>(sv, G, P.box, th0, steps, th, &J, red, L);
+        fl |= refine_block<NTR, kObjPrior>(sv, G, P.box, th0, steps, th, &J, red, L);
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) th[j] = th0[j];

@@ -5,10 +5,10 @@ namespace act {
 
 // --------------------------------------------------------------------------
 // FP64: one lane per atom, atoms synthesised from Eq. (1) in FP64 on the fly,
-// p = <g, r> / |g| with the norm taken over the same samples.
-// blockIdx.y = channel.
+// p = <g, r> / |g| with the norm taken over the same samples (complex atoms:
+// p = |<g, r>| / |E|).  blockIdx.y = channel.
 // --------------------------------------------------------------------------
-template <bool RERUN>
+template <bool RERUN, bool CPLX>
 __global__ void __launch_bounds__(256) k_search_f64(GridDev g0, const double* __restrict__ resid,
                                                    SearchCtl ctl) {
     const int b = blockIdx.y;
@@ -26,12 +26,21 @@ __global__ void __launch_bounds__(256) k_search_f64(GridDev g0, const double* __
         double th[4];
         grid_theta(g, i, th);
         const double inv_dt = 1.0 / exp(th[3]);
-        double s = 0.0, q = 0.0;
+        double s = 0.0, q = 0.0, sb = 0.0;
         for (int k = 0; k < g.n; ++k) {
-            double v = atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt);
-            s += v * r[k];
-            q += v * v;
+            if constexpr (CPLX) {
+                double re, im, e;
+                atom_parts64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt, re, im, e);
+                s += re * r[k];
+                sb += im * r[k];
+                q += e * e;
+            } else {
+                double v = atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt);
+                s += v * r[k];
+                q += v * v;
+            }
         }
+        if constexpr (CPLX) s = sqrt(s * s + sb * sb);
         const double p = q > 0.0 ? s / sqrt(q) : 0.0;
         if (ctl.dump) {
             if (valid) ctl.dump[(size_t)b * ctl.dump_count + j] = p;
@@ -50,10 +59,13 @@ act_status launch_search_f64(act_plan_s* p, int batch, const SearchCtl& ctl, con
     const long long cap = (long long)device_cus() * 16;
     blocks = blocks < cap ? blocks : cap;
     if (blocks < 1) blocks = 1;
+    const bool cx = p->desc.complex_atoms != 0;
     if (ctl.pass)
-        hipLaunchKernelGGL(k_search_f64<true>, dim3((unsigned)blocks, batch), dim3(256), 0, s, p->grid, resid, ctl);
+        hipLaunchKernelGGL((cx ? k_search_f64<true, true> : k_search_f64<true, false>), dim3((unsigned)blocks, batch),
+                           dim3(256), 0, s, p->grid, resid, ctl);
     else
-        hipLaunchKernelGGL(k_search_f64<false>, dim3((unsigned)blocks, batch), dim3(256), 0, s, p->grid, resid, ctl);
+        hipLaunchKernelGGL((cx ? k_search_f64<false, true> : k_search_f64<false, false>),
+                           dim3((unsigned)blocks, batch), dim3(256), 0, s, p->grid, resid, ctl);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

@@ -22,6 +22,12 @@
 // lane reads 8 contiguous values of A and of B.  Each stage is accumulated
 // into fresh registers and then added to the total, so an FP32 score is a
 // chain of at most 128 + N/128 roundings (certified margin).
+//
+// Complex atoms E exp(i phi) need both parts of the same product: with the
+// B operand [C r ; -S r] unchanged, <r, E sin phi> = sum V (C r) + (-U)(-S r),
+// a second accumulator fed by [V | -U]; the score is sqrt(a^2 + b^2) / |E|.
+#include <type_traits>
+
 #include "act_emit.h"
 
 namespace act {
@@ -55,7 +61,7 @@ struct TileArgs {
     int b, tc, m, clb, fcc, n, n_pad_ch;  // n: samples of the channel
 };
 
-template <bool RERUN, bool DUMP, bool RAGGED>
+template <bool RERUN, bool DUMP, bool RAGGED, bool CPLX = false>
 __device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __restrict__ r,
                            const SearchCtl& ctl, const TileArgs& ta, f32x4 (*bl)[SY_COLS][SY_STAGE / 4 + 1],
                            float* s_red, float* s_M) {
@@ -69,11 +75,15 @@ __device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __
         const float* urow = sy.U + (size_t)(row_ok ? cl : 0) * sy.W;
         const float* vrow = sy.V + (size_t)(row_ok ? cl : 0) * sy.W;
         const int h = lane >> 5;
-        f32x16 tot[2], acc[2];
+        static_assert(!(CPLX && RAGGED), "complex atoms: plain plans only");
+        f32x16 tot[2], acc[2], totb[2], accb[2];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) tot[cb][v] = 0.0f;
+            for (int v = 0; v < 16; ++v) {
+                tot[cb][v] = 0.0f;
+                if constexpr (CPLX) totb[cb][v] = 0.0f;
+            }
 
         for (int n0 = 0; n0 < ta.n_pad_ch; n0 += SY_STAGE) {
             __syncthreads();
@@ -95,7 +105,10 @@ __device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) acc[cb][v] = 0.0f;
+                for (int v = 0; v < 16; ++v) {
+                    acc[cb][v] = 0.0f;
+                    if constexpr (CPLX) accb[cb][v] = 0.0f;
+                }
             for (int s16 = 0; s16 < SY_STAGE; s16 += 16) {
                 const int e0 = n0 + s16 + 8 * h - m + g.n_pad;  // factor column of this lane's 8 samples
                 f32x4 ua = {0, 0, 0, 0}, ub = {0, 0, 0, 0}, va = {0, 0, 0, 0}, vb = {0, 0, 0, 0};
@@ -116,13 +129,29 @@ __device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __
                         acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ub[j], cc[j], acc[cb], 0, 0, 0);
                         acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(va[j], sa[j], acc[cb], 0, 0, 0);
                         acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(vb[j], sc[j], acc[cb], 0, 0, 0);
+                        if constexpr (CPLX) {
+                            accb[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(va[j], ca[j], accb[cb], 0, 0, 0);
+                            accb[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(vb[j], cc[j], accb[cb], 0, 0, 0);
+                            accb[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ua[j], sa[j], accb[cb], 0, 0, 0);
+                            accb[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ub[j], sc[j], accb[cb], 0, 0, 0);
+                        }
                     }
                 }
             }
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) tot[cb][v] += acc[cb][v];
+                for (int v = 0; v < 16; ++v) {
+                    tot[cb][v] += acc[cb][v];
+                    if constexpr (CPLX) totb[cb][v] += accb[cb][v];
+                }
+        }
+        if constexpr (CPLX) {
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+                    tot[cb][v] = sqrtf(tot[cb][v] * tot[cb][v] + totb[cb][v] * totb[cb][v]);
         }
 
         // ---- epilogue: rows = cl (A rows), columns = f_c; scale by 1/|g|
@@ -193,7 +222,7 @@ __device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __
 }
 
 // plain plans: grid x = (tc, cl block, f_c chunk) tiles, y = channel
-template <bool RERUN, bool DUMP>
+template <bool RERUN, bool DUMP, bool CPLX>
 __global__ void __launch_bounds__(256) k_search_synth_f32(GridDev g, SynthDev sy,
                                                           const float* __restrict__ shadow,
                                                           SearchCtl ctl, int n_clb, int n_fcc) {
@@ -214,7 +243,7 @@ __global__ void __launch_bounds__(256) k_search_synth_f32(GridDev g, SynthDev sy
         ta.m = sy.tc_shift[ta.tc];
         ta.n = g.n;
         ta.n_pad_ch = g.n_pad;
-        synth_tile<RERUN, DUMP, false>(g, sy, r, ctl, ta, bl, s_red, &s_M);
+        synth_tile<RERUN, DUMP, false, CPLX>(g, sy, r, ctl, ta, bl, s_red, &s_M);
     }
 }
 
@@ -301,15 +330,22 @@ act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ct
     long long blocks = tiles;
     const long long cap = (long long)device_cus() * 4;
     blocks = blocks < cap ? blocks : cap;
-    if (ctl.dump)
-        hipLaunchKernelGGL((k_search_synth_f32<false, true>), dim3((unsigned)blocks, batch), dim3(256), 0, s,
-                           p->grid, sy, sh, ctl, n_clb, n_fcc);
-    else if (ctl.pass)
-        hipLaunchKernelGGL((k_search_synth_f32<true, false>), dim3((unsigned)blocks, batch), dim3(256), 0, s,
-                           p->grid, sy, sh, ctl, n_clb, n_fcc);
+    auto go = [&](auto cplx) {
+        constexpr bool C = decltype(cplx)::value;
+        if (ctl.dump)
+            hipLaunchKernelGGL((k_search_synth_f32<false, true, C>), dim3((unsigned)blocks, batch), dim3(256), 0, s,
+                               p->grid, sy, sh, ctl, n_clb, n_fcc);
+        else if (ctl.pass)
+            hipLaunchKernelGGL((k_search_synth_f32<true, false, C>), dim3((unsigned)blocks, batch), dim3(256), 0, s,
+                               p->grid, sy, sh, ctl, n_clb, n_fcc);
+        else
+            hipLaunchKernelGGL((k_search_synth_f32<false, false, C>), dim3((unsigned)blocks, batch), dim3(256), 0,
+                               s, p->grid, sy, sh, ctl, n_clb, n_fcc);
+    };
+    if (p->desc.complex_atoms)
+        go(std::true_type{});
     else
-        hipLaunchKernelGGL((k_search_synth_f32<false, false>), dim3((unsigned)blocks, batch), dim3(256), 0, s,
-                           p->grid, sy, sh, ctl, n_clb, n_fcc);
+        go(std::false_type{});
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

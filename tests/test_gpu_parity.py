@@ -35,9 +35,10 @@ def A():
     return act
 
 
-def gpu_decompose(grid, signals, order, prec, dict_, refine_steps=30, cand_cap=0, support_cut=False):
+def gpu_decompose(grid, signals, order, prec, dict_, refine_steps=30, cand_cap=0, support_cut=False,
+                  complex_atoms=False):
     plan = A().Plan(grid, dict_=dict_, prec=prec, max_batch=signals.shape[0], cand_cap=cand_cap,
-                    refine_steps=refine_steps, support_cut=support_cut)
+                    refine_steps=refine_steps, support_cut=support_cut, complex_atoms=complex_atoms)
     out = plan.decompose(torch.from_numpy(signals), order)
     torch.cuda.synchronize()
     res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
@@ -45,12 +46,13 @@ def gpu_decompose(grid, signals, order, prec, dict_, refine_steps=30, cand_cap=0
     return res
 
 
-def hessian_condition(oracle, grid, r, theta0, theta):
+def hessian_condition(oracle, grid, r, theta0, theta, complex_atoms=False):
     """Condition number of the Hessian of J at theta in the refinement's
     scaled coordinates (central differences of the oracle's gradient), over
     the unfrozen axes; inf when the optimum sits on the grid hull."""
+    objective = oracle.objective_complex if complex_atoms else oracle.objective
     step, lo, hi = oracle.refine_box(grid)
-    h = oracle.refine_scales(grid, theta0)
+    h = oracle.refine_scales(grid, theta0, complex_atoms)
     free = [j for j in range(4) if h[j] > 0]
     if any(theta[j] <= lo[j] + 1e-12 * max(1, abs(lo[j])) or theta[j] >= hi[j] - 1e-12 * max(1, abs(hi[j]))
            for j in free):
@@ -59,8 +61,8 @@ def hessian_condition(oracle, grid, r, theta0, theta):
     for a, j in enumerate(free):
         e = np.zeros(4)
         e[j] = 1e-5 * h[j]
-        gp = oracle.objective(grid.fs, theta + e, r)[1] * h
-        gm = oracle.objective(grid.fs, theta - e, r)[1] * h
+        gp = objective(grid.fs, theta + e, r)[1] * h
+        gm = objective(grid.fs, theta - e, r)[1] * h
         H[a] = (gp - gm)[free] / 2e-5
     H = 0.5 * (H + H.T)
     w = np.abs(np.linalg.eigvalsh(H))
@@ -689,3 +691,233 @@ def test_lem_covering_families_is_exhaustive_on_gpu(oracle):
     th = np.array([[g.theta(int(i)) for i in row] for row in ref["index"]])
     np.testing.assert_allclose(gpu["theta"], th, rtol=0, atol=1e-12)
     np.testing.assert_allclose(gpu["energy"], ref["energy"], rtol=1e-11, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# complex (analytic) atoms
+# --------------------------------------------------------------------------
+
+def assert_complex_parity(gpu, ref, grid, oracle, signals, label, refine_steps):
+    """Complex-atom pursuit, order by order, as assert_decomposition_parity:
+    each GPU step against the oracle's step on the GPU's own residual
+    (selection by |<g_hat, r>|, refinement of its square, least-squares
+    amplitude pair), and the normalised residues of the two chains while they
+    hold the same atoms."""
+    step, _, _ = oracle.refine_box(grid)
+    B, order = ref["index"].shape
+    compared = 0
+    for b in range(B):
+        s = signals[b]
+        sn = float(np.linalg.norm(s))
+        np.testing.assert_allclose(gpu["energy"][b, 0], ref["energy"][b, 0], rtol=1e-12)
+        rg, rr, chain = s.copy(), s.copy(), True
+        for k in range(order):
+            gi = int(gpu["index"][b, k])
+            p = oracle.correlate_complex(grid, rg)
+            i_o, gap = oracle.argmax(p)
+            if gi != i_o:
+                assert gap <= GAP_EXCUSE, (label, b, k, gi, i_o, gap)
+                assert p[gi] >= (1 - 2 * GAP_EXCUSE) * p[i_o], (label, b, k, p[gi], p[i_o])
+            if chain and gi != int(ref["index"][b, k]):
+                ri = int(ref["index"][b, k])
+                p1 = oracle.correlate_complex(grid, rr, ri, 1)[0]
+                drift = float(np.linalg.norm(rg - rr))
+                assert ref["gap"][b, k] <= GAP_EXCUSE or ref["gap"][b, k] * p1 <= 2.0 * drift, \
+                    (label, b, k, gi, ri, ref["gap"][b, k], p1, drift)
+                chain = False
+            th_g = gpu["theta"][b, k]
+            th0 = oracle.grid_theta(grid, gi)
+            th_o, J_o, _ = oracle.refine_complex(grid, rg, th0, refine_steps)
+            scale = np.maximum(np.abs(th_o), step)
+            dth = np.abs(th_g - th_o) / scale
+            if not np.all(dth <= 1e-6):
+                th_long, _, _ = oracle.refine_complex(grid, rg, th0, 10 * max(refine_steps, 1))
+                converged = np.all(np.abs(th_long - th_o) <= 1e-8 * scale)
+                cond = hessian_condition(oracle, grid, rg, th0, th_o, complex_atoms=True)
+                assert not (converged and cond <= 1e8), (label, b, k, "converged", cond, dth)
+                J_g = oracle.objective_complex(grid.fs, th_g, rg)[0]
+                assert abs(J_g - J_o) <= 1e-6 * J_o + 1e-9 * sn * sn, (label, b, k, cond, J_g, J_o, dth)
+                chain = False
+            u, v = oracle.atom_complex(grid.fs, grid.n, th_g)
+            al_o, be_o = oracle.fit_complex(grid.fs, th_g, rg)
+            al_g, be_g = gpu["coef"][b, k]
+            w_o = al_o * u + be_o * v
+            w_g = al_g * u + be_g * v
+            assert np.linalg.norm(w_g - w_o) <= 1e-9 * np.linalg.norm(w_o) + 1e-12 * sn, \
+                (label, b, k, (al_g, be_g), (al_o, be_o))
+            rg = rg - w_g
+            if chain:
+                ur, vr = oracle.atom_complex(grid.fs, grid.n, ref["theta"][b, k])
+                rr = rr - (ref["coef_re"][b, k] * ur + ref["coef_im"][b, k] * vr)
+            e_own = float(rg @ rg)
+            assert abs(gpu["energy"][b, k + 1] - e_own) <= 1e-9 * e_own + 1e-12 * sn * sn, \
+                (label, b, k, gpu["energy"][b, k + 1], e_own)
+            if chain:
+                assert abs(gpu["energy"][b, k + 1] - ref["energy"][b, k + 1]) <= 1e-6 * sn * sn, \
+                    (label, b, k, gpu["energy"][b, k + 1], ref["energy"][b, k + 1])
+            compared += 1
+        np.testing.assert_allclose(gpu["approx"][b] + gpu["resid"][b], s, rtol=0, atol=1e-12 * np.abs(s).max())
+        np.testing.assert_allclose(gpu["resid"][b], rg, rtol=0, atol=1e-10 * sn)
+    return compared
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_complex_correlate_matches_oracle(oracle, prec, tol):
+    """|<g_hat, r>| of complex atoms, FP64 synthesis and the FP32 MFMA
+    factored synthesis (two accumulators of the same product), on the
+    65,536-atom grid and on a grid with partial tiles and n = 300."""
+    wl = W.plain_1x512()
+    g = wl.grid
+    r = wl.signals[0]
+    plan = A().Plan(g, dict_="synth", prec=prec, complex_atoms=True)
+    for begin, count in [(0, 4096), (31000, 2500), (g.size - 300, 300)]:
+        p_gpu = plan.act_correlate(r, begin, count).cpu().numpy()[0]
+        p_ref = oracle.correlate_complex(g, r, begin, count)
+        err = np.max(np.abs(p_gpu - p_ref)) / np.linalg.norm(r)
+        assert err <= tol, (prec, begin, err)
+    g2 = W.Grid(256.0, 300, W.Axis(0.0, 18 * 16 / 256.0, 18, True), W.Axis(2.0, 60.0, 70, False),
+                W.Axis(-15.0, 15.0, 9, False), W.Axis(math.log(0.05), 0.0, 15, False))
+    sig = np.random.default_rng(61).standard_normal((2, g2.n))
+    plan2 = A().Plan(g2, dict_="synth", prec=prec, max_batch=2, complex_atoms=True)
+    p = plan2.act_correlate(sig, 0, g2.size).cpu().numpy()
+    for b in range(2):
+        assert np.max(np.abs(p[b] - oracle.correlate_complex(g2, sig[b]))) <= tol * np.linalg.norm(sig[b])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("steps", [30, 0])
+def test_complex_decompose_matches_oracle(oracle, prec, steps):
+    wl = W.plain_1x512()
+    order = wl.order if steps else 8
+    ref = oracle.decompose_complex(wl.grid, wl.signals, order, refine_steps=steps)
+    gpu = gpu_decompose(wl.grid, wl.signals, order, prec, "synth", refine_steps=steps, complex_atoms=True)
+    assert gpu["coef"].shape == (1, order, 2)
+    assert assert_complex_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, steps) == order
+
+
+def test_complex_batch_partial_tiles_and_edge_channels(oracle):
+    """Several channels on the n = 300 grid (partial stage, cl blocks and f_c
+    chunks), with an all-zero channel and one holding a NaN."""
+    g = W.Grid(256.0, 300, W.Axis(0.0, 18 * 16 / 256.0, 18, True), W.Axis(2.0, 60.0, 70, False),
+               W.Axis(-15.0, 15.0, 9, False), W.Axis(math.log(0.05), 0.0, 15, False))
+    rng = np.random.default_rng(62)
+    sig = rng.standard_normal((4, g.n))
+    sig[2] = 0.0
+    sig[3, 40] = np.nan
+    for prec in ("f64", "f32"):
+        gpu = gpu_decompose(g, sig, 4, prec, "synth", refine_steps=30, complex_atoms=True)
+        ref = oracle.decompose_complex(g, sig[:2], 4, refine_steps=30)
+        assert_complex_parity({k: (v[:2] if v is not None else None) for k, v in gpu.items()},
+                              ref, g, oracle, sig[:2], "cplx-" + prec, 30)
+        assert gpu["flags"][3] & A().FLAG_NONFINITE
+        assert gpu["flags"][2] == 0
+        np.testing.assert_array_equal(gpu["energy"][2], 0.0)
+        np.testing.assert_array_equal(gpu["coef"][2], 0.0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_complex_atoms_remove_any_phase_on_gpu(oracle, prec):
+    """A near-analytic on-grid chirplet at an arbitrary carrier phase is
+    selected and removed in one order (residual energy <= 1e-20 of the
+    signal's) by the amplitude-and-phase fit."""
+    g = W.eeg_grid(512, 32, 16, 16, 8)
+    rng = np.random.default_rng(63)
+    for psi in (0.3, 1.9, 4.0):
+        while True:
+            j = int(rng.integers(g.size))
+            th = g.theta(j)
+            dt = math.exp(th[3])
+            if th[1] * dt >= 2.0 and 8 * dt <= th[0] <= g.n / g.fs - 8 * dt:
+                break
+        u, v = oracle.atom_complex(g.fs, g.n, th)
+        s = 1.7 * (math.cos(psi) * u - math.sin(psi) * v)
+        gpu = gpu_decompose(g, s[None, :], 1, prec, "synth", refine_steps=30, complex_atoms=True)
+        assert gpu["index"][0, 0] == j
+        assert gpu["energy"][0, 1] <= 1e-20 * gpu["energy"][0, 0]
+        np.testing.assert_allclose(gpu["coef"][0, 0], [1.7 * math.cos(psi), -1.7 * math.sin(psi)], rtol=1e-9)
+
+
+def test_complex_refine_and_reconstruct(oracle):
+    """act_refine of a complex plan maximises |<g_hat, r>|^2 like the oracle
+    wherever the oracle's 30 iterations have converged (its result does not
+    move with 300); elsewhere (long chirps through zero frequency, where the
+    complex score is far from the real one's optimum) the two iterations need
+    not follow the same path, and the GPU's J must not fall below its start.
+    act_reconstruct sums alpha E cos phi + beta E sin phi."""
+    wl = W.refine_pairs(pairs=24)
+    g = wl.grid
+    plan = A().Plan(g, dict_="synth", prec="f64", max_batch=2, complex_atoms=True)
+    th, J, _ = plan.act_refine(wl.signals, wl.theta0, 30)
+    th, J = th.cpu().numpy(), J.cpu().numpy()
+    step, _, _ = oracle.refine_box(g)
+    tight = 0
+    for p in range(wl.signals.shape[0]):
+        th_o, J_o, _ = oracle.refine_complex(g, wl.signals[p], wl.theta0[p], 30)
+        th_l, J_l, _ = oracle.refine_complex(g, wl.signals[p], wl.theta0[p], 300)
+        scale = np.maximum(np.abs(th_o), step)
+        if abs(J_l - J_o) <= 1e-12 * J_l and np.all(np.abs(th_l - th_o) <= 1e-8 * scale):
+            np.testing.assert_allclose(J[p], J_o, rtol=1e-9)
+            assert np.all(np.abs(th[p] - th_o) <= 1e-6 * scale), (p, th[p], th_o)
+            tight += 1
+        else:
+            J0 = oracle.objective_complex(g.fs, wl.theta0[p], wl.signals[p])[0]
+            assert J[p] >= J0 * (1 - 1e-12), (p, J[p], J0)
+    assert tight >= 16, tight
+    rng = np.random.default_rng(64)
+    theta = th[:12].reshape(2, 6, 4)
+    coef = rng.standard_normal((2, 6, 2))
+    out = plan.act_reconstruct(theta, coef).cpu().numpy()
+    for b in range(2):
+        ref = np.zeros(g.n)
+        for k in range(6):
+            u, v = oracle.atom_complex(g.fs, g.n, theta[b, k])
+            ref += coef[b, k, 0] * u + coef[b, k, 1] * v
+        np.testing.assert_allclose(out[b], ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_complex_invalid_combinations_are_refused():
+    act = A()
+    g = W.eeg_grid(512, 4, 4, 4, 2)
+    for kw in (dict(dict_="table", prec="f32"), dict(dict_="synth", prec="f16"),
+               dict(dict_="synth", prec="f64", prior_act=True), dict(dict_="synth", prec="f32", ragged=True)):
+        with pytest.raises(act.ActError) as e:
+            act.Plan(g, complex_atoms=True, **kw)
+        assert e.value.status == act.ACT_ERR_UNSUPPORTED, kw
+    plan = act.Plan(g, dict_="synth", prec="f64", complex_atoms=True)
+    with pytest.raises(act.ActError) as e:
+        plan.act_value_and_grad(torch.zeros(1, g.n, dtype=torch.float64, device="cuda"),
+                                torch.zeros(1, 4, dtype=torch.float64))
+    assert e.value.status == act.ACT_ERR_UNSUPPORTED
+
+
+def test_complex_full_size_64x2048(oracle):
+    """64 channels x N = 2048 on the 2,097,152-atom grid with complex atoms
+    (FP32 MFMA synthesis + FP64 rescoring): per order and for sampled
+    channels, no sampled atom beats the winner's oracle score, the refined
+    parameters equal the oracle's refinement from the same grid point, and
+    the amplitude pair and energies follow."""
+    wl = W.batched_64x2048()
+    g = wl.grid
+    order = 2
+    gpu = gpu_decompose(g, wl.signals, order, "f32", "synth", refine_steps=30, complex_atoms=True)
+    step, _, _ = oracle.refine_box(g)
+    rng = np.random.default_rng(65)
+    sample = rng.choice(g.size, 1500, replace=False)
+    for b in (0, 31, 63):
+        r = wl.signals[b].copy()
+        for k in range(order):
+            rn = float(np.linalg.norm(r))
+            i = int(gpu["index"][b, k])
+            p_win = oracle.correlate_complex(g, r, i, 1)[0]
+            p_s = np.array([oracle.correlate_complex(g, r, int(j), 1)[0] for j in sample])
+            assert np.all(p_s <= p_win + 1e-12 * rn)
+            th, J, _ = oracle.refine_complex(g, r, oracle.grid_theta(g, i), 30)
+            dth = np.abs(gpu["theta"][b, k] - th)
+            assert np.all(dth <= 1e-6 * np.maximum(np.abs(th), step)), (b, k, dth)
+            ab = oracle.fit_complex(g.fs, gpu["theta"][b, k], r)
+            np.testing.assert_allclose(gpu["coef"][b, k], ab, rtol=1e-6, atol=1e-9 * np.abs(ab).max())
+            u, v = oracle.atom_complex(g.fs, g.n, gpu["theta"][b, k])
+            r = r - (gpu["coef"][b, k, 0] * u + gpu["coef"][b, k, 1] * v)
+            assert abs(gpu["energy"][b, k + 1] - float(r @ r)) <= 1e-6 * float(r @ r)
+    assert np.all(np.diff(gpu["energy"], axis=1) <= 0)
+    assert np.all(gpu["flags"] & A().FLAG_CAND_OVERFLOW == 0)
