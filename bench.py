@@ -45,6 +45,9 @@ WORKLOADS = {
     # support-truncated: GMAC/s still counts the dense work (dense-equivalent rate)
     "f16-64x2048-synth-cut": ("batched_64x2048", dict(dict_="synth", prec="f16", support_cut=True), "mfma_f16", 0),
     "plain-1x512": ("plain_1x512", dict(dict_="synth", prec="f64"), "f64", 0),
+    # complex (analytic) atoms: two correlations per atom (real and imaginary part)
+    "complex-f32-64x2048-synth": ("batched_64x2048", dict(dict_="synth", prec="f32", complex_atoms=True),
+                                  "mfma_f32", 0),
 }
 KERNELS = {("table", "f32"): ("k_search_f32_table", "act_search_f32t.hip"),
            ("table", "bf16"): ("k_search_bf16_table", "act_search_bf16.hip"),
@@ -140,7 +143,8 @@ def run_workload(name: str, steps: int, warmup: int):
         "dtype": plan_kw["prec"],
         "config": {"workload": wl.name, "atoms": g.size, "n_samples": g.n, "channels": B,
                    "order": order, "dict": plan_kw["dict_"], "refine_steps": wl.refine_steps,
-                   "support_cut": bool(plan_kw.get("support_cut", False)), "parallelism": "single-gpu"},
+                   "support_cut": bool(plan_kw.get("support_cut", False)),
+                   "complex_atoms": bool(plan_kw.get("complex_atoms", False)), "parallelism": "single-gpu"},
         "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
         "candidate_overflow_channels": int(((flags & act.FLAG_CAND_OVERFLOW) != 0).sum()),
     }
@@ -161,7 +165,8 @@ def run_workload(name: str, steps: int, warmup: int):
     elif kind in ("mfma_f32", "mfma_f16"):
         # factored synthesis: the matrix cores execute 2 x (atoms x N x B)
         # multiply-adds; the roofline counts the dense correlation's flops
-        algo = 2.0 * g.size * g.n * B
+        # (complex atoms: both parts, 2 x atoms x N x B multiply-adds)
+        algo = 2.0 * g.size * g.n * B * (2 if plan_kw.get("complex_atoms") else 1)
         achieved = algo / (search_ms * 1e-3) / 1e12
         peak = PEAK_TFLOPS[kind[5:] + "_mfma"]
         res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
@@ -383,7 +388,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
     ap.add_argument("--companions", default="fp32-1x2048-synth,bf16-64x2048,f16-64x2048-synth,"
-                                            "f16-64x2048-synth-cut,ragged-1000-f16,ragged-1000-f16-cut",
+                                            "f16-64x2048-synth-cut,complex-f32-64x2048-synth,"
+                                            "ragged-1000-f16,ragged-1000-f16-cut",
                     help="comma-separated companion workloads of the default run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
