@@ -184,6 +184,26 @@ __device__ __forceinline__ void h16_tile(const GridDev& g, const H16Dev& hd, con
         fm_ss = hd.S + (size_t)(fm_ok ? fc : 0) * W + (g.n_pad - t.m);
     }
     for (int n0 = n_first; n0 < n_end; n0 += H_KS) {
+        constexpr int KB = 2;
+        static_assert(H_KSTEPS == 4 * KB, "four blocks per stage");
+        const bool run = n0 + H_KS - 1 >= t.m - D_w && n0 <= t.m + D_w;
+        f16x8 ua0[H_WRB][KB], va0[H_WRB][KB], ua1[H_WRB][KB], va1[H_WRB][KB];
+        auto load_blk = [&](f16x8 (&ua)[H_WRB][KB], f16x8 (&va)[H_WRB][KB], int blk) {
+            const int eb = n0 + 16 * KB * blk - t.m + g.n_pad + 8 * KB * (lane >> 5);
+#pragma unroll
+            for (int rb = 0; rb < H_WRB; ++rb) {
+                const f16x8* up = reinterpret_cast<const f16x8*>(hd.U + (size_t)arow[rb] * W + eb);
+                const f16x8* vp = reinterpret_cast<const f16x8*>(hd.V + (size_t)arow[rb] * W + eb);
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    ua[rb][j] = up[j];
+                    va[rb][j] = vp[j];
+                }
+            }
+        };
+        // the first block's A fragments load while B is formed
+        if (run) load_blk(ua0, va0, 0);
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
         // ---- B stage: each thread forms 8-sample chunks of its column; k-slot
         // order: in each 32-sample block, half h and k-step s' of a lane hold
@@ -229,24 +249,11 @@ __device__ __forceinline__ void h16_tile(const GridDev& g, const H16Dev& hd, con
 
         // ---- MFMA over the stage: four blocks of two k-steps in two register
         // buffers, each block's A fragments loaded while the previous block
-        // runs; a wave whose rows' supports miss the stage skips it
-        if (n0 + H_KS - 1 >= t.m - D_w && n0 <= t.m + D_w) {
-            constexpr int KB = 2;
-            static_assert(H_KSTEPS == 4 * KB, "four blocks per stage");
-            f16x8 ua0[H_WRB][KB], va0[H_WRB][KB], ua1[H_WRB][KB], va1[H_WRB][KB];
-            auto load_blk = [&](f16x8 (&ua)[H_WRB][KB], f16x8 (&va)[H_WRB][KB], int blk) {
-                const int eb = n0 + 16 * KB * blk - t.m + g.n_pad + 8 * KB * (lane >> 5);
-#pragma unroll
-                for (int rb = 0; rb < H_WRB; ++rb) {
-                    const f16x8* up = reinterpret_cast<const f16x8*>(hd.U + (size_t)arow[rb] * W + eb);
-                    const f16x8* vp = reinterpret_cast<const f16x8*>(hd.V + (size_t)arow[rb] * W + eb);
-#pragma unroll
-                    for (int j = 0; j < KB; ++j) {
-                        ua[rb][j] = up[j];
-                        va[rb][j] = vp[j];
-                    }
-                }
-            };
+        // runs; a wave whose rows' supports miss the stage skips it.  The
+        // scheduling barriers keep that order: at this register budget the
+        // compiler would otherwise move each load next to its first use and
+        // wait out the full L2 latency before every block.
+        if (run) {
             auto run_blk = [&](const f16x8 (&ua)[H_WRB][KB], const f16x8 (&va)[H_WRB][KB], int blk) {
 #pragma unroll
                 for (int sp = 0; sp < KB; ++sp) {
@@ -263,12 +270,16 @@ __device__ __forceinline__ void h16_tile(const GridDev& g, const H16Dev& hd, con
                     }
                 }
             };
-            load_blk(ua0, va0, 0);
             load_blk(ua1, va1, 1);
+            __builtin_amdgcn_sched_barrier(0);
             run_blk(ua0, va0, 0);
+            __builtin_amdgcn_sched_barrier(0);
             load_blk(ua0, va0, 2);
+            __builtin_amdgcn_sched_barrier(0);
             run_blk(ua1, va1, 1);
+            __builtin_amdgcn_sched_barrier(0);
             load_blk(ua1, va1, 3);
+            __builtin_amdgcn_sched_barrier(0);
             run_blk(ua0, va0, 2);
             run_blk(ua1, va1, 3);
         }
