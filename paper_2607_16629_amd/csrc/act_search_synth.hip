@@ -85,7 +85,19 @@ __device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __
                 if constexpr (CPLX) totb[cb][v] = 0.0f;
             }
 
+        // A operands of one 16-sample group: rows past the dictionary read row
+        // 0 (their scores are masked in the epilogue), so the loads need no branch
+        auto load_a = [&](f32x4 (&a)[4], int n0, int s16) {
+            const int e0 = n0 + s16 + 8 * h - m + g.n_pad;  // factor column of this lane's 8 samples
+            a[0] = *reinterpret_cast<const f32x4*>(urow + e0);
+            a[1] = *reinterpret_cast<const f32x4*>(urow + e0 + 4);
+            a[2] = *reinterpret_cast<const f32x4*>(vrow + e0);
+            a[3] = *reinterpret_cast<const f32x4*>(vrow + e0 + 4);
+        };
         for (int n0 = 0; n0 < ta.n_pad_ch; n0 += SY_STAGE) {
+            f32x4 abuf[2][4];
+            load_a(abuf[0], n0, 0);  // in flight while B is formed
+            __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
             // B operand of this stage: C_fc(n-m) r(n) and -S_fc(n-m) r(n)
             for (int q = threadIdx.x; q < SY_COLS * SY_STAGE; q += 256) {
@@ -109,15 +121,14 @@ __device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __
                     acc[cb][v] = 0.0f;
                     if constexpr (CPLX) accb[cb][v] = 0.0f;
                 }
+            // groups of 16 samples, the next group's A loaded while this one runs
+            // (the scheduling barriers keep the loads ahead of the MFMAs)
+#pragma unroll
             for (int s16 = 0; s16 < SY_STAGE; s16 += 16) {
-                const int e0 = n0 + s16 + 8 * h - m + g.n_pad;  // factor column of this lane's 8 samples
-                f32x4 ua = {0, 0, 0, 0}, ub = {0, 0, 0, 0}, va = {0, 0, 0, 0}, vb = {0, 0, 0, 0};
-                if (row_ok) {
-                    ua = *reinterpret_cast<const f32x4*>(urow + e0);
-                    ub = *reinterpret_cast<const f32x4*>(urow + e0 + 4);
-                    va = *reinterpret_cast<const f32x4*>(vrow + e0);
-                    vb = *reinterpret_cast<const f32x4*>(vrow + e0 + 4);
-                }
+                if (s16 + 16 < SY_STAGE) load_a(abuf[((s16 >> 4) + 1) & 1], n0, s16 + 16);
+                __builtin_amdgcn_sched_barrier(0);
+                const f32x4 ua = abuf[(s16 >> 4) & 1][0], ub = abuf[(s16 >> 4) & 1][1];
+                const f32x4 va = abuf[(s16 >> 4) & 1][2], vb = abuf[(s16 >> 4) & 1][3];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
                     const int col = cb * 32 + (lane & 31);
@@ -137,6 +148,7 @@ __device__ void synth_tile(const GridDev& g, const SynthDev& sy, const float* __
                         }
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
