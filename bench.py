@@ -98,6 +98,9 @@ def cpu_baseline(wl, seconds: float):
                       f"[0, {count}) of {g.size} ({dt:.1f} s, OpenMP over atoms)"}
 
 
+TUNE = True  # pick the search's launch shape with act_tune before timing (--no-tune: built-in defaults)
+
+
 def run_workload(name: str, steps: int, warmup: int):
     import torch
     from paper_2607_16629_amd import act
@@ -116,6 +119,7 @@ def run_workload(name: str, steps: int, warmup: int):
         resid.copy_(sig)
         plan.act_decompose(resid, order, out)
 
+    shape = plan.act_tune(sig, reps=2) if TUNE else None  # untimed: shape choice on the input
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -147,6 +151,7 @@ def run_workload(name: str, steps: int, warmup: int):
                    "complex_atoms": bool(plan_kw.get("complex_atoms", False)), "parallelism": "single-gpu"},
         "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
         "candidate_overflow_channels": int(((flags & act.FLAG_CAND_OVERFLOW) != 0).sum()),
+        "launch_shape": shape,
     }
     kname, ksrc = KERNELS[(plan_kw["dict_"], plan_kw["prec"])]
     if kind == "hbm":
@@ -210,6 +215,7 @@ def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False):
         resid.copy_(sig)
         plan.act_decompose_ragged(resid, lt, ot, order, out)
 
+    shape = plan.act_tune(sig, reps=1, lengths=lt, offsets=ot) if TUNE else None
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -243,6 +249,7 @@ def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False):
                        "refine_steps": wl.refine_steps, "parallelism": "single-gpu"},
             "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
             "candidate_overflow_channels": int(((flags & act.FLAG_CAND_OVERFLOW) != 0).sum()),
+            "launch_shape": shape,
             "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                          "frac": round(achieved / peak, 4), "traffic": None,
                          "kernel": kname + "_ragged", "avg_launch_ms": round(search_ms, 5),
@@ -279,6 +286,8 @@ def run_sweep(steps: int, warmup: int):
         return (time.perf_counter() - t0) / reps, e / e[:, :1]
 
     new_plan = act.Plan(g, dict_="synth", prec="f32", max_batch=B, refine_steps=wl.refine_steps)
+    if TUNE:
+        new_plan.act_tune(sig, reps=2)
     t_new, e_new = timed_run(new_plan, order, steps, warmup)
     new_plan.close()
     old_plan = act.Plan(g, dict_="synth", prec="f64", max_batch=B, refine_steps=wl.refine_steps, prior_act=True)
@@ -391,9 +400,12 @@ def main():
                                             "f16-64x2048-synth-cut,complex-f32-64x2048-synth,"
                                             "ragged-1000-f16,ragged-1000-f16-cut",
                     help="comma-separated companion workloads of the default run")
+    ap.add_argument("--no-tune", action="store_true", help="time the built-in launch shapes (no act_tune)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    global TUNE
+    TUNE = not args.no_tune
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)

@@ -256,6 +256,42 @@ act_status act_reconstruct(act_plan_t plan, int32_t batch, int32_t order, const 
 act_status act_correlate(act_plan_t plan, int32_t batch, const double* resid_dev,
                          int64_t atom_begin, int64_t atom_count, double* score_dev, void* stream);
 
+/* Launch shape of the coarse search kernel (a tuning choice; results do not
+ * depend on it: the certified selection is exact for every shape). */
+typedef struct {
+    int32_t grid_per_cu;    /* persistent search workgroups per compute unit */
+    int32_t chan_per_fc;    /* FP16 synthesis of several channels: channels that share an f_c among a
+                               tile's 128 columns (power of two <= 64); 0 for the other searches */
+    int32_t from_cache;     /* 1: taken from the cache file without timing */
+    int32_t reserved;
+    double ms;              /* mean search time per launch with this shape */
+} act_launch_shape;
+
+/* Autotuner of the batched search's tile and grid shapes (the stacked channels
+ * of Sec. V-A and uneven batches): times the plan's pass-0 coarse search on
+ * `batch` channels of resid_dev for every candidate shape -- workgroups per CU
+ * of the persistent grid and, for the FP16 synthesis of several channels, the
+ * channels per f_c of a tile -- `reps` launches each, and keeps the fastest for
+ * later act_decompose / act_correlate calls with this batch size (captured
+ * graphs are rebuilt).
+ *   resid_dev, len_dev, off_dev  as act_decompose; read only.  The plan's
+ *               search copy of the residual and its candidate workspace are
+ *               overwritten.
+ *   reps        timed launches per candidate (1..100).
+ *   cache_path  text file of earlier choices or NULL: a line for the same
+ *               device, plan shape and batch is applied without timing; a new
+ *               choice is appended (one line: device, CU count, dict, prec,
+ *               n_samples, axis counts, ragged, divisor, support_cut,
+ *               complex_atoms, batch, grid_per_cu, chan_per_fc, ms).
+ *   out         the choice, or NULL.
+ * Synchronises `stream`.  Errors: ACT_ERR_INVALID (batch outside
+ * [1, max_batch], reps outside [1, 100], NULL residual, ragged pointers
+ * missing), ACT_ERR_UNSUPPORTED (prior_act plans: their search has no tunable
+ * shape), ACT_ERR_HIP. */
+act_status act_tune(act_plan_t plan, int32_t batch, const int32_t* len_dev, const int64_t* off_dev,
+                    const double* resid_dev, int32_t reps, const char* cache_path, act_launch_shape* out,
+                    void* stream);
+
 /* Phase timing of act_decompose, for measurement.  While enabled, every
  * launch of each phase of an order -- 0: search, 1: exact-threshold rerun,
  * 2: FP64 rescoring, 3: select/refine/update -- is bracketed by HIP events on

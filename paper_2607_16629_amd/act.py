@@ -53,11 +53,16 @@ class _PlanDesc(ctypes.Structure):
 
 
 EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_decompose", "act_lem_decompose",
-           "act_refine", "act_value_and_grad", "act_reconstruct", "act_correlate", "act_timing_enable",
-           "act_timing_read", "act_status_string", "act_last_error")
+           "act_refine", "act_value_and_grad", "act_reconstruct", "act_correlate", "act_tune",
+           "act_timing_enable", "act_timing_read", "act_status_string", "act_last_error")
 PHASES = ("search", "rerun", "rescore", "select_refine_update")
 
 _lib = None
+
+
+class _LaunchShape(ctypes.Structure):
+    _fields_ = [("grid_per_cu", ctypes.c_int32), ("chan_per_fc", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class _LemDesc(ctypes.Structure):
@@ -105,6 +110,8 @@ def load() -> ctypes.CDLL:
     lib.act_reconstruct.restype = ctypes.c_int
     lib.act_correlate.argtypes = [vp, i32, vp, i64, i64, vp, vp]
     lib.act_correlate.restype = ctypes.c_int
+    lib.act_tune.argtypes = [vp, i32, vp, vp, vp, i32, ctypes.c_char_p, ctypes.POINTER(_LaunchShape), vp]
+    lib.act_tune.restype = ctypes.c_int
     lib.act_timing_enable.argtypes = [vp, i32]
     lib.act_timing_enable.restype = ctypes.c_int
     lib.act_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64)]
@@ -343,6 +350,24 @@ class Plan:
         _check(load().act_reconstruct(self._h, B, order, _ptr(theta), _ptr(coef), None, None,
                                       _ptr(out), _stream()))
         return out
+
+    def act_tune(self, resid, reps: int = 3, cache: Optional[str] = None, lengths=None, offsets=None) -> dict:
+        """Times the search's launch shapes on `resid` (plain: [B, N] f64; ragged:
+        the packed signals with lengths/offsets) and keeps the fastest for this
+        batch size; `cache` is an optional text file of earlier choices."""
+        if self.ragged:
+            resid = _device_tensor(resid, torch.float64).reshape(-1)
+            lengths = _device_tensor(lengths, torch.int32)
+            offsets = _device_tensor(offsets, torch.int64)
+            B, lp, op = lengths.shape[0], _ptr(lengths), _ptr(offsets)
+        else:
+            resid = _device_tensor(resid, torch.float64).reshape(-1, self.grid.n)
+            B, lp, op = resid.shape[0], None, None
+        shape = _LaunchShape()
+        _check(load().act_tune(self._h, B, lp, op, _ptr(resid), int(reps),
+                               cache.encode() if cache else None, ctypes.byref(shape), _stream()))
+        return {"grid_per_cu": shape.grid_per_cu, "chan_per_fc": shape.chan_per_fc,
+                "from_cache": bool(shape.from_cache), "ms": shape.ms}
 
     def act_correlate(self, resid, begin: int, count: int) -> torch.Tensor:
         resid = _device_tensor(resid, torch.float64).reshape(-1, self.grid.n)

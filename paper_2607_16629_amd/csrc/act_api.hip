@@ -112,6 +112,7 @@ extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* 
     p->search_resid = resid_dev;
     p->call_len = len_dev;
     p->call_off = (const long long*)off_dev;
+    select_shape(p, batch);
     auto enqueue_all = [&](hipStream_t q) -> act_status {
         act_status st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, q);
         if (st != ACT_OK) return st;
@@ -293,6 +294,7 @@ extern "C" act_status act_correlate(act_plan_t p, int32_t batch, const double* r
     ACT_REQUIRE(resid_dev && score_dev, "act_correlate: NULL pointer");
     hipStream_t s = (hipStream_t)stream;
     p->last_stream = s;
+    select_shape(p, batch);
     if (p->desc.prec != ACT_PREC_F64) {
         act_status st = launch_to_shadow(p, batch, resid_dev, s);
         if (st != ACT_OK) return st;

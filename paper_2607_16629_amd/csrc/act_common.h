@@ -257,6 +257,11 @@ struct act_plan_s {
 
     hipStream_t last_stream = nullptr;
 
+    // search launch shapes chosen by act_tune, per batch size; `shape` is the
+    // one the launchers use (zeros: built-in defaults)
+    std::vector<std::pair<int, act_launch_shape>> shapes;
+    act_launch_shape shape{};
+
     // captured act_decompose sequences, keyed by every argument (small LRU)
     struct GraphEntry {
         std::vector<uintptr_t> key;
@@ -277,6 +282,11 @@ struct act_plan_s {
 };
 
 namespace act {
+// launch shapes (act_tune.hip): select the tuned shape of a batch size, and the
+// persistent grid of a search kernel (workgroups per CU, default `def`)
+void select_shape(act_plan_s* p, int batch);
+long long grid_cap(const act_plan_s* p, int def);
+int device_cus();
 // search launchers (act_search.hip)
 act_status launch_search(act_plan_s* p, int batch, int pass, hipStream_t s);
 act_status launch_correlate(act_plan_s* p, int batch, const double* resid, long long begin,

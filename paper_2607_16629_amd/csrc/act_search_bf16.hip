@@ -192,7 +192,7 @@ act_status launch_search_bf16t(act_plan_s* p, int batch, const SearchCtl& ctl, h
         tc = (ctl.dump_begin + ctl.dump_count + BF_TILE - 1) / BF_TILE - tb;
     }
     long long blocks = tc;
-    const long long cap = (long long)device_cus() * 2;
+    const long long cap = grid_cap(p, 2);
     blocks = blocks < cap ? blocks : cap;
     const u16x8* table = (const u16x8*)p->table;
     const unsigned short* sh = (const unsigned short*)p->shadow;

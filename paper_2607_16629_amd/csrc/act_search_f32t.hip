@@ -113,7 +113,9 @@ static void launch_f32t(act_plan_s* p, int batch, hipStream_t s, const SearchCtl
     const long long total = ctl.dump ? ctl.dump_count : p->atoms;
     const long long nbatch = (total + (64 / BT) - 1) / (64 / BT);
     long long blocks = (nbatch + 3) / 4;
-    blocks = blocks < (long long)cus * 8 ? blocks : (long long)cus * 8;
+    const long long cap = grid_cap(p, 8);
+    (void)cus;
+    blocks = blocks < cap ? blocks : cap;
     if (blocks < 1) blocks = 1;
     if (ctl.pass)
         hipLaunchKernelGGL((k_search_f32_table<NCH, BT, true>), dim3((unsigned)blocks, groups), dim3(256), 0,

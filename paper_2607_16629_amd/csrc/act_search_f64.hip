@@ -56,7 +56,7 @@ act_status launch_search_f64(act_plan_s* p, int batch, const SearchCtl& ctl, con
     // ragged plans: every channel's dictionary is at most the widest one
     const long long total = ctl.dump ? ctl.dump_count : p->atoms;
     long long blocks = (total + 255) / 256;
-    const long long cap = (long long)device_cus() * 16;
+    const long long cap = grid_cap(p, 16);
     blocks = blocks < cap ? blocks : cap;
     if (blocks < 1) blocks = 1;
     const bool cx = p->desc.complex_atoms != 0;

@@ -620,7 +620,7 @@ act_status launch_search_h16(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     const int n_rb = (p->n_cl + H_RW - 1) / H_RW;
     if (p->desc.ragged) {
         const int n_fg = (n_fc + 1) / 2;
-        const unsigned blocks = (unsigned)device_cus() * 2;
+        const unsigned blocks = (unsigned)grid_cap(p, 2);
         if (ctl.pass)
             hipLaunchKernelGGL((k_search_h16_ragged<true>), dim3(blocks), dim3(256), 0, s, p->grid, hd, ctl, batch,
                                n_rb, n_fg, p->items);
@@ -630,16 +630,18 @@ act_status launch_search_h16(act_plan_s* p, int batch, const SearchCtl& ctl, hip
         ACT_HIP(hipGetLastError());
         return ACT_OK;
     }
-    // one channel: 64 f_c columns; several: cpf channels x 128/cpf f_c
+    // one channel: 64 f_c columns; several: cpf channels x 128/cpf f_c (by
+    // default the smallest power of two covering the batch, at most 64)
     const bool multi = batch > 1;
     int cpf = 1;
     while (multi && cpf < batch && cpf < 64) cpf *= 2;
+    if (multi && p->shape.chan_per_fc > 0) cpf = p->shape.chan_per_fc;
     const int TC = multi ? 128 : 64;
     const int n_fg = (n_fc + TC / cpf - 1) / (TC / cpf);
     const int n_bg = (batch + cpf - 1) / cpf;
     const long long tiles = (long long)p->grid.cnt[0] * n_rb * n_fg * n_bg;
     long long blocks = (tiles + 7) / 8 * 8;
-    const long long cap = (long long)device_cus() * 2;
+    const long long cap = grid_cap(p, 2);  // a multiple of 8 (XCD dealing)
     blocks = blocks < cap ? blocks : cap;
     const dim3 grid((unsigned)blocks), blk(256);
 #define H16_LAUNCH(WCB, RR, DD)                                                                      \

@@ -328,7 +328,7 @@ act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ct
     const int n_fcc = (p->grid.cnt[1] + SY_COLS - 1) / SY_COLS;
     const float* sh = (const float*)p->shadow;
     if (p->desc.ragged) {
-        const unsigned blocks = (unsigned)device_cus() * 2;
+        const unsigned blocks = (unsigned)grid_cap(p, 2);
         if (ctl.pass)
             hipLaunchKernelGGL((k_search_synth_f32_ragged<true>), dim3(blocks), dim3(256), 0, s, p->grid, sy,
                                sh, ctl, batch, n_clb, n_fcc, p->items);
@@ -340,7 +340,7 @@ act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ct
     }
     const long long tiles = (long long)p->grid.cnt[0] * n_clb * n_fcc;
     long long blocks = tiles;
-    const long long cap = (long long)device_cus() * 4;
+    const long long cap = grid_cap(p, 4);
     blocks = blocks < cap ? blocks : cap;
     auto go = [&](auto cplx) {
         constexpr bool C = decltype(cplx)::value;

@@ -45,7 +45,8 @@ def test_library_exports_every_declared_symbol(lib):
 def test_struct_layout_matches_header(tmp_path):
     """Sizes and field offsets of the binding's structs equal the C header's,
     as compiled by gcc from include/act.h."""
-    fields = {"act_axis": A._Axis, "act_grid": A._Grid, "act_plan_desc": A._PlanDesc}
+    fields = {"act_axis": A._Axis, "act_grid": A._Grid, "act_plan_desc": A._PlanDesc,
+              "act_launch_shape": A._LaunchShape, "act_lem_desc": A._LemDesc}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "act.h"', "int main(void) {"]
     for cname, py in fields.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -99,6 +100,7 @@ def test_null_arguments_rejected(lib):
     assert lib.act_reconstruct(None, 1, 1, None, None, None, None, None, None) == A.ACT_ERR_INVALID
     assert lib.act_value_and_grad(None, 1, 0, None, None, None, None, None, None) == A.ACT_ERR_INVALID
     assert lib.act_correlate(None, 1, None, 0, 1, None, None) == A.ACT_ERR_INVALID
+    assert lib.act_tune(None, 1, None, None, None, 3, None, None, None) == A.ACT_ERR_INVALID
     assert lib.act_plan_query(None, 0) == -1
     lib.act_plan_destroy(None)
 

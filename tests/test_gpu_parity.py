@@ -921,3 +921,47 @@ def test_complex_full_size_64x2048(oracle):
             assert abs(gpu["energy"][b, k + 1] - float(r @ r)) <= 1e-6 * float(r @ r)
     assert np.all(np.diff(gpu["energy"], axis=1) <= 0)
     assert np.all(gpu["flags"] & A().FLAG_CAND_OVERFLOW == 0)
+
+
+# --------------------------------------------------------------------------
+# launch-shape autotuner
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,dict_", [("f32", "table"), ("bf16", "table"), ("f16", "synth"), ("f32", "synth")])
+def test_tuned_shapes_change_no_result(oracle, prec, dict_, tmp_path):
+    """act_tune picks a launch shape by timing; decompositions with the tuned
+    shape are bit-identical to the default shape's, the choice is cached per
+    (device, plan shape, batch) and reapplied from the cache without timing."""
+    g = W.eeg_grid(512, 32, 16, 16, 8)
+    wl = W.batched_64x2048(channels=6, grid=g, order=4)
+    sig = torch.from_numpy(wl.signals)
+    plan = A().Plan(g, dict_=dict_, prec=prec, max_batch=6, refine_steps=30)
+    ref = {k: v.cpu().numpy() for k, v in plan.decompose(sig, 4).items() if v is not None}
+    cache = str(tmp_path / "tune.txt")
+    shape = plan.act_tune(sig, reps=2, cache=cache)
+    assert shape["grid_per_cu"] >= 1 and shape["ms"] > 0 and not shape["from_cache"]
+    if prec == "f16":
+        assert shape["chan_per_fc"] in (1, 2, 4, 8)
+    got = {k: v.cpu().numpy() for k, v in plan.decompose(sig, 4).items() if v is not None}
+    for k in ("index", "theta", "coef", "energy", "resid", "flags"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+    again = plan.act_tune(sig, reps=2, cache=cache)
+    assert again["from_cache"] and again["grid_per_cu"] == shape["grid_per_cu"]
+    assert again["chan_per_fc"] == shape["chan_per_fc"]
+    assert len([l for l in open(cache) if l.strip()]) == 1
+    # the other batch size keeps the default shape and its own results
+    one = {k: v.cpu().numpy() for k, v in plan.decompose(sig[:1], 4).items() if v is not None}
+    np.testing.assert_array_equal(one["index"], ref["index"][:1])
+
+
+def test_tuned_ragged_shape_changes_no_result(oracle):
+    wl = _ragged_case(12, 200, 700, (16, 8, 4), 3)
+    packed, lens, offs = wl.signals, wl.lengths.copy(), wl.offsets
+    g = W.ragged_grid(int(lens.max()), 32, 16, 8, 4)
+    plan = A().Plan(g, dict_="synth", prec="f16", max_batch=12, refine_steps=30, ragged=True, ragged_tc_div=32)
+    ref = {k: v.cpu().numpy() for k, v in plan.decompose_ragged(packed, lens, offs, 3).items() if v is not None}
+    shape = plan.act_tune(packed, reps=2, lengths=lens, offsets=offs)
+    assert shape["grid_per_cu"] in (1, 2, 3, 4)
+    got = {k: v.cpu().numpy() for k, v in plan.decompose_ragged(packed, lens, offs, 3).items() if v is not None}
+    for k in ("index", "theta", "coef", "energy", "resid"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
