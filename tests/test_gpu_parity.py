@@ -965,3 +965,41 @@ def test_tuned_ragged_shape_changes_no_result(oracle):
     got = {k: v.cpu().numpy() for k, v in plan.decompose_ragged(packed, lens, offs, 3).items() if v is not None}
     for k in ("index", "theta", "coef", "energy", "resid"):
         np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+
+
+# --------------------------------------------------------------------------
+# degenerate dictionaries
+# --------------------------------------------------------------------------
+
+def _degenerate_cases():
+    rng = np.random.default_rng(71)
+    # one atom: every order selects it; after the first the residual is
+    # orthogonal to it and every later score is zero (a tie at index 0)
+    one = W.Grid(256.0, 64, W.Axis(0.125, 0.125, 1, False), W.Axis(12.0, 12.0, 1, False),
+                 W.Axis(3.0, 3.0, 1, False), W.Axis(math.log(0.05), math.log(0.05), 1, False))
+    # one-sample signals: the t_c = 0 atoms all equal the single sample's unit vector
+    single = W.Grid(256.0, 1, W.Axis(0.0, 0.0, 1, False), W.Axis(1.0, 64.0, 4, False),
+                    W.Axis(-20.0, 20.0, 3, False), W.Axis(math.log(0.05), 0.0, 2, False))
+    # time centres far past the signal with narrow envelopes: those atoms
+    # vanish on the samples (norm below 1e-300) and score zero
+    outside = W.Grid(256.0, 256, W.Axis(0.0, 40.0, 9, False), W.Axis(4.0, 40.0, 5, False),
+                     W.Axis(-10.0, 10.0, 3, False), W.Axis(math.log(0.01), math.log(0.05), 3, False))
+    return [("one-atom", one, rng.standard_normal((2, one.n))),
+            ("one-sample", single, rng.standard_normal((2, single.n))),
+            ("outside", outside, rng.standard_normal((2, outside.n)))]
+
+
+@pytest.mark.parametrize("case", [0, 1, 2])
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table")])
+def test_degenerate_dictionaries(oracle, case, prec, dict_):
+    name, g, sig = _degenerate_cases()[case]
+    order = 3
+    ref = oracle.decompose(g, sig, order, refine_steps=30)
+    gpu = gpu_decompose(g, sig, order, prec, dict_, refine_steps=30)
+    assert np.all(np.isfinite(gpu["energy"])) and np.all(np.isfinite(gpu["coef"]))
+    assert np.all(np.diff(gpu["energy"], axis=1) <= 1e-12 * gpu["energy"][:, :1])
+    assert assert_decomposition_parity(gpu, ref, g, oracle, sig, f"{name}-{prec}", 30) == 2 * order
+    if name == "outside":
+        # zero-norm atoms are never selected while any atom has a nonzero score
+        p = oracle.correlate(g, sig[0])
+        assert np.all(p[gpu["index"][0, :1]] != 0.0)
