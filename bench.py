@@ -45,6 +45,9 @@ WORKLOADS = {
     # support-truncated: GMAC/s still counts the dense work (dense-equivalent rate)
     "f16-64x2048-synth-cut": ("batched_64x2048", dict(dict_="synth", prec="f16", support_cut=True), "mfma_f16", 0),
     "plain-1x512": ("plain_1x512", dict(dict_="synth", prec="f64"), "f64", 0),
+    # FP16 lag table of one time centre: the dense correlation as one matrix product
+    "lag-f16-64x2048": ("batched_64x2048", dict(dict_="lag", prec="f16"), "mfma_f16", 0),
+    "lag-f16-1x2048": ("fp32_1x2048", dict(dict_="lag", prec="f16"), "mfma_f16", 0),
     # complex (analytic) atoms: two correlations per atom (real and imaginary part)
     "complex-f32-64x2048-synth": ("batched_64x2048", dict(dict_="synth", prec="f32", complex_atoms=True),
                                   "mfma_f32", 0),
@@ -53,7 +56,8 @@ KERNELS = {("table", "f32"): ("k_search_f32_table", "act_search_f32t.hip"),
            ("table", "bf16"): ("k_search_bf16_table", "act_search_bf16.hip"),
            ("synth", "f32"): ("k_search_synth_f32", "act_search_synth.hip"),
            ("synth", "f16"): ("k_search_h16", "act_search_h16.hip"),
-           ("synth", "f64"): ("k_search_f64", "act_search_f64.hip")}
+           ("synth", "f64"): ("k_search_f64", "act_search_f64.hip"),
+           ("lag", "f16"): ("k_search_lag", "act_search_lag.hip")}
 
 
 def source_sha(*names) -> str:
@@ -172,13 +176,16 @@ def run_workload(name: str, steps: int, warmup: int):
         # multiply-adds; the roofline counts the dense correlation's flops
         # (complex atoms: both parts, 2 x atoms x N x B multiply-adds)
         algo = 2.0 * g.size * g.n * B * (2 if plan_kw.get("complex_atoms") else 1)
+        lag = plan_kw["dict_"] == "lag"
         achieved = algo / (search_ms * 1e-3) / 1e12
         peak = PEAK_TFLOPS[kind[5:] + "_mfma"]
         res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                            "kernel": kname, "avg_launch_ms": round(search_ms, 5),
                            "algorithmic_flops_per_launch": algo,
-                           "executed_mfma_flops_per_launch": 2 * algo}
+                           # the factored synthesis runs two products per sample; the lag
+                           # table the dense ones (plus its stages' span of lags)
+                           "executed_mfma_flops_per_launch": algo if lag else 2 * algo}
     else:
         # FP64 on-the-fly synthesis, ~60 FP64 operations per atom sample
         ops = g.size * g.n * B * 60

@@ -68,7 +68,11 @@ typedef struct {
 /* Dictionary source of the coarse search. */
 enum {
     ACT_DICT_SYNTH = 0, /* atoms synthesised on the device inside the search */
-    ACT_DICT_TABLE = 1  /* atoms streamed from an HBM-resident table built by act_plan */
+    ACT_DICT_TABLE = 1, /* atoms streamed from an HBM-resident table built by act_plan */
+    ACT_DICT_LAG = 2    /* one time centre's atoms over every lag in an HBM-resident FP16 table
+                           (time centres on integer samples that are multiples of 8): the scores
+                           of all (channel, time centre) rows are one dense matrix product with
+                           the residual's shifted windows; ACT_PREC_F16 only, plain plans */
 };
 
 /* Arithmetic of the coarse search (rescoring, refinement, coefficients and

@@ -18,12 +18,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libact.so")
 
 ACT_OK, ACT_ERR_INVALID, ACT_ERR_NOMEM, ACT_ERR_HIP, ACT_ERR_UNSUPPORTED = range(5)
-ACT_DICT_SYNTH, ACT_DICT_TABLE = 0, 1
+ACT_DICT_SYNTH, ACT_DICT_TABLE, ACT_DICT_LAG = 0, 1, 2
 ACT_PREC_F64, ACT_PREC_F32, ACT_PREC_BF16, ACT_PREC_F16 = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_REFINE_REJECTED, FLAG_CAND_OVERFLOW, FLAG_RAGGED_EMPTY, FLAG_BAD_LENGTH = 1, 2, 8, 16, 32
 Q_ATOMS, Q_TABLE_BYTES, Q_N_PAD, Q_CAND_CAP, Q_WORKSPACE_BYTES = range(5)
 
-_DICTS = {"synth": ACT_DICT_SYNTH, "table": ACT_DICT_TABLE}
+_DICTS = {"synth": ACT_DICT_SYNTH, "table": ACT_DICT_TABLE, "lag": ACT_DICT_LAG}
 _PRECS = {"f64": ACT_PREC_F64, "f32": ACT_PREC_F32, "bf16": ACT_PREC_BF16, "f16": ACT_PREC_F16}
 
 

@@ -231,6 +231,9 @@ struct act_plan_s {
     double* lem_cand = nullptr;      // LEM: [B][lem_cap][4] candidate parameters
     double* lem_score = nullptr;     // LEM: [B][lem_cap] candidate scores
     int lem_cap = 0;
+    int lag_q_pad = 0;        // ACT_DICT_LAG: table columns (n_fc n_c n_ld padded to 256)
+    double shift_eps = 0.0;   // synthesised / lag searches: relative score error of rounding the
+                              // time centres to integer samples
     double trunc_tail = 0.0;  // largest sqrt(envelope tail energy) outside the supports
     double rho_max = 0.0;     // max over atoms of |envelope|_2 / |g|_2
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
@@ -325,6 +328,10 @@ act_status launch_to_shadow(act_plan_s* p, int batch, const double* resid, hipSt
 int f32_chain_length(int n_pad);
 int synth_chain_length(int n_pad);
 int h16_chain_length(int n_pad);
+int lag_chain_length(int n_pad);
+act_status build_lag_table(act_plan_s* p, hipStream_t s);
+struct SearchCtl;
+act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s);
 act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double* theta,
                               const double* coef, const int* len, const long long* off, double* out,
                               hipStream_t s);

@@ -265,6 +265,22 @@ act_status build_synth(act_plan_s* p, hipStream_t s) {
     return ACT_OK;
 }
 
+// Lag-table plans: FP64 norms of every atom (FP32 copies for the search) and
+// the FP16 lag table.
+act_status build_lag(act_plan_s* p, hipStream_t s) {
+    unsigned long long* rb = nullptr;
+    ACT_HIP(hipMalloc((void**)&rb, sizeof(unsigned long long)));
+    ACT_HIP(hipMemsetAsync(rb, 0, sizeof(unsigned long long), s));
+    const int cus = device_cus();
+    hipLaunchKernelGGL(k_norms_rho, dim3((unsigned)std::min<long long>((p->atoms + 3) / 4, cus * 32LL)), dim3(256),
+                       0, s, p->grid, p->inv_norm, p->inv_norm32, rb, 0);
+    ACT_HIP(hipGetLastError());
+    act_status st = build_lag_table(p, s);
+    ACT_HIP(hipStreamSynchronize(s));
+    ACT_HIP(hipFree(rb));
+    return st;
+}
+
 // Half-supports of the FP16 search's envelopes: for each log-duration the
 // smallest D (in samples) whose envelope tail energy over lags |d| > D (inside
 // the table's lag range) is at most 2^-48, from the FP64 prefix sums.  They
@@ -380,7 +396,8 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     if ((st = validate_axis(gr.fc_hz, "fc_hz")) != ACT_OK) return st;
     if ((st = validate_axis(gr.c_hz_per_s, "c_hz_per_s")) != ACT_OK) return st;
     if ((st = validate_axis(gr.logdt_ln_s, "logdt_ln_s")) != ACT_OK) return st;
-    ACT_REQUIRE(desc->dict == ACT_DICT_SYNTH || desc->dict == ACT_DICT_TABLE, "act_plan: unknown dict");
+    ACT_REQUIRE(desc->dict == ACT_DICT_SYNTH || desc->dict == ACT_DICT_TABLE || desc->dict == ACT_DICT_LAG,
+                "act_plan: unknown dict");
     ACT_REQUIRE(desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32 || desc->prec == ACT_PREC_BF16 ||
                     desc->prec == ACT_PREC_F16,
                 "act_plan: unknown prec");
@@ -418,6 +435,11 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             return ACT_ERR_UNSUPPORTED;
         }
     }
+    if (desc->dict == ACT_DICT_LAG && !(desc->prec == ACT_PREC_F16 && !desc->ragged && !desc->complex_atoms &&
+                                        !desc->prior_act && !desc->support_cut)) {
+        set_error("act_plan: ACT_DICT_LAG is the FP16 lag-table search of plain plans of real atoms");
+        return ACT_ERR_UNSUPPORTED;
+    }
     if (desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_BF16) {
         set_error("act_plan: this precision / dictionary pair is not implemented in this build");
         return ACT_ERR_UNSUPPORTED;
@@ -437,6 +459,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     // the FP32 GEMV's per-lane FMAs plus its reduction tree; the MFMA path is
     // bounded by one rounding per sample
     p->chain = desc->prec == ACT_PREC_BF16  ? p->n_pad
+               : desc->dict == ACT_DICT_LAG ? lag_chain_length(p->n_pad)
                : desc->prec == ACT_PREC_F16 ? h16_chain_length(p->n_pad)
                : desc->dict == ACT_DICT_SYNTH ? synth_chain_length(p->n_pad)
                                               : f32_chain_length(p->n_pad);
@@ -538,33 +561,67 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             set_error("act_plan: a ragged batch of max_batch signals has more than 2^31 search tiles");
             return fail(ACT_ERR_UNSUPPORTED);
         }
-    } else if (synth32) {
-        // time centres must sit on integer samples that are multiples of 16
+    } else if (synth32 || desc->dict == ACT_DICT_LAG) {
+        // time centres must sit on integer samples (multiples of 16 for the
+        // synthesised searches, of 8 for the lag table) inside the signal; the
+        // residual distance to the integer enters the certified bound
+        const int mult = desc->dict == ACT_DICT_LAG ? 8 : 16;
         std::vector<int> shift(ax[0]->count);
+        double delta = 0.0;
         for (int j = 0; j < ax[0]->count; ++j) {
             const double mv = vals[p->grid.off[0] + j] * gr.fs_hz;
             const double mr = std::nearbyint(mv);
             if (!(std::fabs(mv - mr) <= 1e-6 * std::max(1.0, std::fabs(mv))) || mr < 0 ||
-                mr >= gr.n_samples || ((long long)mr % 16) != 0) {
-                set_error("act_plan: the MFMA synthesised searches need time centres on integer sample "
-                          "offsets that are multiples of 16 inside the signal");
+                mr >= gr.n_samples || ((long long)mr % mult) != 0) {
+                set_error(std::string("act_plan: the MFMA synthesised and lag-table searches need time centres "
+                                      "on integer sample offsets that are multiples of ") +
+                          std::to_string(mult) + " inside the signal");
                 return fail(ACT_ERR_UNSUPPORTED);
             }
             shift[j] = (int)mr;
+            delta = std::max(delta, std::fabs(mv - mr));
+        }
+        // |d g / d n| <= (2 pi (|f_c| + 2 |c| T) + T / dt^2) / fs over |tau| <= T = n / fs,
+        // so shifting by delta samples moves a score by at most delta sqrt(2 n) times
+        // that over |g_w| >= 1 (the centre sample, g(0) = 1, is present)
+        {
+            double fmax = 0.0, cmax = 0.0, dtmin = INFINITY;
+            for (int j = 0; j < ax[1]->count; ++j) fmax = std::max(fmax, std::fabs(vals[p->grid.off[1] + j]));
+            for (int j = 0; j < ax[2]->count; ++j) cmax = std::max(cmax, std::fabs(vals[p->grid.off[2] + j]));
+            for (int j = 0; j < ax[3]->count; ++j) dtmin = std::min(dtmin, std::exp(vals[p->grid.off[3] + j]));
+            const double T = gr.n_samples / gr.fs_hz;
+            const double slope = (2.0 * M_PI * (fmax + 2.0 * cmax * T) + T / (dtmin * dtmin)) / gr.fs_hz;
+            p->shift_eps = delta > 0.0 ? 1.01 * delta * std::sqrt(2.0 * gr.n_samples) * slope : 0.0;
         }
         p->n_cl = ax[2]->count * ax[3]->count;
         p->fac_w = 2 * p->n_pad;
         const size_t ucl = (size_t)p->n_cl * p->fac_w * sizeof(float);
         const size_t ufc = (size_t)ax[1]->count * p->fac_w * sizeof(float);
-        PLAN_HIP(hipMalloc(&p->fac_u, ucl));
-        PLAN_HIP(hipMalloc(&p->fac_v, ucl));
-        PLAN_HIP(hipMalloc(&p->fac_c, ufc));
-        PLAN_HIP(hipMalloc(&p->fac_s, ufc));
+        if (synth32) {
+            PLAN_HIP(hipMalloc(&p->fac_u, ucl));
+            PLAN_HIP(hipMalloc(&p->fac_v, ucl));
+            PLAN_HIP(hipMalloc(&p->fac_c, ufc));
+            PLAN_HIP(hipMalloc(&p->fac_s, ufc));
+        }
         PLAN_HIP(hipMalloc((void**)&p->inv_norm, (size_t)atoms * sizeof(double)));
         PLAN_HIP(hipMalloc((void**)&p->inv_norm32, (size_t)atoms * sizeof(float)));
         PLAN_HIP(hipMalloc((void**)&p->tc_shift, shift.size() * sizeof(int)));
         PLAN_HIP(hipMemcpyAsync(p->tc_shift, shift.data(), shift.size() * sizeof(int), hipMemcpyHostToDevice, s));
         p->table_bytes = 0;
+        if (desc->dict == ACT_DICT_LAG) {
+            const long long Q = (long long)ax[1]->count * p->n_cl;
+            p->lag_q_pad = (int)((Q + 255) / 256 * 256);
+            p->table_bytes = (size_t)p->lag_q_pad * (2 * p->n_pad) * 2;
+            size_t free_b = 0, total_b = 0;
+            PLAN_HIP(hipMemGetInfo(&free_b, &total_b));
+            if (p->table_bytes + (64ull << 20) > free_b) {
+                set_error("act_plan: lag table of " + std::to_string(p->table_bytes) +
+                          " bytes does not fit in free device memory");
+                return fail(ACT_ERR_NOMEM);
+            }
+            PLAN_HIP(hipMalloc(&p->table, p->table_bytes));
+            PLAN_HIP(hipMalloc((void**)&p->rscale, B * sizeof(float)));
+        }
     }
     if (synth32 && desc->prec == ACT_PREC_F16) {
         const size_t u16b = (size_t)p->n_cl * p->fac_w * 2;
@@ -602,6 +659,9 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
 
     act_status bs = build_tables(p, s);
     if (bs != ACT_OK) return fail(bs);
+    if (desc->dict == ACT_DICT_LAG) {
+        if ((bs = build_lag(p, s)) != ACT_OK) return fail(bs);
+    }
     if (synth32) {
         bs = build_synth(p, s);
         if (bs != ACT_OK) return fail(bs);

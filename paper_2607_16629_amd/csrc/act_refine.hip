@@ -32,6 +32,7 @@ struct PlanDev {
     double* ebmul;           // ACT_PREC_F16: [B] per-atom bound factor
     unsigned* tmax;          // ACT_PREC_F16: [B][n_tc] pass-0 upper bound per time centre
     double trunc_tail;       // ACT_PREC_F16 with support_cut: skipped envelope tail (relative)
+    double shift_eps;        // synthesised / lag searches: time centres rounded to samples (relative)
     bool per_atom;           // gmax holds the max lower bound, cand_score upper bounds
     bool cplx;               // complex atoms: scores |<g_hat, r>|, two-part update
 };
@@ -63,7 +64,8 @@ static PlanDev view(const act_plan_s* p) {
     v.ebmul = p->ebmul;
     v.tmax = p->tmax;
     v.trunc_tail = p->trunc_tail;
-    v.per_atom = p->desc.prec == ACT_PREC_F16;
+    v.shift_eps = p->shift_eps;
+    v.per_atom = p->desc.prec == ACT_PREC_F16 && p->desc.dict == ACT_DICT_SYNTH;
     v.cplx = p->desc.complex_atoms != 0;
     return v;
 }
@@ -97,6 +99,17 @@ __device__ double score_bound(const PlanDev& P, double rn, double er, double sca
     const double rt = rn + er;
     const double m = (double)P.chain;
     const double gam = m * u32 / (1.0 - m * u32);
+    if (P.dict == ACT_DICT_LAG) {
+        // FP16 lag table: |fl16(fl32(g)) - g| <= (u16 + u32) |g| + 2^-25 per
+        // sample, so over the atom's window (|g_w| >= 1, at most 2N samples) the
+        // table error is <= (u16 + u32 + 2^-25 sqrt(2N)) |r~| after 1/|g_w|; the
+        // FP16 products are exact in FP32, their sum carries gamma_m; the FP32
+        // 1/|g| and the scalings add <= 3 u |r~|; the search copy's error |e_r|
+        const double u16 = 4.8828125e-04;
+        const double eg = u16 + u32 + 2.98023223876953125e-08 * sqrt(2.0 * n);
+        (void)scale;
+        return 1.01 * (eg * rt + er + gam * (1.0 + eg) * rt + 3.0 * u32 * rt + P.shift_eps * rt);
+    }
     if (P.prec == ACT_PREC_F16) {
         // additive part of the per-atom bound (the part that scales with
         // |E_w| / |g_w| is h16_bound_mul): the FP16 search copy's own error
@@ -108,10 +121,10 @@ __device__ double score_bound(const PlanDev& P, double rn, double er, double sca
         (void)scale;
         // support cut: the skipped products sum to at most sqrt(tail) |r| / |g_w|
         // (|g| <= E and Cauchy-Schwarz), and |g_w| >= 1
-        return 1.01 * (er + 6.0 * u32 * rt + sub * rt + P.trunc_tail * rt);
+        return 1.01 * (er + 6.0 * u32 * rt + sub * rt + P.trunc_tail * rt + P.shift_eps * rt);
     }
     if (P.dict == ACT_DICT_SYNTH && P.cplx) {
-        const double part = (5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er;
+        const double part = (5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er + P.shift_eps * rt;
         return 1.01 * (1.4142135623730951 * part + 6.0 * u32 * rt);
     }
     if (P.dict == ACT_DICT_SYNTH) {
@@ -119,7 +132,8 @@ __device__ double score_bound(const PlanDev& P, double rn, double er, double sca
         // (factors, r, the carrier product, the MFMA product) plus the chain,
         // against sum_n (|U C| + |V S|)|r_n| <= sqrt(2) |E| |r| = sqrt(2) rho |g| |r|;
         // the scaling by 1/|g| in FP32 adds 2 u |p|.
-        return 1.01 * ((5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er + 3.0 * u32 * rn);
+        return 1.01 * ((5.0 * u32 + gam) * 1.4142135623730951 * P.rho_max * rt + er + 3.0 * u32 * rn +
+                       P.shift_eps * rt);
     }
     return 1.01 * (P.eg_max * rt + er + gam * (1.0 + P.eg_max) * rt);
 }

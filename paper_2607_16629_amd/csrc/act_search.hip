@@ -29,6 +29,7 @@ int device_cus() {
 
 static act_status dispatch(act_plan_s* p, int batch, hipStream_t s, const SearchCtl& ctl,
                            const double* resid64) {
+    if (p->desc.dict == ACT_DICT_LAG) return launch_search_lag(p, batch, ctl, s);
     if (p->desc.prec == ACT_PREC_F64) return launch_search_f64(p, batch, ctl, resid64, s);
     if (p->desc.prec == ACT_PREC_F32 && p->desc.dict == ACT_DICT_TABLE)
         return launch_search_f32t(p, batch, ctl, s);

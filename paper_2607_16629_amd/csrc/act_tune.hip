@@ -37,7 +37,9 @@ static std::vector<act_launch_shape> candidates(const act_plan_s* p, int batch) 
     std::vector<int> grids;
     std::vector<int> cpfs = {0};
     const auto& d = p->desc;
-    if (d.prec == ACT_PREC_F64) {
+    if (d.dict == ACT_DICT_LAG) {
+        grids = {1, 2};
+    } else if (d.prec == ACT_PREC_F64) {
         grids = {4, 8, 16, 32};
     } else if (d.dict == ACT_DICT_TABLE && d.prec == ACT_PREC_F32) {
         grids = {2, 4, 8, 16};

@@ -159,9 +159,11 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_s
 # rounding terms below 2^-8; 8e-3 |r| is the resulting certified bound.
 # FP16 factored synthesis: (2 u16 + 5 u32 + gamma) sqrt(2) rho |r| with
 # u16 = 2^-11 and rho (|envelope| / |atom|) below 1.5 on these grids: 2.5e-3 |r|.
+# FP16 lag table: (u16 + u32 + gamma_{2N+2}) |r| plus the FP16 search copy's
+# own rounding (<= u16 |r|): 1.5e-3 |r| at N = 512.
 @pytest.mark.parametrize("prec,dict_,tol", [("f64", "synth", 1e-12), ("f32", "table", 1e-5),
                                             ("bf16", "table", 8e-3), ("f32", "synth", 1e-5),
-                                            ("f16", "synth", 2.5e-3)])
+                                            ("f16", "synth", 2.5e-3), ("f16", "lag", 1.5e-3)])
 def test_correlate_matches_oracle(oracle, prec, dict_, tol):
     wl = W.plain_1x512()
     g = wl.grid
@@ -197,7 +199,8 @@ def test_correlate_many_channels_and_ragged_tail(oracle, prec, tol):
 
 @pytest.mark.parametrize("prec,dict_,cut", [("f64", "synth", False), ("f32", "table", False),
                                             ("bf16", "table", False), ("f32", "synth", False),
-                                            ("f16", "synth", False), ("f16", "synth", True)])
+                                            ("f16", "synth", False), ("f16", "synth", True),
+                                            ("f16", "lag", False)])
 def test_decompose_plain_1x512(oracle, prec, dict_, cut):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, wl.order, refine_steps=30)
@@ -207,7 +210,7 @@ def test_decompose_plain_1x512(oracle, prec, dict_, cut):
 
 
 @pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table"),
-                                        ("f32", "synth"), ("f16", "synth")])
+                                        ("f32", "synth"), ("f16", "synth"), ("f16", "lag")])
 def test_decompose_without_refinement_is_exact_mp(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, 8, refine_steps=0)
@@ -401,7 +404,8 @@ def test_graph_replays_match_direct_launches():
         assert torch.equal(resid, ref_r), rep
 
 
-@pytest.mark.parametrize("prec,dict_,cap", [("f32", "table", 2), ("bf16", "table", 40), ("f16", "synth", 8)])
+@pytest.mark.parametrize("prec,dict_,cap", [("f32", "table", 2), ("bf16", "table", 40), ("f16", "synth", 8),
+                                            ("f16", "lag", 8)])
 def test_small_candidate_capacity_reruns_exactly(oracle, prec, dict_, cap):
     """A tiny capacity forces the exact-threshold rerun pass; the result must
     not change."""
@@ -411,7 +415,7 @@ def test_small_candidate_capacity_reruns_exactly(oracle, prec, dict_, cap):
     assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, 0)
 
 
-@pytest.mark.parametrize("prec,dict_", [("bf16", "table"), ("f16", "synth")])
+@pytest.mark.parametrize("prec,dict_", [("bf16", "table"), ("f16", "synth"), ("f16", "lag")])
 def test_batch_of_70_channels(oracle, prec, dict_):
     """More than one 64-channel tile, a reduced grid; the oracle checks a
     few channels from both tiles (channels are independent)."""
@@ -424,8 +428,8 @@ def test_batch_of_70_channels(oracle, prec, dict_):
     assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick], prec, 30) >= 15
 
 
-@pytest.mark.parametrize("dict_", ["table", "synth"])
-def test_fp32_full_size_2m_atoms(oracle, dict_):
+@pytest.mark.parametrize("prec,dict_", [("f32", "table"), ("f32", "synth"), ("f16", "lag")])
+def test_fp32_full_size_2m_atoms(oracle, prec, dict_):
     """Single channel at EEG-like scale (N = 2048, 2,097,152 atoms): the
     oracle cannot run the whole pursuit, so each order is checked one by one:
     the winner's oracle score matches, no sampled atom beats it, the refined
@@ -434,7 +438,7 @@ def test_fp32_full_size_2m_atoms(oracle, dict_):
     wl = W.fp32_1x2048()
     g = wl.grid
     order = 3
-    gpu = gpu_decompose(g, wl.signals, order, "f32", dict_, refine_steps=30)
+    gpu = gpu_decompose(g, wl.signals, order, prec, dict_, refine_steps=30)
     step, _, _ = oracle.refine_box(g)
     rng = np.random.default_rng(12)
     sample = rng.choice(g.size, 20000, replace=False)
@@ -458,7 +462,7 @@ def test_fp32_full_size_2m_atoms(oracle, dict_):
 
 
 @pytest.mark.parametrize("prec,dict_,cut", [("bf16", "table", False), ("f16", "synth", False),
-                                            ("f16", "synth", True)])
+                                            ("f16", "synth", True), ("f16", "lag", False)])
 def test_full_size_64x2048(oracle, prec, dict_, cut):
     """64 channels x N = 2048 on the 2,097,152-atom grid, BF16 table or FP16
     synthesis + FP64 rescoring: per order and for sampled channels, the
@@ -927,7 +931,8 @@ def test_complex_full_size_64x2048(oracle):
 # launch-shape autotuner
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,dict_", [("f32", "table"), ("bf16", "table"), ("f16", "synth"), ("f32", "synth")])
+@pytest.mark.parametrize("prec,dict_", [("f32", "table"), ("bf16", "table"), ("f16", "synth"), ("f32", "synth"),
+                                        ("f16", "lag")])
 def test_tuned_shapes_change_no_result(oracle, prec, dict_, tmp_path):
     """act_tune picks a launch shape by timing; decompositions with the tuned
     shape are bit-identical to the default shape's, the choice is cached per
@@ -940,7 +945,7 @@ def test_tuned_shapes_change_no_result(oracle, prec, dict_, tmp_path):
     cache = str(tmp_path / "tune.txt")
     shape = plan.act_tune(sig, reps=2, cache=cache)
     assert shape["grid_per_cu"] >= 1 and shape["ms"] > 0 and not shape["from_cache"]
-    if prec == "f16":
+    if prec == "f16" and dict_ == "synth":
         assert shape["chan_per_fc"] in (1, 2, 4, 8)
     got = {k: v.cpu().numpy() for k, v in plan.decompose(sig, 4).items() if v is not None}
     for k in ("index", "theta", "coef", "energy", "resid", "flags"):
@@ -1003,3 +1008,40 @@ def test_degenerate_dictionaries(oracle, case, prec, dict_):
         # zero-norm atoms are never selected while any atom has a nonzero score
         p = oracle.correlate(g, sig[0])
         assert np.all(p[gpu["index"][0, :1]] != 0.0)
+
+
+def test_lag_table_partial_tiles_and_edge_channels(oracle):
+    """FP16 lag table on n = 300 (a partial last stage), 9,450 columns (a
+    partial column block), time centres every 16 samples, five channels (a
+    partial channel group) with an all-zero and a NaN channel: correlations
+    within the certified bound and pursuits step by step."""
+    g = W.Grid(256.0, 300, W.Axis(0.0, 18 * 16 / 256.0, 18, True), W.Axis(2.0, 60.0, 70, False),
+               W.Axis(-15.0, 15.0, 9, False), W.Axis(math.log(0.05), 0.0, 15, False))
+    rng = np.random.default_rng(81)
+    sig = rng.standard_normal((5, g.n))
+    plan = A().Plan(g, dict_="lag", prec="f16", max_batch=5)
+    p = plan.act_correlate(sig, 0, g.size).cpu().numpy()
+    for b in range(5):
+        ref = oracle.correlate(g, sig[b])
+        assert np.max(np.abs(p[b] - ref)) <= 1.5e-3 * np.linalg.norm(sig[b])
+    sig[3] = 0.0
+    sig[4, 123] = np.nan
+    gpu = gpu_decompose(g, sig, 4, "f16", "lag", refine_steps=60)
+    ref = oracle.decompose(g, sig[:3], 4, refine_steps=60)
+    assert_decomposition_parity({k: (v[:3] if v is not None else None) for k, v in gpu.items()},
+                                ref, g, oracle, sig[:3], "lag-edge", 60)
+    assert gpu["flags"][4] & A().FLAG_NONFINITE
+    np.testing.assert_array_equal(gpu["energy"][3], 0.0)
+
+
+def test_lag_table_rejects_unaligned_time_centres():
+    act = A()
+    g = W.Grid(256.0, 512, W.Axis(0.0, 2.0, 13, True), W.Axis(2.0, 60.0, 8, False),
+               W.Axis(-15.0, 15.0, 3, False), W.Axis(math.log(0.05), 0.0, 3, False))
+    with pytest.raises(act.ActError) as e:
+        act.Plan(g, dict_="lag", prec="f16")
+    assert e.value.status == act.ACT_ERR_UNSUPPORTED
+    for kw in (dict(prec="f32"), dict(prec="f16", ragged=True), dict(prec="f16", complex_atoms=True)):
+        with pytest.raises(act.ActError) as e:
+            act.Plan(W.eeg_grid(512, 32, 8, 4, 2), dict_="lag", **kw)
+        assert e.value.status == act.ACT_ERR_UNSUPPORTED, kw
