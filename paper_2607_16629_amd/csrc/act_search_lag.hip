@@ -298,7 +298,8 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
                 const int sl = row & (ld.CB - 1), t = row >> ld.cb_log2;
                 const float T = L.M[sl];
                 const int b = ch0 + sl, tc = tc0 + t;
-                if (T == INFINITY || tc >= ld.n_tc) continue;
+                // rows whose largest |p~| misses the threshold emit nothing
+                if (T == INFINITY || tc >= ld.n_tc || bitsf(L.rmax[row]) < T) continue;
                 const float rinv = L.rinv[sl];
 #pragma unroll
                 for (int cb = 0; cb < WCB; ++cb) {
