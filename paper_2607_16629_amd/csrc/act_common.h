@@ -232,6 +232,10 @@ struct act_plan_s {
     double* lem_score = nullptr;     // LEM: [B][lem_cap] candidate scores
     int lem_cap = 0;
     int lag_q_pad = 0;        // ACT_DICT_LAG: table columns (n_fc n_c n_ld padded to 256)
+    float* lag_inv = nullptr; // ACT_DICT_LAG: [n_tc][lag_q_pad] FP32 1/|g| in the table's column order
+    int* lag_span = nullptr;  // ACT_DICT_LAG: [lag_q_pad / 32] k-step range of each block's nonzero entries
+    int* lag_order = nullptr; // ACT_DICT_LAG: tile column-block orders (128-column tiles, then 256)
+    int lag_order_wide = 0;   // ACT_DICT_LAG: offset of the 256-column order in lag_order
     double shift_eps = 0.0;   // synthesised / lag searches: relative score error of rounding the
                               // time centres to integer samples
     double trunc_tail = 0.0;  // largest sqrt(envelope tail energy) outside the supports

@@ -366,7 +366,7 @@ static void free_plan(act_plan_s* p) {
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
                     p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->lem_cand, p->lem_score, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
-                    p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun};
+                    p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun, p->lag_inv, p->lag_span, p->lag_order};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto& ge : p->graphs) {
@@ -621,6 +621,9 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             }
             PLAN_HIP(hipMalloc(&p->table, p->table_bytes));
             PLAN_HIP(hipMalloc((void**)&p->rscale, B * sizeof(float)));
+            PLAN_HIP(hipMalloc((void**)&p->lag_inv, (size_t)ax[0]->count * p->lag_q_pad * sizeof(float)));
+            PLAN_HIP(hipMalloc((void**)&p->lag_span, (size_t)(p->lag_q_pad / 32) * 2 * sizeof(int)));
+            PLAN_HIP(hipMalloc((void**)&p->lag_order, (size_t)(p->lag_q_pad / 128 + p->lag_q_pad / 256) * sizeof(int)));
         }
     }
     if (synth32 && desc->prec == ACT_PREC_F16) {

@@ -16,17 +16,25 @@
 // e = d + N_pad in [0, 2 N_pad), pre-swizzled in MFMA B-operand order: for 32
 // columns and a k-step of 16 lags the 64 lanes' 16-byte operands are one
 // contiguous KiB, so every wave streams its B fragments straight from L2.
+// Columns run log-duration major.  The envelope of a log-duration rounds to
+// FP16 zero a few durations from its centre, so a tile's columns are zero
+// outside a common band of lags; each tile runs only the k-steps inside the
+// band of its columns (found from the table itself at plan time).  The
+// skipped products are exact zeros: the scores are those of the full product.
 // R: per 128-lag stage, 128 rows x 128 lags in LDS (two buffers), each row
 // read from the FP16 search copy of its channel.
 // Workgroup = 4 waves; tile = 128 rows x (128 or 256) columns; wave w owns
 // every row (4 row blocks of 32) and 32 or 64 columns.  Tiles are dealt to the
 // 8 XCDs in contiguous ranges with the row blocks of one column block adjacent,
-// so the concurrent tiles of an XCD share their G columns in its L2.
+// so the concurrent tiles of an XCD share their G columns in its L2; column
+// blocks are ordered so that every XCD gets the same mix of band widths.
 //
 // Certified emission with a uniform bound per channel (the FP16 table's
 // rounding, the search copy's rounding, the FP32 accumulation): every atom
 // with |p~| >= M - 2 E_b is emitted, M the running maximum.
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "act_emit.h"
 
@@ -65,12 +73,17 @@ __device__ __forceinline__ float half_wave_max(float x) {
 
 struct LagDev {
     const f16x8* G;          // [Q_pad/32][LS][64] pre-swizzled lag table
-    const float* inv_norm;   // [atoms] FP32 1/|g|
+    const float* inv;        // [n_tc][Qp] FP32 1/|g| in the table's column order (0 past Q)
+    const int2* span;        // [Q_pad/32] k-steps [lo, hi) holding the block's nonzero entries
+    const int* order;        // [column blocks] tile column-block order (balanced over the XCDs)
     const int* tc_shift;     // [n_tc] integer sample of each time centre (increasing)
     const _Float16* shadow;  // [B][n_pad] fl16(fl32(r) s_b), zero past n
     const float* rscale;     // [B] s_b
     int LS;                  // k-steps of lags (2 N_pad / 16)
     int Q;                   // columns (n_fc n_c n_ld)
+    int Qp;                  // padded columns (row stride of inv)
+    int FC;                  // n_fc n_c: columns of one log-duration
+    int n_ld;
     int n_tc;
     int CB, TB;              // channels x time centres of a tile's 128 rows (CB TB = 128)
     int cb_log2;             // log2 CB (CB is a power of two): row = t CB + slot
@@ -78,11 +91,19 @@ struct LagDev {
 
 struct LagLds {
     f16x8 a[2][LG_ROWS][LG_PAD / 8];  // R stages; after the main loop: the tile's 1/|g| [TB][cols]
-    unsigned rmax[LG_ROWS];  // row maxima of |p~| (float bits)
+    float gm[4][32];         // per wave: max |p~| over the rows r = 32 rb + g of every rb, per g
     float M[LG_ROWS];        // emission threshold per channel slot
     float rinv[LG_ROWS];     // 1/s_b per channel slot
+    unsigned emit;           // bit g: some row 32 rb + g reaches its channel's threshold
 };
 static_assert(sizeof(f16x8) * 2 * LG_ROWS * (LG_PAD / 8) >= 128 * 128 * sizeof(float), "1/|g| staging fits");
+
+// flat atom index of table column qc (columns are ordered log-duration major:
+// qc = ld FC + (f_c n_c + c); atoms are (f_c, c, ld) with ld fastest)
+__device__ __forceinline__ long long lag_atom(const LagDev& ld, int tc, int qc) {
+    const int l = qc / ld.FC, fcc = qc - l * ld.FC;
+    return (long long)tc * ld.Q + (long long)fcc * ld.n_ld + l;
+}
 
 template <int WCB, bool RERUN, bool DUMP>
 __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, SearchCtl ctl, int batch,
@@ -96,24 +117,43 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
     for (long long x = blockIdx.x; x < 8 * chunk; x += gridDim.x) {
         const long long tid = (x % 8) * chunk + x / 8;
         if (tid >= tiles) continue;
-        const int cbk = (int)(tid / n_rbk);
+        const int cbk = ld.order[(int)(tid / n_rbk)];
         const int rbk = (int)(tid % n_rbk);
         const int cg = rbk % n_cg, tg = rbk / n_cg;
         const int ch0 = cg * ld.CB, tc0 = tg * ld.TB;
-        // skip tiles none of whose channels take part
-        int live = 0;
-        if (threadIdx.x < ld.CB && ch0 + (int)threadIdx.x < batch) {
-            const int b = ch0 + threadIdx.x;
-            live = DUMP || (ctl.ebound[b] >= 0.0 && (!RERUN || ctl.need_rerun[b]));
-        }
-        if (!__syncthreads_or(live)) continue;
+        const int q0 = cbk * COLS;
 
-        // lags that meet the tile's rows: e = d + N_pad with 0 <= d + m < n
+        // lags that meet the tile's rows, e = d + N_pad with 0 <= d + m < n,
+        // cut to the k-steps where the tile's columns hold nonzero entries:
+        // the skipped products are exact zeros, so every score is unchanged
         const int tc_last = min(tc0 + ld.TB, ld.n_tc) - 1;
         const int m_min = ld.tc_shift[tc0], m_max = ld.tc_shift[tc_last];
-        const int e_first = (g.n_pad - m_max) / LG_S * LG_S;
-        const int e_end = min(2 * g.n_pad, g.n_pad + g.n - m_min);
-        const int ns = (e_end - e_first + LG_S - 1) / LG_S;
+        int klo = ld.LS, khi = 0;
+#pragma unroll
+        for (int j = 0; j < 4 * WCB; ++j) {
+            const int2 sp = ld.span[cbk * 4 * WCB + j];
+            klo = min(klo, sp.x);
+            khi = max(khi, sp.y);
+        }
+        const int e_first = max((g.n_pad - m_max) / LG_S, 16 * klo / LG_S) * LG_S;
+        const int e_end = min(min(2 * g.n_pad, g.n_pad + g.n - m_min), 16 * khi);
+        const int ns = e_end > e_first ? (e_end - e_first + LG_S - 1) / LG_S : 0;
+
+        // per channel slot: certified bound, running maximum, residual scale
+        // (read now, used by the epilogue)
+        int live = 0;
+        double eb = -1.0;
+        float pre_gmax = 0.0f, rsc = 0.0f;
+        if (threadIdx.x < ld.CB && ch0 + (int)threadIdx.x < batch) {
+            const int b = ch0 + threadIdx.x;
+            eb = ctl.ebound[b];
+            rsc = ld.rscale[b];
+            if (!DUMP) pre_gmax = load_gmax(&ctl.gmax[b]);
+            live = DUMP || (eb >= 0.0 && (!RERUN || ctl.need_rerun[b]));
+        }
+        if (threadIdx.x == 0) L.emit = 0u;
+        // the rerun pass skips most tiles: vote before any load
+        if (RERUN && !__syncthreads_or(live)) continue;
 
         // this thread's chunks of the R stages: chunk c = threadIdx.x + 256 i is
         // (row c / 16, lags 8 (c % 16) ..); a row past the batch or the time
@@ -186,15 +226,27 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             }
         };
 
+        // the first stage's loads and the first 1024 of the tile's inverse
+        // norms (held until the epilogue) go out before the liveness vote
+        if (ns > 0) {
+            load_R(0);
+            load_G(gh[0], 0, 0);
+        }
+        const int n_inv = ld.TB * COLS;
+        float4 inv_pf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        {
+            const int idx = 4 * threadIdx.x, t = idx / COLS, c = idx % COLS;
+            if (idx < n_inv && tc0 + t < ld.n_tc)
+                inv_pf = *reinterpret_cast<const float4*>(ld.inv + (size_t)(tc0 + t) * ld.Qp + q0 + c);
+        }
+        // skip tiles none of whose channels take part
+        if (!RERUN && !__syncthreads_or(live)) continue;
+
         // ---- software pipeline over stages: R of stage s+1 loads while stage
         // s runs (two LDS buffers, one barrier per stage: the other buffer was
         // last read before the previous barrier); G half-stages load one half
         // ahead (the scheduling barriers keep the loads ahead of the MFMAs)
-        if (ns > 0) {
-            load_R(0);
-            load_G(gh[0], 0, 0);
-            store_R(0);
-        }
+        if (ns > 0) store_R(0);
         __syncthreads();
         auto step = [&](int s, auto bufc) {
             constexpr int buf = decltype(bufc)::value;
@@ -215,115 +267,160 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             if (s + 1 < ns) step(s + 1, std::integral_constant<int, 1>{});
         }
 
-        // ---- epilogue: p = P inv_norm / s_b, row maxima, per-channel running
-        // maximum, certified emission.  The tile's inverse norms (TB time
-        // centres x cols, contiguous per time centre) are staged in the freed
-        // R buffers with coalesced loads.
+        // ---- epilogue: p = P inv_norm / s_b (kept in acc), per-channel
+        // maxima and running maximum, certified emission of the rows that
+        // reach the threshold.  The tile's inverse norms (TB time centres x
+        // cols, contiguous per time centre) are staged in the freed R buffers.
         float* invs = reinterpret_cast<float*>(&L.a[0][0][0]);
-        const int n_fc_cl = ld.Q;
+        if (4 * (int)threadIdx.x < n_inv) *reinterpret_cast<float4*>(invs + 4 * threadIdx.x) = inv_pf;
+        for (int base = 1024; base < n_inv; base += 4096) {
+            float4 vv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = base + 1024 * u + 4 * threadIdx.x, t = idx / COLS, c = idx % COLS;
+                vv[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (idx < n_inv && tc0 + t < ld.n_tc)
+                    vv[u] = *reinterpret_cast<const float4*>(ld.inv + (size_t)(tc0 + t) * ld.Qp + q0 + c);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = base + 1024 * u + 4 * threadIdx.x;
+                if (idx < n_inv) *reinterpret_cast<float4*>(invs + idx) = vv[u];
+            }
+        }
+        if (threadIdx.x < LG_ROWS) L.rinv[threadIdx.x] = rsc > 0.0f ? 1.0f / rsc : 0.0f;
         // the epilogue's lane-dependent addresses are tile-invariant; an opaque
         // copy of the lane index keeps them from being hoisted out of the tile
         // loop (they would stay live across it and spill)
         int elane = lane;
         asm volatile("" : "+v"(elane));
-        const int q0 = cbk * COLS;
-        for (int idx = threadIdx.x; idx < ld.TB * COLS; idx += 256) {
-            const int t = idx / COLS, c = idx % COLS;
-            const int tc = tc0 + t, q = q0 + c;
-            invs[idx] = (tc < ld.n_tc && q < n_fc_cl) ? ld.inv_norm[(long long)tc * n_fc_cl + q] : 0.0f;
-        }
-        if (threadIdx.x < LG_ROWS) {
-            L.rmax[threadIdx.x] = 0u;
-            const int b = ch0 + threadIdx.x;
-            L.rinv[threadIdx.x] = (threadIdx.x < ld.CB && b < batch) ? 1.0f / ld.rscale[b] : 0.0f;
-        }
         __syncthreads();
-#pragma unroll
-        for (int rb = 0; rb < LG_RB; ++rb)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int row = rb * 32 + lg_row(v, elane);
-                const int sl = row & (ld.CB - 1), t = row >> ld.cb_log2;
-                const int b = ch0 + sl, tc = tc0 + t;
-                const float rinv = L.rinv[sl];  // 0 past the batch
-                float m = 0.0f;
-#pragma unroll
-                for (int cb = 0; cb < WCB; ++cb) {
-                    const int c = (w * WCB + cb) * 32 + (elane & 31);
-                    const float p = (acc[rb][cb][v] * invs[t * COLS + c]) * rinv;  // 0 past the dictionary
-                    if (DUMP) {
-                        const long long i = (long long)tc * n_fc_cl + q0 + c;
-                        if (b < batch && tc < ld.n_tc && q0 + c < n_fc_cl && i >= ctl.dump_begin &&
-                            i < ctl.dump_begin + ctl.dump_count)
-                            ctl.dump[(size_t)b * ctl.dump_count + (i - ctl.dump_begin)] = p;
-                    } else {
-                        m = fmaxf(m, fabsf(p));
-                    }
-                }
-                if (!DUMP) {
-                    // lanes 0-31 share one row, lanes 32-63 another
-                    m = half_wave_max(m);
-                    if ((elane & 31) == 31) atomicMax(&L.rmax[row], fbits(m));
-                }
-                // bound the loads in flight (register pressure of the unrolled epilogue)
-                __builtin_amdgcn_sched_barrier(0);
-            }
+        // A lane's rows are r = 32 rb + g, g = lg_row(v, lane): the channel
+        // slot g % CB does not depend on rb (CB divides 32), so a channel's
+        // maximum takes the rb blocks in registers and one half-wave reduction
+        // per v.
         if (DUMP) {
-            __syncthreads();
-            continue;
-        }
-        __syncthreads();
-        if (threadIdx.x < ld.CB) {
-            const int sl = threadIdx.x, b = ch0 + sl;
-            float M = INFINITY;
-            if (b < batch && ctl.ebound[b] >= 0.0 && (!RERUN || ctl.need_rerun[b])) {
-                float wm = 0.0f;
-                for (int r = sl; r < LG_ROWS; r += ld.CB) wm = fmaxf(wm, bitsf(L.rmax[r]));
-                const float cur = load_gmax(&ctl.gmax[b]);
-                M = cur;
-                if (!RERUN && wm > cur) M = fmaxf(bitsf(atomicMax(&ctl.gmax[b], fbits(wm))), wm);
-                const double Td = (double)M - 2.0 * ctl.ebound[b];
-                float T = (float)Td;
-                if ((double)T > Td) T = nextafterf(T, -INFINITY);
-                M = T;
-            }
-            L.M[sl] = M;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int rb = 0; rb < LG_RB; ++rb)
+            for (int rb = 0; rb < LG_RB; ++rb)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int row = rb * 32 + lg_row(v, elane);
-                const int sl = row & (ld.CB - 1), t = row >> ld.cb_log2;
-                const float T = L.M[sl];
-                const int b = ch0 + sl, tc = tc0 + t;
-                // rows whose largest |p~| misses the threshold emit nothing
-                if (T == INFINITY || tc >= ld.n_tc || bitsf(L.rmax[row]) < T) continue;
-                const float rinv = L.rinv[sl];
+                for (int v = 0; v < 16; ++v) {
+                    const int row = rb * 32 + lg_row(v, elane);
+                    const int sl = row & (ld.CB - 1), t = row >> ld.cb_log2;
+                    const float rinv = L.rinv[sl];
+                    const int b = ch0 + sl, tc = tc0 + t;
 #pragma unroll
-                for (int cb = 0; cb < WCB; ++cb) {
-                    const int c = (w * WCB + cb) * 32 + (elane & 31);
-                    // the same FP32 operations as the row maxima: the same p
-                    const float p = (acc[rb][cb][v] * invs[t * COLS + c]) * rinv;
-                    if (q0 + c < n_fc_cl && fabsf(p) >= T) {
-                        const int j = atomicAdd(&ctl.cand_count[b], 1);
-                        if (j < ctl.cap) {
-                            ctl.cand_idx[(size_t)b * ctl.cap + j] = (unsigned)((long long)tc * n_fc_cl + q0 + c);
-                            ctl.cand_score[(size_t)b * ctl.cap + j] = p;
+                    for (int cb = 0; cb < WCB; ++cb) {
+                        const int c = (w * WCB + cb) * 32 + (elane & 31);
+                        const float p = (acc[rb][cb][v] * invs[t * COLS + c]) * rinv;
+                        if (b < batch && tc < ld.n_tc && q0 + c < ld.Q) {
+                            const long long i = lag_atom(ld, tc, q0 + c);
+                            if (i >= ctl.dump_begin && i < ctl.dump_begin + ctl.dump_count)
+                                ctl.dump[(size_t)b * ctl.dump_count + (i - ctl.dump_begin)] = p;
                         }
                     }
                 }
-                __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();
+            continue;
+        }
+        // the scale factors of v + 1 load while v computes; the maxima are
+        // stored after the loop (no store between the loads)
+        float sc[2][LG_RB][WCB], ri[2], gmv[16];
+        auto load_sc = [&](int v, float (&dst)[LG_RB][WCB], float& r) {
+            const int gr = lg_row(v, elane);
+            r = L.rinv[gr & (ld.CB - 1)];  // 0 past the batch
+#pragma unroll
+            for (int rb = 0; rb < LG_RB; ++rb) {
+                const int t = (rb * 32 + gr) >> ld.cb_log2;
+#pragma unroll
+                for (int cb = 0; cb < WCB; ++cb)
+                    dst[rb][cb] = invs[t * COLS + (w * WCB + cb) * 32 + (elane & 31)];  // 0 past the dictionary
             }
-        __syncthreads();  // L.rmax / L.M / the R buffers are rewritten by the next tile
+        };
+        load_sc(0, sc[0], ri[0]);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            if (v + 1 < 16) load_sc(v + 1, sc[(v + 1) & 1], ri[(v + 1) & 1]);
+            float m = 0.0f;
+#pragma unroll
+            for (int rb = 0; rb < LG_RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < WCB; ++cb) {
+                    const float p = (acc[rb][cb][v] * sc[v & 1][rb][cb]) * ri[v & 1];
+                    acc[rb][cb][v] = p;
+                    m = fmaxf(m, fabsf(p));
+                }
+            // lanes 0-31 share g, lanes 32-63 hold g + 4
+            gmv[v] = half_wave_max(m);
+        }
+        if ((elane & 31) == 31) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) L.gm[w][lg_row(v, elane)] = gmv[v];
+        }
+        __syncthreads();
+        // per channel slot: the threshold M - 2 E_b (M the running maximum,
+        // raised by this tile's maximum), and the row groups that reach it
+        if (threadIdx.x < ld.CB) {
+            const int sl = threadIdx.x, b = ch0 + sl;
+            float T = INFINITY;
+            if (live) {
+                float wm = 0.0f;
+                for (int gr = sl; gr < 32; gr += ld.CB)
+                    wm = fmaxf(wm, fmaxf(fmaxf(L.gm[0][gr], L.gm[1][gr]), fmaxf(L.gm[2][gr], L.gm[3][gr])));
+                float M = pre_gmax;  // rerun: the final maximum of pass 0
+                if (!RERUN && wm > M) {
+                    atomicMax(&ctl.gmax[b], fbits(wm));
+                    M = wm;
+                }
+                const double Td = (double)M - 2.0 * eb;
+                T = (float)Td;
+                if ((double)T > Td) T = nextafterf(T, -INFINITY);
+                unsigned bits = 0u;
+                for (int gr = sl; gr < 32; gr += ld.CB)
+                    if (fmaxf(fmaxf(L.gm[0][gr], L.gm[1][gr]), fmaxf(L.gm[2][gr], L.gm[3][gr])) >= T)
+                        bits |= 1u << gr;
+                if (bits) atomicOr(&L.emit, bits);
+            }
+            L.M[sl] = T;
+        }
+        __syncthreads();
+        const unsigned em = __builtin_amdgcn_readfirstlane(L.emit);
+        if (em) {
+#pragma unroll
+            for (int rb = 0; rb < LG_RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    // the wave's two row groups of v: g = 8 (v / 4) + v % 4 and g + 4
+                    if (!((em >> (8 * (v >> 2) + (v & 3))) & 0x11u)) continue;
+                    const int gr = lg_row(v, elane);
+                    const int row = rb * 32 + gr, t = row >> ld.cb_log2, tc = tc0 + t;
+                    if (((em >> gr) & 1u) && tc < ld.n_tc) {
+                        const int sl = gr & (ld.CB - 1), b = ch0 + sl;
+                        const float T = L.M[sl];
+#pragma unroll
+                        for (int cb = 0; cb < WCB; ++cb) {
+                            const int c = (w * WCB + cb) * 32 + (elane & 31);
+                            const float p = acc[rb][cb][v];
+                            if (q0 + c < ld.Q && fabsf(p) >= T) {
+                                const int j = atomicAdd(&ctl.cand_count[b], 1);
+                                if (j < ctl.cap) {
+                                    ctl.cand_idx[(size_t)b * ctl.cap + j] = (unsigned)lag_atom(ld, tc, q0 + c);
+                                    ctl.cand_score[(size_t)b * ctl.cap + j] = p;
+                                }
+                            }
+                        }
+                    }
+                }
+        }
+        __syncthreads();  // L.gm / L.M / L.emit / the R buffers are rewritten by the next tile
     }
 }
 
 // The lag table: G_q(d) in FP64, rounded to FP32 and then FP16 (RNE), written
-// in MFMA B-operand order; columns past Q are zero.
+// in MFMA B-operand order; columns past Q are zero.  Columns run log-duration
+// major, qc = ld FC + (f_c n_c + c), so a tile's columns share an envelope and
+// its nonzero lags.
 __global__ void k_build_lag_table(GridDev g, int Q_pad, f16x8* __restrict__ G) {
-    const int n_cl = g.cnt[2] * g.cnt[3];
+    const int FC = g.cnt[1] * g.cnt[2];
     const int LS = 2 * g.n_pad / 16;
     const long long frags = (long long)(Q_pad / 32) * LS * 64;  // one f16x8 per (column block, k-step, lane)
     for (long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x; f < frags;
@@ -332,16 +429,16 @@ __global__ void k_build_lag_table(GridDev g, int Q_pad, f16x8* __restrict__ G) {
         const long long qs = f / 64;
         const int ls = (int)(qs % LS);
         const int qb = (int)(qs / LS);
-        const int q = qb * 32 + (lane & 31);
+        const int qc = qb * 32 + (lane & 31);
         f16x8 out;
-        if (q >= g.cnt[1] * n_cl) {
+        if (qc >= FC * g.cnt[3]) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) out[j] = (_Float16)0.0f;
         } else {
-            const int fc = q / n_cl, cl = q % n_cl;
-            const double f0 = g.axis[g.off[1] + fc];
-            const double c = g.axis[g.off[2] + cl / g.cnt[3]];
-            const double inv_dt = 1.0 / exp(g.axis[g.off[3] + cl % g.cnt[3]]);
+            const int il = qc / FC, fcc = qc % FC;
+            const double f0 = g.axis[g.off[1] + fcc / g.cnt[2]];
+            const double c = g.axis[g.off[2] + fcc % g.cnt[2]];
+            const double inv_dt = 1.0 / exp(g.axis[g.off[3] + il]);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int e = 16 * ls + 8 * (lane >> 5) + j;
@@ -355,13 +452,96 @@ __global__ void k_build_lag_table(GridDev g, int Q_pad, f16x8* __restrict__ G) {
     }
 }
 
+// Per 32-column block: the first and one past the last k-step holding a
+// nonzero entry (lo = LS, hi = 0 for an all-zero block).  One workgroup per block.
+__global__ void __launch_bounds__(256) k_lag_span(const f16x8* __restrict__ G, int LS, int2* __restrict__ span) {
+    __shared__ int lo, hi;
+    if (threadIdx.x == 0) {
+        lo = LS;
+        hi = 0;
+    }
+    __syncthreads();
+    const uint4* blk = reinterpret_cast<const uint4*>(G) + (size_t)blockIdx.x * LS * 64;
+    int mlo = LS, mhi = 0;
+    for (int f = threadIdx.x; f < LS * 64; f += 256) {
+        const uint4 u = blk[f];
+        // any half with a nonzero magnitude (the sign bit alone is a zero)
+        if (((u.x | u.y | u.z | u.w) & 0x7fff7fffu) != 0u) {
+            const int ks = f / 64;
+            mlo = min(mlo, ks);
+            mhi = max(mhi, ks + 1);
+        }
+    }
+    atomicMin(&lo, mlo);
+    atomicMax(&hi, mhi);
+    __syncthreads();
+    if (threadIdx.x == 0) span[blockIdx.x] = make_int2(lo, hi);
+}
+
+// 1/|g| in the table's column order: inv[tc][qc] (zero past Q)
+__global__ void k_lag_inv(GridDev g, int Q_pad, const float* __restrict__ inv_norm32, float* __restrict__ inv) {
+    const int FC = g.cnt[1] * g.cnt[2], n_ld = g.cnt[3];
+    const int Q = FC * n_ld;
+    const long long total = (long long)g.cnt[0] * Q_pad;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int tc = (int)(k / Q_pad), qc = (int)(k % Q_pad);
+        float v = 0.0f;
+        if (qc < Q) {
+            const int il = qc / FC, fcc = qc % FC;
+            v = inv_norm32[(long long)tc * Q + (long long)fcc * n_ld + il];
+        }
+        inv[k] = v;
+    }
+}
+
+// Tile column-block order for tiles of `cols` columns: blocks sorted by their
+// count of nonzero k-steps (longest first), dealt round-robin to the 8 XCDs'
+// contiguous tile ranges so that each XCD gets the same mix.
+static std::vector<int> lag_block_order(const std::vector<int2>& span, int Q, int cols) {
+    const int n_cbk = (Q + cols - 1) / cols, per = cols / 32;
+    std::vector<std::pair<int, int>> len(n_cbk);
+    for (int k = 0; k < n_cbk; ++k) {
+        int lo = 1 << 30, hi = 0;
+        for (int j = 0; j < per; ++j) {
+            lo = std::min(lo, span[(size_t)k * per + j].x);
+            hi = std::max(hi, span[(size_t)k * per + j].y);
+        }
+        len[k] = {hi > lo ? hi - lo : 0, k};
+    }
+    std::stable_sort(len.begin(), len.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    std::vector<int> order;
+    order.reserve(n_cbk);
+    for (int bin = 0; bin < 8; ++bin)
+        for (int s = bin; s < n_cbk; s += 8) order.push_back(len[s].second);
+    return order;
+}
+
 act_status build_lag_table(act_plan_s* p, hipStream_t s) {
     const int Q_pad = p->lag_q_pad;
-    const long long frags = (long long)(Q_pad / 32) * (2 * p->n_pad / 16) * 64;
+    const int LS = 2 * p->n_pad / 16;
+    const long long frags = (long long)(Q_pad / 32) * LS * 64;
     const long long blocks = std::min<long long>((frags + 255) / 256, (long long)device_cus() * 64);
     hipLaunchKernelGGL(k_build_lag_table, dim3((unsigned)blocks), dim3(256), 0, s, p->grid, Q_pad,
                        (f16x8*)p->table);
     ACT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_lag_span, dim3((unsigned)(Q_pad / 32)), dim3(256), 0, s, (const f16x8*)p->table, LS,
+                       (int2*)p->lag_span);
+    ACT_HIP(hipGetLastError());
+    const long long inv_n = (long long)p->grid.cnt[0] * Q_pad;
+    hipLaunchKernelGGL(k_lag_inv, dim3((unsigned)std::min<long long>((inv_n + 255) / 256, device_cus() * 64LL)),
+                       dim3(256), 0, s, p->grid, Q_pad, p->inv_norm32, p->lag_inv);
+    ACT_HIP(hipGetLastError());
+    std::vector<int2> span(Q_pad / 32);
+    ACT_HIP(hipMemcpyAsync(span.data(), p->lag_span, span.size() * sizeof(int2), hipMemcpyDeviceToHost, s));
+    ACT_HIP(hipStreamSynchronize(s));
+    const int Q = p->grid.cnt[1] * p->n_cl;
+    std::vector<int> order = lag_block_order(span, Q, 128);
+    p->lag_order_wide = (int)order.size();
+    const std::vector<int> wide = lag_block_order(span, Q, 256);
+    order.insert(order.end(), wide.begin(), wide.end());
+    ACT_HIP(hipMemcpyAsync(p->lag_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    ACT_HIP(hipStreamSynchronize(s));
     return ACT_OK;
 }
 
@@ -372,12 +552,16 @@ int lag_chain_length(int n_pad) { return 2 * n_pad + 2; }
 act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s) {
     LagDev ld;
     ld.G = (const f16x8*)p->table;
-    ld.inv_norm = p->inv_norm32;
+    ld.inv = p->lag_inv;
+    ld.span = (const int2*)p->lag_span;
     ld.tc_shift = p->tc_shift;
     ld.shadow = (const _Float16*)p->shadow;
     ld.rscale = p->rscale;
     ld.LS = 2 * p->n_pad / 16;
     ld.Q = p->grid.cnt[1] * p->n_cl;
+    ld.Qp = p->lag_q_pad;
+    ld.FC = p->grid.cnt[1] * p->grid.cnt[2];
+    ld.n_ld = p->grid.cnt[3];
     ld.n_tc = p->grid.cnt[0];
     // rows: the smallest power of two of channels covering the batch (at most
     // 32) times the time centres that fill 128 rows
@@ -393,6 +577,7 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     const bool wide = batch > 1;
     const int cols = wide ? 256 : 128;
     const int n_cbk = (ld.Q + cols - 1) / cols;
+    ld.order = p->lag_order + (wide ? p->lag_order_wide : 0);
     const long long tiles = (long long)n_cbk * n_cg * n_tg;
     long long blocks = (tiles + 7) / 8 * 8;
     const long long cap = grid_cap(p, 1);  // LDS: one workgroup per CU
