@@ -243,7 +243,10 @@ struct act_plan_s {
     double eg_max = 0.0;      // max over atoms of |fl(g_hat) - g_hat|_2 (table rounding)
 
     // per-channel workspace [max_batch]
-    void* shadow = nullptr;   // [B][n_pad] fp32 or bf16 copy of the residual
+    void* shadow = nullptr;   // [B][sh_stride] fp32 / bf16 / fp16 copy of the residual (row 0)
+    void* shadow_alloc = nullptr;  // its allocation (lag-table plans: one zero guard row first)
+    int sh_stride = 0;        // shadow row stride in elements: n_pad; lag-table plans 2 n_pad, the
+                              // n_pad elements after each row zero, so window reads need no bounds
     unsigned* cand_idx = nullptr;   // [B][cap]
     float* cand_score = nullptr;    // [B][cap] search score
     double* cand_p64 = nullptr;     // [B][cap] FP64 rescore

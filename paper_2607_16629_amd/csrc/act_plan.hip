@@ -365,7 +365,7 @@ static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
-                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->lem_cand, p->lem_score, p->shadow, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->lem_cand, p->lem_score, p->shadow_alloc, p->cand_idx, p->cand_score, p->cand_p64,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun, p->lag_inv, p->lag_span, p->lag_order};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -612,6 +612,11 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             const long long Q = (long long)ax[1]->count * p->n_cl;
             p->lag_q_pad = (int)((Q + 255) / 256 * 256);
             p->table_bytes = (size_t)p->lag_q_pad * (2 * p->n_pad) * 2;
+            if ((2.0 * p->max_batch + 1.0) * p->n_pad * 2.0 >= 2147483648.0) {
+                set_error("act_plan: the lag-table search addresses its FP16 residual copy with 32-bit offsets; "
+                          "max_batch x padded length is too large");
+                return fail(ACT_ERR_INVALID);
+            }
             size_t free_b = 0, total_b = 0;
             PLAN_HIP(hipMemGetInfo(&free_b, &total_b));
             if (p->table_bytes + (64ull << 20) > free_b) {
@@ -647,8 +652,17 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMalloc((void**)&p->prior_part, B * prior_workspace_blocks() * sizeof(double)));
         PLAN_HIP(hipMalloc((void**)&p->prior_pidx, B * prior_workspace_blocks() * sizeof(long long)));
     }
-    PLAN_HIP(hipMalloc(&p->shadow, B * p->n_pad * elt));
-    PLAN_HIP(hipMemsetAsync(p->shadow, 0, B * p->n_pad * elt, s));
+    {
+        // lag-table plans: rows 2 n_pad apart after a zero guard of n_pad, so
+        // every lag window of a row lies inside the allocation and reads zeros
+        // outside the row's samples
+        const bool guard = desc->dict == ACT_DICT_LAG;
+        p->sh_stride = guard ? 2 * p->n_pad : p->n_pad;
+        const size_t sh_elems = guard ? (2 * B + 1) * p->n_pad : B * p->n_pad;
+        PLAN_HIP(hipMalloc(&p->shadow_alloc, sh_elems * elt));
+        PLAN_HIP(hipMemsetAsync(p->shadow_alloc, 0, sh_elems * elt, s));
+        p->shadow = (char*)p->shadow_alloc + (guard ? p->n_pad * elt : 0);
+    }
     PLAN_HIP(hipMalloc((void**)&p->cand_idx, B * cap * sizeof(unsigned)));
     PLAN_HIP(hipMalloc((void**)&p->cand_score, B * cap * sizeof(float)));
     PLAN_HIP(hipMalloc((void**)&p->cand_p64, B * cap * sizeof(double)));

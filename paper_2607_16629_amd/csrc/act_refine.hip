@@ -16,6 +16,7 @@ struct PlanDev {
     int prec, dict, cap, chain;
     double eg_max, rho_max;
     void* shadow;
+    int sh_stride;           // shadow row stride (elements)
     unsigned* cand_idx;
     float* cand_score;
     double* cand_p64;
@@ -48,6 +49,7 @@ static PlanDev view(const act_plan_s* p) {
     v.chain = p->chain;
     v.eg_max = p->eg_max;
     v.shadow = p->shadow;
+    v.sh_stride = p->sh_stride;
     v.cand_idx = p->cand_idx;
     v.cand_score = p->cand_score;
     v.cand_p64 = p->cand_p64;
@@ -197,15 +199,15 @@ __device__ double refresh_channel(const PlanDev& P, int b, const double* r, int 
         if (P.prec == ACT_PREC_F16) {
             // search copy r~ = fl16(fl32(r) s) / s, stored scaled
             const _Float16 h = (_Float16)((float)v * scale);
-            ((_Float16*)P.shadow)[(size_t)b * P.g.n_pad + k] = h;
+            ((_Float16*)P.shadow)[(size_t)b * P.sh_stride + k] = h;
             back = (double)(float)h / (double)scale;
         } else if (P.prec == ACT_PREC_BF16) {
             unsigned short h = bf16_rne((float)v);
-            ((unsigned short*)P.shadow)[(size_t)b * P.g.n_pad + k] = h;
+            ((unsigned short*)P.shadow)[(size_t)b * P.sh_stride + k] = h;
             back = (double)__uint_as_float(((unsigned)h) << 16);
         } else {
             const float f = (float)v;
-            ((float*)P.shadow)[(size_t)b * P.g.n_pad + k] = f;
+            ((float*)P.shadow)[(size_t)b * P.sh_stride + k] = f;
             back = (double)f;
         }
         acc[0] += v * v;
@@ -261,16 +263,16 @@ __global__ void __launch_bounds__(256) k_to_shadow(PlanDev P, const double* __re
         if (threadIdx.x == 0) P.rscale[b] = sc;
         for (int k = threadIdx.x; k < P.g.n_pad; k += blockDim.x) {
             const double v = k < P.g.n ? resid[(size_t)b * P.g.n + k] : 0.0;
-            ((_Float16*)P.shadow)[(size_t)b * P.g.n_pad + k] = (_Float16)((float)v * sc);
+            ((_Float16*)P.shadow)[(size_t)b * P.sh_stride + k] = (_Float16)((float)v * sc);
         }
         return;
     }
     for (int k = threadIdx.x; k < P.g.n_pad; k += blockDim.x) {
         const double v = k < P.g.n ? resid[(size_t)b * P.g.n + k] : 0.0;
         if (P.prec == ACT_PREC_BF16)
-            ((unsigned short*)P.shadow)[(size_t)b * P.g.n_pad + k] = bf16_rne((float)v);
+            ((unsigned short*)P.shadow)[(size_t)b * P.sh_stride + k] = bf16_rne((float)v);
         else
-            ((float*)P.shadow)[(size_t)b * P.g.n_pad + k] = (float)v;
+            ((float*)P.shadow)[(size_t)b * P.sh_stride + k] = (float)v;
     }
 }
 

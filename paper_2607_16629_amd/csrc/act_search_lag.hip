@@ -77,7 +77,9 @@ struct LagDev {
     const int2* span;        // [Q_pad/32] k-steps [lo, hi) holding the block's nonzero entries
     const int* order;        // [column blocks] tile column-block order (balanced over the XCDs)
     const int* tc_shift;     // [n_tc] integer sample of each time centre (increasing)
-    const _Float16* shadow;  // [B][n_pad] fl16(fl32(r) s_b), zero past n
+    const char* shadow;      // FP16 search copies fl16(fl32(r) s_b): allocation base; row b at
+                             // element n_pad + b sh_stride, zero past n and in the n_pad-element guards
+    int sh_stride;           // row stride (2 n_pad)
     const float* rscale;     // [B] s_b
     int LS;                  // k-steps of lags (2 N_pad / 16)
     int Q;                   // columns (n_fc n_c n_ld)
@@ -156,29 +158,24 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         if (RERUN && !__syncthreads_or(live)) continue;
 
         // this thread's chunks of the R stages: chunk c = threadIdx.x + 256 i is
-        // (row c / 16, lags 8 (c % 16) ..); a row past the batch or the time
-        // centres reads nothing (zero)
+        // (row c / 16, lags 8 (c % 16) ..).  The window of every lag lies in
+        // the row's guarded slot of the search copy (zero outside the
+        // signal), so the loads need no bounds; a row past the batch or the
+        // time centres reads a valid row and scores zero (1/s_b or 1/|g| is 0).
         constexpr int NCH = LG_ROWS * (LG_S / 8) / 256;
-        int rch[NCH], rm[NCH];
+        unsigned roff[NCH];  // byte offset of the chunk at e = 0
 #pragma unroll
         for (int i = 0; i < NCH; ++i) {
             const int c = threadIdx.x + 256 * i, row = c / 16;
-            const int b = ch0 + (row & (ld.CB - 1)), tc = tc0 + (row >> ld.cb_log2);
-            const bool ok = b < batch && tc < ld.n_tc;
-            rch[i] = ok ? b : -1;
-            rm[i] = ok ? ld.tc_shift[tc] + 8 * (c % 16) - g.n_pad : 0;
+            const int b = min(ch0 + (row & (ld.CB - 1)), batch - 1);
+            const int tc = min(tc0 + (row >> ld.cb_log2), ld.n_tc - 1);
+            roff[i] = 2u * (unsigned)(b * ld.sh_stride + ld.tc_shift[tc] + 8 * (c % 16));
         }
         f16x8 rst[NCH];
         auto load_R = [&](int s) {
-            const int E0 = e_first + LG_S * s;
+            const unsigned e0 = 2u * (unsigned)(e_first + LG_S * s);
 #pragma unroll
-            for (int i = 0; i < NCH; ++i) {
-                const int n0 = E0 + rm[i];  // first sample of the chunk (a multiple of 8)
-                f16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (rch[i] >= 0 && n0 >= 0 && n0 < g.n_pad)
-                    v = *reinterpret_cast<const f16x8*>(ld.shadow + (size_t)rch[i] * g.n_pad + n0);
-                rst[i] = v;
-            }
+            for (int i = 0; i < NCH; ++i) rst[i] = *reinterpret_cast<const f16x8*>(ld.shadow + (roff[i] + e0));
         };
         auto store_R = [&](int buf) {
 #pragma unroll
@@ -197,32 +194,40 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
                 for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.0f;
 
         // B fragments of this wave's columns: k-step ls of column block qb at
-        // G + (qb LS + ls) 64 + lane; loaded half a stage (4 k-steps) ahead
-        const f16x8* gcol[WCB];
+        // byte (qb LS + ls) 1 KiB + 16 lane; loaded half a stage (4 k-steps) ahead
+        const char* gblk[WCB];
 #pragma unroll
         for (int cb = 0; cb < WCB; ++cb)
-            gcol[cb] = ld.G + ((size_t)(cbk * 4 * WCB + w * WCB + cb) * ld.LS) * 64 + lane;
+            gblk[cb] = reinterpret_cast<const char*>(ld.G) + (size_t)(cbk * 4 * WCB + w * WCB + cb) * ld.LS * 1024;
+        const unsigned glane = 16u * (unsigned)lane;
         constexpr int HK = LG_KS / 2;
         f16x8 gh[2][HK][WCB];  // [half of the stage][k-step][column block]
         auto load_G = [&](f16x8 (&dst)[HK][WCB], int s, int half) {
-            const int ls0 = (e_first + LG_S * s) / 16 + HK * half;
+            const unsigned o = 1024u * (unsigned)((e_first + LG_S * s) / 16 + HK * half) + glane;
 #pragma unroll
             for (int ks = 0; ks < HK; ++ks)
 #pragma unroll
-                for (int cb = 0; cb < WCB; ++cb) dst[ks][cb] = gcol[cb][(size_t)(ls0 + ks) * 64];
+                for (int cb = 0; cb < WCB; ++cb)
+                    dst[ks][cb] = *reinterpret_cast<const f16x8*>(gblk[cb] + (o + 1024u * ks));
         };
+        // A fragments one k-step ahead of the MFMAs that use them
         auto mfma_half = [&](const f16x8 (&src)[HK][WCB], int buf, int half) {
+            f16x8 af[2][LG_RB];
+            auto load_A = [&](f16x8 (&dst)[LG_RB], int ks) {
+                const int k8 = 2 * (HK * half + ks) + (lane >> 5);
+#pragma unroll
+                for (int rb = 0; rb < LG_RB; ++rb) dst[rb] = L.a[buf][rb * 32 + (lane & 31)][k8];
+            };
+            load_A(af[0], 0);
 #pragma unroll
             for (int ks = 0; ks < HK; ++ks) {
-                const int k8 = 2 * (HK * half + ks) + (lane >> 5);
-                f16x8 af[LG_RB];
-#pragma unroll
-                for (int rb = 0; rb < LG_RB; ++rb) af[rb] = L.a[buf][rb * 32 + (lane & 31)][k8];
+                if (ks + 1 < HK) load_A(af[(ks + 1) & 1], ks + 1);
 #pragma unroll
                 for (int rb = 0; rb < LG_RB; ++rb)
 #pragma unroll
                     for (int cb = 0; cb < WCB; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb], src[ks][cb], acc[rb][cb], 0, 0, 0);
+                        acc[rb][cb] =
+                            __builtin_amdgcn_mfma_f32_32x32x16_f16(af[ks & 1][rb], src[ks][cb], acc[rb][cb], 0, 0, 0);
             }
         };
 
@@ -243,9 +248,11 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         if (!RERUN && !__syncthreads_or(live)) continue;
 
         // ---- software pipeline over stages: R of stage s+1 loads while stage
-        // s runs (two LDS buffers, one barrier per stage: the other buffer was
-        // last read before the previous barrier); G half-stages load one half
-        // ahead (the scheduling barriers keep the loads ahead of the MFMAs)
+        // s runs and is stored to the other LDS buffer after the first half
+        // (one barrier per stage: that buffer was last read before the
+        // previous barrier); G half-stages load one half ahead.  The
+        // scheduling barriers keep the global loads ahead of the MFMAs and let
+        // LDS reads move across.
         if (ns > 0) store_R(0);
         __syncthreads();
         auto step = [&](int s, auto bufc) {
@@ -253,13 +260,13 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             const int nxt = s + 1 < ns ? s + 1 : s;  // the last stage reloads itself: in range, unused
             load_R(nxt);
             load_G(gh[1], s, 1);
-            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_sched_barrier(0x100);
             mfma_half(gh[0], buf, 0);
-            __builtin_amdgcn_sched_barrier(0);
-            load_G(gh[0], nxt, 0);
-            __builtin_amdgcn_sched_barrier(0);
-            mfma_half(gh[1], buf, 1);
+            __builtin_amdgcn_sched_barrier(0x100);
             store_R(buf ^ 1);
+            load_G(gh[0], nxt, 0);
+            __builtin_amdgcn_sched_barrier(0x100);
+            mfma_half(gh[1], buf, 1);
             __syncthreads();
         };
         for (int s = 0; s < ns; s += 2) {
@@ -555,7 +562,8 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     ld.inv = p->lag_inv;
     ld.span = (const int2*)p->lag_span;
     ld.tc_shift = p->tc_shift;
-    ld.shadow = (const _Float16*)p->shadow;
+    ld.shadow = (const char*)p->shadow_alloc;
+    ld.sh_stride = p->sh_stride;
     ld.rscale = p->rscale;
     ld.LS = 2 * p->n_pad / 16;
     ld.Q = p->grid.cnt[1] * p->n_cl;
