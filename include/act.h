@@ -159,6 +159,17 @@ enum { ACT_Q_ATOMS = 0, ACT_Q_TABLE_BYTES = 1, ACT_Q_N_PAD = 2, ACT_Q_CAND_CAP =
        ACT_Q_WORKSPACE_BYTES = 4 };
 int64_t act_plan_query(act_plan_t plan, int32_t key);
 
+/* Matrix-core work of one pass-0 coarse search of `batch` channels, in flops
+ * (2 per multiply-add), with every channel taking part: for ACT_DICT_LAG
+ * plans, the sum over the launch's tiles of their stages x 128 rows x the
+ * tile's columns x 128 lags x 2.  Tiles run only the lags where their columns
+ * hold nonzero FP16 entries, so this is well below the dense count
+ * 2 atoms n_samples batch (padding rows and columns included).  Diagnostic
+ * for utilisation figures; host-only, no device work.  Errors:
+ * ACT_ERR_INVALID (NULL plan or flops, batch outside [1, max_batch]),
+ * ACT_ERR_UNSUPPORTED (plans of other dictionaries). */
+act_status act_search_flops(act_plan_t plan, int32_t batch, double* flops);
+
 /* Residue-based matching pursuit of `batch` channels for `order` orders
  * (Sec. III-A, Fig. "simplified residue-driven ACT iteration"):
  *   resid_dev   in: the signals, out: the residuals r_P.  f64, channel b at

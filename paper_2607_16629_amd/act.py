@@ -52,7 +52,7 @@ class _PlanDesc(ctypes.Structure):
                 ("prior_act", ctypes.c_int32), ("complex_atoms", ctypes.c_int32)]
 
 
-EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_decompose", "act_lem_decompose",
+EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_search_flops", "act_decompose", "act_lem_decompose",
            "act_refine", "act_value_and_grad", "act_reconstruct", "act_correlate", "act_tune",
            "act_timing_enable", "act_timing_read", "act_status_string", "act_last_error")
 PHASES = ("search", "rerun", "rescore", "select_refine_update")
@@ -100,6 +100,8 @@ def load() -> ctypes.CDLL:
     lib.act_plan_destroy.restype = None
     lib.act_plan_query.argtypes = [vp, i32]
     lib.act_plan_query.restype = i64
+    lib.act_search_flops.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+    lib.act_search_flops.restype = i32
     lib.act_decompose.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.act_decompose.restype = ctypes.c_int
     lib.act_refine.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp]
@@ -207,6 +209,12 @@ class Plan:
 
     def query(self, key: int) -> int:
         return int(load().act_plan_query(self._h, key))
+
+    def search_flops(self, batch: int) -> float:
+        """Matrix-core flops of one pass-0 search of `batch` channels (lag-table plans)."""
+        out = ctypes.c_double(0.0)
+        _check(load().act_search_flops(self._h, int(batch), ctypes.byref(out)))
+        return out.value
 
     @property
     def atoms(self) -> int:

@@ -236,6 +236,8 @@ struct act_plan_s {
     int* lag_span = nullptr;  // ACT_DICT_LAG: [lag_q_pad / 32] k-step range of each block's nonzero entries
     int* lag_order = nullptr; // ACT_DICT_LAG: tile column-block orders (128-column tiles, then 256)
     int lag_order_wide = 0;   // ACT_DICT_LAG: offset of the 256-column order in lag_order
+    std::vector<int> lag_span_host;  // ACT_DICT_LAG: host copy of lag_span (lo, hi pairs)
+    std::vector<int> tc_shift_host;  // host copy of tc_shift
     double shift_eps = 0.0;   // synthesised / lag searches: relative score error of rounding the
                               // time centres to integer samples
     double trunc_tail = 0.0;  // largest sqrt(envelope tail energy) outside the supports
@@ -337,6 +339,7 @@ int synth_chain_length(int n_pad);
 int h16_chain_length(int n_pad);
 int lag_chain_length(int n_pad);
 act_status build_lag_table(act_plan_s* p, hipStream_t s);
+double lag_search_flops(const act_plan_s* p, int batch);
 struct SearchCtl;
 act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s);
 act_status launch_reconstruct(act_plan_s* p, int batch, int order, const double* theta,

@@ -607,6 +607,7 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         PLAN_HIP(hipMalloc((void**)&p->inv_norm32, (size_t)atoms * sizeof(float)));
         PLAN_HIP(hipMalloc((void**)&p->tc_shift, shift.size() * sizeof(int)));
         PLAN_HIP(hipMemcpyAsync(p->tc_shift, shift.data(), shift.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        p->tc_shift_host = shift;
         p->table_bytes = 0;
         if (desc->dict == ACT_DICT_LAG) {
             const long long Q = (long long)ax[1]->count * p->n_cl;
@@ -707,4 +708,15 @@ extern "C" int64_t act_plan_query(act_plan_t p, int32_t key) {
         case ACT_Q_WORKSPACE_BYTES: return (int64_t)p->workspace_bytes;
         default: return -1;
     }
+}
+
+extern "C" act_status act_search_flops(act_plan_t p, int32_t batch, double* flops) {
+    ACT_REQUIRE(p != nullptr && flops != nullptr, "act_search_flops: plan or flops is NULL");
+    ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, "act_search_flops: batch outside [1, max_batch]");
+    if (p->desc.dict != ACT_DICT_LAG) {
+        set_error("act_search_flops: only the lag-table search has a counted matrix-core workload");
+        return ACT_ERR_UNSUPPORTED;
+    }
+    *flops = lag_search_flops(p, batch);
+    return ACT_OK;
 }

@@ -543,6 +543,11 @@ act_status build_lag_table(act_plan_s* p, hipStream_t s) {
     ACT_HIP(hipMemcpyAsync(span.data(), p->lag_span, span.size() * sizeof(int2), hipMemcpyDeviceToHost, s));
     ACT_HIP(hipStreamSynchronize(s));
     const int Q = p->grid.cnt[1] * p->n_cl;
+    p->lag_span_host.resize(2 * span.size());
+    for (size_t k = 0; k < span.size(); ++k) {
+        p->lag_span_host[2 * k] = span[k].x;
+        p->lag_span_host[2 * k + 1] = span[k].y;
+    }
     std::vector<int> order = lag_block_order(span, Q, 128);
     p->lag_order_wide = (int)order.size();
     const std::vector<int> wide = lag_block_order(span, Q, 256);
@@ -550,6 +555,35 @@ act_status build_lag_table(act_plan_s* p, hipStream_t s) {
     ACT_HIP(hipMemcpyAsync(p->lag_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
     ACT_HIP(hipStreamSynchronize(s));
     return ACT_OK;
+}
+
+// Flops one pass-0 launch executes on the matrix cores: every tile's stages
+// (its rows' lag window cut to its columns' band) x 128 rows x the tile's
+// columns x 128 lags x 2 -- the tiling of launch_search_lag and k_search_lag.
+double lag_search_flops(const act_plan_s* p, int batch) {
+    const int n_tc = p->grid.cnt[0], Q = p->grid.cnt[1] * p->n_cl, n_pad = p->n_pad, n = p->grid.n;
+    int CB = 1;
+    while (CB < batch && CB < 32) CB *= 2;
+    const int TB = LG_ROWS / CB, n_cg = (batch + CB - 1) / CB, n_tg = (n_tc + TB - 1) / TB;
+    const int cols = batch > 1 ? 256 : 128, per = cols / 32, n_cbk = (Q + cols - 1) / cols;
+    const int LS = 2 * n_pad / 16;
+    long long stages = 0;
+    for (int k = 0; k < n_cbk; ++k) {
+        int klo = LS, khi = 0;
+        for (int j = 0; j < per; ++j) {
+            klo = std::min(klo, p->lag_span_host[2 * (k * per + j)]);
+            khi = std::max(khi, p->lag_span_host[2 * (k * per + j) + 1]);
+        }
+        for (int tg = 0; tg < n_tg; ++tg) {
+            const int tc0 = tg * TB, tc_last = std::min(tc0 + TB, n_tc) - 1;
+            const int m_min = p->tc_shift_host[tc0], m_max = p->tc_shift_host[tc_last];
+            const int e_first = std::max((n_pad - m_max) / LG_S, 16 * klo / LG_S) * LG_S;
+            const int e_end = std::min(std::min(2 * n_pad, n_pad + n - m_min), 16 * khi);
+            const int ns = e_end > e_first ? (e_end - e_first + LG_S - 1) / LG_S : 0;
+            stages += (long long)ns * n_cg;
+        }
+    }
+    return (double)stages * LG_ROWS * cols * LG_S * 2.0;
 }
 
 // FP32 accumulation chain of one score: at most one rounding per lag (2 N_pad)

@@ -102,6 +102,8 @@ def test_null_arguments_rejected(lib):
     assert lib.act_correlate(None, 1, None, 0, 1, None, None) == A.ACT_ERR_INVALID
     assert lib.act_tune(None, 1, None, None, None, 3, None, None, None) == A.ACT_ERR_INVALID
     assert lib.act_plan_query(None, 0) == -1
+    flops = ctypes.c_double(0.0)
+    assert lib.act_search_flops(None, 1, ctypes.byref(flops)) == A.ACT_ERR_INVALID
     lib.act_plan_destroy(None)
 
 

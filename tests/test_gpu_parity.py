@@ -1034,6 +1034,33 @@ def test_lag_table_partial_tiles_and_edge_channels(oracle):
     np.testing.assert_array_equal(gpu["energy"][3], 0.0)
 
 
+def test_lag_search_flops_counts_the_band_stages():
+    """The executed matrix-core work of the lag-table search: a whole number
+    of 128-lag stages of 128-row tiles, the same for every batch with the same
+    channel groups, below the dense count of the table's full lag range, and
+    unsupported for other dictionaries."""
+    act = A()
+    g = W.eeg_grid(2048, 64, 64, 32, 16)
+    plan = act.Plan(g, dict_="lag", prec="f16", max_batch=64)
+    unit = 128 * 256 * 128 * 2.0  # one stage of a 256-column tile
+    f64 = plan.search_flops(64)
+    assert f64 > 0 and f64 % unit == 0
+    assert plan.search_flops(33) == f64  # two groups of 32 channels either way
+    assert plan.search_flops(32) == f64 / 2
+    # every tile running all 2 n_pad lags of the table
+    n_pad = plan.query(act.Q_N_PAD)
+    full = (g.size // g.tc.count // 256) * 2 * (g.tc.count // 4) * (2 * n_pad // 128) * unit
+    assert f64 < 0.7 * full
+    assert plan.search_flops(1) % (128 * 128 * 128 * 2.0) == 0
+    with pytest.raises(act.ActError) as e:
+        plan.search_flops(65)
+    assert e.value.status == act.ACT_ERR_INVALID
+    other = act.Plan(W.eeg_grid(512, 8, 8, 4, 2), dict_="synth", prec="f32")
+    with pytest.raises(act.ActError) as e:
+        other.search_flops(1)
+    assert e.value.status == act.ACT_ERR_UNSUPPORTED
+
+
 def test_lag_table_rejects_unaligned_time_centres():
     act = A()
     g = W.Grid(256.0, 512, W.Axis(0.0, 2.0, 13, True), W.Axis(2.0, 60.0, 8, False),
