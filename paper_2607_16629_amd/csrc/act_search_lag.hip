@@ -97,6 +97,8 @@ struct LagLds {
     float M[LG_ROWS];        // emission threshold per channel slot
     float rinv[LG_ROWS];     // 1/s_b per channel slot
     unsigned emit;           // bit g: some row 32 rb + g reaches its channel's threshold
+    unsigned cnt[32];        // per channel slot: the tile's candidates, then their running position
+    int base[32];            // per channel slot: first list entry reserved for the tile
 };
 static_assert(sizeof(f16x8) * 2 * LG_ROWS * (LG_PAD / 8) >= 128 * 128 * sizeof(float), "1/|g| staging fits");
 
@@ -154,6 +156,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             live = DUMP || (eb >= 0.0 && (!RERUN || ctl.need_rerun[b]));
         }
         if (threadIdx.x == 0) L.emit = 0u;
+        if (threadIdx.x < 32) L.cnt[threadIdx.x] = 0u;
         // the rerun pass skips most tiles: vote before any load
         if (RERUN && !__syncthreads_or(live)) continue;
 
@@ -390,33 +393,51 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             L.M[sl] = T;
         }
         __syncthreads();
+        // Emission in two sweeps over the flagged row groups: count each
+        // channel slot's candidates in LDS, reserve their list entries with
+        // one device atomic per slot, then place them.
         const unsigned em = __builtin_amdgcn_readfirstlane(L.emit);
         if (em) {
+            auto sweep = [&](bool place) {
 #pragma unroll
-            for (int rb = 0; rb < LG_RB; ++rb)
+                for (int rb = 0; rb < LG_RB; ++rb)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    // the wave's two row groups of v: g = 8 (v / 4) + v % 4 and g + 4
-                    if (!((em >> (8 * (v >> 2) + (v & 3))) & 0x11u)) continue;
-                    const int gr = lg_row(v, elane);
-                    const int row = rb * 32 + gr, t = row >> ld.cb_log2, tc = tc0 + t;
-                    if (((em >> gr) & 1u) && tc < ld.n_tc) {
-                        const int sl = gr & (ld.CB - 1), b = ch0 + sl;
-                        const float T = L.M[sl];
+                    for (int v = 0; v < 16; ++v) {
+                        // the wave's two row groups of v: g = 8 (v / 4) + v % 4 and g + 4
+                        if (!((em >> (8 * (v >> 2) + (v & 3))) & 0x11u)) continue;
+                        const int gr = lg_row(v, elane);
+                        const int row = rb * 32 + gr, t = row >> ld.cb_log2, tc = tc0 + t;
+                        if (((em >> gr) & 1u) && tc < ld.n_tc) {
+                            const int sl = gr & (ld.CB - 1), b = ch0 + sl;
+                            const float T = L.M[sl];
 #pragma unroll
-                        for (int cb = 0; cb < WCB; ++cb) {
-                            const int c = (w * WCB + cb) * 32 + (elane & 31);
-                            const float p = acc[rb][cb][v];
-                            if (q0 + c < ld.Q && fabsf(p) >= T) {
-                                const int j = atomicAdd(&ctl.cand_count[b], 1);
-                                if (j < ctl.cap) {
-                                    ctl.cand_idx[(size_t)b * ctl.cap + j] = (unsigned)lag_atom(ld, tc, q0 + c);
-                                    ctl.cand_score[(size_t)b * ctl.cap + j] = p;
+                            for (int cb = 0; cb < WCB; ++cb) {
+                                const int c = (w * WCB + cb) * 32 + (elane & 31);
+                                const float p = acc[rb][cb][v];
+                                if (q0 + c < ld.Q && fabsf(p) >= T) {
+                                    if (!place) {
+                                        atomicAdd(&L.cnt[sl], 1u);
+                                    } else {
+                                        const int j = L.base[sl] + (int)atomicAdd(&L.cnt[sl], 1u);
+                                        if (j < ctl.cap) {
+                                            ctl.cand_idx[(size_t)b * ctl.cap + j] = (unsigned)lag_atom(ld, tc, q0 + c);
+                                            ctl.cand_score[(size_t)b * ctl.cap + j] = p;
+                                        }
+                                    }
                                 }
                             }
                         }
                     }
-                }
+            };
+            sweep(false);
+            __syncthreads();
+            if (threadIdx.x < ld.CB) {
+                const unsigned n = L.cnt[threadIdx.x];
+                L.base[threadIdx.x] = n ? atomicAdd(&ctl.cand_count[ch0 + threadIdx.x], (int)n) : 0;
+                L.cnt[threadIdx.x] = 0u;
+            }
+            __syncthreads();
+            sweep(true);
         }
         __syncthreads();  // L.gm / L.M / L.emit / the R buffers are rewritten by the next tile
     }
