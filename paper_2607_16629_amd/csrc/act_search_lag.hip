@@ -232,6 +232,16 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
                         acc[rb][cb] =
                             __builtin_amdgcn_mfma_f32_32x32x16_f16(af[ks & 1][rb], src[ks][cb], acc[rb][cb], 0, 0, 0);
             }
+            // order: the first k-step's A reads, then each k-step's MFMAs in
+            // pairs with one A read of the next k-step between them
+            __builtin_amdgcn_sched_group_barrier(0x100, LG_RB, 0);
+#pragma unroll
+            for (int ks = 0; ks < HK; ++ks)
+#pragma unroll
+                for (int rb = 0; rb < LG_RB; ++rb) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, WCB, 0);
+                    if (ks + 1 < HK) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
         };
 
         // the first stage's loads and the first 1024 of the tile's inverse
