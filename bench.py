@@ -51,6 +51,8 @@ WORKLOADS = {
     # complex (analytic) atoms: two correlations per atom (real and imaginary part)
     "complex-f32-64x2048-synth": ("batched_64x2048", dict(dict_="synth", prec="f32", complex_atoms=True),
                                   "mfma_f32", 0),
+    "complex-lag-f16-64x2048": ("batched_64x2048", dict(dict_="lag", prec="f16", complex_atoms=True),
+                                "mfma_f16", 0),
 }
 KERNELS = {("table", "f32"): ("k_search_f32_table", "act_search_f32t.hip"),
            ("table", "bf16"): ("k_search_bf16_table", "act_search_bf16.hip"),

@@ -273,7 +273,7 @@ act_status build_lag(act_plan_s* p, hipStream_t s) {
     ACT_HIP(hipMemsetAsync(rb, 0, sizeof(unsigned long long), s));
     const int cus = device_cus();
     hipLaunchKernelGGL(k_norms_rho, dim3((unsigned)std::min<long long>((p->atoms + 3) / 4, cus * 32LL)), dim3(256),
-                       0, s, p->grid, p->inv_norm, p->inv_norm32, rb, 0);
+                       0, s, p->grid, p->inv_norm, p->inv_norm32, rb, p->desc.complex_atoms);
     ACT_HIP(hipGetLastError());
     act_status st = build_lag_table(p, s);
     ACT_HIP(hipStreamSynchronize(s));
@@ -415,9 +415,11 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     }
     ACT_REQUIRE(desc->complex_atoms == 0 || desc->complex_atoms == 1, "act_plan: complex_atoms must be 0 or 1");
     if (desc->complex_atoms &&
-        !(desc->dict == ACT_DICT_SYNTH && (desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32) &&
+        !(((desc->dict == ACT_DICT_SYNTH && (desc->prec == ACT_PREC_F64 || desc->prec == ACT_PREC_F32)) ||
+           (desc->dict == ACT_DICT_LAG && desc->prec == ACT_PREC_F16)) &&
           !desc->ragged && !desc->prior_act && !desc->support_cut)) {
-        set_error("act_plan: complex_atoms needs a plain ACT_DICT_SYNTH plan with ACT_PREC_F64 or ACT_PREC_F32");
+        set_error("act_plan: complex_atoms needs a plain ACT_DICT_SYNTH plan with ACT_PREC_F64 or ACT_PREC_F32, "
+                  "or an ACT_DICT_LAG plan");
         return ACT_ERR_UNSUPPORTED;
     }
     ACT_REQUIRE(!(desc->prec == ACT_PREC_F64 && desc->dict == ACT_DICT_TABLE),
@@ -435,9 +437,9 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             return ACT_ERR_UNSUPPORTED;
         }
     }
-    if (desc->dict == ACT_DICT_LAG && !(desc->prec == ACT_PREC_F16 && !desc->ragged && !desc->complex_atoms &&
-                                        !desc->prior_act && !desc->support_cut)) {
-        set_error("act_plan: ACT_DICT_LAG is the FP16 lag-table search of plain plans of real atoms");
+    if (desc->dict == ACT_DICT_LAG && !(desc->prec == ACT_PREC_F16 && !desc->ragged && !desc->prior_act &&
+                                        !desc->support_cut)) {
+        set_error("act_plan: ACT_DICT_LAG is the FP16 lag-table search of plain plans");
         return ACT_ERR_UNSUPPORTED;
     }
     if (desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_BF16) {
@@ -611,7 +613,10 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         p->table_bytes = 0;
         if (desc->dict == ACT_DICT_LAG) {
             const long long Q = (long long)ax[1]->count * p->n_cl;
-            p->lag_q_pad = (int)((Q + 255) / 256 * 256);
+            // complex atoms: a 32-column block of cos parts, then the block of
+            // their sin parts
+            const long long cols = desc->complex_atoms ? 2 * ((Q + 31) / 32 * 32) : Q;
+            p->lag_q_pad = (int)((cols + 255) / 256 * 256);
             p->table_bytes = (size_t)p->lag_q_pad * (2 * p->n_pad) * 2;
             if ((2.0 * p->max_batch + 1.0) * p->n_pad * 2.0 >= 2147483648.0) {
                 set_error("act_plan: the lag-table search addresses its FP16 residual copy with 32-bit offsets; "

@@ -110,6 +110,14 @@ __device__ double score_bound(const PlanDev& P, double rn, double er, double sca
         const double u16 = 4.8828125e-04;
         const double eg = u16 + u32 + 2.98023223876953125e-08 * sqrt(2.0 * n);
         (void)scale;
+        if (P.cplx) {
+            // complex atoms: each part a = <E cos phi, r>, b = <E sin phi, r>
+            // carries the real bound with |E_w cos phi| <= |E_w| (|E_w| >= 1);
+            // |sqrt(a~^2 + b~^2) - sqrt(a^2 + b^2)| <= |(da, db)| <= sqrt(2) x
+            // that, and the squares, sum, root and the two scalings add 6 u |r~|
+            const double part = eg * rt + er + gam * (1.0 + eg) * rt + P.shift_eps * rt;
+            return 1.01 * (1.4142135623730951 * part + 6.0 * u32 * rt);
+        }
         return 1.01 * (eg * rt + er + gam * (1.0 + eg) * rt + 3.0 * u32 * rt + P.shift_eps * rt);
     }
     if (P.prec == ACT_PREC_F16) {

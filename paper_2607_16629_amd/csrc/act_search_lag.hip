@@ -109,11 +109,17 @@ __device__ __forceinline__ long long lag_atom(const LagDev& ld, int tc, int qc) 
     return (long long)tc * ld.Q + (long long)fcc * ld.n_ld + l;
 }
 
-template <int WCB, bool RERUN, bool DUMP>
+// CPLX: complex atoms.  A wave's two column blocks are the cos and sin parts
+// of the same 32 atoms, so a lane's two accumulators are (a, b) of one atom and
+// its score is sqrt(a^2 + b^2) / |E_w|.
+template <int WCB, bool RERUN, bool DUMP, bool CPLX>
 __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, SearchCtl ctl, int batch,
                                                        int n_cbk, int n_cg, int n_tg) {
+    static_assert(!CPLX || WCB == 2, "complex atoms pair two column blocks");
     __shared__ LagLds L;
     constexpr int COLS = 4 * WCB * 32;
+    constexpr int ACOLS = CPLX ? COLS / 2 : COLS;  // atoms of a tile
+    constexpr int NA = CPLX ? 1 : WCB;              // atoms of a lane per accumulator row
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long n_rbk = (long long)n_cg * n_tg;
     const long long tiles = (long long)n_cbk * n_rbk;
@@ -126,6 +132,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         const int cg = rbk % n_cg, tg = rbk / n_cg;
         const int ch0 = cg * ld.CB, tc0 = tg * ld.TB;
         const int q0 = cbk * COLS;
+        const int aq0 = cbk * ACOLS;  // first atom (in the table's order) of the tile
 
         // lags that meet the tile's rows, e = d + N_pad with 0 <= d + m < n,
         // cut to the k-steps where the tile's columns hold nonzero entries:
@@ -250,12 +257,12 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             load_R(0);
             load_G(gh[0], 0, 0);
         }
-        const int n_inv = ld.TB * COLS;
+        const int n_inv = ld.TB * ACOLS;
         float4 inv_pf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         {
-            const int idx = 4 * threadIdx.x, t = idx / COLS, c = idx % COLS;
+            const int idx = 4 * threadIdx.x, t = idx / ACOLS, c = idx % ACOLS;
             if (idx < n_inv && tc0 + t < ld.n_tc)
-                inv_pf = *reinterpret_cast<const float4*>(ld.inv + (size_t)(tc0 + t) * ld.Qp + q0 + c);
+                inv_pf = *reinterpret_cast<const float4*>(ld.inv + (size_t)(tc0 + t) * ld.Qp + aq0 + c);
         }
         // skip tiles none of whose channels take part
         if (!RERUN && !__syncthreads_or(live)) continue;
@@ -297,10 +304,10 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             float4 vv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int idx = base + 1024 * u + 4 * threadIdx.x, t = idx / COLS, c = idx % COLS;
+                const int idx = base + 1024 * u + 4 * threadIdx.x, t = idx / ACOLS, c = idx % ACOLS;
                 vv[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if (idx < n_inv && tc0 + t < ld.n_tc)
-                    vv[u] = *reinterpret_cast<const float4*>(ld.inv + (size_t)(tc0 + t) * ld.Qp + q0 + c);
+                    vv[u] = *reinterpret_cast<const float4*>(ld.inv + (size_t)(tc0 + t) * ld.Qp + aq0 + c);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -314,6 +321,11 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         // loop (they would stay live across it and spill)
         int elane = lane;
         asm volatile("" : "+v"(elane));
+        // the lane's atom of accumulator block cb (tile order) and its raw score
+        auto acol = [&](int cb) { return CPLX ? w * 32 + (elane & 31) : (w * WCB + cb) * 32 + (elane & 31); };
+        auto raw = [&](int rb, int cb, int v) {
+            return CPLX ? sqrtf(acc[rb][0][v] * acc[rb][0][v] + acc[rb][1][v] * acc[rb][1][v]) : acc[rb][cb][v];
+        };
         __syncthreads();
         // A lane's rows are r = 32 rb + g, g = lg_row(v, lane): the channel
         // slot g % CB does not depend on rb (CB divides 32), so a channel's
@@ -329,11 +341,11 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
                     const float rinv = L.rinv[sl];
                     const int b = ch0 + sl, tc = tc0 + t;
 #pragma unroll
-                    for (int cb = 0; cb < WCB; ++cb) {
-                        const int c = (w * WCB + cb) * 32 + (elane & 31);
-                        const float p = (acc[rb][cb][v] * invs[t * COLS + c]) * rinv;
-                        if (b < batch && tc < ld.n_tc && q0 + c < ld.Q) {
-                            const long long i = lag_atom(ld, tc, q0 + c);
+                    for (int cb = 0; cb < NA; ++cb) {
+                        const int c = acol(cb);
+                        const float p = (raw(rb, cb, v) * invs[t * ACOLS + c]) * rinv;
+                        if (b < batch && tc < ld.n_tc && aq0 + c < ld.Q) {
+                            const long long i = lag_atom(ld, tc, aq0 + c);
                             if (i >= ctl.dump_begin && i < ctl.dump_begin + ctl.dump_count)
                                 ctl.dump[(size_t)b * ctl.dump_count + (i - ctl.dump_begin)] = p;
                         }
@@ -352,8 +364,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             for (int rb = 0; rb < LG_RB; ++rb) {
                 const int t = (rb * 32 + gr) >> ld.cb_log2;
 #pragma unroll
-                for (int cb = 0; cb < WCB; ++cb)
-                    dst[rb][cb] = invs[t * COLS + (w * WCB + cb) * 32 + (elane & 31)];  // 0 past the dictionary
+                for (int cb = 0; cb < NA; ++cb) dst[rb][cb] = invs[t * ACOLS + acol(cb)];  // 0 past the dictionary
             }
         };
         load_sc(0, sc[0], ri[0]);
@@ -364,8 +375,8 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
 #pragma unroll
             for (int rb = 0; rb < LG_RB; ++rb)
 #pragma unroll
-                for (int cb = 0; cb < WCB; ++cb) {
-                    const float p = (acc[rb][cb][v] * sc[v & 1][rb][cb]) * ri[v & 1];
+                for (int cb = 0; cb < NA; ++cb) {
+                    const float p = (raw(rb, cb, v) * sc[v & 1][rb][cb]) * ri[v & 1];
                     acc[rb][cb][v] = p;
                     m = fmaxf(m, fabsf(p));
                 }
@@ -421,16 +432,16 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
                             const int sl = gr & (ld.CB - 1), b = ch0 + sl;
                             const float T = L.M[sl];
 #pragma unroll
-                            for (int cb = 0; cb < WCB; ++cb) {
-                                const int c = (w * WCB + cb) * 32 + (elane & 31);
+                            for (int cb = 0; cb < NA; ++cb) {
+                                const int c = acol(cb);
                                 const float p = acc[rb][cb][v];
-                                if (q0 + c < ld.Q && fabsf(p) >= T) {
+                                if (aq0 + c < ld.Q && fabsf(p) >= T) {
                                     if (!place) {
                                         atomicAdd(&L.cnt[sl], 1u);
                                     } else {
                                         const int j = L.base[sl] + (int)atomicAdd(&L.cnt[sl], 1u);
                                         if (j < ctl.cap) {
-                                            ctl.cand_idx[(size_t)b * ctl.cap + j] = (unsigned)lag_atom(ld, tc, q0 + c);
+                                            ctl.cand_idx[(size_t)b * ctl.cap + j] = (unsigned)lag_atom(ld, tc, aq0 + c);
                                             ctl.cand_score[(size_t)b * ctl.cap + j] = p;
                                         }
                                     }
@@ -457,7 +468,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
 // in MFMA B-operand order; columns past Q are zero.  Columns run log-duration
 // major, qc = ld FC + (f_c n_c + c), so a tile's columns share an envelope and
 // its nonzero lags.
-__global__ void k_build_lag_table(GridDev g, int Q_pad, f16x8* __restrict__ G) {
+__global__ void k_build_lag_table(GridDev g, int Q_pad, int cplx, f16x8* __restrict__ G) {
     const int FC = g.cnt[1] * g.cnt[2];
     const int LS = 2 * g.n_pad / 16;
     const long long frags = (long long)(Q_pad / 32) * LS * 64;  // one f16x8 per (column block, k-step, lane)
@@ -467,7 +478,10 @@ __global__ void k_build_lag_table(GridDev g, int Q_pad, f16x8* __restrict__ G) {
         const long long qs = f / 64;
         const int ls = (int)(qs % LS);
         const int qb = (int)(qs / LS);
-        const int qc = qb * 32 + (lane & 31);
+        // complex atoms: block 2 k holds the cos parts of atoms 32 k.., block
+        // 2 k + 1 their sin parts
+        const int qc = cplx ? (qb >> 1) * 32 + (lane & 31) : qb * 32 + (lane & 31);
+        const bool sin_part = cplx && (qb & 1);
         f16x8 out;
         if (qc >= FC * g.cnt[3]) {
 #pragma unroll
@@ -482,7 +496,8 @@ __global__ void k_build_lag_table(GridDev g, int Q_pad, f16x8* __restrict__ G) {
                 const int e = 16 * ls + 8 * (lane >> 5) + j;
                 const double tau = (double)(e - g.n_pad) / g.fs;
                 const double u = tau * inv_dt;
-                const double v = exp(-0.5 * u * u) * cospi(2.0 * (c * tau * tau + f0 * tau));
+                const double ph = 2.0 * (c * tau * tau + f0 * tau);
+                const double v = exp(-0.5 * u * u) * (sin_part ? sinpi(ph) : cospi(ph));
                 out[j] = (_Float16)(float)v;
             }
         }
@@ -516,7 +531,8 @@ __global__ void __launch_bounds__(256) k_lag_span(const f16x8* __restrict__ G, i
     if (threadIdx.x == 0) span[blockIdx.x] = make_int2(lo, hi);
 }
 
-// 1/|g| in the table's column order: inv[tc][qc] (zero past Q)
+// 1/|g| in the table's atom order: inv[tc][qc] (zero past Q); Q_pad is the row
+// length (the table's columns, or half of them for complex atoms)
 __global__ void k_lag_inv(GridDev g, int Q_pad, const float* __restrict__ inv_norm32, float* __restrict__ inv) {
     const int FC = g.cnt[1] * g.cnt[2], n_ld = g.cnt[3];
     const int Q = FC * n_ld;
@@ -561,27 +577,29 @@ act_status build_lag_table(act_plan_s* p, hipStream_t s) {
     const long long frags = (long long)(Q_pad / 32) * LS * 64;
     const long long blocks = std::min<long long>((frags + 255) / 256, (long long)device_cus() * 64);
     hipLaunchKernelGGL(k_build_lag_table, dim3((unsigned)blocks), dim3(256), 0, s, p->grid, Q_pad,
-                       (f16x8*)p->table);
+                       p->desc.complex_atoms, (f16x8*)p->table);
     ACT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_lag_span, dim3((unsigned)(Q_pad / 32)), dim3(256), 0, s, (const f16x8*)p->table, LS,
                        (int2*)p->lag_span);
     ACT_HIP(hipGetLastError());
-    const long long inv_n = (long long)p->grid.cnt[0] * Q_pad;
+    const int inv_row = p->desc.complex_atoms ? Q_pad / 2 : Q_pad;
+    const long long inv_n = (long long)p->grid.cnt[0] * inv_row;
     hipLaunchKernelGGL(k_lag_inv, dim3((unsigned)std::min<long long>((inv_n + 255) / 256, device_cus() * 64LL)),
-                       dim3(256), 0, s, p->grid, Q_pad, p->inv_norm32, p->lag_inv);
+                       dim3(256), 0, s, p->grid, inv_row, p->inv_norm32, p->lag_inv);
     ACT_HIP(hipGetLastError());
     std::vector<int2> span(Q_pad / 32);
     ACT_HIP(hipMemcpyAsync(span.data(), p->lag_span, span.size() * sizeof(int2), hipMemcpyDeviceToHost, s));
     ACT_HIP(hipStreamSynchronize(s));
     const int Q = p->grid.cnt[1] * p->n_cl;
+    const int ncols = p->desc.complex_atoms ? 2 * ((Q + 31) / 32 * 32) : Q;
     p->lag_span_host.resize(2 * span.size());
     for (size_t k = 0; k < span.size(); ++k) {
         p->lag_span_host[2 * k] = span[k].x;
         p->lag_span_host[2 * k + 1] = span[k].y;
     }
-    std::vector<int> order = lag_block_order(span, Q, 128);
+    std::vector<int> order = lag_block_order(span, ncols, 128);
     p->lag_order_wide = (int)order.size();
-    const std::vector<int> wide = lag_block_order(span, Q, 256);
+    const std::vector<int> wide = lag_block_order(span, ncols, 256);
     order.insert(order.end(), wide.begin(), wide.end());
     ACT_HIP(hipMemcpyAsync(p->lag_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
     ACT_HIP(hipStreamSynchronize(s));
@@ -593,10 +611,12 @@ act_status build_lag_table(act_plan_s* p, hipStream_t s) {
 // columns x 128 lags x 2 -- the tiling of launch_search_lag and k_search_lag.
 double lag_search_flops(const act_plan_s* p, int batch) {
     const int n_tc = p->grid.cnt[0], Q = p->grid.cnt[1] * p->n_cl, n_pad = p->n_pad, n = p->grid.n;
+    const bool cplx = p->desc.complex_atoms != 0;
+    const int ncols = cplx ? 2 * ((Q + 31) / 32 * 32) : Q;
     int CB = 1;
     while (CB < batch && CB < 32) CB *= 2;
     const int TB = LG_ROWS / CB, n_cg = (batch + CB - 1) / CB, n_tg = (n_tc + TB - 1) / TB;
-    const int cols = batch > 1 ? 256 : 128, per = cols / 32, n_cbk = (Q + cols - 1) / cols;
+    const int cols = (batch > 1 || cplx) ? 256 : 128, per = cols / 32, n_cbk = (ncols + cols - 1) / cols;
     const int LS = 2 * n_pad / 16;
     long long stages = 0;
     for (int k = 0; k < n_cbk; ++k) {
@@ -632,7 +652,8 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     ld.rscale = p->rscale;
     ld.LS = 2 * p->n_pad / 16;
     ld.Q = p->grid.cnt[1] * p->n_cl;
-    ld.Qp = p->lag_q_pad;
+    const bool cplx = p->desc.complex_atoms != 0;
+    ld.Qp = cplx ? p->lag_q_pad / 2 : p->lag_q_pad;  // row length of the inverse norms (atoms)
     ld.FC = p->grid.cnt[1] * p->grid.cnt[2];
     ld.n_ld = p->grid.cnt[3];
     ld.n_tc = p->grid.cnt[0];
@@ -646,27 +667,33 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     while ((1 << ld.cb_log2) < CB) ++ld.cb_log2;
     const int n_cg = (batch + CB - 1) / CB;
     const int n_tg = (ld.n_tc + ld.TB - 1) / ld.TB;
-    // one channel: 128 columns per tile (twice the tiles); several: 256
-    const bool wide = batch > 1;
+    // one channel of real atoms: 128 columns per tile (twice the tiles);
+    // otherwise 256 (complex atoms: 128 atoms, cos and sin blocks paired)
+    const bool wide = batch > 1 || cplx;
     const int cols = wide ? 256 : 128;
-    const int n_cbk = (ld.Q + cols - 1) / cols;
+    const int ncols = cplx ? 2 * ((ld.Q + 31) / 32 * 32) : ld.Q;
+    const int n_cbk = (ncols + cols - 1) / cols;
     ld.order = p->lag_order + (wide ? p->lag_order_wide : 0);
     const long long tiles = (long long)n_cbk * n_cg * n_tg;
     long long blocks = (tiles + 7) / 8 * 8;
     const long long cap = grid_cap(p, 1);  // LDS: one workgroup per CU
     blocks = blocks < cap ? blocks : cap;
     const dim3 grid((unsigned)blocks), blk(256);
-#define LAG_LAUNCH(WCB, RR, DD)                                                                       \
-    hipLaunchKernelGGL((k_search_lag<WCB, RR, DD>), grid, blk, 0, s, p->grid, ld, ctl, batch, n_cbk, n_cg, \
+#define LAG_LAUNCH(WCB, RR, DD, CX)                                                                       \
+    hipLaunchKernelGGL((k_search_lag<WCB, RR, DD, CX>), grid, blk, 0, s, p->grid, ld, ctl, batch, n_cbk, n_cg, \
                        n_tg)
-    if (wide) {
-        if (ctl.dump) LAG_LAUNCH(2, false, true);
-        else if (ctl.pass) LAG_LAUNCH(2, true, false);
-        else LAG_LAUNCH(2, false, false);
+    if (cplx) {
+        if (ctl.dump) LAG_LAUNCH(2, false, true, true);
+        else if (ctl.pass) LAG_LAUNCH(2, true, false, true);
+        else LAG_LAUNCH(2, false, false, true);
+    } else if (wide) {
+        if (ctl.dump) LAG_LAUNCH(2, false, true, false);
+        else if (ctl.pass) LAG_LAUNCH(2, true, false, false);
+        else LAG_LAUNCH(2, false, false, false);
     } else {
-        if (ctl.dump) LAG_LAUNCH(1, false, true);
-        else if (ctl.pass) LAG_LAUNCH(1, true, false);
-        else LAG_LAUNCH(1, false, false);
+        if (ctl.dump) LAG_LAUNCH(1, false, true, false);
+        else if (ctl.pass) LAG_LAUNCH(1, true, false, false);
+        else LAG_LAUNCH(1, false, false, false);
     }
 #undef LAG_LAUNCH
     ACT_HIP(hipGetLastError());

@@ -765,15 +765,18 @@ def assert_complex_parity(gpu, ref, grid, oracle, signals, label, refine_steps):
     return compared
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_complex_correlate_matches_oracle(oracle, prec, tol):
-    """|<g_hat, r>| of complex atoms, FP64 synthesis and the FP32 MFMA
-    factored synthesis (two accumulators of the same product), on the
-    65,536-atom grid and on a grid with partial tiles and n = 300."""
+@pytest.mark.parametrize("dict_,prec,tol", [("synth", "f64", 1e-12), ("synth", "f32", 1e-5),
+                                            ("lag", "f16", 2.5e-3)])
+def test_complex_correlate_matches_oracle(oracle, dict_, prec, tol):
+    """|<g_hat, r>| of complex atoms: FP64 synthesis, the FP32 MFMA factored
+    synthesis (two accumulators of the same product) and the FP16 lag table
+    (cos and sin parts of each atom in paired column blocks; within its
+    certified bound, about sqrt(2) x the real one), on the 65,536-atom grid and
+    on a grid with partial tiles and n = 300."""
     wl = W.plain_1x512()
     g = wl.grid
     r = wl.signals[0]
-    plan = A().Plan(g, dict_="synth", prec=prec, complex_atoms=True)
+    plan = A().Plan(g, dict_=dict_, prec=prec, complex_atoms=True)
     for begin, count in [(0, 4096), (31000, 2500), (g.size - 300, 300)]:
         p_gpu = plan.act_correlate(r, begin, count).cpu().numpy()[0]
         p_ref = oracle.correlate_complex(g, r, begin, count)
@@ -782,19 +785,19 @@ def test_complex_correlate_matches_oracle(oracle, prec, tol):
     g2 = W.Grid(256.0, 300, W.Axis(0.0, 18 * 16 / 256.0, 18, True), W.Axis(2.0, 60.0, 70, False),
                 W.Axis(-15.0, 15.0, 9, False), W.Axis(math.log(0.05), 0.0, 15, False))
     sig = np.random.default_rng(61).standard_normal((2, g2.n))
-    plan2 = A().Plan(g2, dict_="synth", prec=prec, max_batch=2, complex_atoms=True)
+    plan2 = A().Plan(g2, dict_=dict_, prec=prec, max_batch=2, complex_atoms=True)
     p = plan2.act_correlate(sig, 0, g2.size).cpu().numpy()
     for b in range(2):
         assert np.max(np.abs(p[b] - oracle.correlate_complex(g2, sig[b]))) <= tol * np.linalg.norm(sig[b])
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "synth"), ("f16", "lag")])
 @pytest.mark.parametrize("steps", [30, 0])
-def test_complex_decompose_matches_oracle(oracle, prec, steps):
+def test_complex_decompose_matches_oracle(oracle, prec, dict_, steps):
     wl = W.plain_1x512()
     order = wl.order if steps else 8
     ref = oracle.decompose_complex(wl.grid, wl.signals, order, refine_steps=steps)
-    gpu = gpu_decompose(wl.grid, wl.signals, order, prec, "synth", refine_steps=steps, complex_atoms=True)
+    gpu = gpu_decompose(wl.grid, wl.signals, order, prec, dict_, refine_steps=steps, complex_atoms=True)
     assert gpu["coef"].shape == (1, order, 2)
     assert assert_complex_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, steps) == order
 
@@ -808,8 +811,8 @@ def test_complex_batch_partial_tiles_and_edge_channels(oracle):
     sig = rng.standard_normal((4, g.n))
     sig[2] = 0.0
     sig[3, 40] = np.nan
-    for prec in ("f64", "f32"):
-        gpu = gpu_decompose(g, sig, 4, prec, "synth", refine_steps=30, complex_atoms=True)
+    for prec, dict_ in (("f64", "synth"), ("f32", "synth"), ("f16", "lag")):
+        gpu = gpu_decompose(g, sig, 4, prec, dict_, refine_steps=30, complex_atoms=True)
         ref = oracle.decompose_complex(g, sig[:2], 4, refine_steps=30)
         assert_complex_parity({k: (v[:2] if v is not None else None) for k, v in gpu.items()},
                               ref, g, oracle, sig[:2], "cplx-" + prec, 30)
@@ -819,8 +822,8 @@ def test_complex_batch_partial_tiles_and_edge_channels(oracle):
         np.testing.assert_array_equal(gpu["coef"][2], 0.0)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_complex_atoms_remove_any_phase_on_gpu(oracle, prec):
+@pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "synth"), ("f16", "lag")])
+def test_complex_atoms_remove_any_phase_on_gpu(oracle, prec, dict_):
     """A near-analytic on-grid chirplet at an arbitrary carrier phase is
     selected and removed in one order (residual energy <= 1e-20 of the
     signal's) by the amplitude-and-phase fit."""
@@ -835,7 +838,7 @@ def test_complex_atoms_remove_any_phase_on_gpu(oracle, prec):
                 break
         u, v = oracle.atom_complex(g.fs, g.n, th)
         s = 1.7 * (math.cos(psi) * u - math.sin(psi) * v)
-        gpu = gpu_decompose(g, s[None, :], 1, prec, "synth", refine_steps=30, complex_atoms=True)
+        gpu = gpu_decompose(g, s[None, :], 1, prec, dict_, refine_steps=30, complex_atoms=True)
         assert gpu["index"][0, 0] == j
         assert gpu["energy"][0, 1] <= 1e-20 * gpu["energy"][0, 0]
         np.testing.assert_allclose(gpu["coef"][0, 0], [1.7 * math.cos(psi), -1.7 * math.sin(psi)], rtol=1e-9)
@@ -894,16 +897,17 @@ def test_complex_invalid_combinations_are_refused():
     assert e.value.status == act.ACT_ERR_UNSUPPORTED
 
 
-def test_complex_full_size_64x2048(oracle):
+@pytest.mark.parametrize("prec,dict_", [("f32", "synth"), ("f16", "lag")])
+def test_complex_full_size_64x2048(oracle, prec, dict_):
     """64 channels x N = 2048 on the 2,097,152-atom grid with complex atoms
-    (FP32 MFMA synthesis + FP64 rescoring): per order and for sampled
-    channels, no sampled atom beats the winner's oracle score, the refined
-    parameters equal the oracle's refinement from the same grid point, and
-    the amplitude pair and energies follow."""
+    (FP32 MFMA synthesis or the FP16 lag table, + FP64 rescoring): per order
+    and for sampled channels, no sampled atom beats the winner's oracle score,
+    the refined parameters equal the oracle's refinement from the same grid
+    point, and the amplitude pair and energies follow."""
     wl = W.batched_64x2048()
     g = wl.grid
     order = 2
-    gpu = gpu_decompose(g, wl.signals, order, "f32", "synth", refine_steps=30, complex_atoms=True)
+    gpu = gpu_decompose(g, wl.signals, order, prec, dict_, refine_steps=30, complex_atoms=True)
     step, _, _ = oracle.refine_box(g)
     rng = np.random.default_rng(65)
     sample = rng.choice(g.size, 1500, replace=False)
@@ -1068,7 +1072,7 @@ def test_lag_table_rejects_unaligned_time_centres():
     with pytest.raises(act.ActError) as e:
         act.Plan(g, dict_="lag", prec="f16")
     assert e.value.status == act.ACT_ERR_UNSUPPORTED
-    for kw in (dict(prec="f32"), dict(prec="f16", ragged=True), dict(prec="f16", complex_atoms=True)):
+    for kw in (dict(prec="f32"), dict(prec="f16", ragged=True), dict(prec="f16", support_cut=True)):
         with pytest.raises(act.ActError) as e:
             act.Plan(W.eeg_grid(512, 32, 8, 4, 2), dict_="lag", **kw)
         assert e.value.status == act.ACT_ERR_UNSUPPORTED, kw
