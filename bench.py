@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
     ap.add_argument("--companions", default="fp32-1x2048-synth,lag-f16-1x2048,bf16-64x2048,lag-f16-64x2048,"
-                                            "f16-64x2048-synth,f16-64x2048-synth-cut,complex-f32-64x2048-synth,"
+                                            "f16-64x2048-synth,f16-64x2048-synth-cut,complex-f32-64x2048-synth,complex-lag-f16-64x2048,"
                                             "ragged-1000-f16,ragged-1000-f16-cut",
                     help="comma-separated companion workloads of the default run")
     ap.add_argument("--no-tune", action="store_true", help="time the built-in launch shapes (no act_tune)")
