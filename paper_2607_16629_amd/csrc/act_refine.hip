@@ -539,13 +539,7 @@ __device__ void sums_obj_cplx(const double* __restrict__ r, int n, double fs, co
     for (int j = 0; j < 13; ++j) acc[j] = 0.0;
     int k0, k1;
     support_window(n, fs, th, k0, k1);
-#pragma unroll 1
-    for (int k = k0 + threadIdx.x; k < k1; k += TB) {
-        const double tau = sample_time(k, fs) - th[0];
-        const double u = tau * inv_dt;
-        const double e = exp(-0.5 * u * u);
-        double si, co;
-        sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
+    walk_atom<TB>(k0, k1, fs, th, inv_dt, [&](int k, double tau, double e, double co, double si) {
         const double rk = r[k];
         const double de0 = e * tau * idt2, de3 = e * tau * tau * idt2;
         const double dp0 = -kTwoPi * (2.0 * c * tau + fc), dp1 = kTwoPi * tau, dp2 = kTwoPi * tau * tau;
@@ -563,7 +557,7 @@ __device__ void sums_obj_cplx(const double* __restrict__ r, int n, double fs, co
         acc[10] += rk * (si * de3);
         acc[11] += 2.0 * e * de0;
         acc[12] += 2.0 * e * de3;
-    }
+    });
     block_sum<TB, 13>(acc, red);
 }
 
