@@ -202,10 +202,11 @@ def run_workload(name: str, steps: int, warmup: int):
     return res, wl
 
 
-def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False):
+def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False, dict_: str = "synth"):
     """Uneven batch: 1000 signals of log-uniform length 256..16384 in one
     act_decompose call, each with its own grid (floor(N/32) time centres,
-    64 f_c x 32 c x 16 dt), 15 orders, synthesised search + FP64 rescoring."""
+    64 f_c x 32 c x 16 dt), 15 orders, synthesised search (or the FP16 lag
+    table) + FP64 rescoring."""
     import numpy as np
     import torch
     from paper_2607_16629_amd import act
@@ -214,7 +215,7 @@ def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False):
     lens = wl.lengths
     B, order = len(lens), wl.order
     per_tc = 64 * 32 * 16
-    plan = act.Plan(W.ragged_grid(int(lens.max()), 32, 64, 32, 16), dict_="synth", prec=prec, max_batch=B,
+    plan = act.Plan(W.ragged_grid(int(lens.max()), 32, 64, 32, 16), dict_=dict_, prec=prec, max_batch=B,
                     refine_steps=wl.refine_steps, ragged=True, ragged_tc_div=32, support_cut=cut)
     sig = torch.from_numpy(wl.signals).cuda()
     resid = torch.empty_like(sig)
@@ -248,8 +249,9 @@ def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False):
     algo = 2.0 * macs
     achieved = algo / (search_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec + "_mfma"]
-    kname, _ = KERNELS[("synth", prec)]
-    return {"workload": wl.name + "-" + prec + ("-cut" if cut else ""),
+    kname, _ = KERNELS[(dict_, prec)]
+    lag = dict_ == "lag"
+    return {"workload": wl.name + "-" + prec + ("-cut" if cut else "") + ("-lag" if lag else ""),
             "value": round(macs * order * steps / wall / 1e9, 3),
             "unit": "GMAC/s", "ms_per_step": round(wall * 1e3 / steps, 3),
             "mp_iters_per_s": round(order * steps / wall, 3),
@@ -257,15 +259,17 @@ def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False):
             "search_only_gmac_per_s": round(macs / (search_ms * 1e-3) / 1e9, 3),
             "dtype": prec,
             "config": {"workload": wl.name, "signals": B, "n_min": int(lens.min()), "n_max": int(lens.max()),
-                       "dense_macs_per_order": macs, "order": order, "dict": "synth", "support_cut": cut,
+                       "dense_macs_per_order": macs, "order": order, "dict": dict_, "support_cut": cut,
                        "refine_steps": wl.refine_steps, "parallelism": "single-gpu"},
             "phases_ms_per_order": {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items()},
             "candidate_overflow_channels": int(((flags & act.FLAG_CAND_OVERFLOW) != 0).sum()),
             "launch_shape": shape,
             "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                          "frac": round(achieved / peak, 4), "traffic": None,
-                         "kernel": kname + "_ragged", "avg_launch_ms": round(search_ms, 5),
-                         "algorithmic_flops_per_launch": algo, "executed_mfma_flops_per_launch": 2 * algo}}
+                         "kernel": kname + ("" if lag else "_ragged"), "avg_launch_ms": round(search_ms, 5),
+                         "algorithmic_flops_per_launch": algo,
+                         # the lag table runs its tiles' nonzero bands (counted per call on the device only)
+                         "executed_mfma_flops_per_launch": None if lag else 2 * algo}}
 
 
 def run_sweep(steps: int, warmup: int):
@@ -404,13 +408,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp32-1x2048",
                     choices=sorted(WORKLOADS) + ["refine-4096", "ragged-1000-f16", "ragged-1000-f32",
-                                                 "ragged-1000-f16-cut", "eeg-sweep", "lem-eeg"])
+                                                 "ragged-1000-f16-cut", "ragged-1000-f16-lag", "eeg-sweep", "lem-eeg"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
     ap.add_argument("--companions", default="fp32-1x2048-synth,lag-f16-1x2048,bf16-64x2048,lag-f16-64x2048,"
                                             "f16-64x2048-synth,f16-64x2048-synth-cut,complex-f32-64x2048-synth,complex-lag-f16-64x2048,"
-                                            "ragged-1000-f16,ragged-1000-f16-cut",
+                                            "ragged-1000-f16,ragged-1000-f16-cut,ragged-1000-f16-lag",
                     help="comma-separated companion workloads of the default run")
     ap.add_argument("--no-tune", action="store_true", help="time the built-in launch shapes (no act_tune)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -450,7 +454,7 @@ def main():
         return
     if args.workload.startswith("ragged-1000"):
         parts = args.workload.split("-")
-        res = run_ragged(args.steps, args.warmup, parts[2], parts[-1] == "cut")
+        res = run_ragged(args.steps, args.warmup, parts[2], parts[-1] == "cut", "lag" if parts[-1] == "lag" else "synth")
         line = {"metric": METRIC, "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
                 "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -472,7 +476,7 @@ def main():
                 # the uneven batch (15 orders of 1000 signals, ~3.3e13 MACs per
                 # order) takes seconds per step: one timed step after one warm-up
                 parts = name.split("-")
-                comp[name] = run_ragged(1, 1, parts[2], parts[-1] == "cut")
+                comp[name] = run_ragged(1, 1, parts[2], parts[-1] == "cut", "lag" if parts[-1] == "lag" else "synth")
             else:
                 comp[name], _ = run_workload(name, args.steps, args.warmup)
         line["companions"] = comp

@@ -72,7 +72,9 @@ enum {
     ACT_DICT_LAG = 2    /* one time centre's atoms over every lag in an HBM-resident FP16 table
                            (time centres on integer samples that are multiples of 8): the scores
                            of all (channel, time centre) rows are one dense matrix product with
-                           the residual's shifted windows; ACT_PREC_F16 only, plain plans */
+                           the residual's shifted windows; ACT_PREC_F16 only; plain plans (real
+                           or complex atoms) and ragged plans of real atoms (ragged_tc_div a
+                           multiple of 8) */
 };
 
 /* Arithmetic of the coarse search (rescoring, refinement, coefficients and
@@ -82,7 +84,8 @@ enum {
     ACT_PREC_F32 = 1,  /* FP32 correlation, certified FP64 rescoring of the candidates */
     ACT_PREC_BF16 = 2, /* BF16 x BF16 -> FP32 MFMA correlation, certified FP64 rescoring */
     ACT_PREC_F16 = 3   /* FP16 x FP16 -> FP32 MFMA correlation over factor tables
-                          (ACT_DICT_SYNTH only), certified FP64 rescoring */
+                          (ACT_DICT_SYNTH) or the lag table (ACT_DICT_LAG), certified FP64
+                          rescoring */
 };
 
 /* Per-channel flags written by act_decompose / act_refine. */
@@ -167,7 +170,8 @@ int64_t act_plan_query(act_plan_t plan, int32_t key);
  * 2 atoms n_samples batch (padding rows and columns included).  Diagnostic
  * for utilisation figures; host-only, no device work.  Errors:
  * ACT_ERR_INVALID (NULL plan or flops, batch outside [1, max_batch]),
- * ACT_ERR_UNSUPPORTED (plans of other dictionaries). */
+ * ACT_ERR_UNSUPPORTED (plans of other dictionaries, and ragged plans, whose
+ * tiles depend on the call's lengths). */
 act_status act_search_flops(act_plan_t plan, int32_t batch, double* flops);
 
 /* Residue-based matching pursuit of `batch` channels for `order` orders

@@ -237,6 +237,9 @@ struct act_plan_s {
     int* lag_order = nullptr; // ACT_DICT_LAG: tile column-block orders (128-column tiles, then 256)
     int lag_order_wide = 0;   // ACT_DICT_LAG: offset of the 256-column order in lag_order
     std::vector<int> lag_span_host;  // ACT_DICT_LAG: host copy of lag_span (lo, hi pairs)
+    float* lag_rho = nullptr;  // ragged ACT_DICT_LAG: [256-column blocks][lag_rho_d] bound of |g_full| / |g_w|
+    int lag_rho_d = 0;         // ragged ACT_DICT_LAG: distances to the signal end below which lag_rho applies
+    int* lag_rows = nullptr;   // ragged ACT_DICT_LAG: per call, [channel groups + 1] prefix of time groups
     std::vector<int> tc_shift_host;  // host copy of tc_shift
     double shift_eps = 0.0;   // synthesised / lag searches: relative score error of rounding the
                               // time centres to integer samples
@@ -311,6 +314,7 @@ act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s);
 act_status build_h16_factors(act_plan_s* p, hipStream_t s);
 act_status build_supports(act_plan_s* p, hipStream_t s);
 act_status launch_h16_ragged_prep(act_plan_s* p, int batch, hipStream_t s);
+act_status launch_lag_ragged_prep(act_plan_s* p, int batch, hipStream_t s);
 act_status launch_prior_init(act_plan_s* p, int batch, const double* resid, hipStream_t s);
 act_status launch_prior_order(act_plan_s* p, int batch, int k, int order, double* resid, double* approx,
                               double* theta, double* coef, long long* index, double* energy, double* gap,

@@ -366,7 +366,8 @@ static void free_plan(act_plan_s* p) {
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
                     p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->lem_cand, p->lem_score, p->shadow_alloc, p->cand_idx, p->cand_score, p->cand_p64,
-                    p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun, p->lag_inv, p->lag_span, p->lag_order};
+                    p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun, p->lag_inv, p->lag_span, p->lag_order,
+                    p->lag_rho, p->lag_rows};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto& ge : p->graphs) {
@@ -428,18 +429,23 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     ACT_REQUIRE(desc->cand_cap >= 0 && desc->refine_steps >= 0, "act_plan: negative cand_cap/refine_steps");
     if (desc->ragged) {
         ACT_REQUIRE(desc->ragged_tc_div >= 1, "act_plan: ragged plans need ragged_tc_div >= 1");
-        if (!(desc->dict == ACT_DICT_SYNTH && desc->prec != ACT_PREC_BF16)) {
-            set_error("act_plan: ragged plans support the synthesised FP64, FP32 and FP16 searches");
+        if (!((desc->dict == ACT_DICT_SYNTH && desc->prec != ACT_PREC_BF16) ||
+              (desc->dict == ACT_DICT_LAG && desc->prec == ACT_PREC_F16))) {
+            set_error("act_plan: ragged plans support the synthesised FP64, FP32 and FP16 searches and the lag table");
             return ACT_ERR_UNSUPPORTED;
         }
-        if (desc->prec != ACT_PREC_F64 && desc->ragged_tc_div % 16 != 0) {
+        if (desc->dict == ACT_DICT_SYNTH && desc->prec != ACT_PREC_F64 && desc->ragged_tc_div % 16 != 0) {
             set_error("act_plan: the ragged MFMA synthesised searches need ragged_tc_div a multiple of 16");
             return ACT_ERR_UNSUPPORTED;
         }
+        if (desc->dict == ACT_DICT_LAG && desc->ragged_tc_div % 8 != 0) {
+            set_error("act_plan: the ragged lag-table search needs ragged_tc_div a multiple of 8");
+            return ACT_ERR_UNSUPPORTED;
+        }
     }
-    if (desc->dict == ACT_DICT_LAG && !(desc->prec == ACT_PREC_F16 && !desc->ragged && !desc->prior_act &&
-                                        !desc->support_cut)) {
-        set_error("act_plan: ACT_DICT_LAG is the FP16 lag-table search of plain plans");
+    if (desc->dict == ACT_DICT_LAG && !(desc->prec == ACT_PREC_F16 && !desc->prior_act && !desc->support_cut &&
+                                        !(desc->ragged && desc->complex_atoms))) {
+        set_error("act_plan: ACT_DICT_LAG is the FP16 lag-table search (complex atoms on plain plans only)");
         return ACT_ERR_UNSUPPORTED;
     }
     if (desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_BF16) {
@@ -518,6 +524,9 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         p->grid.cnt[0] = std::max(1, gr.n_samples / desc->ragged_tc_div);
         p->grid.atoms = (long long)p->grid.cnt[0] * p->grid.cnt[1] * p->grid.cnt[2] * p->grid.cnt[3];
         p->atoms = p->grid.atoms;
+        // the widest channel's time-centre spacing, as a channel of that length computes it
+        const int ntc = p->grid.cnt[0];
+        p->grid.tc_step = ((double)(ntc * desc->ragged_tc_div) / gr.fs_hz) / (double)ntc;
     }
 
     const size_t B = (size_t)p->max_batch, cap = (size_t)p->cap;
@@ -568,9 +577,19 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
         // synthesised searches, of 8 for the lag table) inside the signal; the
         // residual distance to the integer enters the certified bound
         const int mult = desc->dict == ACT_DICT_LAG ? 8 : 16;
-        std::vector<int> shift(ax[0]->count);
+        const int n_tc = p->grid.cnt[0];
+        std::vector<int> shift(n_tc);
         double delta = 0.0;
-        for (int j = 0; j < ax[0]->count; ++j) {
+        for (int j = 0; j < n_tc && desc->ragged; ++j) {
+            // ragged (lag table): centre j of a channel with ntc centres sits at
+            // j ((ntc div / fs) / ntc) s; its sample is j div, at most delta away
+            shift[j] = j * desc->ragged_tc_div;
+            for (int ntc = j + 1; ntc <= n_tc; ++ntc) {
+                const double step = ((double)(ntc * desc->ragged_tc_div) / gr.fs_hz) / (double)ntc;
+                delta = std::max(delta, std::fabs((double)j * step * gr.fs_hz - (double)shift[j]));
+            }
+        }
+        for (int j = 0; j < n_tc && !desc->ragged; ++j) {
             const double mv = vals[p->grid.off[0] + j] * gr.fs_hz;
             const double mr = std::nearbyint(mv);
             if (!(std::fabs(mv - mr) <= 1e-6 * std::max(1.0, std::fabs(mv))) || mr < 0 ||
@@ -632,7 +651,17 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             }
             PLAN_HIP(hipMalloc(&p->table, p->table_bytes));
             PLAN_HIP(hipMalloc((void**)&p->rscale, B * sizeof(float)));
-            PLAN_HIP(hipMalloc((void**)&p->lag_inv, (size_t)ax[0]->count * p->lag_q_pad * sizeof(float)));
+            PLAN_HIP(hipMalloc((void**)&p->lag_inv, (size_t)p->grid.cnt[0] * p->lag_q_pad * sizeof(float)));
+            if (desc->ragged) {
+                PLAN_HIP(hipMalloc((void**)&p->perm, B * sizeof(int)));
+                PLAN_HIP(hipMalloc((void**)&p->lag_rows, (B / 32 + 2) * sizeof(int)));
+                // distances to the end below which an atom's tail beyond the end
+                // can matter: 7 of the longest duration (tail energy < e^-49 dt fs)
+                double ldmax = -INFINITY;
+                for (int j = 0; j < ax[3]->count; ++j) ldmax = std::max(ldmax, vals[p->grid.off[3] + j]);
+                p->lag_rho_d = (int)std::min<double>(p->n_pad, std::ceil(7.0 * std::exp(ldmax) * gr.fs_hz) + 2.0);
+                PLAN_HIP(hipMalloc((void**)&p->lag_rho, (size_t)(p->lag_q_pad / 256) * p->lag_rho_d * sizeof(float)));
+            }
             PLAN_HIP(hipMalloc((void**)&p->lag_span, (size_t)(p->lag_q_pad / 32) * 2 * sizeof(int)));
             PLAN_HIP(hipMalloc((void**)&p->lag_order, (size_t)(p->lag_q_pad / 128 + p->lag_q_pad / 256) * sizeof(int)));
         }
@@ -718,8 +747,8 @@ extern "C" int64_t act_plan_query(act_plan_t p, int32_t key) {
 extern "C" act_status act_search_flops(act_plan_t p, int32_t batch, double* flops) {
     ACT_REQUIRE(p != nullptr && flops != nullptr, "act_search_flops: plan or flops is NULL");
     ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, "act_search_flops: batch outside [1, max_batch]");
-    if (p->desc.dict != ACT_DICT_LAG) {
-        set_error("act_search_flops: only the lag-table search has a counted matrix-core workload");
+    if (p->desc.dict != ACT_DICT_LAG || p->desc.ragged) {
+        set_error("act_search_flops: only the lag-table search of plain plans has a counted matrix-core workload");
         return ACT_ERR_UNSUPPORTED;
     }
     *flops = lag_search_flops(p, batch);

@@ -33,6 +33,7 @@
 // rounding, the search copy's rounding, the FP32 accumulation): every atom
 // with |p~| >= M - 2 E_b is emitted, M the running maximum.
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 #include <vector>
 
@@ -89,6 +90,13 @@ struct LagDev {
     int n_tc;
     int CB, TB;              // channels x time centres of a tile's 128 rows (CB TB = 128)
     int cb_log2;             // log2 CB (CB is a power of two): row = t CB + slot
+    // ragged batches: channels by decreasing length, per channel group the
+    // prefix of its time groups, and the bound of |g_full| / |g_w| per
+    // 256-column block and distance from the centre to the signal's end
+    const int* perm;
+    const int* rows;
+    const float* rho;
+    int rho_d, div;
 };
 
 struct LagLds {
@@ -96,6 +104,9 @@ struct LagLds {
     float gm[4][32];         // per wave: max |p~| over the rows r = 32 rb + g of every rb, per g
     float M[LG_ROWS];        // emission threshold per channel slot
     float rinv[LG_ROWS];     // 1/s_b per channel slot
+    float rrow[LG_ROWS];     // ragged: 1/s_b of the row's channel, 0 for a time centre past its end
+    float rhor[LG_ROWS];     // ragged: the row's bound of |g_full| / |g_w| (1 away from the end)
+    double ebs[32];          // ragged: E_b per channel slot
     unsigned emit;           // bit g: some row 32 rb + g reaches its channel's threshold
     unsigned cnt[32];        // per channel slot: the tile's candidates, then their running position
     int base[32];            // per channel slot: first list entry reserved for the tile
@@ -112,16 +123,33 @@ __device__ __forceinline__ long long lag_atom(const LagDev& ld, int tc, int qc) 
 // CPLX: complex atoms.  A wave's two column blocks are the cos and sin parts
 // of the same 32 atoms, so a lane's two accumulators are (a, b) of one atom and
 // its score is sqrt(a^2 + b^2) / |E_w|.
-template <int WCB, bool RERUN, bool DUMP, bool CPLX>
+//
+// RAG: uneven-length batch.  Slots take channels in order of decreasing length
+// (ld.perm), so a 32-channel group's longest signal comes first; only its time
+// groups form tiles.  Every score is normalised by the atom's norm over the
+// longest window [0, n_max) (the plan's 1/|g|).  The search copy is zero past
+// a channel's end, so that score is the true one times |g_w| / |g_full| <= 1,
+// and the true score is at most rho times it, rho <= sqrt(1 + tail energy of
+// the atom beyond the end) (|g_w| >= 1).  A row of a channel emits its atoms
+// by the upper bound (|p~| + E_b) rho - E_b against M - 2 E_b and stores that
+// bound as the candidate's score; rho = 1 beyond ld.rho_d samples from the end.
+template <int WCB, bool RERUN, bool DUMP, bool CPLX, bool RAG>
 __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, SearchCtl ctl, int batch,
                                                        int n_cbk, int n_cg, int n_tg) {
     static_assert(!CPLX || WCB == 2, "complex atoms pair two column blocks");
+    static_assert(!RAG || (WCB == 2 && !CPLX && !DUMP), "ragged: real atoms, 256-column tiles, search only");
     __shared__ LagLds L;
+    // the rerun pass: nothing to do unless some channel's list overflowed
+    if (RERUN) {
+        int any = 0;
+        for (int b = threadIdx.x; b < batch; b += blockDim.x) any |= ctl.need_rerun[b];
+        if (!__syncthreads_or(any)) return;
+    }
     constexpr int COLS = 4 * WCB * 32;
     constexpr int ACOLS = CPLX ? COLS / 2 : COLS;  // atoms of a tile
     constexpr int NA = CPLX ? 1 : WCB;              // atoms of a lane per accumulator row
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long long n_rbk = (long long)n_cg * n_tg;
+    const long long n_rbk = RAG ? (long long)ld.rows[n_cg] : (long long)n_cg * n_tg;
     const long long tiles = (long long)n_cbk * n_rbk;
     const long long chunk = (tiles + 7) / 8;
     for (long long x = blockIdx.x; x < 8 * chunk; x += gridDim.x) {
@@ -129,15 +157,31 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         if (tid >= tiles) continue;
         const int cbk = ld.order[(int)(tid / n_rbk)];
         const int rbk = (int)(tid % n_rbk);
-        const int cg = rbk % n_cg, tg = rbk / n_cg;
+        int cg, tg;
+        if (RAG) {
+            cg = 0;
+            while (cg + 1 < n_cg && ld.rows[cg + 1] <= rbk) ++cg;
+            tg = rbk - ld.rows[cg];
+        } else {
+            cg = rbk % n_cg;
+            tg = rbk / n_cg;
+        }
         const int ch0 = cg * ld.CB, tc0 = tg * ld.TB;
+        // the channel of slot sl (-1 past the batch); lengths outside [0, n] count as 0
+        auto chan = [&](int sl) { const int k = ch0 + sl; return k < batch ? (RAG ? ld.perm[k] : k) : -1; };
+        auto chan_len = [&](int b) {
+            const int nb = RAG ? ctl.len[b] : g.n;
+            return (nb < 0 || nb > g.n) ? 0 : nb;
+        };
+        const int n_long = RAG ? chan_len(chan(0)) : g.n;  // the group's longest signal
+        const int n_tc_t = RAG ? n_long / ld.div : ld.n_tc;
         const int q0 = cbk * COLS;
         const int aq0 = cbk * ACOLS;  // first atom (in the table's order) of the tile
 
         // lags that meet the tile's rows, e = d + N_pad with 0 <= d + m < n,
         // cut to the k-steps where the tile's columns hold nonzero entries:
         // the skipped products are exact zeros, so every score is unchanged
-        const int tc_last = min(tc0 + ld.TB, ld.n_tc) - 1;
+        const int tc_last = min(tc0 + ld.TB, n_tc_t) - 1;
         const int m_min = ld.tc_shift[tc0], m_max = ld.tc_shift[tc_last];
         int klo = ld.LS, khi = 0;
 #pragma unroll
@@ -147,7 +191,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             khi = max(khi, sp.y);
         }
         const int e_first = max((g.n_pad - m_max) / LG_S, 16 * klo / LG_S) * LG_S;
-        const int e_end = min(min(2 * g.n_pad, g.n_pad + g.n - m_min), 16 * khi);
+        const int e_end = min(min(2 * g.n_pad, g.n_pad + n_long - m_min), 16 * khi);
         const int ns = e_end > e_first ? (e_end - e_first + LG_S - 1) / LG_S : 0;
 
         // per channel slot: certified bound, running maximum, residual scale
@@ -156,11 +200,26 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         double eb = -1.0;
         float pre_gmax = 0.0f, rsc = 0.0f;
         if (threadIdx.x < ld.CB && ch0 + (int)threadIdx.x < batch) {
-            const int b = ch0 + threadIdx.x;
+            const int b = chan(threadIdx.x);
             eb = ctl.ebound[b];
             rsc = ld.rscale[b];
             if (!DUMP) pre_gmax = load_gmax(&ctl.gmax[b]);
             live = DUMP || (eb >= 0.0 && (!RERUN || ctl.need_rerun[b]));
+        }
+        // ragged: per row, 1/s_b (0 for a time centre past the channel's end) and rho
+        float rrow_v = 0.0f, rhor_v = 1.0f;
+        if (RAG && threadIdx.x < LG_ROWS) {
+            const int sl = threadIdx.x & (ld.CB - 1), t = threadIdx.x >> ld.cb_log2;
+            const int b = chan(sl);
+            if (b >= 0) {
+                const int nb = chan_len(b), tc = tc0 + t;
+                if (tc < nb / ld.div) {
+                    const float sc = ld.rscale[b];
+                    rrow_v = sc > 0.0f ? 1.0f / sc : 0.0f;
+                    const int dl = nb - ld.tc_shift[tc];
+                    rhor_v = dl < ld.rho_d ? ld.rho[(size_t)cbk * ld.rho_d + dl] : 1.0f;
+                }
+            }
         }
         if (threadIdx.x == 0) L.emit = 0u;
         if (threadIdx.x < 32) L.cnt[threadIdx.x] = 0u;
@@ -177,8 +236,9 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
 #pragma unroll
         for (int i = 0; i < NCH; ++i) {
             const int c = threadIdx.x + 256 * i, row = c / 16;
-            const int b = min(ch0 + (row & (ld.CB - 1)), batch - 1);
-            const int tc = min(tc0 + (row >> ld.cb_log2), ld.n_tc - 1);
+            const int bs = chan(row & (ld.CB - 1));
+            const int b = RAG ? (bs >= 0 ? bs : chan(0)) : min(ch0 + (row & (ld.CB - 1)), batch - 1);
+            const int tc = min(tc0 + (row >> ld.cb_log2), n_tc_t - 1);
             roff[i] = 2u * (unsigned)(b * ld.sh_stride + ld.tc_shift[tc] + 8 * (c % 16));
         }
         f16x8 rst[NCH];
@@ -316,6 +376,11 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             }
         }
         if (threadIdx.x < LG_ROWS) L.rinv[threadIdx.x] = rsc > 0.0f ? 1.0f / rsc : 0.0f;
+        if (RAG && threadIdx.x < LG_ROWS) {
+            L.rrow[threadIdx.x] = rrow_v;
+            L.rhor[threadIdx.x] = rhor_v;
+        }
+        if (RAG && threadIdx.x < ld.CB) L.ebs[threadIdx.x] = eb;
         // the epilogue's lane-dependent addresses are tile-invariant; an opaque
         // copy of the lane index keeps them from being hoisted out of the tile
         // loop (they would stay live across it and spill)
@@ -356,12 +421,13 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         }
         // the scale factors of v + 1 load while v computes; the maxima are
         // stored after the loop (no store between the loads)
-        float sc[2][LG_RB][WCB], ri[2], gmv[16];
-        auto load_sc = [&](int v, float (&dst)[LG_RB][WCB], float& r) {
+        float sc[2][LG_RB][WCB], ri[2][LG_RB], gmv[16];
+        auto load_sc = [&](int v, float (&dst)[LG_RB][WCB], float (&r)[LG_RB]) {
             const int gr = lg_row(v, elane);
-            r = L.rinv[gr & (ld.CB - 1)];  // 0 past the batch
+            const float r0 = RAG ? 0.0f : L.rinv[gr & (ld.CB - 1)];  // 0 past the batch
 #pragma unroll
             for (int rb = 0; rb < LG_RB; ++rb) {
+                r[rb] = RAG ? L.rrow[rb * 32 + gr] : r0;
                 const int t = (rb * 32 + gr) >> ld.cb_log2;
 #pragma unroll
                 for (int cb = 0; cb < NA; ++cb) dst[rb][cb] = invs[t * ACOLS + acol(cb)];  // 0 past the dictionary
@@ -376,7 +442,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             for (int rb = 0; rb < LG_RB; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < NA; ++cb) {
-                    const float p = (raw(rb, cb, v) * sc[v & 1][rb][cb]) * ri[v & 1];
+                    const float p = (raw(rb, cb, v) * sc[v & 1][rb][cb]) * ri[v & 1][rb];
                     acc[rb][cb][v] = p;
                     m = fmaxf(m, fabsf(p));
                 }
@@ -391,7 +457,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         // per channel slot: the threshold M - 2 E_b (M the running maximum,
         // raised by this tile's maximum), and the row groups that reach it
         if (threadIdx.x < ld.CB) {
-            const int sl = threadIdx.x, b = ch0 + sl;
+            const int sl = threadIdx.x, b = chan(sl);
             float T = INFINITY;
             if (live) {
                 float wm = 0.0f;
@@ -406,9 +472,16 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
                 T = (float)Td;
                 if ((double)T > Td) T = nextafterf(T, -INFINITY);
                 unsigned bits = 0u;
-                for (int gr = sl; gr < 32; gr += ld.CB)
-                    if (fmaxf(fmaxf(L.gm[0][gr], L.gm[1][gr]), fmaxf(L.gm[2][gr], L.gm[3][gr])) >= T)
-                        bits |= 1u << gr;
+                for (int gr = sl; gr < 32; gr += ld.CB) {
+                    const float gmg = fmaxf(fmaxf(L.gm[0][gr], L.gm[1][gr]), fmaxf(L.gm[2][gr], L.gm[3][gr]));
+                    bool f = gmg >= T;
+                    if (RAG) {
+                        // the group's largest upper bound of a true score
+                        const float rh = fmaxf(fmaxf(L.rhor[gr], L.rhor[32 + gr]), fmaxf(L.rhor[64 + gr], L.rhor[96 + gr]));
+                        f = ((double)gmg + eb) * rh - eb >= (double)T;
+                    }
+                    if (f) bits |= 1u << gr;
+                }
                 if (bits) atomicOr(&L.emit, bits);
             }
             L.M[sl] = T;
@@ -428,14 +501,23 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
                         if (!((em >> (8 * (v >> 2) + (v & 3))) & 0x11u)) continue;
                         const int gr = lg_row(v, elane);
                         const int row = rb * 32 + gr, t = row >> ld.cb_log2, tc = tc0 + t;
-                        if (((em >> gr) & 1u) && tc < ld.n_tc) {
-                            const int sl = gr & (ld.CB - 1), b = ch0 + sl;
+                        if (((em >> gr) & 1u) && (RAG ? L.rrow[row] > 0.0f : tc < ld.n_tc)) {
+                            const int sl = gr & (ld.CB - 1), b = chan(sl);
                             const float T = L.M[sl];
 #pragma unroll
                             for (int cb = 0; cb < NA; ++cb) {
                                 const int c = acol(cb);
-                                const float p = acc[rb][cb][v];
-                                if (aq0 + c < ld.Q && fabsf(p) >= T) {
+                                float p = acc[rb][cb][v];
+                                bool hit = fabsf(p) >= T;
+                                if (RAG) {
+                                    // upper bound of the true score, rounded up to FP32
+                                    const float rh = L.rhor[row];
+                                    const double e2 = L.ebs[sl];
+                                    const double ub = rh == 1.0f ? (double)fabsf(p) : ((double)fabsf(p) + e2) * rh - e2;
+                                    hit = ub >= (double)T;
+                                    p = __double2float_ru(ub);
+                                }
+                                if (aq0 + c < ld.Q && hit) {
                                     if (!place) {
                                         atomicAdd(&L.cnt[sl], 1u);
                                     } else {
@@ -454,7 +536,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
             __syncthreads();
             if (threadIdx.x < ld.CB) {
                 const unsigned n = L.cnt[threadIdx.x];
-                L.base[threadIdx.x] = n ? atomicAdd(&ctl.cand_count[ch0 + threadIdx.x], (int)n) : 0;
+                L.base[threadIdx.x] = n ? atomicAdd(&ctl.cand_count[chan(threadIdx.x)], (int)n) : 0;
                 L.cnt[threadIdx.x] = 0u;
             }
             __syncthreads();
@@ -549,6 +631,51 @@ __global__ void k_lag_inv(GridDev g, int Q_pad, const float* __restrict__ inv_no
     }
 }
 
+// Ragged plans: rho[cbk][dl] >= |g_full| / |g_w| for every atom of the
+// 256-column block cbk whose window [-m, dl) ends dl lags after its centre,
+// g_full its window over the longest signal.  |g_full|^2 - |g_w|^2 is at most
+// the tail energy T(dl) = sum_{d >= dl} g(d)^2, and the window holds the lags
+// [0, dl), so |g_w|^2 >= max(1, W(dl)), W(dl) = sum_{0 <= d < dl} g(d)^2
+// (g(0) = 1): the ratio is <= sqrt(1 + T(dl) / max(1, W(dl))).  FP64 sums over
+// d < D (the rest is below e^-49 dt fs); W is shrunk and the root widened by
+// 1e-9 and rounded up to FP32.  One workgroup of 256 columns per block.
+__global__ void __launch_bounds__(256) k_lag_rho(GridDev g, int D, float* __restrict__ rho) {
+    __shared__ double wm[4];
+    const int FC = g.cnt[1] * g.cnt[2], Q = FC * g.cnt[3];
+    const int qc = blockIdx.x * 256 + threadIdx.x;
+    const bool ok = qc < Q;
+    double f0 = 0.0, c = 0.0, inv_dt = 0.0;
+    if (ok) {
+        const int il = qc / FC, fcc = qc % FC;
+        f0 = g.axis[g.off[1] + fcc / g.cnt[2]];
+        c = g.axis[g.off[2] + fcc % g.cnt[2]];
+        inv_dt = 1.0 / exp(g.axis[g.off[3] + il]);
+    }
+    auto g2 = [&](int d) {
+        const double tau = (double)d / g.fs, u = tau * inv_dt;
+        const double v = exp(-0.5 * u * u) * cospi(2.0 * (c * tau * tau + f0 * tau));
+        return v * v;
+    };
+    double tot = 0.0;  // sum_{0 <= d < D} g(d)^2
+    if (ok)
+        for (int d = 0; d < D; ++d) tot += g2(d);
+    double T = 0.0;
+    for (int d = D - 1; d >= 1; --d) {
+        if (ok) T += g2(d);
+        const double W = (tot - T) * (1.0 - 1e-9) - 1e-9 * tot;  // lower bound of sum_{0 <= d' < d}
+        double r = sqrt(1.0 + T / fmax(1.0, W)) * (1.0 + 1e-9);
+        r = wave_max(r);
+        if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = r;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+            rho[(size_t)blockIdx.x * D + d] = __double2float_ru(m);
+            if (d == 1) rho[(size_t)blockIdx.x * D] = __double2float_ru(m);
+        }
+        __syncthreads();
+    }
+}
+
 // Tile column-block order for tiles of `cols` columns: blocks sorted by their
 // count of nonzero k-steps (longest first), dealt round-robin to the 8 XCDs'
 // contiguous tile ranges so that each XCD gets the same mix.
@@ -582,6 +709,11 @@ act_status build_lag_table(act_plan_s* p, hipStream_t s) {
     hipLaunchKernelGGL(k_lag_span, dim3((unsigned)(Q_pad / 32)), dim3(256), 0, s, (const f16x8*)p->table, LS,
                        (int2*)p->lag_span);
     ACT_HIP(hipGetLastError());
+    if (p->desc.ragged) {
+        hipLaunchKernelGGL(k_lag_rho, dim3((unsigned)(Q_pad / 256)), dim3(256), 0, s, p->grid, p->lag_rho_d,
+                           p->lag_rho);
+        ACT_HIP(hipGetLastError());
+    }
     const int inv_row = p->desc.complex_atoms ? Q_pad / 2 : Q_pad;
     const long long inv_n = (long long)p->grid.cnt[0] * inv_row;
     hipLaunchKernelGGL(k_lag_inv, dim3((unsigned)std::min<long long>((inv_n + 255) / 256, device_cus() * 64LL)),
@@ -641,6 +773,52 @@ double lag_search_flops(const act_plan_s* p, int batch) {
 // plus the scalings.
 int lag_chain_length(int n_pad) { return 2 * n_pad + 2; }
 
+// channels per tile: the smallest power of two covering the batch, at most 32
+static int lag_channel_block(int batch) {
+    int CB = 1;
+    while (CB < batch && CB < 32) CB *= 2;
+    return CB;
+}
+
+// Ragged batches, per call: channels by decreasing length (ties: lower index
+// first) and, per group of CB channels, the prefix of the time groups of its
+// longest signal.  Lengths outside [0, n_max] count as 0 (flagged elsewhere).
+__global__ void __launch_bounds__(1024) k_lag_ragged_prep(const int* __restrict__ len, int batch, int n_max, int div,
+                                                          int CB, int TB, int* __restrict__ perm,
+                                                          int* __restrict__ rows) {
+    for (int b = threadIdx.x; b < batch; b += blockDim.x) {
+        int nb = len[b];
+        nb = (nb < 0 || nb > n_max) ? 0 : nb;
+        int rank = 0;
+        for (int j = 0; j < batch; ++j) {
+            int nj = len[j];
+            nj = (nj < 0 || nj > n_max) ? 0 : nj;
+            rank += (nj > nb || (nj == nb && j < b)) ? 1 : 0;
+        }
+        perm[rank] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int ncg = (batch + CB - 1) / CB;
+        int acc = 0;
+        for (int cg = 0; cg < ncg; ++cg) {
+            rows[cg] = acc;
+            int n = len[perm[cg * CB]];
+            n = (n < 0 || n > n_max) ? 0 : n;
+            acc += (n / div + TB - 1) / TB;
+        }
+        rows[ncg] = acc;
+    }
+}
+
+act_status launch_lag_ragged_prep(act_plan_s* p, int batch, hipStream_t s) {
+    const int CB = lag_channel_block(batch);
+    hipLaunchKernelGGL(k_lag_ragged_prep, dim3(1), dim3(1024), 0, s, p->call_len, batch, p->grid.n,
+                       p->desc.ragged_tc_div, CB, LG_ROWS / CB, p->perm, p->lag_rows);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
 act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s) {
     LagDev ld;
     ld.G = (const f16x8*)p->table;
@@ -657,10 +835,19 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     ld.FC = p->grid.cnt[1] * p->grid.cnt[2];
     ld.n_ld = p->grid.cnt[3];
     ld.n_tc = p->grid.cnt[0];
+    const bool rag = p->desc.ragged != 0;
+    ld.perm = p->perm;
+    ld.rows = p->lag_rows;
+    ld.rho = p->lag_rho;
+    ld.rho_d = p->lag_rho_d;
+    ld.div = rag ? p->desc.ragged_tc_div : 1;
+    if (rag && ctl.dump) {
+        set_error("act_correlate: the ragged lag-table search has no score dump");
+        return ACT_ERR_UNSUPPORTED;
+    }
     // rows: the smallest power of two of channels covering the batch (at most
     // 32) times the time centres that fill 128 rows
-    int CB = 1;
-    while (CB < batch && CB < 32) CB *= 2;
+    int CB = lag_channel_block(batch);
     ld.CB = CB;
     ld.TB = LG_ROWS / CB;
     ld.cb_log2 = 0;
@@ -669,31 +856,35 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     const int n_tg = (ld.n_tc + ld.TB - 1) / ld.TB;
     // one channel of real atoms: 128 columns per tile (twice the tiles);
     // otherwise 256 (complex atoms: 128 atoms, cos and sin blocks paired)
-    const bool wide = batch > 1 || cplx;
+    const bool wide = batch > 1 || cplx || rag;
     const int cols = wide ? 256 : 128;
     const int ncols = cplx ? 2 * ((ld.Q + 31) / 32 * 32) : ld.Q;
     const int n_cbk = (ncols + cols - 1) / cols;
     ld.order = p->lag_order + (wide ? p->lag_order_wide : 0);
-    const long long tiles = (long long)n_cbk * n_cg * n_tg;
+    // ragged: the tile count is known on the device only; a full persistent grid
+    const long long tiles = rag ? LLONG_MAX / 2 : (long long)n_cbk * n_cg * n_tg;
     long long blocks = (tiles + 7) / 8 * 8;
     const long long cap = grid_cap(p, 1);  // LDS: one workgroup per CU
     blocks = blocks < cap ? blocks : cap;
     const dim3 grid((unsigned)blocks), blk(256);
-#define LAG_LAUNCH(WCB, RR, DD, CX)                                                                       \
-    hipLaunchKernelGGL((k_search_lag<WCB, RR, DD, CX>), grid, blk, 0, s, p->grid, ld, ctl, batch, n_cbk, n_cg, \
+#define LAG_LAUNCH(WCB, RR, DD, CX, RG)                                                                       \
+    hipLaunchKernelGGL((k_search_lag<WCB, RR, DD, CX, RG>), grid, blk, 0, s, p->grid, ld, ctl, batch, n_cbk, n_cg, \
                        n_tg)
-    if (cplx) {
-        if (ctl.dump) LAG_LAUNCH(2, false, true, true);
-        else if (ctl.pass) LAG_LAUNCH(2, true, false, true);
-        else LAG_LAUNCH(2, false, false, true);
+    if (rag) {
+        if (ctl.pass) LAG_LAUNCH(2, true, false, false, true);
+        else LAG_LAUNCH(2, false, false, false, true);
+    } else if (cplx) {
+        if (ctl.dump) LAG_LAUNCH(2, false, true, true, false);
+        else if (ctl.pass) LAG_LAUNCH(2, true, false, true, false);
+        else LAG_LAUNCH(2, false, false, true, false);
     } else if (wide) {
-        if (ctl.dump) LAG_LAUNCH(2, false, true, false);
-        else if (ctl.pass) LAG_LAUNCH(2, true, false, false);
-        else LAG_LAUNCH(2, false, false, false);
+        if (ctl.dump) LAG_LAUNCH(2, false, true, false, false);
+        else if (ctl.pass) LAG_LAUNCH(2, true, false, false, false);
+        else LAG_LAUNCH(2, false, false, false, false);
     } else {
-        if (ctl.dump) LAG_LAUNCH(1, false, true, false);
-        else if (ctl.pass) LAG_LAUNCH(1, true, false, false);
-        else LAG_LAUNCH(1, false, false, false);
+        if (ctl.dump) LAG_LAUNCH(1, false, true, false, false);
+        else if (ctl.pass) LAG_LAUNCH(1, true, false, false, false);
+        else LAG_LAUNCH(1, false, false, false, false);
     }
 #undef LAG_LAUNCH
     ACT_HIP(hipGetLastError());

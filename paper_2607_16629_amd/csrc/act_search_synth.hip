@@ -363,6 +363,7 @@ act_status launch_search_synth_f32(act_plan_s* p, int batch, const SearchCtl& ct
 }
 
 act_status launch_ragged_items(act_plan_s* p, int batch, hipStream_t s) {
+    if (p->desc.ragged && p->desc.dict == ACT_DICT_LAG) return launch_lag_ragged_prep(p, batch, s);
     if (!(p->desc.ragged && p->items)) return ACT_OK;
     if (p->desc.prec == ACT_PREC_F16) return launch_h16_ragged_prep(p, batch, s);
     const int n_clb = (p->n_cl + SY_ROWS - 1) / SY_ROWS;

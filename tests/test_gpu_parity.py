@@ -288,11 +288,14 @@ def _ragged_case(count, n_min, n_max, fc_c_ld, order, seed=5):
 
 
 @pytest.mark.parametrize("prec,dict_,cut", [("f64", "synth", False), ("f32", "synth", False),
-                                            ("f16", "synth", False), ("f16", "synth", True)])
+                                            ("f16", "synth", False), ("f16", "synth", True),
+                                            ("f16", "lag", False)])
 def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_, cut):
     """Uneven lengths in one call: every signal has its own dictionary
     (floor(N/32) time centres); each is checked against the oracle run on that
-    signal alone; lengths below 32 samples are flagged empty."""
+    signal alone; lengths below 32 samples are flagged empty.  The lag table
+    scores with the longest window's norms and emits by the bound of the true
+    score near each signal's end."""
     wl = _ragged_case(9, 20, 900, (8, 6, 4), 4)
     lens = wl.lengths.copy()
     nmax = int(lens.max())
@@ -322,14 +325,16 @@ def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_, cut):
     np.testing.assert_allclose(rec[ok], res["approx"][ok], rtol=0, atol=1e-12 * np.abs(wl.signals).max())
 
 
-def test_ragged_bad_lengths_are_flagged_and_queue_replays_match():
+@pytest.mark.parametrize("prec,dict_", [("f32", "synth"), ("f16", "lag")])
+def test_ragged_bad_lengths_are_flagged_and_queue_replays_match(prec, dict_):
     """Lengths outside [0, n_samples] are flagged and skipped without touching
     the other channels; repeated calls (captured-graph replays of the
-    synthesised search's tile queue) reproduce the direct launches bit for bit."""
+    synthesised search's tile queue, or of the lag table's per-call channel
+    order) reproduce the direct launches bit for bit."""
     act = A()
     wl = _ragged_case(5, 40, 400, (8, 6, 4), 3, seed=9)
     lens = wl.lengths.copy()
-    plan = act.Plan(W.ragged_grid(int(lens.max()), 32, 8, 6, 4), dict_="synth", prec="f32",
+    plan = act.Plan(W.ragged_grid(int(lens.max()), 32, 8, 6, 4), dict_=dict_, prec=prec,
                     max_batch=len(lens), refine_steps=30, ragged=True, ragged_tc_div=32)
     good = plan.decompose_ragged(wl.signals, lens, wl.offsets, 3)
     bad = lens.copy()
@@ -1072,7 +1077,8 @@ def test_lag_table_rejects_unaligned_time_centres():
     with pytest.raises(act.ActError) as e:
         act.Plan(g, dict_="lag", prec="f16")
     assert e.value.status == act.ACT_ERR_UNSUPPORTED
-    for kw in (dict(prec="f32"), dict(prec="f16", ragged=True), dict(prec="f16", support_cut=True)):
+    for kw in (dict(prec="f32"), dict(prec="f16", ragged=True, ragged_tc_div=12),
+               dict(prec="f16", ragged=True, ragged_tc_div=32, complex_atoms=True), dict(prec="f16", support_cut=True)):
         with pytest.raises(act.ActError) as e:
             act.Plan(W.eeg_grid(512, 32, 8, 4, 2), dict_="lag", **kw)
         assert e.value.status == act.ACT_ERR_UNSUPPORTED, kw
