@@ -9,8 +9,8 @@
 // therefore one product with K = the lags:
 //   P[(b, m)][q] = sum_d R[(b, m)][d] G[d][q],   R[(b, m)][d] = r_b(d + m)
 // (zero outside the signal).  The matrix cores execute the dense
-// correlation's multiply-adds (plus a stage's span of lags), not the factored
-// synthesis' two products per sample.
+// correlation's multiply-adds (within each tile's nonzero lag band), not the
+// factored synthesis' two products per sample.
 //
 // G: FP16 (RNE of the FP64 value), columns padded to a multiple of 256, lags
 // e = d + N_pad in [0, 2 N_pad), pre-swizzled in MFMA B-operand order: for 32
@@ -32,6 +32,11 @@
 // Certified emission with a uniform bound per channel (the FP16 table's
 // rounding, the search copy's rounding, the FP32 accumulation): every atom
 // with |p~| >= M - 2 E_b is emitted, M the running maximum.
+//
+// Complex atoms (Eq. (1) as written) store each 32-atom block's cos and sin
+// parts as two adjacent column blocks; uneven-length batches share the
+// longest signal's table and bound each row's true score near its signal's
+// end (see k_search_lag).
 #include <algorithm>
 #include <climits>
 #include <type_traits>
