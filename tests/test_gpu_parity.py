@@ -325,6 +325,37 @@ def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_, cut):
     np.testing.assert_allclose(rec[ok], res["approx"][ok], rtol=0, atol=1e-12 * np.abs(wl.signals).max())
 
 
+@pytest.mark.parametrize("count", [1, 34])
+def test_ragged_lag_channel_groups_match_per_signal_oracle(oracle, count):
+    """The ragged lag table with one signal (a 1-channel tile of 128 time
+    centres) and with 34 signals (two 32-channel groups, the second holding
+    two): every signal's pursuit against the oracle run on it alone."""
+    wl = _ragged_case(count, 40, 420, (8, 6, 4), 3, seed=21 + count)
+    lens = wl.lengths.copy()
+    nmax = int(lens.max())
+    plan = A().Plan(W.ragged_grid(nmax, 32, 8, 6, 4), dict_="lag", prec="f16", max_batch=len(lens),
+                    refine_steps=60, ragged=True, ragged_tc_div=32)
+    gpu = plan.decompose_ragged(wl.signals, lens, wl.offsets, 3)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in gpu.items() if v is not None}
+    checked = 0
+    for b in range(len(lens)):
+        n, o = int(lens[b]), int(wl.offsets[b])
+        s = wl.signals[o:o + n]
+        if n < 32:
+            assert res["flags"][b] & A().FLAG_RAGGED_EMPTY
+            continue
+        g = wl.grids[b]
+        ref = oracle.decompose(g, s, 3, refine_steps=60)
+        sub = {"index": res["index"][b:b + 1], "theta": res["theta"][b:b + 1],
+               "coef": res["coef"][b:b + 1], "energy": res["energy"][b:b + 1],
+               "gap": res["gap"][b:b + 1], "approx": res["approx"][None, o:o + n],
+               "resid": res["resid"][None, o:o + n]}
+        checked += assert_decomposition_parity(sub, ref, g, oracle, s[None, :], f"raglag{b}", 60)
+    assert checked >= min(3, 2 * len(lens))
+    assert np.all(res["flags"] & A().FLAG_CAND_OVERFLOW == 0)
+
+
 @pytest.mark.parametrize("prec,dict_", [("f32", "synth"), ("f16", "lag")])
 def test_ragged_bad_lengths_are_flagged_and_queue_replays_match(prec, dict_):
     """Lengths outside [0, n_samples] are flagged and skipped without touching
