@@ -191,6 +191,9 @@ def run_workload(name: str, steps: int, warmup: int):
                            "algorithmic_flops_per_launch": algo,
                            "executed_mfma_flops_per_launch": executed,
                            "executed_frac": round(executed / (search_ms * 1e-3) / (peak * 1e12), 4)}
+        if lag:
+            # the lag table skips exact zeros: frac is a dense-equivalent rate
+            res["roofline"]["dense_equivalent"] = True
     else:
         # FP64 on-the-fly synthesis, ~60 FP64 operations per atom sample
         ops = g.size * g.n * B * 60
@@ -269,7 +272,8 @@ def run_ragged(steps: int, warmup: int, prec: str = "f16", cut: bool = False, di
                          "kernel": kname + ("" if lag else "_ragged"), "avg_launch_ms": round(search_ms, 5),
                          "algorithmic_flops_per_launch": algo,
                          # the lag table runs its tiles' nonzero bands (counted per call on the device only)
-                         "executed_mfma_flops_per_launch": None if lag else 2 * algo}}
+                         "executed_mfma_flops_per_launch": None if lag else 2 * algo,
+                         "dense_equivalent": lag}}
 
 
 def run_sweep(steps: int, warmup: int):
