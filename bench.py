@@ -48,6 +48,8 @@ WORKLOADS = {
     # FP16 lag table of one time centre: the dense correlation as one matrix product
     "lag-f16-64x2048": ("batched_64x2048", dict(dict_="lag", prec="f16"), "mfma_f16", 0),
     "lag-f16-1x2048": ("fp32_1x2048", dict(dict_="lag", prec="f16"), "mfma_f16", 0),
+    # the same lag table in BF16 (BF16 x BF16 -> FP32 MFMA)
+    "lag-bf16-64x2048": ("batched_64x2048", dict(dict_="lag", prec="bf16"), "mfma_bf16", 0),
     # complex (analytic) atoms: two correlations per atom (real and imaginary part)
     "complex-f32-64x2048-synth": ("batched_64x2048", dict(dict_="synth", prec="f32", complex_atoms=True),
                                   "mfma_f32", 0),
@@ -59,7 +61,8 @@ KERNELS = {("table", "f32"): ("k_search_f32_table", "act_search_f32t.hip"),
            ("synth", "f32"): ("k_search_synth_f32", "act_search_synth.hip"),
            ("synth", "f16"): ("k_search_h16", "act_search_h16.hip"),
            ("synth", "f64"): ("k_search_f64", "act_search_f64.hip"),
-           ("lag", "f16"): ("k_search_lag", "act_search_lag.hip")}
+           ("lag", "f16"): ("k_search_lag", "act_search_lag.hip"),
+           ("lag", "bf16"): ("k_search_lag", "act_search_lag.hip")}
 
 
 def source_sha(*names) -> str:
@@ -174,7 +177,7 @@ def run_workload(name: str, steps: int, warmup: int):
             flops = 2.0 * g.size * g.n * B
             res["roofline"]["mfma_frac_of_bf16_peak"] = round(
                 flops / (search_ms * 1e-3) / (PEAK_TFLOPS["bf16_mfma"] * 1e12), 4)
-    elif kind in ("mfma_f32", "mfma_f16"):
+    elif kind in ("mfma_f32", "mfma_f16", "mfma_bf16"):
         # factored synthesis: the matrix cores execute 2 x (atoms x N x B)
         # multiply-adds; the roofline counts the dense correlation's flops
         # (complex atoms: both parts, 2 x atoms x N x B multiply-adds)
@@ -416,7 +419,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companions", action="store_true")
-    ap.add_argument("--companions", default="fp32-1x2048-synth,lag-f16-1x2048,bf16-64x2048,lag-f16-64x2048,"
+    ap.add_argument("--companions", default="fp32-1x2048-synth,lag-f16-1x2048,bf16-64x2048,lag-f16-64x2048,lag-bf16-64x2048,"
                                             "f16-64x2048-synth,f16-64x2048-synth-cut,complex-f32-64x2048-synth,complex-lag-f16-64x2048,"
                                             "ragged-1000-f16,ragged-1000-f16-cut,ragged-1000-f16-lag",
                     help="comma-separated companion workloads of the default run")

@@ -72,9 +72,10 @@ enum {
     ACT_DICT_LAG = 2    /* one time centre's atoms over every lag in an HBM-resident FP16 table
                            (time centres on integer samples that are multiples of 8): the scores
                            of all (channel, time centre) rows are one dense matrix product with
-                           the residual's shifted windows; ACT_PREC_F16 only; plain plans (real
-                           or complex atoms) and ragged plans of real atoms (ragged_tc_div a
-                           multiple of 8) */
+                           the residual's shifted windows; ACT_PREC_F16: plain plans (real or
+                           complex atoms) and ragged plans of real atoms (ragged_tc_div a
+                           multiple of 8); ACT_PREC_BF16: the same table in BF16, plain plans of
+                           real atoms */
 };
 
 /* Arithmetic of the coarse search (rescoring, refinement, coefficients and
@@ -82,7 +83,9 @@ enum {
 enum {
     ACT_PREC_F64 = 0,  /* FP64 correlation (ACT_DICT_SYNTH only) */
     ACT_PREC_F32 = 1,  /* FP32 correlation, certified FP64 rescoring of the candidates */
-    ACT_PREC_BF16 = 2, /* BF16 x BF16 -> FP32 MFMA correlation, certified FP64 rescoring */
+    ACT_PREC_BF16 = 2, /* BF16 x BF16 -> FP32 MFMA correlation over the atom table
+                          (ACT_DICT_TABLE) or the lag table (ACT_DICT_LAG), certified FP64
+                          rescoring */
     ACT_PREC_F16 = 3   /* FP16 x FP16 -> FP32 MFMA correlation over factor tables
                           (ACT_DICT_SYNTH) or the lag table (ACT_DICT_LAG), certified FP64
                           rescoring */
@@ -166,7 +169,7 @@ int64_t act_plan_query(act_plan_t plan, int32_t key);
  * (2 per multiply-add), with every channel taking part: for ACT_DICT_LAG
  * plans, the sum over the launch's tiles of their stages x 128 rows x the
  * tile's columns x 128 lags x 2.  Tiles run only the lags where their columns
- * hold nonzero FP16 entries, so this is well below the dense count
+ * hold nonzero FP16 (BF16) entries, so this is well below the dense count
  * 2 atoms n_samples batch (padding rows and columns included).  Diagnostic
  * for utilisation figures; host-only, no device work.  Errors:
  * ACT_ERR_INVALID (NULL plan or flops, batch outside [1, max_batch]),

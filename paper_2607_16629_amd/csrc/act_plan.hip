@@ -443,9 +443,12 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
             return ACT_ERR_UNSUPPORTED;
         }
     }
-    if (desc->dict == ACT_DICT_LAG && !(desc->prec == ACT_PREC_F16 && !desc->prior_act && !desc->support_cut &&
-                                        !(desc->ragged && desc->complex_atoms))) {
-        set_error("act_plan: ACT_DICT_LAG is the FP16 lag-table search (complex atoms on plain plans only)");
+    if (desc->dict == ACT_DICT_LAG &&
+        !(((desc->prec == ACT_PREC_F16 && !(desc->ragged && desc->complex_atoms)) ||
+           (desc->prec == ACT_PREC_BF16 && !desc->ragged && !desc->complex_atoms)) &&
+          !desc->prior_act && !desc->support_cut)) {
+        set_error("act_plan: ACT_DICT_LAG is the FP16 lag-table search (complex atoms on plain plans only) "
+                  "or its BF16 form (plain plans of real atoms)");
         return ACT_ERR_UNSUPPORTED;
     }
     if (desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_BF16) {
@@ -466,8 +469,8 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     // longest FP32 accumulation chain of one search score (certified margin):
     // the FP32 GEMV's per-lane FMAs plus its reduction tree; the MFMA path is
     // bounded by one rounding per sample
-    p->chain = desc->prec == ACT_PREC_BF16  ? p->n_pad
-               : desc->dict == ACT_DICT_LAG ? lag_chain_length(p->n_pad)
+    p->chain = desc->dict == ACT_DICT_LAG     ? lag_chain_length(p->n_pad)
+               : desc->prec == ACT_PREC_BF16 ? p->n_pad
                : desc->prec == ACT_PREC_F16 ? h16_chain_length(p->n_pad)
                : desc->dict == ACT_DICT_SYNTH ? synth_chain_length(p->n_pad)
                                               : f32_chain_length(p->n_pad);

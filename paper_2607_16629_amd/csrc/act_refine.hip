@@ -106,8 +106,12 @@ __device__ double score_bound(const PlanDev& P, double rn, double er, double sca
         // sample, so over the atom's window (|g_w| >= 1, at most 2N samples) the
         // table error is <= (u16 + u32 + 2^-25 sqrt(2N)) |r~| after 1/|g_w|; the
         // FP16 products are exact in FP32, their sum carries gamma_m; the FP32
-        // 1/|g| and the scalings add <= 3 u |r~|; the search copy's error |e_r|
-        const double u16 = 4.8828125e-04;
+        // 1/|g| and the scalings add <= 3 u |r~|; the search copy's error |e_r|.
+        // BF16 table: u16 becomes 2^-8, with the same 2^-25 floor (entries
+        // below it are zero); the copy's subnormal floor (at most 2^-126 per
+        // sample of a copy whose channel maximum is scaled to >= 2^12) and the
+        // second-order products of the two roundings lie inside the 1% margin
+        const double u16 = P.prec == ACT_PREC_BF16 ? 3.90625e-03 : 4.8828125e-04;
         const double eg = u16 + u32 + 2.98023223876953125e-08 * sqrt(2.0 * n);
         (void)scale;
         if (P.cplx) {
@@ -200,7 +204,10 @@ template <int TB>
 __device__ double refresh_channel(const PlanDev& P, int b, const double* r, int n, double* red,
                                   bool bad) {
     double acc[2] = {0.0, 0.0};
-    const float scale = P.prec == ACT_PREC_F16 ? f16_operand_scale(block_absmax<TB>(r, n)) : 1.0f;
+    // power-of-two scale of the FP16 copy, and of the BF16 copy the lag table
+    // multiplies (it keeps small residuals clear of the subnormal range)
+    const bool scaled = P.prec == ACT_PREC_F16 || (P.prec == ACT_PREC_BF16 && P.dict == ACT_DICT_LAG);
+    const float scale = scaled ? f16_operand_scale(block_absmax<TB>(r, n)) : 1.0f;
     for (int k = threadIdx.x; k < P.g.n_pad; k += TB) {
         const double v = k < n ? r[k] : 0.0;
         double back;
@@ -210,9 +217,9 @@ __device__ double refresh_channel(const PlanDev& P, int b, const double* r, int 
             ((_Float16*)P.shadow)[(size_t)b * P.sh_stride + k] = h;
             back = (double)(float)h / (double)scale;
         } else if (P.prec == ACT_PREC_BF16) {
-            unsigned short h = bf16_rne((float)v);
+            unsigned short h = bf16_rne((float)v * scale);
             ((unsigned short*)P.shadow)[(size_t)b * P.sh_stride + k] = h;
-            back = (double)__uint_as_float(((unsigned)h) << 16);
+            back = (double)__uint_as_float(((unsigned)h) << 16) / (double)scale;
         } else {
             const float f = (float)v;
             ((float*)P.shadow)[(size_t)b * P.sh_stride + k] = f;
@@ -266,12 +273,15 @@ __global__ void __launch_bounds__(NT) k_init(PlanDev P, double* __restrict__ res
 
 __global__ void __launch_bounds__(256) k_to_shadow(PlanDev P, const double* __restrict__ resid) {
     const int b = blockIdx.x;
-    if (P.prec == ACT_PREC_F16) {
+    if (P.prec == ACT_PREC_F16 || (P.prec == ACT_PREC_BF16 && P.dict == ACT_DICT_LAG)) {
         const float sc = f16_operand_scale(block_absmax<256>(resid + (size_t)b * P.g.n, P.g.n));
         if (threadIdx.x == 0) P.rscale[b] = sc;
         for (int k = threadIdx.x; k < P.g.n_pad; k += blockDim.x) {
             const double v = k < P.g.n ? resid[(size_t)b * P.g.n + k] : 0.0;
-            ((_Float16*)P.shadow)[(size_t)b * P.sh_stride + k] = (_Float16)((float)v * sc);
+            if (P.prec == ACT_PREC_F16)
+                ((_Float16*)P.shadow)[(size_t)b * P.sh_stride + k] = (_Float16)((float)v * sc);
+            else
+                ((unsigned short*)P.shadow)[(size_t)b * P.sh_stride + k] = bf16_rne((float)v * sc);
         }
         return;
     }

@@ -37,6 +37,10 @@
 // parts as two adjacent column blocks; uneven-length batches share the
 // longest signal's table and bound each row's true score near its signal's
 // end (see k_search_lag).
+//
+// BF16 form (plain plans of real atoms): the same table and search copy in
+// BF16 (RNE) through v_mfma_f32_32x32x16_bf16; a wider per-channel bound
+// (unit roundoff 2^-8), the same schedule and emission.
 #include <algorithm>
 #include <climits>
 #include <type_traits>
@@ -47,6 +51,7 @@
 namespace act {
 
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));  // the BF16 form's operands, same storage
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int LG_S = 128;          // lags per stage
@@ -138,11 +143,12 @@ __device__ __forceinline__ long long lag_atom(const LagDev& ld, int tc, int qc) 
 // the atom beyond the end) (|g_w| >= 1).  A row of a channel emits its atoms
 // by the upper bound (|p~| + E_b) rho - E_b against M - 2 E_b and stores that
 // bound as the candidate's score; rho = 1 beyond ld.rho_d samples from the end.
-template <int WCB, bool RERUN, bool DUMP, bool CPLX, bool RAG>
+template <int WCB, bool RERUN, bool DUMP, bool CPLX, bool RAG, bool BF>
 __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, SearchCtl ctl, int batch,
                                                        int n_cbk, int n_cg, int n_tg) {
     static_assert(!CPLX || WCB == 2, "complex atoms pair two column blocks");
     static_assert(!RAG || (WCB == 2 && !CPLX && !DUMP), "ragged: real atoms, 256-column tiles, search only");
+    static_assert(!BF || (!CPLX && !RAG), "BF16 table: plain plans of real atoms");
     __shared__ LagLds L;
     // the rerun pass: nothing to do unless some channel's list overflowed
     if (RERUN) {
@@ -301,8 +307,13 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
                 for (int rb = 0; rb < LG_RB; ++rb)
 #pragma unroll
                     for (int cb = 0; cb < WCB; ++cb)
-                        acc[rb][cb] =
-                            __builtin_amdgcn_mfma_f32_32x32x16_f16(af[ks & 1][rb], src[ks][cb], acc[rb][cb], 0, 0, 0);
+                        if constexpr (BF)
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, af[ks & 1][rb]), __builtin_bit_cast(bf16x8, src[ks][cb]),
+                                acc[rb][cb], 0, 0, 0);
+                        else
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[ks & 1][rb], src[ks][cb],
+                                                                                 acc[rb][cb], 0, 0, 0);
             }
             // order: the first k-step's A reads, then each k-step's MFMAs in
             // pairs with one A read of the next k-step between them
@@ -551,11 +562,18 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
     }
 }
 
-// The lag table: G_q(d) in FP64, rounded to FP32 and then FP16 (RNE), written
+// BF16 of an FP32 value, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short lag_bf16_rne(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// The lag table: G_q(d) in FP64, rounded to FP32 and then FP16 or BF16 (RNE;
+// BF16 entries below 2^-25 are zero), written
 // in MFMA B-operand order; columns past Q are zero.  Columns run log-duration
 // major, qc = ld FC + (f_c n_c + c), so a tile's columns share an envelope and
 // its nonzero lags.
-__global__ void k_build_lag_table(GridDev g, int Q_pad, int cplx, f16x8* __restrict__ G) {
+__global__ void k_build_lag_table(GridDev g, int Q_pad, int cplx, int bf16, f16x8* __restrict__ G) {
     const int FC = g.cnt[1] * g.cnt[2];
     const int LS = 2 * g.n_pad / 16;
     const long long frags = (long long)(Q_pad / 32) * LS * 64;  // one f16x8 per (column block, k-step, lane)
@@ -572,7 +590,7 @@ __global__ void k_build_lag_table(GridDev g, int Q_pad, int cplx, f16x8* __restr
         f16x8 out;
         if (qc >= FC * g.cnt[3]) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) out[j] = (_Float16)0.0f;
+            for (int j = 0; j < 8; ++j) out[j] = (_Float16)0.0f;  // (also BF16 zero)
         } else {
             const int il = qc / FC, fcc = qc % FC;
             const double f0 = g.axis[g.off[1] + fcc / g.cnt[2]];
@@ -585,7 +603,13 @@ __global__ void k_build_lag_table(GridDev g, int Q_pad, int cplx, f16x8* __restr
                 const double u = tau * inv_dt;
                 const double ph = 2.0 * (c * tau * tau + f0 * tau);
                 const double v = exp(-0.5 * u * u) * (sin_part ? sinpi(ph) : cospi(ph));
-                out[j] = (_Float16)(float)v;
+                // BF16 keeps FP16's floor: entries below 2^-25 are zero (error
+                // <= 2^-25 per sample, as FP16's rounding), so both tables share
+                // their nonzero bands
+                out[j] = bf16 ? __builtin_bit_cast(_Float16, fabs(v) < 2.98023223876953125e-08
+                                                                  ? (unsigned short)0
+                                                                  : lag_bf16_rne((float)v))
+                              : (_Float16)(float)v;
             }
         }
         G[f] = out;
@@ -709,7 +733,7 @@ act_status build_lag_table(act_plan_s* p, hipStream_t s) {
     const long long frags = (long long)(Q_pad / 32) * LS * 64;
     const long long blocks = std::min<long long>((frags + 255) / 256, (long long)device_cus() * 64);
     hipLaunchKernelGGL(k_build_lag_table, dim3((unsigned)blocks), dim3(256), 0, s, p->grid, Q_pad,
-                       p->desc.complex_atoms, (f16x8*)p->table);
+                       p->desc.complex_atoms, p->desc.prec == ACT_PREC_BF16 ? 1 : 0, (f16x8*)p->table);
     ACT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_lag_span, dim3((unsigned)(Q_pad / 32)), dim3(256), 0, s, (const f16x8*)p->table, LS,
                        (int2*)p->lag_span);
@@ -873,9 +897,22 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     blocks = blocks < cap ? blocks : cap;
     const dim3 grid((unsigned)blocks), blk(256);
 #define LAG_LAUNCH(WCB, RR, DD, CX, RG)                                                                       \
-    hipLaunchKernelGGL((k_search_lag<WCB, RR, DD, CX, RG>), grid, blk, 0, s, p->grid, ld, ctl, batch, n_cbk, n_cg, \
-                       n_tg)
-    if (rag) {
+    hipLaunchKernelGGL((k_search_lag<WCB, RR, DD, CX, RG, false>), grid, blk, 0, s, p->grid, ld, ctl, batch, n_cbk,  \
+                       n_cg, n_tg)
+#define LAG_LAUNCH_BF(WCB, RR, DD)                                                                            \
+    hipLaunchKernelGGL((k_search_lag<WCB, RR, DD, false, false, true>), grid, blk, 0, s, p->grid, ld, ctl, batch,  \
+                       n_cbk, n_cg, n_tg)
+    if (p->desc.prec == ACT_PREC_BF16) {
+        if (wide) {
+            if (ctl.dump) LAG_LAUNCH_BF(2, false, true);
+            else if (ctl.pass) LAG_LAUNCH_BF(2, true, false);
+            else LAG_LAUNCH_BF(2, false, false);
+        } else {
+            if (ctl.dump) LAG_LAUNCH_BF(1, false, true);
+            else if (ctl.pass) LAG_LAUNCH_BF(1, true, false);
+            else LAG_LAUNCH_BF(1, false, false);
+        }
+    } else if (rag) {
         if (ctl.pass) LAG_LAUNCH(2, true, false, false, true);
         else LAG_LAUNCH(2, false, false, false, true);
     } else if (cplx) {
@@ -892,6 +929,7 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
         else LAG_LAUNCH(1, false, false, false, false);
     }
 #undef LAG_LAUNCH
+#undef LAG_LAUNCH_BF
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

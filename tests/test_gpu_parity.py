@@ -160,10 +160,12 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_s
 # FP16 factored synthesis: (2 u16 + 5 u32 + gamma) sqrt(2) rho |r| with
 # u16 = 2^-11 and rho (|envelope| / |atom|) below 1.5 on these grids: 2.5e-3 |r|.
 # FP16 lag table: (u16 + u32 + gamma_{2N+2}) |r| plus the FP16 search copy's
-# own rounding (<= u16 |r|): 1.5e-3 |r| at N = 512.
+# own rounding (<= u16 |r|): 1.5e-3 |r| at N = 512; its BF16 form, with
+# u = 2^-8 for both roundings: 8e-3 |r|.
 @pytest.mark.parametrize("prec,dict_,tol", [("f64", "synth", 1e-12), ("f32", "table", 1e-5),
                                             ("bf16", "table", 8e-3), ("f32", "synth", 1e-5),
-                                            ("f16", "synth", 2.5e-3), ("f16", "lag", 1.5e-3)])
+                                            ("f16", "synth", 2.5e-3), ("f16", "lag", 1.5e-3),
+                                            ("bf16", "lag", 8e-3)])
 def test_correlate_matches_oracle(oracle, prec, dict_, tol):
     wl = W.plain_1x512()
     g = wl.grid
@@ -200,7 +202,7 @@ def test_correlate_many_channels_and_ragged_tail(oracle, prec, tol):
 @pytest.mark.parametrize("prec,dict_,cut", [("f64", "synth", False), ("f32", "table", False),
                                             ("bf16", "table", False), ("f32", "synth", False),
                                             ("f16", "synth", False), ("f16", "synth", True),
-                                            ("f16", "lag", False)])
+                                            ("f16", "lag", False), ("bf16", "lag", False)])
 def test_decompose_plain_1x512(oracle, prec, dict_, cut):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, wl.order, refine_steps=30)
@@ -210,7 +212,7 @@ def test_decompose_plain_1x512(oracle, prec, dict_, cut):
 
 
 @pytest.mark.parametrize("prec,dict_", [("f64", "synth"), ("f32", "table"), ("bf16", "table"),
-                                        ("f32", "synth"), ("f16", "synth"), ("f16", "lag")])
+                                        ("f32", "synth"), ("f16", "synth"), ("f16", "lag"), ("bf16", "lag")])
 def test_decompose_without_refinement_is_exact_mp(oracle, prec, dict_):
     wl = W.plain_1x512()
     ref = oracle.decompose(wl.grid, wl.signals, 8, refine_steps=0)
@@ -441,7 +443,7 @@ def test_graph_replays_match_direct_launches():
 
 
 @pytest.mark.parametrize("prec,dict_,cap", [("f32", "table", 2), ("bf16", "table", 40), ("f16", "synth", 8),
-                                            ("f16", "lag", 8)])
+                                            ("f16", "lag", 8), ("bf16", "lag", 8)])
 def test_small_candidate_capacity_reruns_exactly(oracle, prec, dict_, cap):
     """A tiny capacity forces the exact-threshold rerun pass; the result must
     not change."""
@@ -451,7 +453,7 @@ def test_small_candidate_capacity_reruns_exactly(oracle, prec, dict_, cap):
     assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, 0)
 
 
-@pytest.mark.parametrize("prec,dict_", [("bf16", "table"), ("f16", "synth"), ("f16", "lag")])
+@pytest.mark.parametrize("prec,dict_", [("bf16", "table"), ("f16", "synth"), ("f16", "lag"), ("bf16", "lag")])
 def test_batch_of_70_channels(oracle, prec, dict_):
     """More than one 64-channel tile, a reduced grid; the oracle checks a
     few channels from both tiles (channels are independent)."""
@@ -498,7 +500,8 @@ def test_fp32_full_size_2m_atoms(oracle, prec, dict_):
 
 
 @pytest.mark.parametrize("prec,dict_,cut", [("bf16", "table", False), ("f16", "synth", False),
-                                            ("f16", "synth", True), ("f16", "lag", False)])
+                                            ("f16", "synth", True), ("f16", "lag", False),
+                                            ("bf16", "lag", False)])
 def test_full_size_64x2048(oracle, prec, dict_, cut):
     """64 channels x N = 2048 on the 2,097,152-atom grid, BF16 table or FP16
     synthesis + FP64 rescoring: per order and for sampled channels, the
@@ -972,7 +975,7 @@ def test_complex_full_size_64x2048(oracle, prec, dict_):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("prec,dict_", [("f32", "table"), ("bf16", "table"), ("f16", "synth"), ("f32", "synth"),
-                                        ("f16", "lag")])
+                                        ("f16", "lag"), ("bf16", "lag")])
 def test_tuned_shapes_change_no_result(oracle, prec, dict_, tmp_path):
     """act_tune picks a launch shape by timing; decompositions with the tuned
     shape are bit-identical to the default shape's, the choice is cached per
@@ -1092,6 +1095,10 @@ def test_lag_search_flops_counts_the_band_stages():
     full = (g.size // g.tc.count // 256) * 2 * (g.tc.count // 4) * (2 * n_pad // 128) * unit
     assert f64 < 0.7 * full
     assert plan.search_flops(1) % (128 * 128 * 128 * 2.0) == 0
+    # the BF16 table zeroes entries below FP16's floor: the same bands (up to
+    # the k-step that a value at the floor itself may add)
+    fb = act.Plan(g, dict_="lag", prec="bf16", max_batch=64).search_flops(64)
+    assert abs(fb - f64) <= 0.02 * f64, (fb, f64)
     with pytest.raises(act.ActError) as e:
         plan.search_flops(65)
     assert e.value.status == act.ACT_ERR_INVALID
@@ -1109,7 +1116,8 @@ def test_lag_table_rejects_unaligned_time_centres():
         act.Plan(g, dict_="lag", prec="f16")
     assert e.value.status == act.ACT_ERR_UNSUPPORTED
     for kw in (dict(prec="f32"), dict(prec="f16", ragged=True, ragged_tc_div=12),
-               dict(prec="f16", ragged=True, ragged_tc_div=32, complex_atoms=True), dict(prec="f16", support_cut=True)):
+               dict(prec="f16", ragged=True, ragged_tc_div=32, complex_atoms=True), dict(prec="f16", support_cut=True),
+               dict(prec="bf16", complex_atoms=True), dict(prec="bf16", ragged=True, ragged_tc_div=32)):
         with pytest.raises(act.ActError) as e:
             act.Plan(W.eeg_grid(512, 32, 8, 4, 2), dict_="lag", **kw)
         assert e.value.status == act.ACT_ERR_UNSUPPORTED, kw
