@@ -153,9 +153,37 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+// v plus the value that DPP control CTRL moves into this lane; rows outside
+// ROWS (and lanes without a source) add zero
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+    return v + __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave with DPP row moves (no LDS traffic): lane
+// pairs, quads, half rows, rows (mirrors); rows 1 and 3 then add rows 0 and 2
+// (row_bcast15) and row 3 adds rows 0-1 (row_bcast31), so lane 63 holds the
+// total, returned to every lane.  Fixed order: deterministic.
+__device__ __forceinline__ double wave_total(double v) {
+    v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);  // row_mirror
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast15 into rows 1, 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast31 into rows 2, 3
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Sum NV doubles over a block of NT threads; every thread receives the totals.
 // `lds` must hold block_sum_lds(NT, NV) doubles.  Deterministic: fixed order
-// (wave butterflies, then thread j adds the wave partials of value j in order).
+// (the wave's DPP tree, then every thread adds the wave partials in order).
+// Called by every thread of the block (it holds barriers).
 constexpr int block_sum_lds(int nt, int nv) { return nv * (nt / kWave + 1); }
 
 template <int NT, int NV>
@@ -164,21 +192,19 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    for (int j = 0; j < NV; ++j) v[j] = wave_total(v[j]);
     if (lane == 0) {
 #pragma unroll
         for (int j = 0; j < NV; ++j) lds[j * NW + w] = v[j];
     }
     __syncthreads();
-    if (threadIdx.x < NV) {
-        double s = 0.0;
-#pragma unroll 1
-        for (int k = 0; k < NW; ++k) s += lds[threadIdx.x * NW + k];
-        lds[NV * NW + threadIdx.x] = s;
-    }
-    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = lds[NV * NW + j];
+    for (int j = 0; j < NV; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) s += lds[j * NW + k];
+        v[j] = s;
+    }
     __syncthreads();
 }
 
