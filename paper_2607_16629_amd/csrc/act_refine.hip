@@ -1051,21 +1051,21 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
 // --------------------------------------------------------------------------
 // refinement alone, forward/adjoint alone, reconstruction
 // --------------------------------------------------------------------------
-template <int MODE>
-__global__ void __launch_bounds__(NTR) k_refine_many(GridDev g, BoxDev box,
+template <int MODE, int TB>
+__global__ void __launch_bounds__(TB) k_refine_many(GridDev g, BoxDev box,
                                                      const double* __restrict__ resid,
                                                      const double* __restrict__ theta0, int steps,
                                                      double* __restrict__ theta,
                                                      double* __restrict__ value,
                                                      int* __restrict__ flags) {
-    __shared__ double red[block_sum_lds(NTR, 13)];
+    __shared__ double red[block_sum_lds(TB, 13)];
     __shared__ RefineLds L;
     const int p = blockIdx.x;
     const double* r = resid + (size_t)p * g.n;
     double th0[4], th[4], J;
 #pragma unroll
     for (int j = 0; j < 4; ++j) th0[j] = theta0[p * 4 + j];
-    const int fl = refine_block<NTR, MODE>(r, g, box, th0, steps, th, &J, red, L);
+    const int fl = refine_block<TB, MODE>(r, g, box, th0, steps, th, &J, red, L);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) theta[p * 4 + j] = th[j];
@@ -1268,8 +1268,15 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
 
 act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const double* theta0,
                               int steps, double* theta, double* value, int* flags, hipStream_t s) {
-    hipLaunchKernelGGL((p->desc.complex_atoms ? k_refine_many<kObjComplex> : k_refine_many<kObjReal>), dim3(m),
-                       dim3(NTR), 0, s, p->grid, p->box, resid, theta0, steps, theta, value, flags);
+    // more than two pairs per CU: 128-thread blocks, several per CU, so that
+    // the CU's FP64 units stay busy; otherwise NTR threads per pair (each
+    // pair's own latency sets the time)
+    const bool many = (long long)m > 2LL * device_cus();
+    const bool cx = p->desc.complex_atoms != 0;
+    auto kern = many ? (cx ? k_refine_many<kObjComplex, 128> : k_refine_many<kObjReal, 128>)
+                     : (cx ? k_refine_many<kObjComplex, NTR> : k_refine_many<kObjReal, NTR>);
+    hipLaunchKernelGGL(kern, dim3(m), dim3(many ? 128 : NTR), 0, s, p->grid, p->box, resid, theta0, steps, theta,
+                       value, flags);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

@@ -541,16 +541,31 @@ def test_full_size_64x2048(oracle, prec, dict_, cut):
 # refinement, forward / adjoint, reconstruction
 # --------------------------------------------------------------------------
 
-def test_refine_many_matches_oracle(oracle):
-    wl = W.refine_pairs(pairs=48)
+@pytest.mark.parametrize("pairs", [48, 1100])
+def test_refine_many_matches_oracle(oracle, pairs):
+    """act_refine against the oracle's L-BFGS; 1,100 pairs (more than two per
+    CU) take the 128-thread blocks, 48 the 256-thread ones.  Sampled pairs of
+    the large batch are checked."""
+    wl = W.refine_pairs(pairs=pairs)
     g = wl.grid
     plan = A().Plan(g, dict_="synth", prec="f64")
     th, J, fl = plan.act_refine(wl.signals, wl.theta0, 30)
     th, J = th.cpu().numpy(), J.cpu().numpy()
-    th_ref, J_ref, _ = oracle.refine_many(g, wl.signals, wl.theta0, 30)
+    pick = np.arange(pairs) if pairs <= 64 else np.r_[0:24, pairs // 2:pairs // 2 + 8, pairs - 24:pairs]
+    th_ref, J_ref, _ = oracle.refine_many(g, wl.signals[pick], wl.theta0[pick], 30)
     step, _, _ = oracle.refine_box(g)
-    np.testing.assert_allclose(J, J_ref, rtol=1e-9)
-    bad = np.abs(th - th_ref) > 1e-6 * np.maximum(np.abs(th_ref), step)
+    if pairs <= 64:
+        tight = np.ones(len(pick), dtype=bool)
+    else:
+        # a pair that has not converged in 30 steps follows a path that the
+        # summation order moves: there only J is compared, to 1e-6 (the rule
+        # of the decomposition checks)
+        _, J_long, _ = oracle.refine_many(g, wl.signals[pick], wl.theta0[pick], 300)
+        tight = np.abs(J_long - J_ref) <= 1e-12 * np.abs(J_ref)
+        assert tight.sum() >= len(pick) // 2, tight.sum()
+        np.testing.assert_allclose(J[pick][~tight], J_ref[~tight], rtol=1e-6)
+    np.testing.assert_allclose(J[pick][tight], J_ref[tight], rtol=1e-9)
+    bad = np.abs(th[pick][tight] - th_ref[tight]) > 1e-6 * np.maximum(np.abs(th_ref[tight]), step)
     assert not bad.any(), np.argwhere(bad)
 
 
