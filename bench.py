@@ -188,8 +188,11 @@ def run_workload(name: str, steps: int, warmup: int):
         # the factored synthesis runs two products per sample; the lag table
         # only its tiles' nonzero lag bands (counted by the library)
         executed = lag_flops if lag else 2 * algo
+        # lag table: HBM bytes per launch from the committed counter summary
+        # (the table's re-reads by row tiles are served by L2 or not)
+        traffic = committed_traffic(name, source_sha(ksrc, "act_emit.h")) if lag else None
         res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                            "kernel": kname, "avg_launch_ms": round(search_ms, 5),
                            "algorithmic_flops_per_launch": algo,
                            "executed_mfma_flops_per_launch": executed,
