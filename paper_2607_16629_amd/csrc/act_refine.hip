@@ -309,6 +309,17 @@ __global__ void k_overflow(PlanDev P, int batch) {
     }
 }
 
+// Samples [k0, k1) within 9 durations of the centre.  Outside them the
+// envelope is below e^-40.5 = 2.6e-18 (times at most 81 in a derivative term),
+// so the refinement's sums over the window differ from the sums over all n
+// samples by less than 1e-15 of their size (the rescore's, by less than FP64
+// rounding).
+__device__ __forceinline__ void support_window(int n, double fs, const double th[4], int& k0, int& k1) {
+    const double half = 9.0 * exp(th[3]) * fs, c = th[0] * fs;
+    k0 = (int)fmin((double)n, fmax(0.0, floor(c - half)));
+    k1 = (int)fmax((double)k0, fmin((double)n, ceil(c + half) + 1.0));
+}
+
 // FP64 rescoring: one wave per candidate whose search score lies inside the
 // certified margin of the channel's final maximum; others are marked NaN.
 __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __restrict__ resid) {
@@ -332,8 +343,12 @@ __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __rest
         grid_theta(cg.g, (long long)P.cand_idx[slot], th);
         const double inv_dt = 1.0 / exp(th[3]);
         double s = 0.0, q = 0.0, sb = 0.0;
+        // the atom's support window: the samples beyond it add below
+        // 2.6e-18 sqrt(n) |r| to the score (|g| >= 1), under FP64 rounding
+        int k0, k1;
+        support_window(cg.g.n, cg.g.fs, th, k0, k1);
         if (P.cplx) {
-            for (int k = lane; k < cg.g.n; k += kWave) {
+            for (int k = k0 + lane; k < k1; k += kWave) {
                 double re, im, e;
                 atom_parts64(sample_time(k, cg.g.fs), th[0], th[1], th[2], inv_dt, re, im, e);
                 s += re * r[k];
@@ -342,7 +357,7 @@ __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __rest
             }
             sb = wave_sum(sb);
         } else {
-            for (int k = lane; k < cg.g.n; k += kWave) {
+            for (int k = k0 + lane; k < k1; k += kWave) {
                 const double v = atom_sample64(sample_time(k, cg.g.fs), th[0], th[1], th[2], inv_dt);
                 s += v * r[k];
                 q += v * v;
@@ -432,16 +447,6 @@ __device__ __forceinline__ void walk_atom(int k0, int k1, double fs, const doubl
             visit(kk, tau, e, co, si);
         }
     }
-}
-
-// Samples [k0, k1) within 9 durations of the centre.  Outside them the
-// envelope is below e^-40.5 = 2.6e-18 (times at most 81 in a derivative term),
-// so the refinement's sums over the window differ from the sums over all n
-// samples by less than 1e-15 of their size.
-__device__ __forceinline__ void support_window(int n, double fs, const double th[4], int& k0, int& k1) {
-    const double half = 9.0 * exp(th[3]) * fs, c = th[0] * fs;
-    k0 = (int)fmin((double)n, fmax(0.0, floor(c - half)));
-    k1 = (int)fmax((double)k0, fmin((double)n, ceil(c + half) + 1.0));
 }
 
 // Sums of the objective: {<r,g>, <g,g>, <r,d_j g> (4), <g,d_j g> (4)}, over every
