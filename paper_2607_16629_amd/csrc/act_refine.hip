@@ -849,14 +849,16 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
 constexpr int NTR = 256;            // threads of the refinement kernels (fastest measured)
 constexpr int NWR = NTR / kWave;
 
-__global__ void __launch_bounds__(NTR) k_select_refine_update(
+template <int TB>
+__global__ void __launch_bounds__(TB) k_select_refine_update(
     PlanDev P, int k, int order, int steps, double* __restrict__ resid, double* __restrict__ approx,
     double* __restrict__ theta, double* __restrict__ coef, long long* __restrict__ index,
     double* __restrict__ energy, double* __restrict__ gap, int* __restrict__ flags) {
-    __shared__ double red[block_sum_lds(NTR, 13)];
+    constexpr int NW = TB / kWave;
+    __shared__ double red[block_sum_lds(TB, 13)];
     __shared__ RefineLds L;
-    __shared__ double s_a1[NWR], s_a2[NWR];
-    __shared__ unsigned s_i1[NWR];
+    __shared__ double s_a1[NW], s_a2[NW];
+    __shared__ unsigned s_i1[NW];
     const int b = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
@@ -895,7 +897,7 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
         const int cnt_raw = P.cand_count[b];
         const int cnt = min(cnt_raw, P.cap);
         if (cnt_raw > P.cap) fl |= ACT_FLAG_CAND_OVERFLOW;
-        for (int j = threadIdx.x; j < cnt; j += NTR) {
+        for (int j = threadIdx.x; j < cnt; j += TB) {
             const double v = P.cand_p64[(size_t)b * P.cap + j];
             if (isnan(v)) continue;
             const double a = fabs(v);
@@ -931,7 +933,7 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
     a1 = s_a1[0];
     a2 = s_a2[0];
     i1 = s_i1[0];
-    for (int q = 1; q < NWR; ++q) {
+    for (int q = 1; q < NW; ++q) {
         const double oa1 = s_a1[q], oa2 = s_a2[q];
         const unsigned oi1 = s_i1[q];
         if (oa1 > a1 || (oa1 == a1 && oi1 < i1)) {
@@ -963,9 +965,9 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
     }
     if (steps > 0) {
         if (P.cplx)
-            fl |= refine_block<NTR, kObjComplex>(r, G, box, th0, steps, th, &J, red, L);
+            fl |= refine_block<TB, kObjComplex>(r, G, box, th0, steps, th, &J, red, L);
         else
-            fl |= refine_block<NTR>(r, G, box, th0, steps, th, &J, red, L);
+            fl |= refine_block<TB>(r, G, box, th0, steps, th, &J, red, L);
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) th[j] = th0[j];
@@ -977,7 +979,7 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
         // phi by least squares, r -= alpha u + beta v (a pair that is singular
         // to working precision falls back to the fit on u alone)
         double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int t = threadIdx.x; t < G.n; t += NTR) {
+        for (int t = threadIdx.x; t < G.n; t += TB) {
             double re, im, e;
             atom_parts64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt, re, im, e);
             acc5[0] += re * re;
@@ -986,7 +988,7 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
             acc5[3] += re * r[t];
             acc5[4] += im * r[t];
         }
-        block_sum<NTR, 5>(acc5, red);
+        block_sum<TB, 5>(acc5, red);
         const double uu = acc5[0], vv = acc5[1], uv = acc5[2], ur = acc5[3], vr = acc5[4];
         const double det = uu * vv - uv * uv;
         double al, be;
@@ -997,7 +999,7 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
             al = (vv * ur - uv * vr) / det;
             be = (uu * vr - uv * ur) / det;
         }
-        for (int t = threadIdx.x; t < G.n; t += NTR) {
+        for (int t = threadIdx.x; t < G.n; t += TB) {
             double re, im, e;
             atom_parts64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt, re, im, e);
             const double w = al * re + be * im;
@@ -1005,7 +1007,7 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
             if (approx) approx[cg.off + t] = approx[cg.off + t] + w;
         }
         __syncthreads();
-        const double E = refresh_channel<NTR>(P, b, r, G.n, red, false);
+        const double E = refresh_channel<TB>(P, b, r, G.n, red, false);
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) theta[o * 4 + j] = th[j];
@@ -1021,27 +1023,27 @@ __global__ void __launch_bounds__(NTR) k_select_refine_update(
 
     // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4))
     double acc[1] = {0.0};
-    for (int t = threadIdx.x; t < G.n; t += NTR) {
+    for (int t = threadIdx.x; t < G.n; t += TB) {
         const double v = atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt);
         acc[0] += v * v;
     }
-    block_sum<NTR, 1>(acc, red);
+    block_sum<TB, 1>(acc, red);
     const double nrm = sqrt(acc[0]);
     const bool ok = nrm >= 1e-300;
     acc[0] = 0.0;
-    for (int t = threadIdx.x; t < G.n; t += NTR) {
+    for (int t = threadIdx.x; t < G.n; t += TB) {
         const double v = ok ? atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
         acc[0] += v * r[t];
     }
-    block_sum<NTR, 1>(acc, red);
+    block_sum<TB, 1>(acc, red);
     const double ck = acc[0];
-    for (int t = threadIdx.x; t < G.n; t += NTR) {
+    for (int t = threadIdx.x; t < G.n; t += TB) {
         const double v = ok ? atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
         r[t] = r[t] - ck * v;
         if (approx) approx[cg.off + t] = approx[cg.off + t] + ck * v;
     }
     __syncthreads();
-    const double E = refresh_channel<NTR>(P, b, r, G.n, red, false);
+    const double E = refresh_channel<TB>(P, b, r, G.n, red, false);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) theta[o * 4 + j] = th[j];
@@ -1265,8 +1267,14 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
                                        hipStream_t s) {
     PlanDev v = view(p);
     v.batch = batch;
-    hipLaunchKernelGGL(k_select_refine_update, dim3(batch), dim3(NTR), 0, s, v, k, order,
-                       p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
+    // more than two channels per CU: 128-thread blocks (several per CU keep its
+    // FP64 units busy); otherwise NTR threads (each channel's latency sets the time)
+    if ((long long)batch > 2LL * device_cus())
+        hipLaunchKernelGGL(k_select_refine_update<128>, dim3(batch), dim3(128), 0, s, v, k, order,
+                           p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
+    else
+        hipLaunchKernelGGL(k_select_refine_update<NTR>, dim3(batch), dim3(NTR), 0, s, v, k, order,
+                           p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

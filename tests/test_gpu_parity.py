@@ -469,6 +469,20 @@ def test_batch_of_70_channels(oracle, prec, dict_):
     assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick], prec, 30) >= 15
 
 
+def test_batch_above_two_channels_per_cu(oracle):
+    """600 channels (more than two per CU on a 256-CU device): the per-order
+    select / refine / update runs 128-thread blocks; sampled channels follow
+    the oracle step by step."""
+    g = W.eeg_grid(512, 16, 8, 4, 4)
+    wl = W.batched_64x2048(channels=600, grid=g, order=3)
+    gpu = gpu_decompose(g, wl.signals, 3, "f32", "synth", refine_steps=30)
+    pick = [0, 1, 255, 256, 511, 512, 599]
+    ref = oracle.decompose(g, wl.signals[pick], 3, refine_steps=30)
+    sub = {k: (v[pick] if v is not None else None) for k, v in gpu.items()}
+    assert assert_decomposition_parity(sub, ref, g, oracle, wl.signals[pick], "600ch", 30) >= 14
+    assert np.all(gpu["flags"] & A().FLAG_CAND_OVERFLOW == 0)
+
+
 @pytest.mark.parametrize("prec,dict_", [("f32", "table"), ("f32", "synth"), ("f16", "lag")])
 def test_fp32_full_size_2m_atoms(oracle, prec, dict_):
     """Single channel at EEG-like scale (N = 2048, 2,097,152 atoms): the
