@@ -130,6 +130,13 @@ __device__ __forceinline__ void atom_parts64(double t, double tc, double fc, dou
     im = env * si;
 }
 
+// BF16 bits of an FP32 value, rounded to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
 // sample time of index k
 __device__ __forceinline__ double sample_time(int k, double fs) { return (double)k / fs; }
 

@@ -32,18 +32,6 @@ static double axis_step(const act_axis& a) {
 }
 #pragma clang fp contract(on)
 
-static inline unsigned short f32_to_bf16_rne(float x) {
-    unsigned u;
-    memcpy(&u, &x, 4);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-
-__device__ __forceinline__ unsigned short d_bf16_rne(float x) {
-    unsigned u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
 __device__ __forceinline__ float d_bf16_to_f32(unsigned short h) {
     return __uint_as_float(((unsigned)h) << 16);
 }
@@ -84,7 +72,7 @@ __global__ void __launch_bounds__(256) k_build_table(GridDev g, TOut* __restrict
                 if (WRITE) row[k] = f;
                 back = (double)f;
             } else {
-                unsigned short h = d_bf16_rne(f);
+                unsigned short h = bf16_rne(f);
                 if (WRITE) row[k] = h;
                 back = (double)d_bf16_to_f32(h);
             }

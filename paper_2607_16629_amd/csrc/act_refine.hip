@@ -75,12 +75,6 @@ static PlanDev view(const act_plan_s* p) {
 constexpr int NT = 256;            // threads of every per-channel kernel
 constexpr int NW = NT / kWave;
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-    unsigned u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-
 // Proven bound on |p~ - p| of one channel's search scores, where rn = |r|
 // and er = |r - shadow(r)| (the rounding of the search copy of r):
 //   p~ = fl( sum g~ r~ ),  g~ = g_hat + e_g (|e_g| <= eg_max),  r~ = r + e_r

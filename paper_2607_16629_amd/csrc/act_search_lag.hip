@@ -562,12 +562,6 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
     }
 }
 
-// BF16 of an FP32 value, round to nearest even (finite inputs)
-__device__ __forceinline__ unsigned short lag_bf16_rne(float x) {
-    const unsigned u = __float_as_uint(x);
-    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-
 // The lag table: G_q(d) in FP64, rounded to FP32 and then FP16 or BF16 (RNE;
 // BF16 entries below 2^-25 are zero), written
 // in MFMA B-operand order; columns past Q are zero.  Columns run log-duration
@@ -608,7 +602,7 @@ __global__ void k_build_lag_table(GridDev g, int Q_pad, int cplx, int bf16, f16x
                 // their nonzero bands
                 out[j] = bf16 ? __builtin_bit_cast(_Float16, fabs(v) < 2.98023223876953125e-08
                                                                   ? (unsigned short)0
-                                                                  : lag_bf16_rne((float)v))
+                                                                  : bf16_rne((float)v))
                               : (_Float16)(float)v;
             }
         }
