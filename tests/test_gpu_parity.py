@@ -327,6 +327,55 @@ def test_ragged_batch_matches_per_signal_oracle(oracle, prec, dict_, cut):
     np.testing.assert_allclose(rec[ok], res["approx"][ok], rtol=0, atol=1e-12 * np.abs(wl.signals).max())
 
 
+@pytest.mark.parametrize("dict_,cut", [("lag", False), ("synth", True)])
+def test_full_size_ragged_1000(oracle, dict_, cut):
+    """The uneven batch at full size (1000 signals of 256..16384 samples, each
+    with floor(N/32) x 64 x 32 x 16 atoms), FP16 lag table or support-cut FP16
+    synthesis, in the configuration the benchmark times: for sampled signals
+    and per order, the winner's oracle score on the GPU's own residual is not
+    beaten by 1500 sampled atoms of that signal's grid, the refined parameters
+    equal the oracle's refinement from the same grid point, and the energy
+    follows from the coefficients; no list overflows."""
+    wl = W.ragged_batch()
+    lens = wl.lengths
+    order = 3
+    plan = A().Plan(W.ragged_grid(int(lens.max()), 32, 64, 32, 16), dict_=dict_, prec="f16",
+                    max_batch=len(lens), refine_steps=wl.refine_steps, ragged=True, ragged_tc_div=32,
+                    support_cut=cut)
+    gpu = plan.decompose_ragged(wl.signals, lens, wl.offsets, order)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in gpu.items() if v is not None}
+    assert np.all(res["flags"] & (A().FLAG_CAND_OVERFLOW | A().FLAG_NONFINITE | A().FLAG_BAD_LENGTH) == 0)
+    srt = np.argsort(lens, kind="stable")
+    rng = np.random.default_rng(17)
+    for b in (int(srt[0]), int(srt[len(srt) // 2]), int(srt[-2]), int(srt[-1])):
+        n, o = int(lens[b]), int(wl.offsets[b])
+        g = wl.grids[b]
+        step, _, _ = oracle.refine_box(g)
+        sample = rng.choice(g.size, 1500, replace=False)
+        r = wl.signals[o:o + n].copy()
+        for k in range(order):
+            rn = float(np.linalg.norm(r))
+            i = int(res["index"][b, k])
+            p_win = oracle.correlate(g, r, i, 1)[0]
+            p_s = np.array([oracle.correlate(g, r, int(j), 1)[0] for j in sample])
+            assert np.all(np.abs(p_s) <= abs(p_win) + 1e-12 * rn), (b, k)
+            th, J, _ = oracle.refine(g, r, oracle.grid_theta(g, i), wl.refine_steps)
+            dth = np.abs(res["theta"][b, k] - th)
+            if not np.all(dth <= 1e-6 * np.maximum(np.abs(th), step)):
+                # an optimum the 30 steps leave loose: the objective must agree
+                # (the rule of the decomposition checks)
+                J_g = oracle.objective(g.fs, res["theta"][b, k], r)[0]
+                assert abs(J_g - J) <= 1e-6 * max(J, 1e-9 * float(wl.signals[o:o + n] @ wl.signals[o:o + n])), \
+                    (b, n, k, dth, J_g, J)
+            gu, _ = oracle.atom_unit(g.fs, g.n, res["theta"][b, k])
+            r = r - res["coef"][b, k] * gu
+            assert abs(res["energy"][b, k + 1] - float(r @ r)) <= 1e-6 * float(r @ r), (b, k)
+        np.testing.assert_allclose(res["resid"][o:o + n], r, rtol=0, atol=1e-9 * float(np.linalg.norm(wl.signals[o:o + n])))
+    E = res["energy"]
+    np.testing.assert_allclose(E[:, 1:], E[:, :-1] - res["coef"] ** 2, rtol=0, atol=1e-10 * E[:, :1].max())
+
+
 @pytest.mark.parametrize("count", [1, 34])
 def test_ragged_lag_channel_groups_match_per_signal_oracle(oracle, count):
     """The ragged lag table with one signal (a 1-channel tile of 128 time
@@ -1083,6 +1132,23 @@ def test_degenerate_dictionaries(oracle, case, prec, dict_):
         # zero-norm atoms are never selected while any atom has a nonzero score
         p = oracle.correlate(g, sig[0])
         assert np.all(p[gpu["index"][0, :1]] != 0.0)
+
+
+@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_degenerate_dictionaries_lag(oracle, case, prec):
+    """The lag table on one atom and on one-sample signals; time centres past
+    the signal's end (the third case) are rejected by the plan."""
+    name, g, sig = _degenerate_cases()[case]
+    order = 3
+    ref = oracle.decompose(g, sig, order, refine_steps=30)
+    gpu = gpu_decompose(g, sig, order, prec, "lag", refine_steps=30)
+    assert np.all(np.isfinite(gpu["energy"])) and np.all(np.isfinite(gpu["coef"]))
+    assert np.all(np.diff(gpu["energy"], axis=1) <= 1e-12 * gpu["energy"][:, :1])
+    assert assert_decomposition_parity(gpu, ref, g, oracle, sig, f"{name}-lag-{prec}", 30) == 2 * order
+    with pytest.raises(A().ActError) as e:
+        A().Plan(_degenerate_cases()[2][1], dict_="lag", prec=prec)
+    assert e.value.status == A().ACT_ERR_UNSUPPORTED
 
 
 def test_lag_table_partial_tiles_and_edge_channels(oracle):
