@@ -840,7 +840,8 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
 // --------------------------------------------------------------------------
 // select -> refine -> coefficient -> update, one block per channel
 // --------------------------------------------------------------------------
-constexpr int NTR = 256;            // threads of the refinement kernels (fastest measured)
+constexpr int NTR = 256;            // threads of the refinement kernels at up to two blocks per CU
+                                    // (fastest measured; larger batches use 128)
 constexpr int NWR = NTR / kWave;
 
 template <int TB>
@@ -848,11 +849,11 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
     PlanDev P, int k, int order, int steps, double* __restrict__ resid, double* __restrict__ approx,
     double* __restrict__ theta, double* __restrict__ coef, long long* __restrict__ index,
     double* __restrict__ energy, double* __restrict__ gap, int* __restrict__ flags) {
-    constexpr int NW = TB / kWave;
+    constexpr int NWB = TB / kWave;
     __shared__ double red[block_sum_lds(TB, 13)];
     __shared__ RefineLds L;
-    __shared__ double s_a1[NW], s_a2[NW];
-    __shared__ unsigned s_i1[NW];
+    __shared__ double s_a1[NWB], s_a2[NWB];
+    __shared__ unsigned s_i1[NWB];
     const int b = blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
@@ -927,7 +928,7 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
     a1 = s_a1[0];
     a2 = s_a2[0];
     i1 = s_i1[0];
-    for (int q = 1; q < NW; ++q) {
+    for (int q = 1; q < NWB; ++q) {
         const double oa1 = s_a1[q], oa2 = s_a2[q];
         const unsigned oi1 = s_i1[q];
         if (oa1 > a1 || (oa1 == a1 && oi1 < i1)) {
