@@ -55,9 +55,9 @@ typedef struct {
     int32_t count, half_open;
 } act_axis;
 
-/* Sampling rate, signal length and the four parameter axes of a dictionary
- * (Sec. III-A "sampling the parameter space within user-specified ranges";
- * Table "Parameter ranges"). */
+/* Sampling rate, signal length and the four parameter axes of a dictionary:
+ * the grid of atom parameters the caller's ranges span (Sec. III-A; Table
+ * "Parameter ranges"). */
 typedef struct {
     double fs_hz;
     int32_t n_samples;
@@ -146,14 +146,16 @@ typedef struct {
 typedef struct act_plan_s* act_plan_t;
 
 /* Builds a plan: validates the grid, uploads the axis values, and for
- * ACT_DICT_TABLE synthesises every atom in FP64 on the device, normalises it
- * to unit l2 norm over the n_samples present (Sec. III-A "normalized to unit
- * l2 norm prior to search") and stores it as FP32 or BF16 rows; for
+ * ACT_DICT_TABLE synthesises every atom in FP64 on the device, scales it to
+ * unit l2 norm over the n_samples present before any search (Sec. III-A) and
+ * stores it as FP32 or BF16 rows; for
  * ACT_DICT_SYNTH it builds the small factor tables the search kernels combine.
  * Synchronises `stream` before returning.  On success *out owns all plan
  * memory until act_plan_destroy.  Errors: ACT_ERR_INVALID (counts < 1, n < 1,
  * fs <= 0, non-finite or reversed bounds, unknown dict/prec, F64 with a
- * table, a table larger than the device), ACT_ERR_NOMEM, ACT_ERR_HIP. */
+ * table), ACT_ERR_NOMEM (a table, lag table or lag-energy table larger than
+ * the free device memory: refused before it is allocated; or a failed
+ * allocation), ACT_ERR_HIP. */
 act_status act_plan(const act_plan_desc* desc, void* stream, act_plan_t* out);
 
 /* Frees everything the plan owns (after synchronising its last stream).

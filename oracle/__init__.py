@@ -15,13 +15,19 @@ Two independent implementations live here:
 
 Parity status per function (the pins are in tests/test_oracle_pins.py):
   atoms / norms        pinned: closed-form Gaussian integral, scipy chirp, FFT
-  correlate / argmax   pinned: FFT special case, numpy brute force
+  correlate / argmax   pinned: FFT special case, numpy brute force; the
+                       top-2 gap against a full numpy sort of |p|
+  correlate_many       equal bit for bit to correlate row by row
   objective / gradient pinned: central finite differences, scipy L-BFGS-B optimum
-  refine               pinned: off-grid recovery, scipy optimum, monotone J
+  refine               pinned: off-grid recovery, scipy optimum, monotone J;
+                       its coordinate scales against the Gaussian-moment
+                       closed forms of the unit atom's metric (real and complex)
   decompose            pinned: MP identities, one-iteration recovery, brute force
   reconstruct          pinned: a_P + r_P = s
   LEM search           pinned: exhaustive search when the families cover the
-                       grid (numpy brute force), MP identities
+                       grid (numpy brute force), an independent numpy
+                       implementation of every stage with non-covering
+                       families, MP identities
   complex atoms        pinned: FFT magnitude special case, central differences,
                        one-order recovery at any phase, projection identities
   prior ACT (contrast) pinned: continuous-time norm of Eq. (1)'s prefactor,
@@ -97,6 +103,8 @@ def _load():
         lib.oracle_atom_unit.argtypes = [d, i32, pd, pd]
         lib.oracle_atom_unit.restype = d
         lib.oracle_correlate.argtypes = [pg, pd, i64, i64, pd]
+        lib.oracle_correlate_many.argtypes = [pg, i32, pd, i64, i64, pd]
+        lib.oracle_correlate_complex_many.argtypes = [pg, i32, pd, i64, i64, pd]
         lib.oracle_norms.argtypes = [pg, i64, i64, pd]
         lib.oracle_argmax.argtypes = [pd, i64, pd]
         lib.oracle_argmax.restype = i64
@@ -196,6 +204,35 @@ def correlate(grid, r, begin: int = 0, count: Optional[int] = None) -> np.ndarra
     out = np.zeros(count)
     _load().oracle_correlate(ctypes.byref(g), _p(r), int(begin), int(count), _p(out))
     return out
+
+
+def correlate_many(grid, R, begin: int = 0, count: Optional[int] = None,
+                   complex_atoms: bool = False) -> np.ndarray:
+    """Scores of the atoms [begin, begin+count) against every row of R
+    ([m, N]); row t equals correlate(grid, R[t]) (or correlate_complex) bit
+    for bit.  Each atom is synthesised once for all rows."""
+    g = make_grid(grid)
+    if count is None:
+        count = grid_size(grid) - begin
+    R = _f64(np.atleast_2d(R))
+    assert R.shape[1] == grid.n
+    out = np.zeros((R.shape[0], count))
+    fn = _load().oracle_correlate_complex_many if complex_atoms else _load().oracle_correlate_many
+    fn(ctypes.byref(g), R.shape[0], _p(R), int(begin), int(count), _p(out))
+    return out
+
+
+def argmax_many(grid, R, complex_atoms: bool = False):
+    """Exhaustive arg-max (Sec. III-A) of every row of R over the whole
+    dictionary: (indices, relative top-2 gaps, |p| of the winners)."""
+    P = correlate_many(grid, R, complex_atoms=complex_atoms)
+    idx, gap, top = [], [], []
+    for row in P:
+        i, gp = argmax(row)
+        idx.append(i)
+        gap.append(gp)
+        top.append(abs(row[i]))
+    return np.array(idx, dtype=np.int64), np.array(gap), np.array(top)
 
 
 def norms(grid, begin: int = 0, count: Optional[int] = None) -> np.ndarray:

@@ -146,6 +146,27 @@ void oracle_correlate(const oracle_grid* grid, const double* r, int64_t begin, i
     }
 }
 
+/* The same scores for m residuals at once: p[t][j] = <g_{begin+j}/|g|, r_t>,
+ * r_t = r + t*n, p_t = p + t*count.  Each atom is synthesised once and dotted
+ * with every residual; every dot is the same plain left-to-right sum as in
+ * oracle_correlate, so row t equals oracle_correlate on r_t bit for bit. */
+void oracle_correlate_many(const oracle_grid* grid, int32_t m, const double* r, int64_t begin, int64_t count,
+                           double* p) {
+    int32_t n = grid->n;
+#pragma omp parallel
+    {
+        double* g = (double*)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < count; ++j) {
+            double th[4];
+            oracle_grid_theta(grid, begin + j, th);
+            oracle_atom_unit(grid->fs, n, th, g);
+            for (int32_t t = 0; t < m; ++t) p[(size_t)t * (size_t)count + (size_t)j] = dot(g, r + (size_t)t * n, n);
+        }
+        free(g);
+    }
+}
+
 /* Unit-atom norms of the dictionary (raw |g_i|), for plan checks. */
 void oracle_norms(const oracle_grid* grid, int64_t begin, int64_t count, double* out) {
     int32_t n = grid->n;
@@ -840,6 +861,48 @@ void oracle_correlate_complex(const oracle_grid* grid, const double* r, int64_t 
             q += e * e;
         }
         p[j] = q > 0.0 ? sqrt((a * a + b * b) / q) : 0.0;
+    }
+}
+
+/* |<g_hat, r_t>| for m residuals at once (layout as oracle_correlate_many);
+ * the sums run in the order of oracle_correlate_complex, so row t equals it
+ * bit for bit. */
+void oracle_correlate_complex_many(const oracle_grid* grid, int32_t m, const double* r, int64_t begin,
+                                   int64_t count, double* p) {
+    int32_t n = grid->n;
+#pragma omp parallel
+    {
+        double* env = (double*)malloc(sizeof(double) * (size_t)n);
+        double* co = (double*)malloc(sizeof(double) * (size_t)n);
+        double* si = (double*)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < count; ++j) {
+            double th[4];
+            oracle_grid_theta(grid, begin + j, th);
+            double dt = exp(th[3]), q = 0.0;
+            for (int32_t k = 0; k < n; ++k) {
+                double tau = (double)k / grid->fs - th[0];
+                double u = tau / dt;
+                double e = exp(-0.5 * u * u);
+                double ph = TWO_PI * (th[2] * tau * tau + th[1] * tau);
+                env[k] = e;
+                co[k] = cos(ph);
+                si[k] = sin(ph);
+                q += e * e;
+            }
+            for (int32_t t = 0; t < m; ++t) {
+                const double* rt = r + (size_t)t * n;
+                double a = 0.0, b = 0.0;
+                for (int32_t k = 0; k < n; ++k) {
+                    a += rt[k] * env[k] * co[k];
+                    b += rt[k] * env[k] * si[k];
+                }
+                p[(size_t)t * (size_t)count + (size_t)j] = q > 0.0 ? sqrt((a * a + b * b) / q) : 0.0;
+            }
+        }
+        free(si);
+        free(co);
+        free(env);
     }
 }
 

@@ -201,6 +201,33 @@ def test_tie_break_lowest_index(oracle):
     assert np.all(out["gap"][0] == 0.0)
 
 
+def _sorted_gap(p):
+    """The top-1/top-2 relative gap from a full sort of |p| (numpy)."""
+    a = np.sort(np.abs(np.asarray(p, dtype=np.float64)))
+    return (a[-1] - a[-2]) / a[-1] if a[-1] > 0 else 0.0
+
+
+def test_argmax_gap_matches_a_full_sort(oracle):
+    """The arg-max's index and its relative top-2 gap (|p|_(1) - |p|_(2)) /
+    |p|_(1) against numpy: the first maximum of |p| and a full sort of |p|.
+    Increasing, decreasing and random orders, negative winners, a runner-up
+    that equals the winner, and the scores of a tiny grid."""
+    rng = np.random.default_rng(29)
+    cases = [np.arange(1.0, 9.0),                       # each new maximum demotes the old one
+             np.arange(8.0, 0.0, -1.0),                 # the runner-up arrives after the winner
+             np.array([0.5, -3.0, 2.0, 2.9, -0.1]),     # negative winner, close runner-up
+             np.array([1.0, -4.0, 0.3, 4.0, 2.0]),      # |p| tie: gap 0, lowest index
+             np.array([2.0, 1.0]), np.array([-1.0, 3.0])]
+    cases += [rng.standard_normal(int(m)) for m in rng.integers(2, 5000, size=20)]
+    g = _tiny_grid()
+    cases += [oracle.correlate(g, rng.standard_normal(g.n)) for _ in range(5)]
+    for p in cases:
+        i, gap = oracle.argmax(p)
+        assert i == int(np.argmax(np.abs(p))), p
+        assert abs(gap - _sorted_gap(p)) <= 1e-15, (gap, _sorted_gap(p))
+    assert oracle.argmax(np.zeros(7)) == (0, 0.0)
+
+
 def test_one_iteration_recovery(oracle):
     """An on-grid unit chirplet times alpha is recovered exactly in one
     order: the winner is that atom (Cauchy-Schwarz), c_0 = alpha, r_1 = 0, and
@@ -496,6 +523,38 @@ def test_lem_with_covering_families_is_exhaustive_mp(oracle):
         np.testing.assert_allclose(out["energy"][0], energy, rtol=1e-11, atol=1e-13)
 
 
+def test_lem_stages_match_independent_numpy(oracle):
+    """The hierarchical search's stages (Latin-hypercube map and snap to the
+    level-0 steps, top-k distinct by |<g_hat, r>|, local families at finer
+    steps with members outside the hull dropped, pooled re-rank) against an
+    independent numpy implementation, on a tiny grid whose families do not
+    cover it: level steps of one, a half and a quarter of the grid spacing
+    put the candidates off the grid, so a slip in snapping, the family
+    offsets, the hull test or the ranking changes the selected atoms."""
+    from oracle import brute
+    g = _tiny_grid()
+    step, lo, hi = oracle.refine_box(g)
+    sp = np.array([a.spacing() for a in g.axes])
+    for levels, radius, topk, samples in [(2, (1, 2, 1, 1), 3, 12), (1, (2, 0, 1, 0), 2, 7), (0, (0, 0, 0, 0), 1, 5)]:
+        steps = tuple(tuple(sp * f) for f in (1.0, 0.5, 0.25)[:levels + 1])
+        cfg = W.LemConfig(samples, levels, topk, radius, steps)
+        rng = np.random.default_rng(43 + levels)
+        for trial in range(3):
+            s = rng.standard_normal(g.n)
+            lhs = W.lem_lhs(200 + 10 * levels + trial, 1, 5, samples)
+            out = oracle.lem_decompose(g, s, lhs, cfg, 5, refine_steps=0)
+            th, coef, energy, r = brute.lem_mp(g.fs, g.n, lo, hi, steps, radius, topk, lhs[0], s)
+            np.testing.assert_allclose(out["theta"][0], th, rtol=0, atol=1e-12)
+            np.testing.assert_allclose(out["coef"][0], coef, rtol=0, atol=1e-12 * np.linalg.norm(s))
+            np.testing.assert_allclose(out["energy"][0], energy, rtol=1e-11, atol=1e-13)
+            np.testing.assert_allclose(out["resid"][0], r, rtol=0, atol=1e-12 * np.linalg.norm(s))
+            if levels == 2:
+                # off-grid candidates were reached: some atom is not a grid point
+                on = [np.any(np.all(np.isclose(t, np.array([g.theta(i) for i in range(g.size)]), atol=1e-12), axis=1))
+                      for t in th]
+                assert not all(on)
+
+
 def test_lem_mp_identities(oracle):
     """E_{k+1} = E_k - c_k^2 with unit atoms, monotone energy, a_P + r_P = s,
     on the paper's LEM settings."""
@@ -597,6 +656,36 @@ def test_complex_projection_identities(oracle):
         np.testing.assert_allclose(float(r @ r) - float(r_new @ r_new), float(w @ w), rtol=1e-8, atol=1e-12)
         r = r_new
     np.testing.assert_allclose(out["approx"][0] + out["resid"][0], s, atol=1e-12 * np.abs(s).max())
+
+
+def test_refine_scales_real_atom_gaussian_closed_forms(oracle):
+    """Refinement scales of the real atom (the metric of the unit real atom,
+    G_jj = (|d_j g|^2 - <g, d_j g>^2 / q) / q, q = |g|^2) for interior,
+    densely sampled atoms whose carrier is fast against the envelope
+    (image terms of size exp(-(2 pi f_c dt)^2) vanish).  With E^2 a Gaussian of
+    variance dt^2/2 the sums are Gaussian moments:
+      G_tc = 1/(2 dt^2) + 4 pi^2 (f_c^2 + 2 c^2 dt^2)   (envelope slope and the
+             instantaneous frequency f_c + 2 c tau, whose mean is f_c),
+      G_fc = 2 pi^2 dt^2,  G_c = 3 pi^2 dt^4,  G_logdt = 1/2,
+    where <g, d_j g> vanishes for every axis but log dt (it is q/2 there).
+    Large grid steps make the scales 1/sqrt(G)."""
+    fs, n = 4096.0, 16384
+    big = W.Axis(-1e6, 1e6, 3, False)
+    g = W.Grid(fs, n, W.Axis(0.0, 4.0, 3, False), big, big, W.Axis(-30.0, 30.0, 3, False))
+    for dt, fc, c in [(0.05, 40.0, 0.0), (0.1, 37.0, 3.0), (0.2, 12.5, -4.0), (0.3, 9.0, 1.5)]:
+        assert 2 * math.pi * fc * dt > 3.0
+        th = np.array([2.0, fc, c, math.log(dt)])
+        h = oracle.refine_scales(g, th)
+        G = [1.0 / (2 * dt * dt) + 4 * math.pi ** 2 * (fc * fc + 2 * c * c * dt * dt),
+             2 * math.pi ** 2 * dt * dt, 3 * math.pi ** 2 * dt ** 4, 0.5]
+        np.testing.assert_allclose(h, [1.0 / math.sqrt(x) for x in G], rtol=1e-9)
+    # a grid step below the resolution caps the scale; a one-value axis freezes
+    g2 = W.Grid(fs, n, W.Axis(0.0, 4.0, 3, False), W.Axis(0.0, 80.0, 3, False), W.Axis(0.0, 0.0, 1, False),
+                W.Axis(-30.0, 30.0, 3, False))
+    h2 = oracle.refine_scales(g2, np.array([2.0, 40.0, 0.0, math.log(0.05)]))
+    assert h2[2] == 0.0 and h2[1] == pytest.approx(1.0 / (math.sqrt(2.0) * math.pi * 0.05), rel=1e-9)
+    g3 = W.Grid(fs, n, W.Axis(0.0, 4.0, 3, False), W.Axis(0.0, 0.4, 3, False), big, W.Axis(-30.0, 30.0, 3, False))
+    assert oracle.refine_scales(g3, np.array([2.0, 0.2, 0.0, math.log(0.4)]))[1] == pytest.approx(0.2, rel=1e-15)
 
 
 def test_complex_refine_scales_gaussian_closed_forms(oracle):
