@@ -243,6 +243,28 @@ act_status act_lem_decompose(act_plan_t plan, const act_lem_desc* cfg, int32_t b
                              int32_t order, double* theta_dev, double* coef_dev, double* energy_dev,
                              int32_t* flags_dev, void* stream);
 
+/* Bytes of the device array that act_lem_decompose_noalloc uses as its
+ * workspace (one array per device, held until the process ends). */
+#define ACT_LEM_SCRATCH_BYTES (16u << 20)
+
+/* act_lem_decompose for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same settings, arguments, kernels and results, but the per-channel
+ * candidate workspace (batch x cap x 41 bytes, cap = max(samples,
+ * topk * prod(2 radius_d + 1))) lives in a fixed device array of
+ * ACT_LEM_SCRATCH_BYTES per device instead of plan memory allocated on first
+ * use.  The call allocates nothing (no hipMalloc, no events, no graphs); the
+ * caller still owns every argument buffer.  Every call on one device shares
+ * that array, so calls that overlap in time on one device (two streams, two
+ * threads) race and must be serialised by the caller; the array keeps the
+ * last call's contents, none of which a later call reads.  Phase timing does
+ * not apply.  Errors: as act_lem_decompose, plus ACT_ERR_INVALID when
+ * batch x cap x 41 exceeds ACT_LEM_SCRATCH_BYTES. */
+act_status act_lem_decompose_noalloc(act_plan_t plan, const act_lem_desc* cfg, int32_t batch,
+                                     const double* lhs_dev, double* resid_dev, double* approx_dev,
+                                     int32_t order, double* theta_dev, double* coef_dev, double* energy_dev,
+                                     int32_t* flags_dev, void* stream);
+
 /* Continuous refinement alone (Sec. III-A "BFGS refinement"), for m
  * independent problems: from theta0 maximise J(theta) = <r, g(theta)>^2 /
  * <g(theta), g(theta)> with the plan's L-BFGS (box = the plan grid's hull,

@@ -22,6 +22,7 @@ ACT_DICT_SYNTH, ACT_DICT_TABLE, ACT_DICT_LAG = 0, 1, 2
 ACT_PREC_F64, ACT_PREC_F32, ACT_PREC_BF16, ACT_PREC_F16 = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_REFINE_REJECTED, FLAG_CAND_OVERFLOW, FLAG_RAGGED_EMPTY, FLAG_BAD_LENGTH = 1, 2, 8, 16, 32
 Q_ATOMS, Q_TABLE_BYTES, Q_N_PAD, Q_CAND_CAP, Q_WORKSPACE_BYTES = range(5)
+LEM_SCRATCH_BYTES = 16 << 20  # ACT_LEM_SCRATCH_BYTES: act_lem_decompose_noalloc's device array
 
 _DICTS = {"synth": ACT_DICT_SYNTH, "table": ACT_DICT_TABLE, "lag": ACT_DICT_LAG}
 _PRECS = {"f64": ACT_PREC_F64, "f32": ACT_PREC_F32, "bf16": ACT_PREC_BF16, "f16": ACT_PREC_F16}
@@ -53,6 +54,7 @@ class _PlanDesc(ctypes.Structure):
 
 
 EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_search_flops", "act_decompose", "act_lem_decompose",
+           "act_lem_decompose_noalloc",
            "act_refine", "act_value_and_grad", "act_reconstruct", "act_correlate", "act_tune",
            "act_timing_enable", "act_timing_read", "act_status_string", "act_last_error")
 PHASES = ("search", "rerun", "rescore", "select_refine_update")
@@ -95,6 +97,8 @@ def load() -> ctypes.CDLL:
     lib.act_plan.argtypes = [ctypes.POINTER(_PlanDesc), vp, ctypes.POINTER(vp)]
     lib.act_lem_decompose.argtypes = [vp, ctypes.POINTER(_LemDesc), i32, vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.act_lem_decompose.restype = ctypes.c_int
+    lib.act_lem_decompose_noalloc.argtypes = [vp, ctypes.POINTER(_LemDesc), i32, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.act_lem_decompose_noalloc.restype = ctypes.c_int
     lib.act_plan.restype = ctypes.c_int
     lib.act_plan_destroy.argtypes = [vp]
     lib.act_plan_destroy.restype = None
@@ -291,6 +295,19 @@ class Plan:
         assert tuple(lhs.shape) == (B, order, cfg.samples, 4)
         desc = make_lem_desc(cfg)
         _check(load().act_lem_decompose(
+            self._h, ctypes.byref(desc), B, _ptr(lhs), _ptr(resid), _ptr(out["approx"]), int(order),
+            _ptr(out["theta"]), _ptr(out["coef"]), _ptr(out["energy"]), _ptr(out["flags"]), _stream()))
+        return out
+
+    def act_lem_decompose_noalloc(self, resid: torch.Tensor, lhs: torch.Tensor, cfg, order: int, out: dict):
+        """act_lem_decompose with its workspace in the library's fixed device
+        array (no device allocation inside the call)."""
+        assert resid.is_cuda and resid.dtype == torch.float64 and resid.is_contiguous()
+        assert lhs.is_cuda and lhs.dtype == torch.float64 and lhs.is_contiguous()
+        B = resid.shape[0]
+        assert tuple(lhs.shape) == (B, order, cfg.samples, 4)
+        desc = make_lem_desc(cfg)
+        _check(load().act_lem_decompose_noalloc(
             self._h, ctypes.byref(desc), B, _ptr(lhs), _ptr(resid), _ptr(out["approx"]), int(order),
             _ptr(out["theta"]), _ptr(out["coef"]), _ptr(out["energy"]), _ptr(out["flags"]), _stream()))
         return out

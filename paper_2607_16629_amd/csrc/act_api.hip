@@ -2,6 +2,7 @@
 // stream-ordered launch sequence of the matching pursuit.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "act_common.h"
@@ -185,32 +186,43 @@ extern "C" act_status act_decompose(act_plan_t p, int32_t batch, const int32_t* 
     return ACT_OK;
 }
 
-extern "C" act_status act_lem_decompose(act_plan_t p, const act_lem_desc* cfg, int32_t batch,
-                                        const double* lhs_dev, double* resid_dev, double* approx_dev,
-                                        int32_t order, double* theta_dev, double* coef_dev, double* energy_dev,
-                                        int32_t* flags_dev, void* stream) {
-    ACT_REQUIRE(p != nullptr && cfg != nullptr, "act_lem_decompose: plan or settings NULL");
+// Host checks shared by both LEM entry points; *cap = candidates per stage.
+static act_status check_lem(act_plan_t p, const act_lem_desc* cfg, int32_t batch, const double* lhs_dev,
+                            double* resid_dev, int32_t order, double* theta_dev, double* coef_dev,
+                            double* energy_dev, int32_t* flags_dev, const char* who, long long* cap) {
+    const std::string w(who);
+    ACT_REQUIRE(p != nullptr && cfg != nullptr, w + ": plan or settings NULL");
     if (!(p->desc.dict == ACT_DICT_SYNTH && p->desc.prec == ACT_PREC_F64 && !p->desc.ragged && !p->desc.prior_act &&
           !p->desc.complex_atoms)) {
-        set_error("act_lem_decompose: needs a plain ACT_DICT_SYNTH + ACT_PREC_F64 plan of real atoms");
+        set_error(w + ": needs a plain ACT_DICT_SYNTH + ACT_PREC_F64 plan of real atoms");
         return ACT_ERR_UNSUPPORTED;
     }
-    ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, "act_lem_decompose: batch outside [1, max_batch]");
-    ACT_REQUIRE(order >= 1, "act_lem_decompose: order must be >= 1");
+    ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, w + ": batch outside [1, max_batch]");
+    ACT_REQUIRE(order >= 1, w + ": order must be >= 1");
     ACT_REQUIRE(cfg->samples >= 1 && cfg->levels >= 0 && cfg->levels <= 7 && cfg->topk >= 1 && cfg->topk <= 16,
-                "act_lem_decompose: samples >= 1, levels in [0, 7], topk in [1, 16]");
+                w + ": samples >= 1, levels in [0, 7], topk in [1, 16]");
     long long fam = 1;
     for (int d = 0; d < 4; ++d) {
-        ACT_REQUIRE(cfg->radius[d] >= 0 && cfg->radius[d] <= 64, "act_lem_decompose: radius outside [0, 64]");
+        ACT_REQUIRE(cfg->radius[d] >= 0 && cfg->radius[d] <= 64, w + ": radius outside [0, 64]");
         fam *= 2 * cfg->radius[d] + 1;
     }
     for (int l = 0; l <= cfg->levels; ++l)
         for (int d = 0; d < 4; ++d)
-            ACT_REQUIRE(std::isfinite(cfg->step[l][d]) && cfg->step[l][d] > 0.0, "act_lem_decompose: steps must be > 0");
-    const long long cap = std::max<long long>(cfg->samples, cfg->topk * fam);
-    ACT_REQUIRE(cap <= 8192, "act_lem_decompose: more than 8192 candidates per stage");
-    ACT_REQUIRE(lhs_dev && resid_dev && theta_dev && coef_dev && energy_dev && flags_dev,
-                "act_lem_decompose: NULL pointer");
+            ACT_REQUIRE(std::isfinite(cfg->step[l][d]) && cfg->step[l][d] > 0.0, w + ": steps must be > 0");
+    *cap = std::max<long long>(cfg->samples, cfg->topk * fam);
+    ACT_REQUIRE(*cap <= 8192, w + ": more than 8192 candidates per stage");
+    ACT_REQUIRE(lhs_dev && resid_dev && theta_dev && coef_dev && energy_dev && flags_dev, w + ": NULL pointer");
+    return ACT_OK;
+}
+
+extern "C" act_status act_lem_decompose(act_plan_t p, const act_lem_desc* cfg, int32_t batch,
+                                        const double* lhs_dev, double* resid_dev, double* approx_dev,
+                                        int32_t order, double* theta_dev, double* coef_dev, double* energy_dev,
+                                        int32_t* flags_dev, void* stream) {
+    long long cap = 0;
+    act_status st = check_lem(p, cfg, batch, lhs_dev, resid_dev, order, theta_dev, coef_dev, energy_dev, flags_dev,
+                              "act_lem_decompose", &cap);
+    if (st != ACT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     p->last_stream = s;
     if (p->lem_cap < cap) {  // workspace: candidates, scores and marks per channel
@@ -224,13 +236,76 @@ extern "C" act_status act_lem_decompose(act_plan_t p, const act_lem_desc* cfg, i
         ACT_HIP(hipMalloc((void**)&p->lem_score, (size_t)p->max_batch * cap * (sizeof(double) + 1)));
         p->lem_cap = (int)cap;
     }
-    act_status st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, s);
+    char* used = (char*)(p->lem_score + (size_t)p->max_batch * p->lem_cap);
+    st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, s);
     if (st != ACT_OK) return st;
     for (int k = 0; k < order; ++k) {
         st = timed(p, 3, s, [&] {
-            return launch_lem_order(p, cfg, p->lem_cap, batch, k, order, lhs_dev, resid_dev, approx_dev, theta_dev,
-                                    coef_dev, energy_dev, flags_dev, s);
+            return launch_lem_order(p, cfg, p->lem_cap, p->lem_cand, p->lem_score, used, batch, k, order, lhs_dev,
+                                    resid_dev, approx_dev, theta_dev, coef_dev, energy_dev, flags_dev, s);
         });
+        if (st != ACT_OK) return st;
+    }
+    return ACT_OK;
+}
+
+// Workspace of act_lem_decompose_noalloc: one array per device, held until
+// the process ends.  Host code never passes `scratch` itself (on the host it
+// names a stand-in, not device memory); it takes the device address from
+// hipGetSymbolAddress, once per device with that device current.
+static __device__ __align__(256) char scratch[ACT_LEM_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static act_status scratch_for_current_device(char** out) {
+    int dev = -1;
+    ACT_HIP(hipGetDevice(&dev));
+    ACT_REQUIRE(dev >= 0 && dev < kMaxDevices, "act_lem_decompose_noalloc: device index outside [0, 64)");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        ACT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        ACT_REQUIRE(ptr != nullptr, "act_lem_decompose_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (char*)g_scratch_ptr[dev];
+    return ACT_OK;
+}
+
+extern "C" act_status act_lem_decompose_noalloc(act_plan_t p, const act_lem_desc* cfg, int32_t batch,
+                                                const double* lhs_dev, double* resid_dev, double* approx_dev,
+                                                int32_t order, double* theta_dev, double* coef_dev,
+                                                double* energy_dev, int32_t* flags_dev, void* stream) {
+    long long cap = 0;
+    act_status st = check_lem(p, cfg, batch, lhs_dev, resid_dev, order, theta_dev, coef_dev, energy_dev, flags_dev,
+                              "act_lem_decompose_noalloc", &cap);
+    if (st != ACT_OK) return st;
+    const unsigned long long need = (unsigned long long)batch * (unsigned long long)cap * (4 * sizeof(double) +
+                                                                                          sizeof(double) + 1);
+    if (need > (unsigned long long)ACT_LEM_SCRATCH_BYTES) {
+        set_error("act_lem_decompose_noalloc: batch x candidates per stage x 41 bytes = " + std::to_string(need) +
+                  " exceeds the " + std::to_string((unsigned long long)ACT_LEM_SCRATCH_BYTES) +
+                  "-byte scratch array; use act_lem_decompose");
+        return ACT_ERR_INVALID;
+    }
+    char* base = nullptr;
+    if ((st = scratch_for_current_device(&base)) != ACT_OK) return st;
+    // [batch][cap][4] parameters, then [batch][cap] scores, then [batch][cap] marks;
+    // every entry is written by the kernel before it is read, so no clearing
+    double* cand = (double*)base;
+    double* score = cand + (size_t)batch * cap * 4;
+    char* used = (char*)(score + (size_t)batch * cap);
+    hipStream_t s = (hipStream_t)stream;
+    p->last_stream = s;
+    st = launch_init(p, batch, resid_dev, approx_dev, energy_dev, flags_dev, order, s);
+    if (st != ACT_OK) return st;
+    for (int k = 0; k < order; ++k) {
+        st = launch_lem_order(p, cfg, (int)cap, cand, score, used, batch, k, order, lhs_dev, resid_dev, approx_dev,
+                              theta_dev, coef_dev, energy_dev, flags_dev, s);
         if (st != ACT_OK) return st;
     }
     return ACT_OK;

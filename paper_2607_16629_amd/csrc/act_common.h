@@ -353,9 +353,12 @@ act_status launch_prior_order(act_plan_s* p, int batch, int k, int order, double
                               double* theta, double* coef, long long* index, double* energy, double* gap,
                               int* flags, hipStream_t s);
 size_t prior_workspace_blocks();
-act_status launch_lem_order(act_plan_s* p, const act_lem_desc* cfg, int cap, int batch, int k, int order,
-                            const double* lhs, double* resid, double* approx, double* theta, double* coef,
-                            double* energy, int* flags, hipStream_t s);
+// LEM workspace per channel: cap candidates x (4 parameters + 1 score, FP64)
+// and one mark byte, at cand_ws [B][cap][4], score_ws [B][cap], used_ws [B][cap]
+act_status launch_lem_order(act_plan_s* p, const act_lem_desc* cfg, int cap, double* cand_ws, double* score_ws,
+                            char* used_ws, int batch, int k, int order, const double* lhs, double* resid,
+                            double* approx, double* theta, double* coef, double* energy, int* flags,
+                            hipStream_t s);
 // per-channel kernels (act_refine.hip)
 act_status launch_init(act_plan_s* p, int batch, double* resid, double* approx, double* energy,
                        int* flags, int order, hipStream_t s);

@@ -1667,9 +1667,10 @@ __global__ void __launch_bounds__(NTR) k_lem_order(PlanDev P, LemDev cfg, int k,
     }
 }
 
-act_status launch_lem_order(act_plan_s* p, const act_lem_desc* cfg, int cap, int batch, int k, int order,
-                            const double* lhs, double* resid, double* approx, double* theta, double* coef,
-                            double* energy, int* flags, hipStream_t s) {
+act_status launch_lem_order(act_plan_s* p, const act_lem_desc* cfg, int cap, double* cand_ws, double* score_ws,
+                            char* used_ws, int batch, int k, int order, const double* lhs, double* resid,
+                            double* approx, double* theta, double* coef, double* energy, int* flags,
+                            hipStream_t s) {
     LemDev d;
     d.samples = cfg->samples;
     d.levels = cfg->levels;
@@ -1679,8 +1680,7 @@ act_status launch_lem_order(act_plan_s* p, const act_lem_desc* cfg, int cap, int
     for (int l = 0; l < 8; ++l)
         for (int a = 0; a < 4; ++a) d.step[l][a] = cfg->step[l][a];
     hipLaunchKernelGGL(k_lem_order, dim3(batch), dim3(NTR), 0, s, view(p), d, k, order, p->desc.refine_steps, lhs,
-                       p->lem_cand, p->lem_score, (char*)(p->lem_score + (size_t)p->max_batch * cap), resid,
-                       approx, theta, coef, energy, flags);
+                       cand_ws, score_ws, used_ws, resid, approx, theta, coef, energy, flags);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }

@@ -119,3 +119,10 @@ def test_binding_refuses_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         A.Plan(W.eeg_grid(512, 4, 4, 4, 2))
+
+
+def test_noalloc_scratch_size_matches_header():
+    """The binding's copy of ACT_LEM_SCRATCH_BYTES equals the header's."""
+    m = re.search(r"#define\s+ACT_LEM_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", open(HEADER).read())
+    assert m is not None
+    assert int(m.group(1)) << int(m.group(2)) == A.LEM_SCRATCH_BYTES
