@@ -181,6 +181,20 @@ int64_t act_plan_query(act_plan_t plan, int32_t key);
  * tiles depend on the call's lengths). */
 act_status act_search_flops(act_plan_t plan, int32_t batch, double* flops);
 
+/* Matrix-core work the coarse searches of a lag-table or FP16-synthesis plan
+ * actually executed, as counted by the device: every pass-0 search launch
+ * (the first search of each order, in act_decompose, act_tune or their graph
+ * replays; not the exact-threshold reruns, not act_correlate) adds the MFMA
+ * instructions its waves issued (x 32 x 32 x 16 multiply-adds x 2 = flops)
+ * and 1 to a launch count.  The counts cover every launch since the plan was
+ * built or since the last call of this function, which returns them in
+ * *flops and *launches and resets them.  For uneven batches, whose tiles
+ * depend on the call's lengths, this is the executed work per call (the
+ * launches of one act_decompose call are alike).  Synchronises the plan's
+ * last stream.  Errors: ACT_ERR_INVALID (NULL argument),
+ * ACT_ERR_UNSUPPORTED (other plans), ACT_ERR_HIP. */
+act_status act_search_executed(act_plan_t plan, double* flops, int64_t* launches);
+
 /* Residue-based matching pursuit of `batch` channels for `order` orders
  * (Sec. III-A, Fig. "simplified residue-driven ACT iteration"):
  *   resid_dev   in: the signals, out: the residuals r_P.  f64, channel b at
@@ -276,6 +290,20 @@ act_status act_refine(act_plan_t plan, int32_t m, const double* resid_dev,
                       const double* theta0_dev, int32_t steps, double* theta_dev,
                       double* value_dev, int32_t* flags_dev, void* stream);
 
+/* act_refine with FP32 arithmetic (Sec. III-A refinement; real atoms of the
+ * residue-based ACT): resid_dev is [m][n_samples] float; every objective
+ * evaluation forms each sample's terms in FP32 (the phase reduced modulo one
+ * cycle in FP64, then FP32 envelope, trigonometry, products and per-thread
+ * sums; the block adds the threads' partial sums in FP64).  The coordinate
+ * scales and the 4-parameter L-BFGS bookkeeping stay FP64.  The iteration
+ * stops when the projected gradient is below 1e-6 max(1, J) (FP32 resolves J
+ * to about 1e-7) and the line search's approximate-Wolfe test allows
+ * f_new <= f + 1e-6 |f|; otherwise as act_refine.  value_dev holds J at
+ * theta in the same FP32 arithmetic.  Errors: as act_refine, plus
+ * ACT_ERR_UNSUPPORTED for complex_atoms and prior_act plans. */
+act_status act_refine_f32(act_plan_t plan, int32_t m, const float* resid_dev, const double* theta0_dev,
+                          int32_t steps, double* theta_dev, double* value_dev, int32_t* flags_dev, void* stream);
+
 /* Forward and adjoint of the refinement objective for m (residual, theta)
  * pairs: value J = <r,g>^2/<g,g>, dtheta = dJ/d(t_c, f_c, c, logdt) and
  * optionally dr = dJ/dr = 2 <r, g_hat> g_hat.  dtype ACT_PREC_F64 (resid and
@@ -348,6 +376,23 @@ act_status act_tune(act_plan_t plan, int32_t batch, const int32_t* len_dev, cons
  * read, and clears them.  Errors: ACT_ERR_INVALID (NULL plan or outputs). */
 act_status act_timing_enable(act_plan_t plan, int32_t enable);
 act_status act_timing_read(act_plan_t plan, double* ms, int64_t* launches);
+
+/* Measurement probes (not part of the method), for reporting achievable peaks
+ * beside the datasheet ones.  The caller times each launch on `stream`.
+ * act_probe_read: one grid-stride streaming read of `bytes` (a multiple of
+ *   16) from buf_dev (16-byte aligned device memory the caller owns; use a
+ *   buffer well above the last-level cache), blocks_per_cu x CUs workgroups of
+ *   256 threads, 8 16-byte non-temporal loads in flight per thread; nothing is
+ *   written (sink_dev, one float, is written only for an impossible sum).
+ * act_probe_mfma: blocks_per_cu x CUs workgroups of 4 waves, each wave
+ *   `iters` rounds of 4 independent 32x32 MFMAs (prec ACT_PREC_BF16:
+ *   v_mfma_f32_32x32x16_bf16, ACT_PREC_F16: _f16, ACT_PREC_F32:
+ *   v_mfma_f32_32x32x2_f32) with no memory traffic; *flops = the flops the
+ *   launch executes (2 per multiply-add).
+ * Errors: ACT_ERR_INVALID (bad sizes, alignment or counts), ACT_ERR_HIP. */
+act_status act_probe_read(const void* buf_dev, int64_t bytes, int32_t blocks_per_cu, float* sink_dev, void* stream);
+act_status act_probe_mfma(int32_t prec, int32_t iters, int32_t blocks_per_cu, float* sink_dev, double* flops,
+                          void* stream);
 
 const char* act_status_string(act_status status);
 const char* act_last_error(void);

@@ -53,7 +53,8 @@ class _PlanDesc(ctypes.Structure):
                 ("prior_act", ctypes.c_int32), ("complex_atoms", ctypes.c_int32)]
 
 
-EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_search_flops", "act_decompose", "act_lem_decompose",
+EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_search_flops", "act_search_executed",
+           "act_decompose", "act_lem_decompose", "act_probe_read", "act_probe_mfma", "act_refine_f32",
            "act_lem_decompose_noalloc",
            "act_refine", "act_value_and_grad", "act_reconstruct", "act_correlate", "act_tune",
            "act_timing_enable", "act_timing_read", "act_status_string", "act_last_error")
@@ -106,10 +107,18 @@ def load() -> ctypes.CDLL:
     lib.act_plan_query.restype = i64
     lib.act_search_flops.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     lib.act_search_flops.restype = i32
+    lib.act_search_executed.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.act_search_executed.restype = i32
+    lib.act_probe_read.argtypes = [vp, i64, i32, vp, vp]
+    lib.act_probe_read.restype = i32
+    lib.act_probe_mfma.argtypes = [i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.act_probe_mfma.restype = i32
     lib.act_decompose.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.act_decompose.restype = ctypes.c_int
     lib.act_refine.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp]
     lib.act_refine.restype = ctypes.c_int
+    lib.act_refine_f32.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp]
+    lib.act_refine_f32.restype = ctypes.c_int
     lib.act_value_and_grad.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.act_value_and_grad.restype = ctypes.c_int
     lib.act_reconstruct.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
@@ -175,6 +184,22 @@ def make_desc(grid: Grid, dict_: str = "table", prec: str = "f32", max_batch: in
     return desc
 
 
+def probe_read(buf: torch.Tensor, blocks_per_cu: int, sink: torch.Tensor):
+    """One streaming read of `buf` (a CUDA tensor) on the current stream."""
+    assert buf.is_cuda and buf.is_contiguous() and sink.is_cuda and sink.dtype == torch.float32
+    _check(load().act_probe_read(_ptr(buf), buf.numel() * buf.element_size(), int(blocks_per_cu), _ptr(sink),
+                                 _stream()))
+
+
+def probe_mfma(prec: str, iters: int, blocks_per_cu: int, sink: torch.Tensor) -> float:
+    """One MFMA-loop launch on the current stream; returns its flops."""
+    assert sink.is_cuda and sink.dtype == torch.float32
+    f = ctypes.c_double(0.0)
+    _check(load().act_probe_mfma(_PRECS[prec], int(iters), int(blocks_per_cu), _ptr(sink), ctypes.byref(f),
+                                 _stream()))
+    return f.value
+
+
 class Plan:
     """Owns an act_plan_t.  See include/act.h for every call's contract."""
 
@@ -219,6 +244,14 @@ class Plan:
         out = ctypes.c_double(0.0)
         _check(load().act_search_flops(self._h, int(batch), ctypes.byref(out)))
         return out.value
+
+    def search_executed(self):
+        """(flops, launches) the pass-0 searches executed since the last read,
+        counted on the device (lag-table and FP16 synthesis plans); resets."""
+        f = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(load().act_search_executed(self._h, ctypes.byref(f), ctypes.byref(n)))
+        return f.value, int(n.value)
 
     @property
     def atoms(self) -> int:
@@ -343,14 +376,18 @@ class Plan:
         return out
 
     def act_refine(self, resid, theta0, steps: int):
-        resid = _device_tensor(resid, torch.float64).reshape(-1, self.grid.n)
+        """Refinement of every row: act_refine for an FP64 residual (numpy
+        arrays are taken as FP64), act_refine_f32 for an FP32 CUDA tensor."""
+        f32 = isinstance(resid, torch.Tensor) and resid.dtype == torch.float32
+        resid = _device_tensor(resid, torch.float32 if f32 else torch.float64).reshape(-1, self.grid.n)
         theta0 = _device_tensor(theta0, torch.float64).reshape(-1, 4)
         m = resid.shape[0]
         theta = torch.empty(m, 4, dtype=torch.float64, device=resid.device)
         value = torch.empty(m, dtype=torch.float64, device=resid.device)
         flags = torch.empty(m, dtype=torch.int32, device=resid.device)
-        _check(load().act_refine(self._h, m, _ptr(resid), _ptr(theta0), int(steps), _ptr(theta),
-                                 _ptr(value), _ptr(flags), _stream()))
+        fn = load().act_refine_f32 if f32 else load().act_refine
+        _check(fn(self._h, m, _ptr(resid), _ptr(theta0), int(steps), _ptr(theta), _ptr(value), _ptr(flags),
+                  _stream()))
         return theta, value, flags
 
     def act_value_and_grad(self, resid: torch.Tensor, theta: torch.Tensor, want_dr: bool = True):

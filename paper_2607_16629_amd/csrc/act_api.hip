@@ -323,6 +323,22 @@ extern "C" act_status act_refine(act_plan_t p, int32_t m, const double* resid_de
     return launch_refine_many(p, m, resid_dev, theta0_dev, steps, theta_dev, value_dev, flags_dev, s);
 }
 
+extern "C" act_status act_refine_f32(act_plan_t p, int32_t m, const float* resid_dev, const double* theta0_dev,
+                                     int32_t steps, double* theta_dev, double* value_dev, int32_t* flags_dev,
+                                     void* stream) {
+    ACT_REQUIRE(p != nullptr, "act_refine_f32: plan is NULL");
+    ACT_REQUIRE(!p->desc.ragged, "act_refine_f32: ragged plans are not supported");
+    ACT_REQUIRE(m >= 1 && steps >= 0, "act_refine_f32: m must be >= 1 and steps >= 0");
+    ACT_REQUIRE(resid_dev && theta0_dev && theta_dev && value_dev, "act_refine_f32: NULL pointer");
+    if (p->desc.complex_atoms || p->desc.prior_act) {
+        set_error("act_refine_f32: the FP32 refinement is for the real atoms of the residue-based ACT");
+        return ACT_ERR_UNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    p->last_stream = s;
+    return launch_refine_many_f32(p, m, resid_dev, theta0_dev, steps, theta_dev, value_dev, flags_dev, s);
+}
+
 extern "C" act_status act_value_and_grad(act_plan_t p, int32_t m, int32_t dtype,
                                          const void* resid_dev, const double* theta_dev,
                                          double* value_dev, double* dtheta_dev, void* dr_dev,

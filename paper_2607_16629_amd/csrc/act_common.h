@@ -293,6 +293,8 @@ struct act_plan_s {
     double* ebound = nullptr;       // [B] certified score error bound
     double* rnorm = nullptr;        // [B] |r|
     int* need_rerun = nullptr;      // [B] candidate overflow -> exact-threshold search
+    unsigned long long* exec_count = nullptr;  // [2] MFMA searches: executed MFMA instructions of the
+                                               // pass-0 searches and their launches (act_search_executed)
     size_t workspace_bytes = 0;
 
     const double* search_resid = nullptr;  // FP64 residual the FP64 search reads
@@ -370,6 +372,8 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
 act_status launch_overflow_check(act_plan_s* p, int batch, hipStream_t s);
 act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const double* theta0,
                               int steps, double* theta, double* value, int* flags, hipStream_t s);
+act_status launch_refine_many_f32(act_plan_s* p, int m, const float* resid, const double* theta0, int steps,
+                                  double* theta, double* value, int* flags, hipStream_t s);
 act_status launch_value_and_grad(act_plan_s* p, int m, int dtype, const void* resid,
                                  const double* theta, double* value, double* dtheta, void* dr,
                                  hipStream_t s);

@@ -353,7 +353,7 @@ static void free_plan(act_plan_s* p) {
     if (!p) return;
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
-                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->lem_cand, p->lem_score, p->shadow_alloc, p->cand_idx, p->cand_score, p->cand_p64,
+                    p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->lem_cand, p->lem_score, p->shadow_alloc, p->cand_idx, p->cand_score, p->cand_p64, p->exec_count,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun, p->lag_inv, p->lag_span, p->lag_order,
                     p->lag_rho, p->lag_rows};
     for (void* q : ptrs)
@@ -706,6 +706,10 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     PLAN_HIP(hipMalloc((void**)&p->ebound, B * sizeof(double)));
     PLAN_HIP(hipMalloc((void**)&p->rnorm, B * sizeof(double)));
     PLAN_HIP(hipMalloc((void**)&p->need_rerun, B * sizeof(int)));
+    if (desc->dict == ACT_DICT_LAG || (desc->dict == ACT_DICT_SYNTH && desc->prec == ACT_PREC_F16)) {
+        PLAN_HIP(hipMalloc((void**)&p->exec_count, 2 * sizeof(unsigned long long)));
+        PLAN_HIP(hipMemsetAsync(p->exec_count, 0, 2 * sizeof(unsigned long long), s));
+    }
     p->workspace_bytes = B * p->n_pad * elt + B * cap * 16 + B * 32;
 #undef PLAN_HIP
 
@@ -742,6 +746,24 @@ extern "C" int64_t act_plan_query(act_plan_t p, int32_t key) {
         case ACT_Q_WORKSPACE_BYTES: return (int64_t)p->workspace_bytes;
         default: return -1;
     }
+}
+
+extern "C" act_status act_search_executed(act_plan_t p, double* flops, int64_t* launches) {
+    ACT_REQUIRE(p != nullptr && flops != nullptr && launches != nullptr,
+                "act_search_executed: plan, flops or launches is NULL");
+    if (!p->exec_count) {
+        set_error("act_search_executed: only the lag-table and FP16 synthesised searches count their work");
+        return ACT_ERR_UNSUPPORTED;
+    }
+    ACT_HIP(hipStreamSynchronize(p->last_stream));
+    unsigned long long c[2] = {0, 0};
+    ACT_HIP(hipMemcpy(c, p->exec_count, sizeof c, hipMemcpyDeviceToHost));
+    const unsigned long long zero[2] = {0, 0};
+    ACT_HIP(hipMemcpy(p->exec_count, zero, sizeof zero, hipMemcpyHostToDevice));
+    // v_mfma_f32_32x32x16_{f16,bf16}: 32 x 32 x 16 multiply-adds
+    *flops = (double)c[0] * (32.0 * 32.0 * 16.0 * 2.0);
+    *launches = (int64_t)c[1];
+    return ACT_OK;
 }
 
 extern "C" act_status act_search_flops(act_plan_t p, int32_t batch, double* flops) {

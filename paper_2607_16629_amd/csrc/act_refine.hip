@@ -6,6 +6,8 @@
 // approximation update of Eq. (4) with the energy |r_{k+1}|^2 (Eq. (5)).
 #include <math.h>
 
+#include <type_traits>
+
 #include "act_common.h"
 
 namespace act {
@@ -391,6 +393,19 @@ __device__ __forceinline__ void atom_terms64(double tau, double fc, double c, do
     terms_from(tau, fc, c, inv_dt * inv_dt, e, co, si, gk, d);
 }
 
+// FP32 forward/adjoint: the phase in cycles is formed and reduced modulo 1 in
+// FP64 (an FP32 phase of a long chirp loses whole milliradians); the envelope,
+// trigonometry, products and sums are FP32.
+__device__ __forceinline__ void atom_terms_f32(double tau64, double c, double fc, float inv_dt,
+                                               float& e, float& co, float& si, float& tau) {
+    const double cyc = c * tau64 * tau64 + fc * tau64;
+    const float red_c = (float)(cyc - rint(cyc));
+    sincospif(2.0f * red_c, &si, &co);
+    tau = (float)tau64;
+    const float u = tau * inv_dt;
+    e = expf(-0.5f * u * u);
+}
+
 // Visits this thread's samples k = k0 + threadIdx.x + TB j of [k0, k1) with
 // (k, tau, E, cos phi, sin phi).  A window of at least 4 TB samples advances
 // E and exp(i phi) from the thread's first sample by product recurrences over
@@ -482,6 +497,48 @@ __device__ void sums_obj(const double* __restrict__ r, int n, double fs, const d
             }
         }
     }
+    block_sum<TB, 10>(acc, red);
+}
+
+// The same ten sums in FP32 arithmetic from an FP32 residual, over the
+// support window: each sample's terms (phase reduced modulo one cycle in
+// FP64, then FP32 envelope, trigonometry and products) and each thread's
+// running sums are FP32; the block adds the threads' partial sums in FP64.
+template <int TB>
+__device__ void sums_obj32(const float* __restrict__ r, int n, double fs, const double th[4], double (&acc)[10],
+                           double* red) {
+    int k0, k1;
+    support_window(n, fs, th, k0, k1);
+    const double tc = th[0], fc = th[1], c = th[2];
+    const float inv_dt = (float)(1.0 / exp(th[3]));
+    const float idt2 = inv_dt * inv_dt;
+    const float twopi = 6.2831853071795865f, fcf = (float)fc, cf = (float)c;
+    float a[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) a[j] = 0.0f;
+#pragma unroll 1
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += TB) {
+        float e, co, si, tau;
+        atom_terms_f32(sample_time(k, fs) - tc, c, fc, inv_dt, e, co, si, tau);
+        const float gk = e * co, es = e * si;
+        const float d0 = e * (tau * idt2 * co) + twopi * (2.0f * cf * tau + fcf) * es;
+        const float d1 = -twopi * tau * es;
+        const float d2 = -twopi * tau * tau * es;
+        const float d3 = tau * tau * idt2 * gk;
+        const float rk = r[k];
+        a[0] += rk * gk;
+        a[1] += gk * gk;
+        a[2] += rk * d0;
+        a[3] += rk * d1;
+        a[4] += rk * d2;
+        a[5] += rk * d3;
+        a[6] += gk * d0;
+        a[7] += gk * d1;
+        a[8] += gk * d2;
+        a[9] += gk * d3;
+    }
+#pragma unroll
+    for (int j = 0; j < 10; ++j) acc[j] = (double)a[j];
     block_sum<TB, 10>(acc, red);
 }
 
@@ -653,17 +710,23 @@ __device__ __forceinline__ double obj_prior_from_sums(const double acc[10], doub
 
 // objective of the refinement: 0 = the residue-based ACT's J, 1 = the prior
 // ACT's, 2 = complex atoms' |<g_hat, r>|^2 (the red buffer then holds 13 sums)
-enum { kObjReal = 0, kObjPrior = 1, kObjComplex = 2 };
+// 3 = the residue-based ACT's J with FP32 arithmetic (FP32 residual)
+enum { kObjReal = 0, kObjPrior = 1, kObjComplex = 2, kObjReal32 = 3 };
 
-template <int TB, int MODE = kObjReal>
-__device__ __forceinline__ double refine_eval(const double* r, const GridDev& g, const double th0[4],
+template <int TB, int MODE = kObjReal, typename RT = double>
+__device__ __forceinline__ double refine_eval(const RT* r, const GridDev& g, const double th0[4],
                                               const double h[4], const double u[4], double gu[4],
                                               double* red) {
+    static_assert((MODE == kObjReal32) == std::is_same<RT, float>::value, "FP32 residuals go with kObjReal32");
     double th[4], gr[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) th[j] = th0[j] + h[j] * u[j];
     double J;
-    if constexpr (MODE == kObjComplex) {
+    if constexpr (MODE == kObjReal32) {
+        double acc[10];
+        sums_obj32<TB>(r, g.n, g.fs, th, acc, red);
+        J = obj_from_sums(acc, gr);
+    } else if constexpr (MODE == kObjComplex) {
         double acc[13];
         sums_obj_cplx<TB>(r, g.n, g.fs, th, acc, red);
         J = obj_cplx_from_sums(acc, gr);
@@ -677,10 +740,15 @@ __device__ __forceinline__ double refine_eval(const double* r, const GridDev& g,
     return -J;
 }
 
-template <int TB, int MODE = kObjReal>
-__device__ int refine_block(const double* __restrict__ r, const GridDev& g, const BoxDev& box,
+// FP32 objectives (kObjReal32) resolve J and its gradient to about 1e-7
+// relative instead of 1e-16: the stopping gradient and the approximate-Wolfe
+// tolerance on f follow that working precision.
+template <int TB, int MODE = kObjReal, typename RT = double>
+__device__ int refine_block(const RT* __restrict__ r, const GridDev& g, const BoxDev& box,
                             const double th0[4], int steps, double th_out[4], double* J_out,
                             double* red, RefineLds& L) {
+    constexpr double kStopTol = MODE == kObjReal32 ? 1e-6 : 1e-11;
+    constexpr double kWolfeF = MODE == kObjReal32 ? 1e-6 : 1e-12;
     double h[4], blo[4], bhi[4], u[4] = {0, 0, 0, 0}, gcur[4];
     int flags = 0;
     {
@@ -712,7 +780,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
             bhi[j] = h[j] == 0.0 ? 0.0 : (box.hi[j] - th0[j]) / h[j];
         }
     }
-    double f = refine_eval<TB, MODE>(r, g, th0, h, u, gcur, red);
+    double f = refine_eval<TB, MODE, RT>(r, g, th0, h, u, gcur, red);
     const double f0 = f;
     int nmem = 0, head = 0;
     for (int it = 0; it < steps; ++it) {
@@ -725,7 +793,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
             pgmax = fmax(pgmax, fabs(pg[j]));
         }
         const double Jc = -f;
-        if (pgmax <= 1e-11 * (Jc > 1.0 ? Jc : 1.0)) break;
+        if (pgmax <= kStopTol * (Jc > 1.0 ? Jc : 1.0)) break;
         // two-loop recursion, newest pair first; the alphas are recomputed in
         // the second loop's order from a small register array
         double d[4], al[8];
@@ -781,7 +849,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
                 v = v > bhi[j] ? bhi[j] : v;
                 un[j] = v;
             }
-            fn = refine_eval<TB, MODE>(r, g, th0, h, un, gn, red);
+            fn = refine_eval<TB, MODE, RT>(r, g, th0, h, un, gn, red);
             double dec = 0.0, dnew = 0.0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -789,7 +857,7 @@ __device__ int refine_block(const double* __restrict__ r, const GridDev& g, cons
                 dnew += gn[j] * (un[j] - u[j]);
             }
             const bool armijo = fn <= f + 1e-4 * dec;
-            const bool approx_wolfe = fn <= f + 1e-12 * fabs(f) && dnew >= 0.9 * dec && dnew <= -0.8 * dec;
+            const bool approx_wolfe = fn <= f + kWolfeF * fabs(f) && dnew >= 0.9 * dec && dnew <= -0.8 * dec;
             if (dec < 0.0 && (armijo || approx_wolfe)) {
                 ok = true;
                 break;
@@ -1053,9 +1121,9 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
 // --------------------------------------------------------------------------
 // refinement alone, forward/adjoint alone, reconstruction
 // --------------------------------------------------------------------------
-template <int MODE, int TB>
+template <int MODE, int TB, typename RT = double>
 __global__ void __launch_bounds__(TB) k_refine_many(GridDev g, BoxDev box,
-                                                     const double* __restrict__ resid,
+                                                     const RT* __restrict__ resid,
                                                      const double* __restrict__ theta0, int steps,
                                                      double* __restrict__ theta,
                                                      double* __restrict__ value,
@@ -1063,11 +1131,11 @@ __global__ void __launch_bounds__(TB) k_refine_many(GridDev g, BoxDev box,
     __shared__ double red[block_sum_lds(TB, 13)];
     __shared__ RefineLds L;
     const int p = blockIdx.x;
-    const double* r = resid + (size_t)p * g.n;
+    const RT* r = resid + (size_t)p * g.n;
     double th0[4], th[4], J;
 #pragma unroll
     for (int j = 0; j < 4; ++j) th0[j] = theta0[p * 4 + j];
-    const int fl = refine_block<TB, MODE>(r, g, box, th0, steps, th, &J, red, L);
+    const int fl = refine_block<TB, MODE, RT>(r, g, box, th0, steps, th, &J, red, L);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) theta[p * 4 + j] = th[j];
@@ -1106,19 +1174,6 @@ __global__ void __launch_bounds__(NT) k_vg_f64(GridDev g, const double* __restri
         for (int k = threadIdx.x; k < g.n; k += NT)
             dr[(size_t)p * g.n + k] = f * atom_sample64(sample_time(k, g.fs), th[0], th[1], th[2], inv_dt);
     }
-}
-
-// FP32 forward/adjoint: the phase in cycles is formed and reduced modulo 1 in
-// FP64 (an FP32 phase of a long chirp loses whole milliradians); the envelope,
-// trigonometry, products and sums are FP32.
-__device__ __forceinline__ void atom_terms_f32(double tau64, double c, double fc, float inv_dt,
-                                               float& e, float& co, float& si, float& tau) {
-    const double cyc = c * tau64 * tau64 + fc * tau64;
-    const float red_c = (float)(cyc - rint(cyc));
-    sincospif(2.0f * red_c, &si, &co);
-    tau = (float)tau64;
-    const float u = tau * inv_dt;
-    e = expf(-0.5f * u * u);
 }
 
 __global__ void __launch_bounds__(NT) k_vg_f32(GridDev g, const float* __restrict__ resid,
@@ -1283,6 +1338,16 @@ act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const d
     const bool cx = p->desc.complex_atoms != 0;
     auto kern = many ? (cx ? k_refine_many<kObjComplex, 128> : k_refine_many<kObjReal, 128>)
                      : (cx ? k_refine_many<kObjComplex, NTR> : k_refine_many<kObjReal, NTR>);
+    hipLaunchKernelGGL(kern, dim3(m), dim3(many ? 128 : NTR), 0, s, p->grid, p->box, resid, theta0, steps, theta,
+                       value, flags);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+act_status launch_refine_many_f32(act_plan_s* p, int m, const float* resid, const double* theta0, int steps,
+                                  double* theta, double* value, int* flags, hipStream_t s) {
+    const bool many = (long long)m > 2LL * device_cus();
+    auto kern = many ? k_refine_many<kObjReal32, 128, float> : k_refine_many<kObjReal32, NTR, float>;
     hipLaunchKernelGGL(kern, dim3(m), dim3(many ? 128 : NTR), 0, s, p->grid, p->box, resid, theta0, steps, theta,
                        value, flags);
     ACT_HIP(hipGetLastError());

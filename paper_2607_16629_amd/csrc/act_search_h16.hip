@@ -59,6 +59,9 @@ struct H16Dev {
     const float* inv_full;   // ragged plans: [n_fc][n_cl] 1/|g| over all lags (interior atoms)
     int W, n_cl, n_ld, n_tc;
     int cut;                 // 1: skip samples outside the supports
+    // pass-0 searches: [0] += MFMA instructions the launch executed (every
+    // wave's), [1] += 1 per launch; NULL when not counting
+    unsigned long long* exec;
 };
 
 // Rows are ordered log-duration major (row = il * n_c + ic), so a block of
@@ -130,7 +133,7 @@ __device__ __forceinline__ H16Col h16_col(const GridDev& g, const H16Dev& hd, co
 
 template <int WCB, bool RERUN, bool DUMP, bool RAGGED>
 __device__ __forceinline__ void h16_tile(const GridDev& g, const H16Dev& hd, const SearchCtl& ctl, const H16Tile& t,
-                         H16Lds<WCB>& L) {
+                         H16Lds<WCB>& L, unsigned& stages_run) {
     constexpr int TC = 32 * WCB;   // columns per workgroup
     // wave-uniform values live in scalar registers
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -187,6 +190,7 @@ __device__ __forceinline__ void h16_tile(const GridDev& g, const H16Dev& hd, con
         constexpr int KB = 2;
         static_assert(H_KSTEPS == 4 * KB, "four blocks per stage");
         const bool run = n0 + H_KS - 1 >= t.m - D_w && n0 <= t.m + D_w;
+        stages_run += run ? 1u : 0u;
         f16x8 ua0[H_WRB][KB], va0[H_WRB][KB], ua1[H_WRB][KB], va1[H_WRB][KB];
         auto load_blk = [&](f16x8 (&ua)[H_WRB][KB], f16x8 (&va)[H_WRB][KB], int blk) {
             const int eb = n0 + 16 * KB * blk - t.m + g.n_pad + 8 * KB * (lane >> 5);
@@ -464,6 +468,16 @@ __device__ __forceinline__ void h16_tile(const GridDev& g, const H16Dev& hd, con
     __syncthreads();  // L.M / L.cm are rewritten by the next tile
 }
 
+// Executed-work report of a pass-0 search: one atomic per wave; a stage a
+// wave runs is 4 blocks x 2 k-steps x WCB column blocks x H_WRB row blocks x
+// 2 MFMAs (C and S parts).
+__device__ __forceinline__ void h16_count(const H16Dev& hd, bool skip, unsigned stages_run, int wcb) {
+    if (skip || !hd.exec) return;
+    if ((threadIdx.x & 63) == 0 && stages_run)
+        atomicAdd(&hd.exec[0], (unsigned long long)stages_run * (unsigned long long)(4 * 2 * wcb * H_WRB * 2));
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&hd.exec[1], 1ull);
+}
+
 // Plain plans: tiles (row block, tc, f_c group, channel group), channel group
 // fastest, so that concurrently running tiles read the A rows of one row block
 // over overlapping windows (adjacent time centres); tile ids are dealt to the
@@ -476,6 +490,7 @@ __global__ void __launch_bounds__(256, 2) k_search_h16(GridDev g, H16Dev hd, Sea
     constexpr int TC = 32 * WCB;
     const long long tiles = (long long)g.cnt[0] * n_rb * n_fg * n_bg;
     const long long chunk = (tiles + 7) / 8;
+    unsigned stages_run = 0;  // this wave's stages, counted for the executed-work report
     for (long long x = blockIdx.x; x < 8 * chunk; x += gridDim.x) {
         const long long tid = (x % 8) * chunk + x / 8;
         if (tid >= tiles) continue;
@@ -501,8 +516,9 @@ __global__ void __launch_bounds__(256, 2) k_search_h16(GridDev g, H16Dev hd, Sea
                                                                   bitsf(ctl.gmax[b]))));
         }
         if (!__syncthreads_or(live)) continue;
-        h16_tile<WCB, RERUN, DUMP, false>(g, hd, ctl, t, L);
+        h16_tile<WCB, RERUN, DUMP, false>(g, hd, ctl, t, L, stages_run);
     }
+    h16_count(hd, RERUN || DUMP, stages_run, WCB);
 }
 
 // Ragged plans: channels sorted by decreasing length form groups of 64 (the
@@ -519,6 +535,7 @@ __global__ void __launch_bounds__(256, 2) k_search_h16_ragged(GridDev g, H16Dev 
     const int ng = (batch + 63) / 64;
     const int total = items[batch];
     int* counter = items + batch + 1 + (RERUN ? 1 : 0);
+    unsigned stages_run = 0;  // this wave's stages, counted for the executed-work report
     while (true) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -557,8 +574,9 @@ __global__ void __launch_bounds__(256, 2) k_search_h16_ragged(GridDev g, H16Dev 
                                bitsf(hd.tmax[(size_t)b * hd.n_tc + t.tc]) >= bitsf(ctl.gmax[b])));
         }
         if (!__syncthreads_or(live)) continue;
-        h16_tile<4, RERUN, false, true>(g, hd, ctl, t, L);
+        h16_tile<4, RERUN, false, true>(g, hd, ctl, t, L, stages_run);
     }
+    h16_count(hd, RERUN, stages_run, 4);
 }
 
 // Ragged preparation, once per call: channels ranked by decreasing length
@@ -615,7 +633,8 @@ act_status launch_h16_ragged_prep(act_plan_s* p, int batch, hipStream_t s) {
 }
 
 act_status launch_search_h16(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s) {
-    const H16Dev hd = h16_dev(p);
+    H16Dev hd = h16_dev(p);
+    hd.exec = (ctl.pass == 0 && !ctl.dump) ? p->exec_count : nullptr;
     const int n_fc = p->grid.cnt[1];
     const int n_rb = (p->n_cl + H_RW - 1) / H_RW;
     if (p->desc.ragged) {

@@ -107,6 +107,9 @@ struct LagDev {
     const int* rows;
     const float* rho;
     int rho_d, div;
+    // pass-0 searches: [0] += MFMA instructions the launch executed (every
+    // wave's), [1] += 1 per launch; NULL when not counting
+    unsigned long long* exec;
 };
 
 struct LagLds {
@@ -163,6 +166,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
     const long long n_rbk = RAG ? (long long)ld.rows[n_cg] : (long long)n_cg * n_tg;
     const long long tiles = (long long)n_cbk * n_rbk;
     const long long chunk = (tiles + 7) / 8;
+    unsigned long long stages_run = 0;  // the tiles' stages, counted for the executed-work report
     for (long long x = blockIdx.x; x < 8 * chunk; x += gridDim.x) {
         const long long tid = (x % 8) * chunk + x / 8;
         if (tid >= tiles) continue;
@@ -204,6 +208,7 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         const int e_first = max((g.n_pad - m_max) / LG_S, 16 * klo / LG_S) * LG_S;
         const int e_end = min(min(2 * g.n_pad, g.n_pad + n_long - m_min), 16 * khi);
         const int ns = e_end > e_first ? (e_end - e_first + LG_S - 1) / LG_S : 0;
+        stages_run += (unsigned long long)ns;
 
         // per channel slot: certified bound, running maximum, residual scale
         // (read now, used by the epilogue)
@@ -560,6 +565,11 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
         }
         __syncthreads();  // L.gm / L.M / L.emit / the R buffers are rewritten by the next tile
     }
+    if (!RERUN && !DUMP && ld.exec && threadIdx.x == 0) {
+        // every stage of a tile: 4 waves x 8 k-steps x 4 row blocks x WCB column blocks
+        if (stages_run) atomicAdd(&ld.exec[0], stages_run * (4ull * LG_KS * LG_RB * WCB));
+        if (blockIdx.x == 0) atomicAdd(&ld.exec[1], 1ull);
+    }
 }
 
 // The lag table: G_q(d) in FP64, rounded to FP32 and then FP16 or BF16 (RNE;
@@ -864,6 +874,7 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     ld.rho = p->lag_rho;
     ld.rho_d = p->lag_rho_d;
     ld.div = rag ? p->desc.ragged_tc_div : 1;
+    ld.exec = (ctl.pass == 0 && !ctl.dump) ? p->exec_count : nullptr;
     if (rag && ctl.dump) {
         set_error("act_correlate: the ragged lag-table search has no score dump");
         return ACT_ERR_UNSUPPORTED;

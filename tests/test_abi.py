@@ -19,7 +19,7 @@ HEADER = os.path.join(ROOT, "include", "act.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(act_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(act_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -104,6 +104,19 @@ def test_null_arguments_rejected(lib):
     assert lib.act_plan_query(None, 0) == -1
     flops = ctypes.c_double(0.0)
     assert lib.act_search_flops(None, 1, ctypes.byref(flops)) == A.ACT_ERR_INVALID
+    n = ctypes.c_int64(0)
+    assert lib.act_search_executed(None, ctypes.byref(flops), ctypes.byref(n)) == A.ACT_ERR_INVALID
+    assert lib.act_refine_f32(None, 1, None, None, 1, None, None, None, None) == A.ACT_ERR_INVALID
+    assert lib.act_lem_decompose_noalloc(None, None, 1, None, None, None, 1, None, None, None, None,
+                                         None) == A.ACT_ERR_INVALID
+    # the probes check sizes, alignment and counts before touching a device
+    assert lib.act_probe_read(None, 16, 8, None, None) == A.ACT_ERR_INVALID
+    assert lib.act_probe_read(ctypes.c_void_p(4096), 15, 8, ctypes.c_void_p(4096), None) == A.ACT_ERR_INVALID
+    assert lib.act_probe_read(ctypes.c_void_p(4096), 16, 0, ctypes.c_void_p(4096), None) == A.ACT_ERR_INVALID
+    assert lib.act_probe_mfma(A.ACT_PREC_F64, 10, 2, ctypes.c_void_p(4096), ctypes.byref(flops),
+                              None) == A.ACT_ERR_INVALID
+    assert lib.act_probe_mfma(A.ACT_PREC_BF16, 0, 2, ctypes.c_void_p(4096), ctypes.byref(flops),
+                              None) == A.ACT_ERR_INVALID
     lib.act_plan_destroy(None)
 
 

@@ -515,6 +515,52 @@ def test_refine_many_matches_oracle(oracle, pairs):
     assert not bad.any(), np.argwhere(bad)
 
 
+@pytest.mark.parametrize("pairs", [48, 1100])
+def test_refine_f32_matches_oracle(oracle, pairs):
+    """act_refine_f32 (FP32 objective evaluations) against the oracle's FP64
+    L-BFGS on the same FP32-rounded residuals.  J has several local maxima
+    (carrier lobes, chirp branches), and from a poor start FP32 rounding can
+    steer a line search into another basin than FP64's, so results are
+    matched by optimum: where both runs end within 0.05 of the refinement's
+    coordinate scale of each other and the oracle's optimum is converged (300
+    iterations do not move J), the FP32 result's J, evaluated exactly by the
+    oracle, is within 1e-6 of the oracle's; at least 3/4 of the pairs must
+    be such matches.  Every pair keeps at least the start's J, and the value
+    the kernel reports is within 1e-6 (plus the FP32 score's rounding,
+    1e-6 sqrt(J) |r|) of the exact J at its parameters.
+    1,100 pairs take the 128-thread blocks."""
+    wl = W.refine_pairs(pairs=pairs)
+    g = wl.grid
+    r32 = wl.signals.astype(np.float32)
+    r64 = r32.astype(np.float64)
+    plan = A().Plan(g, dict_="synth", prec="f64")
+    th, J, fl = plan.act_refine(torch.from_numpy(r32).cuda(), wl.theta0, 30)
+    th, J = th.cpu().numpy(), J.cpu().numpy()
+    pick = np.arange(pairs) if pairs <= 64 else np.r_[0:24, pairs // 2:pairs // 2 + 8, pairs - 24:pairs]
+    th_ref, J_ref, _ = oracle.refine_many(g, r64[pick], wl.theta0[pick], 30)
+    _, J_long, _ = oracle.refine_many(g, r64[pick], wl.theta0[pick], 300)
+    conv = np.abs(J_long - J_ref) <= 1e-12 * np.abs(J_ref)
+    h = np.array([oracle.refine_scales(g, wl.theta0[i]) for i in pick])
+    du = np.max(np.abs(th[pick] - th_ref) / np.where(h > 0, h, 1.0), axis=1)
+    same = conv & (du <= 0.05)
+    assert same.sum() >= 3 * len(pick) // 4, (same.sum(), len(pick))
+    J_at = np.array([oracle.objective(g.fs, th[i], r64[i])[0] for i in pick])
+    J_0 = np.array([oracle.objective(g.fs, wl.theta0[i], r64[i])[0] for i in pick])
+    rel = np.abs(J_at - J_ref) / J_ref
+    assert np.all(rel[same] <= 1e-6), (rel[same].max(), pick[same][np.argmax(rel[same])])
+    assert np.all(J_at >= J_0 * (1 - 1e-6))
+    # the reported J is FP32 arithmetic: |dJ| <= 2 sqrt(J) |ds|, |ds| ~ u32 sum |r g| <= u32 |r|
+    rn = np.linalg.norm(r64[pick], axis=1)
+    assert np.all(np.abs(J[pick] - J_at) <= 1e-6 * J_at + 1e-6 * np.sqrt(J_at) * rn)
+    print(f"FP32 refinement, {pairs} pairs: {same.sum()}/{len(pick)} at the oracle's optimum, max J rel err "
+          f"{rel[same].max():.2e}, max distance there {du[same].max():.2e} scale units; other basins: "
+          f"J / J_oracle in [{(J_at / J_ref)[~same].min() if (~same).any() else 1:.3g}, "
+          f"{(J_at / J_ref)[~same].max() if (~same).any() else 1:.3g}]")
+    with pytest.raises(A().ActError):
+        A().Plan(g, dict_="synth", prec="f64", complex_atoms=True).act_refine(torch.from_numpy(r32[:2]).cuda(),
+                                                                              wl.theta0[:2], 30)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_value_and_grad_against_oracle_and_fd(oracle, dtype):
     g = W.eeg_grid(2048, 64, 64, 32, 16)
@@ -1078,6 +1124,72 @@ def test_lag_search_flops_counts_the_band_stages():
     with pytest.raises(act.ActError) as e:
         other.search_flops(1)
     assert e.value.status == act.ACT_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_search_executed_counts_match_the_band_stages(prec):
+    """The device's count of executed MFMA instructions of the lag-table
+    search (act_search_executed) equals the host's count of the tiles' band
+    stages (act_search_flops) for every pass-0 launch of a decomposition, and
+    resets when read."""
+    act = A()
+    wl = W.batched_64x2048(channels=64, grid=W.eeg_grid(1024, 32, 16, 8, 6), order=3)
+    plan = act.Plan(wl.grid, dict_="lag", prec=prec, max_batch=64, refine_steps=0)
+    plan.decompose(torch.from_numpy(wl.signals), 3)
+    torch.cuda.synchronize()
+    flops, launches = plan.search_executed()
+    assert launches == 3
+    assert flops == 3 * plan.search_flops(64)
+    assert plan.search_executed() == (0.0, 0)
+
+
+def test_search_executed_counts_fp16_synthesis():
+    """The FP16 synthesis without the support cut runs every stage of every
+    tile: 2 products per sample, so the device count is twice the dense
+    correlation's flops when the tiles hold no padding; with the cut it is
+    lower.  Plans of other searches have no count."""
+    act = A()
+    g = W.eeg_grid(1024, 32, 16, 32, 16)   # 512 (c, dt) rows and 16 f_c x 64 channels: no padded tiles
+    wl = W.batched_64x2048(channels=64, grid=g, order=2)
+    dense = 2.0 * g.size * g.n * 64
+    got = {}
+    for cut in (False, True):
+        plan = act.Plan(g, dict_="synth", prec="f16", max_batch=64, refine_steps=0, support_cut=cut)
+        plan.decompose(torch.from_numpy(wl.signals), 2)
+        torch.cuda.synchronize()
+        flops, launches = plan.search_executed()
+        assert launches == 2
+        got[cut] = flops / launches
+    assert got[False] == 2.0 * dense
+    assert 0 < got[True] < got[False]
+    with pytest.raises(act.ActError) as e:
+        act.Plan(g, dict_="table", prec="f32").search_executed()
+    assert e.value.status == act.ACT_ERR_UNSUPPORTED
+
+
+def test_peak_probes_run():
+    """The measurement probes launch and report plausible rates: a streaming
+    read of 1 GiB faster than 1 TB/s and MFMA loops above 10% of the
+    datasheet peaks (the benchmark reports the measured values)."""
+    act = A()
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    buf = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+    act.probe_read(buf, 8, sink)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    act.probe_read(buf, 8, sink)
+    b.record()
+    b.synchronize()
+    assert (1 << 30) / (a.elapsed_time(b) * 1e-3) > 1e12
+    for prec, peak in (("bf16", 2.5e15), ("f16", 2.5e15), ("f32", 157.3e12)):
+        act.probe_mfma(prec, 200, 2, sink)
+        a.record()
+        flops = act.probe_mfma(prec, 2000, 2, sink)
+        b.record()
+        b.synchronize()
+        assert flops / (a.elapsed_time(b) * 1e-3) > 0.1 * peak, prec
+    assert float(sink.item()) == 0.0
 
 
 def test_lag_table_rejects_unaligned_time_centres():
