@@ -150,14 +150,24 @@ def measure_peaks():
     sink = torch.zeros(1, dtype=torch.float32, device="cuda")
     buf = torch.zeros(1 << 30, dtype=torch.float32, device="cuda")
     nbytes = buf.numel() * 4
-    act.probe_read(buf, 8, sink)
-    ms = _timed_launches(lambda: act.probe_read(buf, 8, sink), 10)
+    best, shape = 0.0, None
+    for bpc in (2, 4, 8, 16, 32):  # launch shapes: the best one is the achievable rate
+        act.probe_read(buf, bpc, sink)
+        ms = _timed_launches(lambda: act.probe_read(buf, bpc, sink), 7)
+        if nbytes / (ms * 1e-3) / 1e9 > best:
+            best, shape = nbytes / (ms * 1e-3) / 1e9, bpc
+    peaks = {"hbm_read_gbs": round(best, 1), "hbm_read_blocks_per_cu": shape}
+    # a library reduction over the same buffer, as a cross-check of the probe
+    ms = _timed_launches(lambda: buf.sum(), 5)
+    peaks["torch_sum_read_gbs"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
     del buf
-    peaks = {"hbm_read_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
     for prec, iters in (("bf16", 6000), ("f16", 6000), ("f32", 3000)):
-        flops = act.probe_mfma(prec, iters, 2, sink)
-        ms = _timed_launches(lambda: act.probe_mfma(prec, iters, 2, sink), 5)
-        peaks[f"{prec}_mfma_tflops"] = round(flops / (ms * 1e-3) / 1e12, 1)
+        best = 0.0
+        for bpc in (1, 2, 4):
+            flops = act.probe_mfma(prec, iters, bpc, sink)
+            ms = _timed_launches(lambda: act.probe_mfma(prec, iters, bpc, sink), 5)
+            best = max(best, flops / (ms * 1e-3) / 1e12)
+        peaks[f"{prec}_mfma_tflops"] = round(best, 1)
     torch.cuda.synchronize()
     return peaks
 
