@@ -215,6 +215,53 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
     __syncthreads();
 }
 
+// Sum NV doubles over a block of NT threads by transposition through LDS, for
+// the wider reductions of the refinement (NV of 9 to 13): every thread stores
+// its NV partial sums as one row; then P threads per value (P = 16, 8 or 4, as
+// many as NV P <= NT allows) each add NT/P rows pairwise, and the P partials of
+// a value, which sit in P adjacent lanes, are added by DPP moves within their
+// row (each lane of the group then holds the same bits).  Two barriers, one
+// LDS row write and NT/P reads per thread, against NV full wave trees for
+// block_sum.  `lds` must hold block_sum_tr_lds(NT, NV) doubles; every thread
+// receives the totals; deterministic (fixed order).  A block of several groups
+// of NT threads sums each group apart (thread threadIdx.x mod NT of the group,
+// each group with its own `lds`); all groups must call it together (it holds
+// block-wide barriers).
+constexpr int tr_stride(int nv) { return nv | 1; }   // odd row stride: rows start in different banks
+constexpr int tr_parts(int nt, int nv) { return nv * 16 <= nt ? 16 : nv * 8 <= nt ? 8 : 4; }
+constexpr int block_sum_tr_lds(int nt, int nv) { return nt * tr_stride(nv) + nv; }
+
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum_tr(double (&v)[NV], double* lds) {
+    constexpr int SP = tr_stride(NV), P = tr_parts(NT, NV), PER = NT / P;
+    static_assert(NV * P <= NT && NT % P == 0, "block_sum_tr: too many values for the block");
+    static_assert(NT % kWave == 0, "block_sum_tr: groups of whole waves");
+    const int t = (int)(threadIdx.x % NT);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) lds[t * SP + j] = v[j];
+    __syncthreads();
+    if (t < NV * P) {            // whole groups of P lanes: the DPP moves stay inside a group
+        const int j = t / P, part = t % P;
+        double x[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) x[i] = lds[(part + P * i) * SP + j];
+#pragma unroll
+        for (int w = PER / 2; w >= 1; w /= 2) {
+#pragma unroll
+            for (int i = 0; i < w; ++i) x[i] += x[i + w];
+        }
+        double s = x[0];
+        s = dpp_add<0xB1, 0xf>(s);                      // quad_perm [1,0,3,2]
+        s = dpp_add<0x4E, 0xf>(s);                      // quad_perm [2,3,0,1]
+        if constexpr (P >= 8) s = dpp_add<0x141, 0xf>(s);  // row_half_mirror
+        if constexpr (P >= 16) s = dpp_add<0x140, 0xf>(s); // row_mirror
+        if (part == 0) lds[NT * SP + j] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = lds[NT * SP + j];
+}
+
 // order-preserving bit patterns of non-negative floats / doubles
 __device__ __forceinline__ unsigned fbits(float x) { return __float_as_uint(x); }
 __device__ __forceinline__ float bitsf(unsigned u) { return __uint_as_float(u); }
@@ -337,6 +384,7 @@ namespace act {
 void select_shape(act_plan_s* p, int batch);
 long long grid_cap(const act_plan_s* p, int def);
 int device_cus();
+int device_lds_per_block();   // bytes of LDS one workgroup may hold
 // search launchers (act_search.hip)
 act_status launch_search(act_plan_s* p, int batch, int pass, hipStream_t s);
 act_status launch_correlate(act_plan_s* p, int batch, const double* resid, long long begin,

@@ -406,7 +406,7 @@ __device__ __forceinline__ void atom_terms_f32(double tau64, double c, double fc
     e = expf(-0.5f * u * u);
 }
 
-// Visits this thread's samples k = k0 + threadIdx.x + TB j of [k0, k1) with
+// Visits this thread's samples k = k0 + (threadIdx.x mod TB) + TB j of [k0, k1) with
 // (k, tau, E, cos phi, sin phi).  A window of at least 4 TB samples advances
 // E and exp(i phi) from the thread's first sample by product recurrences over
 // the step H = TB / fs:
@@ -421,10 +421,11 @@ __device__ __forceinline__ void atom_terms_f32(double tau64, double c, double fc
 template <int TB, typename F>
 __device__ __forceinline__ void walk_atom(int k0, int k1, double fs, const double th[4], double inv_dt, F&& visit) {
     const double c = th[2], fc = th[1];
-    const int k = k0 + (int)threadIdx.x;
+    const double ifs = 1.0 / fs;   // tau = k/fs - t_c as k (1/fs) - t_c: no division per sample
+    const int k = k0 + (int)(threadIdx.x % TB);   // TB threads per group (the block may hold several)
     if (k1 - k0 >= 4 * TB) {
         const double H = (double)TB / fs, idt2 = inv_dt * inv_dt;
-        const double tau0 = sample_time(k, fs) - th[0];
+        const double tau0 = fma((double)k, ifs, -th[0]);
         const double u = tau0 * inv_dt;
         double e = exp(-0.5 * u * u);
         double rho = exp(-0.5 * (2.0 * tau0 * H + H * H) * idt2);
@@ -435,7 +436,7 @@ __device__ __forceinline__ void walk_atom(int k0, int k1, double fs, const doubl
         sincospi(4.0 * c * H * H, &vs, &vc);
 #pragma unroll 1
         for (int kk = k; kk < k1; kk += TB) {
-            visit(kk, sample_time(kk, fs) - th[0], e, co, si);
+            visit(kk, fma((double)kk, ifs, -th[0]), e, co, si);
             e *= rho;
             rho *= q;
             const double co2 = co * wc - si * ws;
@@ -448,7 +449,7 @@ __device__ __forceinline__ void walk_atom(int k0, int k1, double fs, const doubl
     } else {
 #pragma unroll 1
         for (int kk = k; kk < k1; kk += TB) {
-            const double tau = sample_time(kk, fs) - th[0];
+            const double tau = fma((double)kk, ifs, -th[0]);
             const double u = tau * inv_dt;
             const double e = exp(-0.5 * u * u);
             double si, co;
@@ -458,46 +459,123 @@ __device__ __forceinline__ void walk_atom(int k0, int k1, double fs, const doubl
     }
 }
 
-// Sums of the objective: {<r,g>, <g,g>, <r,d_j g> (4), <g,d_j g> (4)}, over every
-// sample or (WINDOW) over the support window.
-template <int TB, bool WINDOW = false>
+// walk_atom for callers that need only g = E cos phi and E sin phi: the
+// product z = E exp(i phi) = exp(a tau^2 + b tau), a = -1/(2 dt^2) + 2 pi i c,
+// b = 2 pi i f_c, advances by complex factors,
+//   z(tau + H) = z(tau) w(tau),  w(tau) = exp(a (2 tau H + H^2) + b H),
+//   w(tau + H) = w(tau) v,       v = exp(2 a H^2),
+// (|w| and arg w are the rho and psi of walk_atom, |v| and arg v its
+// exp(-H^2/dt^2) and 4 pi c H^2): two complex products per sample, and no
+// separate envelope.  The window rule, ranges and rounding are walk_atom's.
+// visit(k, tau, E cos phi, E sin phi).
+template <int TB, typename F>
+__device__ __forceinline__ void walk_chirp(int k0, int k1, double fs, const double th[4], double inv_dt,
+                                           F&& visit) {
+    const double c = th[2], fc = th[1];
+    const double ifs = 1.0 / fs;
+    const int k = k0 + (int)(threadIdx.x % TB);
+    if (k1 - k0 >= 4 * TB) {
+        const double H = (double)TB / fs, idt2 = inv_dt * inv_dt;
+        const double tau0 = fma((double)k, ifs, -th[0]);
+        const double u = tau0 * inv_dt;
+        const double e = exp(-0.5 * u * u);
+        const double rho = exp(-0.5 * (2.0 * tau0 * H + H * H) * idt2);
+        const double q = exp(-H * H * idt2);
+        double si, co, ws, wc, vs, vc;
+        sincospi(2.0 * (c * tau0 * tau0 + fc * tau0), &si, &co);
+        sincospi(2.0 * (c * (2.0 * tau0 * H + H * H) + fc * H), &ws, &wc);
+        sincospi(4.0 * c * H * H, &vs, &vc);
+        double zr = e * co, zi = e * si, wr = rho * wc, wi = rho * ws;
+        const double vr = q * vc, vi = q * vs;
+#pragma unroll 1
+        for (int kk = k; kk < k1; kk += TB) {
+            visit(kk, fma((double)kk, ifs, -th[0]), zr, zi);
+            const double zr2 = zr * wr - zi * wi;
+            zi = zr * wi + zi * wr;
+            zr = zr2;
+            const double wr2 = wr * vr - wi * vi;
+            wi = wr * vi + wi * vr;
+            wr = wr2;
+        }
+    } else {
+#pragma unroll 1
+        for (int kk = k; kk < k1; kk += TB) {
+            const double tau = fma((double)kk, ifs, -th[0]);
+            const double u = tau * inv_dt;
+            const double e = exp(-0.5 * u * u);
+            double si, co;
+            sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
+            visit(kk, tau, e * co, e * si);
+        }
+    }
+}
+
+// Sums of the objective over every sample: {<r,g>, <g,g>, <r,d_j g> (4),
+// <g,d_j g> (4)}.
+template <int TB>
 __device__ void sums_obj(const double* __restrict__ r, int n, double fs, const double th[4],
                          double (&acc)[10], double* red) {
     const double inv_dt = 1.0 / exp(th[3]);
 #pragma unroll
     for (int j = 0; j < 10; ++j) acc[j] = 0.0;
-    if (WINDOW) {
-        int k0, k1;
-        support_window(n, fs, th, k0, k1);
-        const double idt2 = inv_dt * inv_dt;
-        walk_atom<TB>(k0, k1, fs, th, inv_dt, [&](int k, double tau, double e, double co, double si) {
-            double gk, d[4];
-            terms_from(tau, th[1], th[2], idt2, e, co, si, gk, d);
-            const double rk = r[k];
-            acc[0] += rk * gk;
-            acc[1] += gk * gk;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc[2 + j] += rk * d[j];
-                acc[6 + j] += gk * d[j];
-            }
-        });
-    } else {
 #pragma unroll 1
-        for (int k = threadIdx.x; k < n; k += TB) {
-            double gk, d[4];
-            atom_terms64(sample_time(k, fs) - th[0], th[1], th[2], inv_dt, gk, d);
-            const double rk = r[k];
-            acc[0] += rk * gk;
-            acc[1] += gk * gk;
+    for (int k = threadIdx.x; k < n; k += TB) {
+        double gk, d[4];
+        atom_terms64(sample_time(k, fs) - th[0], th[1], th[2], inv_dt, gk, d);
+        const double rk = r[k];
+        acc[0] += rk * gk;
+        acc[1] += gk * gk;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc[2 + j] += rk * d[j];
-                acc[6 + j] += gk * d[j];
-            }
+        for (int j = 0; j < 4; ++j) {
+            acc[2 + j] += rk * d[j];
+            acc[6 + j] += gk * d[j];
         }
     }
     block_sum<TB, 10>(acc, red);
+}
+
+// The same ten sums over the support window, accumulated as moments in tau:
+// with g = E C, the quadrature part E S, and x one of the products
+// {r g, r E S, g g, g E S}, the twelve sums M_m(x) = sum x tau^m (m = 0, 1, 2)
+// give
+//   <r, d_tc g> = M_1(r g)/dt^2 + 2 pi (2 c M_1(r E S) + f_c M_0(r E S)),
+//   <r, d_fc g> = -2 pi M_1(r E S),   <r, d_c g> = -2 pi M_2(r E S),
+//   <r, d_logdt g> = M_2(r g)/dt^2,
+// and <g, d_j g> alike from (g g, g E S): the per-sample terms of terms_from
+// regrouped (three operations per product, tau^2 formed once), about half
+// the operations per sample.  `red` must hold block_sum_tr_lds(TB, 12)
+// doubles.
+template <int TB>
+__device__ void sums_obj_win(const double* __restrict__ r, int n, double fs, const double th[4],
+                             double (&acc)[10], double* red) {
+    const double inv_dt = 1.0 / exp(th[3]);
+    int k0, k1;
+    support_window(n, fs, th, k0, k1);
+    double m[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) m[j] = 0.0;
+    walk_chirp<TB>(k0, k1, fs, th, inv_dt, [&](int k, double tau, double gk, double es) {
+        const double rk = r[k], t2 = tau * tau;
+        const double x[4] = {rk * gk, rk * es, gk * gk, gk * es};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            m[3 * q] += x[q];
+            m[3 * q + 1] = fma(x[q], tau, m[3 * q + 1]);
+            m[3 * q + 2] = fma(x[q], t2, m[3 * q + 2]);
+        }
+    });
+    block_sum_tr<TB, 12>(m, red);
+    const double idt2 = inv_dt * inv_dt, c2 = 2.0 * th[2], fc = th[1];
+    acc[0] = m[0];
+    acc[1] = m[6];
+    acc[2] = m[1] * idt2 + kTwoPi * (c2 * m[4] + fc * m[3]);
+    acc[3] = -kTwoPi * m[4];
+    acc[4] = -kTwoPi * m[5];
+    acc[5] = m[2] * idt2;
+    acc[6] = m[7] * idt2 + kTwoPi * (c2 * m[10] + fc * m[9]);
+    acc[7] = -kTwoPi * m[10];
+    acc[8] = -kTwoPi * m[11];
+    acc[9] = m[8] * idt2;
 }
 
 // The same ten sums in FP32 arithmetic from an FP32 residual, over the
@@ -513,13 +591,14 @@ __device__ void sums_obj32(const float* __restrict__ r, int n, double fs, const 
     const float inv_dt = (float)(1.0 / exp(th[3]));
     const float idt2 = inv_dt * inv_dt;
     const float twopi = 6.2831853071795865f, fcf = (float)fc, cf = (float)c;
+    const double ifs = 1.0 / fs;
     float a[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) a[j] = 0.0f;
 #pragma unroll 1
-    for (int k = k0 + (int)threadIdx.x; k < k1; k += TB) {
+    for (int k = k0 + (int)(threadIdx.x % TB); k < k1; k += TB) {
         float e, co, si, tau;
-        atom_terms_f32(sample_time(k, fs) - tc, c, fc, inv_dt, e, co, si, tau);
+        atom_terms_f32(fma((double)k, ifs, -tc), c, fc, inv_dt, e, co, si, tau);
         const float gk = e * co, es = e * si;
         const float d0 = e * (tau * idt2 * co) + twopi * (2.0f * cf * tau + fcf) * es;
         const float d1 = -twopi * tau * es;
@@ -539,7 +618,7 @@ __device__ void sums_obj32(const float* __restrict__ r, int n, double fs, const 
     }
 #pragma unroll
     for (int j = 0; j < 10; ++j) acc[j] = (double)a[j];
-    block_sum<TB, 10>(acc, red);
+    block_sum_tr<TB, 10>(acc, red);
 }
 
 // J = s^2/q and dJ/dtheta_j = 2 s <r, d_j g>/q - 2 s^2 <g, d_j g>/q^2.
@@ -549,9 +628,10 @@ __device__ __forceinline__ double obj_from_sums(const double acc[10], double gra
         grad[0] = grad[1] = grad[2] = grad[3] = 0.0;
         return 0.0;
     }
+    const double sq = s * (1.0 / q);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) grad[j] = 2.0 * s * acc[2 + j] / q - 2.0 * s * s * acc[6 + j] / (q * q);
-    return s * s / q;
+    for (int j = 0; j < 4; ++j) grad[j] = 2.0 * sq * (acc[2 + j] - sq * acc[6 + j]);
+    return s * sq;
 }
 
 template <int TB>
@@ -582,7 +662,7 @@ __device__ void sums_scales(int n, double fs, const double th[4], double (&acc)[
             acc[5 + j] += d[j] * d[j];
         }
     });
-    block_sum<TB, 9>(acc, red);
+    block_sum_tr<TB, 9>(acc, red);
 }
 
 __device__ __forceinline__ double dot4(const double* a, const double* b) {
@@ -624,7 +704,7 @@ __device__ void sums_obj_cplx(const double* __restrict__ r, int n, double fs, co
         acc[11] += 2.0 * e * de0;
         acc[12] += 2.0 * e * de3;
     });
-    block_sum<TB, 13>(acc, red);
+    block_sum_tr<TB, 13>(acc, red);
 }
 
 // Coordinate scales for complex atoms: the metric of the unit complex atom
@@ -640,9 +720,10 @@ __device__ void sums_scales_cplx(int n, double fs, const double th[4], double (&
     for (int j = 0; j < 13; ++j) acc[j] = 0.0;
     int k0, k1;
     support_window(n, fs, th, k0, k1);
+    const double ifs = 1.0 / fs;
 #pragma unroll 1
-    for (int k = k0 + threadIdx.x; k < k1; k += TB) {
-        const double tau = sample_time(k, fs) - th[0];
+    for (int k = k0 + (int)(threadIdx.x % TB); k < k1; k += TB) {
+        const double tau = fma((double)k, ifs, -th[0]);
         const double u = tau * inv_dt;
         const double e = exp(-0.5 * u * u);
         const double de[4] = {e * tau * idt2, 0.0, 0.0, e * tau * tau * idt2};
@@ -655,7 +736,7 @@ __device__ void sums_scales_cplx(int n, double fs, const double th[4], double (&
             acc[9 + j] += e * e * dp[j];
         }
     }
-    block_sum<TB, 13>(acc, red);
+    block_sum_tr<TB, 13>(acc, red);
 }
 
 __device__ __forceinline__ double obj_cplx_from_sums(const double acc[13], double grad[4]) {
@@ -664,19 +745,21 @@ __device__ __forceinline__ double obj_cplx_from_sums(const double acc[13], doubl
         grad[0] = grad[1] = grad[2] = grad[3] = 0.0;
         return 0.0;
     }
-    const double J = (a * a + b * b) / q;
+    const double iq = 1.0 / q;
+    const double J = (a * a + b * b) * iq;
     const double dq[4] = {acc[11], 0.0, 0.0, acc[12]};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) grad[j] = (2.0 * a * acc[3 + j] + 2.0 * b * acc[7 + j]) / q - J * dq[j] / q;
+    for (int j = 0; j < 4; ++j) grad[j] = (2.0 * a * acc[3 + j] + 2.0 * b * acc[7 + j] - J * dq[j]) * iq;
     return J;
 }
 
 // --------------------------------------------------------------------------
 // Limited-memory BFGS refinement, block-wide.
 //
-// Every thread runs the same scalar iteration on identical block-reduced
-// values (so control flow is uniform and no thread waits for a controller);
-// the pair memory lives in LDS and only thread 0 writes it.  Specification
+// Every thread runs the same iteration on identical block-reduced values (so
+// control flow is uniform and no thread waits for a controller); each lane
+// keeps one component of the 4-vectors and of the pair memory in registers.
+// Specification
 // (identical to the oracle): coordinates u_j = (theta_j - theta0_j)/s_j with
 // s_j = min(step_j, 1/sqrt(G_jj)), G_jj the Fisher metric of the unit atom
 // along theta_j (axes with one grid value or G_jj <= 0 are frozen); minimise
@@ -691,10 +774,6 @@ __device__ __forceinline__ double obj_cplx_from_sums(const double acc[13], doubl
 // slope test 0.9 dec <= dnew <= -0.8 dec; at most `steps` iterations; the
 // result is kept only if J does not drop.
 // --------------------------------------------------------------------------
-struct RefineLds {
-    double S[8][4], Y[8][4], RHO[8];
-};
-
 // The prior ACT's objective (contrast mode): J = <s, g>^2 with the
 // un-normalised atom P w (P^2 = 1/(sqrt(pi) dt), w the raw atom), so
 // dJ/dtheta_j = 2 P^2 <s,w> <s, d_j w>, plus -J along ln dt.
@@ -713,14 +792,50 @@ __device__ __forceinline__ double obj_prior_from_sums(const double acc[10], doub
 // 3 = the residue-based ACT's J with FP32 arithmetic (FP32 residual)
 enum { kObjReal = 0, kObjPrior = 1, kObjComplex = 2, kObjReal32 = 3 };
 
+// ---- the refinement's 4-parameter vectors, one component per lane: lane j
+// of every quad holds component j = lane & 3 (every quad of the block holds
+// the same vector, so control flow stays uniform).  A dot product is the
+// quad's sum (x0 + x1) + (x2 + x3), which every lane of the quad computes
+// with the same bits (IEEE addition commutes); maxima likewise.
+__device__ __forceinline__ int qcomp() { return (int)(threadIdx.x & 3); }
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double quad_sum(double x) {
+    x = x + dpp_mov64<0xB1>(x);     // quad_perm [1,0,3,2]
+    return x + dpp_mov64<0x4E>(x);  // quad_perm [2,3,0,1]
+}
+
+__device__ __forceinline__ double quad_max(double x) {
+    x = fmax(x, dpp_mov64<0xB1>(x));
+    return fmax(x, dpp_mov64<0x4E>(x));
+}
+
+// component K of the quad's vector, in every lane
+template <int K>
+__device__ __forceinline__ double quad_get(double x) {
+    return dpp_mov64<K | (K << 2) | (K << 4) | (K << 6)>(x);
+}
+
+__device__ __forceinline__ double sel4(const double* v, int j) {
+    return j == 0 ? v[0] : j == 1 ? v[1] : j == 2 ? v[2] : v[3];
+}
+
+// f = -J at theta = theta0 + h u, and this lane's component of df/du
+// (theta0, h and u given by this lane's components).
 template <int TB, int MODE = kObjReal, typename RT = double>
-__device__ __forceinline__ double refine_eval(const RT* r, const GridDev& g, const double th0[4],
-                                              const double h[4], const double u[4], double gu[4],
-                                              double* red) {
+__device__ __forceinline__ double refine_eval(const RT* r, const GridDev& g, double th0j, double hj, double uj,
+                                              double& guj, double* red) {
     static_assert((MODE == kObjReal32) == std::is_same<RT, float>::value, "FP32 residuals go with kObjReal32");
-    double th[4], gr[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) th[j] = th0[j] + h[j] * u[j];
+    const double thj = th0j + hj * uj;
+    const double th[4] = {quad_get<0>(thj), quad_get<1>(thj), quad_get<2>(thj), quad_get<3>(thj)};
+    double gr[4];
     double J;
     if constexpr (MODE == kObjReal32) {
         double acc[10];
@@ -732,24 +847,29 @@ __device__ __forceinline__ double refine_eval(const RT* r, const GridDev& g, con
         J = obj_cplx_from_sums(acc, gr);
     } else {
         double acc[10];
-        sums_obj<TB, true>(r, g.n, g.fs, th, acc, red);
+        sums_obj_win<TB>(r, g.n, g.fs, th, acc, red);
         J = MODE == kObjPrior ? obj_prior_from_sums(acc, 1.0 / exp(th[3]), gr) : obj_from_sums(acc, gr);
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) gu[j] = -h[j] * gr[j];
+    guj = -hj * sel4(gr, qcomp());
     return -J;
 }
 
 // FP32 objectives (kObjReal32) resolve J and its gradient to about 1e-7
 // relative instead of 1e-16: the stopping gradient and the approximate-Wolfe
 // tolerance on f follow that working precision.
+// The L-BFGS state is per lane (component j): u, the gradient, the direction,
+// the box in scaled coordinates, and the 8 newest (s, y) pairs in registers,
+// newest first; 1/(s'y) is uniform.
+// `red` must hold block_sum_tr_lds(TB, 13) doubles.
 template <int TB, int MODE = kObjReal, typename RT = double>
 __device__ int refine_block(const RT* __restrict__ r, const GridDev& g, const BoxDev& box,
                             const double th0[4], int steps, double th_out[4], double* J_out,
-                            double* red, RefineLds& L) {
+                            double* red) {
     constexpr double kStopTol = MODE == kObjReal32 ? 1e-6 : 1e-11;
     constexpr double kWolfeF = MODE == kObjReal32 ? 1e-6 : 1e-12;
-    double h[4], blo[4], bhi[4], u[4] = {0, 0, 0, 0}, gcur[4];
+    const int j = qcomp();
+    const double th0j = sel4(th0, j);
+    double hj, bloj, bhij;
     int flags = 0;
     {
         double Gd[4];
@@ -758,104 +878,74 @@ __device__ int refine_block(const RT* __restrict__ r, const GridDev& g, const Bo
             sums_scales_cplx<TB>(g.n, g.fs, th0, acc, red);
             const double q = acc[0];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                Gd[j] = q > 0.0 ? (acc[1 + j] - (acc[5 + j] * acc[5 + j] + acc[9 + j] * acc[9 + j]) / q) / q : 0.0;
+            for (int k = 0; k < 4; ++k)
+                Gd[k] = q > 0.0 ? (acc[1 + k] - (acc[5 + k] * acc[5 + k] + acc[9 + k] * acc[9 + k]) / q) / q : 0.0;
         } else {
             double acc[9];
             sums_scales<TB>(g.n, g.fs, th0, acc, red);
             const double q = acc[0];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) Gd[j] = q > 0.0 ? (acc[5 + j] - acc[1 + j] * acc[1 + j] / q) / q : 0.0;
+            for (int k = 0; k < 4; ++k) Gd[k] = q > 0.0 ? (acc[5 + k] - acc[1 + k] * acc[1 + k] / q) / q : 0.0;
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double G = Gd[j];
-            if (!(box.hi[j] > box.lo[j]) || !(G > 0.0)) {
-                h[j] = 0.0;
-            } else {
-                const double rr = 1.0 / sqrt(G);
-                h[j] = rr < box.step[j] ? rr : box.step[j];
-            }
-            blo[j] = h[j] == 0.0 ? 0.0 : (box.lo[j] - th0[j]) / h[j];
-            bhi[j] = h[j] == 0.0 ? 0.0 : (box.hi[j] - th0[j]) / h[j];
+        const double G = sel4(Gd, j), loj = sel4(box.lo, j), hij = sel4(box.hi, j), stj = sel4(box.step, j);
+        if (!(hij > loj) || !(G > 0.0)) {
+            hj = 0.0;
+        } else {
+            const double rr = 1.0 / sqrt(G);
+            hj = rr < stj ? rr : stj;
         }
+        bloj = hj == 0.0 ? 0.0 : (loj - th0j) / hj;
+        bhij = hj == 0.0 ? 0.0 : (hij - th0j) / hj;
     }
-    double f = refine_eval<TB, MODE, RT>(r, g, th0, h, u, gcur, red);
+    double uj = 0.0, gj;
+    double f = refine_eval<TB, MODE, RT>(r, g, th0j, hj, uj, gj, red);
     const double f0 = f;
-    int nmem = 0, head = 0;
-    for (int it = 0; it < steps; ++it) {
-        double pg[4], pgmax = 0.0;
+    double S[8], Y[8], RHO[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            pg[j] = gcur[j];
-            if (u[j] <= blo[j] && gcur[j] > 0.0) pg[j] = 0.0;
-            if (u[j] >= bhi[j] && gcur[j] < 0.0) pg[j] = 0.0;
-            pgmax = fmax(pgmax, fabs(pg[j]));
-        }
+    for (int t = 0; t < 8; ++t) S[t] = Y[t] = RHO[t] = 0.0;
+    int nmem = 0;
+    for (int it = 0; it < steps; ++it) {
+        double pgj = gj;
+        if (uj <= bloj && gj > 0.0) pgj = 0.0;
+        if (uj >= bhij && gj < 0.0) pgj = 0.0;
+        const double pgmax = quad_max(fabs(pgj));
         const double Jc = -f;
         if (pgmax <= kStopTol * (Jc > 1.0 ? Jc : 1.0)) break;
-        // two-loop recursion, newest pair first; the alphas are recomputed in
-        // the second loop's order from a small register array
-        double d[4], al[8];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) d[j] = -gcur[j];
+        // two-loop recursion, newest pair first
+        double dj = -gj, al[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
+            al[t] = 0.0;
             if (t < nmem) {
-                const int slot = (head - 1 - t + 8) & 7;
-                const double a = L.RHO[slot] * dot4(L.S[slot], d);
+                const double a = RHO[t] * quad_sum(S[t] * dj);
                 al[t] = a;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) d[j] -= a * L.Y[slot][j];
+                dj -= a * Y[t];
             }
         }
-        double gamma = 1.0;
-        if (nmem > 0) {
-            const int nw = (head - 1 + 8) & 7;
-            gamma = dot4(L.S[nw], L.Y[nw]) / dot4(L.Y[nw], L.Y[nw]);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) d[j] *= gamma;
+        if (nmem > 0) dj *= quad_sum(S[0] * Y[0]) / quad_sum(Y[0] * Y[0]);
 #pragma unroll
         for (int t = 7; t >= 0; --t) {
             if (t < nmem) {
-                const int slot = (head - 1 - t + 8) & 7;
-                const double bb = L.RHO[slot] * dot4(L.Y[slot], d);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) d[j] += (al[t] - bb) * L.S[slot][j];
+                const double bb = RHO[t] * quad_sum(Y[t] * dj);
+                dj += (al[t] - bb) * S[t];
             }
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (h[j] == 0.0) d[j] = 0.0;
-            if (u[j] <= blo[j] && d[j] < 0.0) d[j] = 0.0;
-            if (u[j] >= bhi[j] && d[j] > 0.0) d[j] = 0.0;
-        }
-        if (dot4(gcur, d) >= 0.0) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) d[j] = -pg[j];
-        }
-        double dmax = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) dmax = fmax(dmax, fabs(d[j]));
+        if (hj == 0.0) dj = 0.0;
+        if (uj <= bloj && dj < 0.0) dj = 0.0;
+        if (uj >= bhij && dj > 0.0) dj = 0.0;
+        if (quad_sum(gj * dj) >= 0.0) dj = -pgj;
+        const double dmax = quad_max(fabs(dj));
         double alpha = nmem > 0 ? 1.0 : (dmax > 1.0 ? 1.0 / dmax : 1.0);
-        double un[4], gn[4], fn = 0.0;
+        double unj = uj, gnj = gj, fn = 0.0;
         bool ok = false;
         for (int t = 0; t < 30; ++t) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                double v = u[j] + alpha * d[j];
-                v = v < blo[j] ? blo[j] : v;
-                v = v > bhi[j] ? bhi[j] : v;
-                un[j] = v;
-            }
-            fn = refine_eval<TB, MODE, RT>(r, g, th0, h, un, gn, red);
-            double dec = 0.0, dnew = 0.0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                dec += gcur[j] * (un[j] - u[j]);
-                dnew += gn[j] * (un[j] - u[j]);
-            }
+            double v = uj + alpha * dj;
+            v = v < bloj ? bloj : v;
+            v = v > bhij ? bhij : v;
+            unj = v;
+            fn = refine_eval<TB, MODE, RT>(r, g, th0j, hj, unj, gnj, red);
+            const double dec = quad_sum(gj * (unj - uj));
+            const double dnew = quad_sum(gnj * (unj - uj));
             const bool armijo = fn <= f + 1e-4 * dec;
             const bool approx_wolfe = fn <= f + kWolfeF * fabs(f) && dnew >= 0.9 * dec && dnew <= -0.8 * dec;
             if (dec < 0.0 && (armijo || approx_wolfe)) {
@@ -865,40 +955,34 @@ __device__ int refine_block(const RT* __restrict__ r, const GridDev& g, const Bo
             alpha *= 0.5;
         }
         if (!ok) break;
-        double sv[4], yv[4];
+        const double svj = unj - uj, yvj = gnj - gj;
+        const double sy = quad_sum(svj * yvj);
+        if (sy > 1e-12 * sqrt(quad_sum(svj * svj)) * sqrt(quad_sum(yvj * yvj))) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            sv[j] = un[j] - u[j];
-            yv[j] = gn[j] - gcur[j];
-        }
-        const double sy = dot4(sv, yv);
-        if (sy > 1e-12 * sqrt(dot4(sv, sv)) * sqrt(dot4(yv, yv))) {
-            if (threadIdx.x == 0) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    L.S[head][j] = sv[j];
-                    L.Y[head][j] = yv[j];
-                }
-                L.RHO[head] = 1.0 / sy;
+            for (int t = 7; t > 0; --t) {
+                S[t] = S[t - 1];
+                Y[t] = Y[t - 1];
+                RHO[t] = RHO[t - 1];
             }
-            __syncthreads();
-            head = (head + 1) & 7;
+            S[0] = svj;
+            Y[0] = yvj;
+            RHO[0] = 1.0 / sy;
             if (nmem < 8) ++nmem;
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            u[j] = un[j];
-            gcur[j] = gn[j];
-        }
+        uj = unj;
+        gj = gnj;
         f = fn;
     }
     if (-f >= -f0) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) th_out[j] = th0[j] + h[j] * u[j];
+        const double thj = th0j + hj * uj;
+        th_out[0] = quad_get<0>(thj);
+        th_out[1] = quad_get<1>(thj);
+        th_out[2] = quad_get<2>(thj);
+        th_out[3] = quad_get<3>(thj);
         *J_out = -f;
     } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) th_out[j] = th0[j];
+        for (int k = 0; k < 4; ++k) th_out[k] = th0[k];
         *J_out = -f0;
         flags |= ACT_FLAG_REFINE_REJECTED;
     }
@@ -912,14 +996,18 @@ constexpr int NTR = 256;            // threads of the refinement kernels at up t
                                     // (fastest measured; larger batches use 128)
 constexpr int NWR = NTR / kWave;
 
-template <int TB>
+// CPLX: complex atoms (instantiated apart, so that each kernel carries only
+// its own refinement: the two together exceed the instruction cache).
+// STAGE: the refinement reads the channel's residual from a copy in dynamic
+// LDS (n doubles; the launch passes that size) instead of global memory.
+template <int TB, bool CPLX, bool STAGE>
 __global__ void __launch_bounds__(TB) k_select_refine_update(
     PlanDev P, int k, int order, int steps, double* __restrict__ resid, double* __restrict__ approx,
     double* __restrict__ theta, double* __restrict__ coef, long long* __restrict__ index,
     double* __restrict__ energy, double* __restrict__ gap, int* __restrict__ flags) {
     constexpr int NWB = TB / kWave;
-    __shared__ double red[block_sum_lds(TB, 13)];
-    __shared__ RefineLds L;
+    extern __shared__ double s_dyn[];
+    __shared__ double red[block_sum_tr_lds(TB, 13)];
     __shared__ double s_a1[NWB], s_a2[NWB];
     __shared__ unsigned s_i1[NWB];
     const int b = blockIdx.x;
@@ -940,7 +1028,7 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
         if (threadIdx.x == 0) {
             const double nan = __longlong_as_double(0x7ff8000000000000LL);
             for (int j = 0; j < 4; ++j) theta[o * 4 + j] = nan;
-            if (P.cplx) {
+            if (CPLX) {
                 coef[2 * o] = 0.0;
                 coef[2 * o + 1] = 0.0;
             } else {
@@ -1027,17 +1115,26 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
         box.hi[0] = cg.box_hi0;
     }
     if (steps > 0) {
-        if (P.cplx)
-            fl |= refine_block<TB, kObjComplex>(r, G, box, th0, steps, th, &J, red, L);
-        else
-            fl |= refine_block<TB>(r, G, box, th0, steps, th, &J, red, L);
+        if constexpr (STAGE) {
+            for (int t = threadIdx.x; t < G.n; t += TB) s_dyn[t] = r[t];
+            __syncthreads();
+            if constexpr (CPLX)
+                fl |= refine_block<TB, kObjComplex>(s_dyn, G, box, th0, steps, th, &J, red);
+            else
+                fl |= refine_block<TB>(s_dyn, G, box, th0, steps, th, &J, red);
+        } else {
+            if constexpr (CPLX)
+                fl |= refine_block<TB, kObjComplex>(r, G, box, th0, steps, th, &J, red);
+            else
+                fl |= refine_block<TB>(r, G, box, th0, steps, th, &J, red);
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) th[j] = th0[j];
     }
 
     const double inv_dt = 1.0 / exp(th[3]);
-    if (P.cplx) {
+    if constexpr (CPLX) {
         // complex atom: amplitudes (alpha, beta) of u = E cos phi and v = E sin
         // phi by least squares, r -= alpha u + beta v (a pair that is singular
         // to working precision falls back to the fit on u alone)
@@ -1084,24 +1181,30 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
         return;
     }
 
-    // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4))
-    double acc[1] = {0.0};
+    // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4)):
+    // |w|^2 and <w, r> of the raw atom w in one pass, c = <w, r>/|w|,
+    // r -= c w/|w|.  A staged kernel keeps w in the LDS copy of the residual
+    // (the refinement, which read it, has passed its last barrier; each thread
+    // reads back only the samples it wrote).
+    const double ifs = 1.0 / G.fs;
+    double acc[2] = {0.0, 0.0};
     for (int t = threadIdx.x; t < G.n; t += TB) {
-        const double v = atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt);
+        const double v = atom_sample64((double)t * ifs, th[0], th[1], th[2], inv_dt);
+        if constexpr (STAGE) s_dyn[t] = v;
         acc[0] += v * v;
+        acc[1] += v * r[t];
     }
-    block_sum<TB, 1>(acc, red);
+    block_sum<TB, 2>(acc, red);
     const double nrm = sqrt(acc[0]);
-    const bool ok = nrm >= 1e-300;
-    acc[0] = 0.0;
+    const double inrm = nrm >= 1e-300 ? 1.0 / nrm : 0.0;
+    const double ck = acc[1] * inrm;
     for (int t = threadIdx.x; t < G.n; t += TB) {
-        const double v = ok ? atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
-        acc[0] += v * r[t];
-    }
-    block_sum<TB, 1>(acc, red);
-    const double ck = acc[0];
-    for (int t = threadIdx.x; t < G.n; t += TB) {
-        const double v = ok ? atom_sample64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt) / nrm : 0.0;
+        double w;
+        if constexpr (STAGE)
+            w = s_dyn[t];
+        else
+            w = atom_sample64((double)t * ifs, th[0], th[1], th[2], inv_dt);
+        const double v = w * inrm;
         r[t] = r[t] - ck * v;
         if (approx) approx[cg.off + t] = approx[cg.off + t] + ck * v;
     }
@@ -1121,21 +1224,31 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
 // --------------------------------------------------------------------------
 // refinement alone, forward/adjoint alone, reconstruction
 // --------------------------------------------------------------------------
-template <int MODE, int TB, typename RT = double>
+// STAGE: the pair's residual is read from a copy in dynamic LDS (n values of
+// RT; the launch passes that size).
+template <int MODE, int TB, typename RT, bool STAGE>
 __global__ void __launch_bounds__(TB) k_refine_many(GridDev g, BoxDev box,
                                                      const RT* __restrict__ resid,
                                                      const double* __restrict__ theta0, int steps,
                                                      double* __restrict__ theta,
                                                      double* __restrict__ value,
                                                      int* __restrict__ flags) {
-    __shared__ double red[block_sum_lds(TB, 13)];
-    __shared__ RefineLds L;
+    extern __shared__ double s_dyn[];
+    __shared__ double red[block_sum_tr_lds(TB, 13)];
     const int p = blockIdx.x;
     const RT* r = resid + (size_t)p * g.n;
     double th0[4], th[4], J;
 #pragma unroll
     for (int j = 0; j < 4; ++j) th0[j] = theta0[p * 4 + j];
-    const int fl = refine_block<TB, MODE, RT>(r, g, box, th0, steps, th, &J, red, L);
+    int fl;
+    if constexpr (STAGE) {
+        RT* sr = reinterpret_cast<RT*>(s_dyn);
+        for (int t = threadIdx.x; t < g.n; t += TB) sr[t] = r[t];
+        __syncthreads();
+        fl = refine_block<TB, MODE, RT>(sr, g, box, th0, steps, th, &J, red);
+    } else {
+        fl = refine_block<TB, MODE, RT>(r, g, box, th0, steps, th, &J, red);
+    }
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) theta[p * 4 + j] = th[j];
@@ -1311,6 +1424,16 @@ act_status launch_rescore(act_plan_s* p, int batch, const double* resid, hipStre
     return ACT_OK;
 }
 
+// Whether kernel `kern` with `dyn` bytes of dynamic LDS fits one workgroup.
+static bool lds_fits(const void* kern, size_t dyn) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, kern) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.sharedSizeBytes + dyn <= (size_t)device_lds_per_block();
+}
+
 act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int order, double* resid,
                                        double* approx, double* theta, double* coef,
                                        long long* index, double* energy, double* gap, int* flags,
@@ -1318,40 +1441,54 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
     PlanDev v = view(p);
     v.batch = batch;
     // more than two channels per CU: 128-thread blocks (several per CU keep its
-    // FP64 units busy); otherwise NTR threads (each channel's latency sets the time)
-    if ((long long)batch > 2LL * device_cus())
-        hipLaunchKernelGGL(k_select_refine_update<128>, dim3(batch), dim3(128), 0, s, v, k, order,
-                           p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
-    else
-        hipLaunchKernelGGL(k_select_refine_update<NTR>, dim3(batch), dim3(NTR), 0, s, v, k, order,
-                           p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
+    // FP64 units busy); otherwise NTR threads (each channel's latency sets the
+    // time).  The refinement reads the residual from LDS when the longest
+    // channel fits.
+    const bool small = (long long)batch > 2LL * device_cus();
+    const bool cx = p->desc.complex_atoms != 0;
+    const size_t dyn = (size_t)p->grid.n * sizeof(double);
+    using K = decltype(&k_select_refine_update<NTR, false, false>);
+    static const K kerns[2][2][2] = {   // [small][complex][staged]
+        {{k_select_refine_update<NTR, false, false>, k_select_refine_update<NTR, false, true>},
+         {k_select_refine_update<NTR, true, false>, k_select_refine_update<NTR, true, true>}},
+        {{k_select_refine_update<128, false, false>, k_select_refine_update<128, false, true>},
+         {k_select_refine_update<128, true, false>, k_select_refine_update<128, true, true>}}};
+    const bool stage = p->desc.refine_steps > 0 && lds_fits((const void*)kerns[small][cx][1], dyn);
+    hipLaunchKernelGGL(kerns[small][cx][stage], dim3(batch), dim3(small ? 128 : NTR), stage ? dyn : 0, s, v, k,
+                       order, p->desc.refine_steps, resid, approx, theta, coef, index, energy, gap, flags);
+    ACT_HIP(hipGetLastError());
+    return ACT_OK;
+}
+
+template <int MODE, typename RT>
+static act_status launch_refine_pairs(act_plan_s* p, int m, const RT* resid, const double* theta0, int steps,
+                                      double* theta, double* value, int* flags, hipStream_t s) {
+    // more than two pairs per CU: 128-thread blocks, several per CU, so that
+    // the CU's FP64 units stay busy; otherwise NTR threads per pair (each
+    // pair's own latency sets the time).  The residual is read from LDS when
+    // it fits.
+    const bool many = (long long)m > 2LL * device_cus();
+    const size_t dyn = (size_t)p->grid.n * sizeof(RT);
+    using K = decltype(&k_refine_many<MODE, NTR, RT, false>);
+    K staged = many ? k_refine_many<MODE, 128, RT, true> : k_refine_many<MODE, NTR, RT, true>;
+    K direct = many ? k_refine_many<MODE, 128, RT, false> : k_refine_many<MODE, NTR, RT, false>;
+    const bool stage = lds_fits((const void*)staged, dyn);
+    hipLaunchKernelGGL(stage ? staged : direct, dim3(m), dim3(many ? 128 : NTR), stage ? dyn : 0, s, p->grid,
+                       p->box, resid, theta0, steps, theta, value, flags);
     ACT_HIP(hipGetLastError());
     return ACT_OK;
 }
 
 act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const double* theta0,
                               int steps, double* theta, double* value, int* flags, hipStream_t s) {
-    // more than two pairs per CU: 128-thread blocks, several per CU, so that
-    // the CU's FP64 units stay busy; otherwise NTR threads per pair (each
-    // pair's own latency sets the time)
-    const bool many = (long long)m > 2LL * device_cus();
-    const bool cx = p->desc.complex_atoms != 0;
-    auto kern = many ? (cx ? k_refine_many<kObjComplex, 128> : k_refine_many<kObjReal, 128>)
-                     : (cx ? k_refine_many<kObjComplex, NTR> : k_refine_many<kObjReal, NTR>);
-    hipLaunchKernelGGL(kern, dim3(m), dim3(many ? 128 : NTR), 0, s, p->grid, p->box, resid, theta0, steps, theta,
-                       value, flags);
-    ACT_HIP(hipGetLastError());
-    return ACT_OK;
+    return p->desc.complex_atoms != 0
+               ? launch_refine_pairs<kObjComplex, double>(p, m, resid, theta0, steps, theta, value, flags, s)
+               : launch_refine_pairs<kObjReal, double>(p, m, resid, theta0, steps, theta, value, flags, s);
 }
 
 act_status launch_refine_many_f32(act_plan_s* p, int m, const float* resid, const double* theta0, int steps,
                                   double* theta, double* value, int* flags, hipStream_t s) {
-    const bool many = (long long)m > 2LL * device_cus();
-    auto kern = many ? k_refine_many<kObjReal32, 128, float> : k_refine_many<kObjReal32, NTR, float>;
-    hipLaunchKernelGGL(kern, dim3(m), dim3(many ? 128 : NTR), 0, s, p->grid, p->box, resid, theta0, steps, theta,
-                       value, flags);
-    ACT_HIP(hipGetLastError());
-    return ACT_OK;
+    return launch_refine_pairs<kObjReal32, float>(p, m, resid, theta0, steps, theta, value, flags, s);
 }
 
 act_status launch_value_and_grad(act_plan_s* p, int m, int dtype, const void* resid,
@@ -1445,8 +1582,7 @@ __global__ void __launch_bounds__(NTR) k_prior_select_update(
     double* __restrict__ approx, double* __restrict__ theta, double* __restrict__ coef,
     long long* __restrict__ index, double* __restrict__ energy, double* __restrict__ gap,
     int* __restrict__ flags) {
-    __shared__ double red[block_sum_lds(NTR, 10)];
-    __shared__ RefineLds L;
+    __shared__ double red[block_sum_tr_lds(NTR, 13)];
     __shared__ double s_best[NWR];
     __shared__ long long s_idx[NWR];
     const int b = blockIdx.x;
@@ -1503,7 +1639,7 @@ __global__ void __launch_bounds__(NTR) k_prior_select_update(
     double th0[4], th[4], J = 0.0;
     grid_theta(G, bidx, th0);
     if (steps > 0) {
-        fl |= refine_block<NTR, kObjPrior>(sv, G, P.box, th0, steps, th, &J, red, L);
+        fl |= refine_block<NTR, kObjPrior>(sv, G, P.box, th0, steps, th, &J, red);
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) th[j] = th0[j];
@@ -1626,8 +1762,7 @@ __global__ void __launch_bounds__(NTR) k_lem_order(PlanDev P, LemDev cfg, int k,
                                                    double* __restrict__ resid, double* __restrict__ approx,
                                                    double* __restrict__ theta, double* __restrict__ coef,
                                                    double* __restrict__ energy, int* __restrict__ flags) {
-    __shared__ double red[block_sum_lds(NTR, 10)];
-    __shared__ RefineLds L;
+    __shared__ double red[block_sum_tr_lds(NTR, 13)];
     __shared__ double kept[16][4];
     __shared__ int s_nk;
     const int b = blockIdx.x;
@@ -1694,7 +1829,7 @@ __global__ void __launch_bounds__(NTR) k_lem_order(PlanDev P, LemDev cfg, int k,
     BoxDev box = P.box;
     for (int d = 0; d < 4; ++d) box.step[d] = cfg.step[cfg.levels][d];
     if (steps > 0) {
-        fl |= refine_block<NTR>(r, G, box, th0, steps, th, &J, red, L);
+        fl |= refine_block<NTR>(r, G, box, th0, steps, th, &J, red);
     } else {
         for (int d = 0; d < 4; ++d) th[d] = th0[d];
     }

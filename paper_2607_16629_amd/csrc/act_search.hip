@@ -27,6 +27,17 @@ int device_cus() {
     return cus;
 }
 
+int device_lds_per_block() {
+    static int bytes = 0;
+    if (!bytes) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (bytes <= 0) bytes = 65536;
+    }
+    return bytes;
+}
+
 static act_status dispatch(act_plan_s* p, int batch, hipStream_t s, const SearchCtl& ctl,
                            const double* resid64) {
     if (p->desc.dict == ACT_DICT_LAG) return launch_search_lag(p, batch, ctl, s);
