@@ -487,7 +487,7 @@ __device__ __forceinline__ void walk_chirp(int k0, int k1, double fs, const doub
         sincospi(4.0 * c * H * H, &vs, &vc);
         double zr = e * co, zi = e * si, wr = rho * wc, wi = rho * ws;
         const double vr = q * vc, vi = q * vs;
-#pragma unroll 1
+#pragma unroll 2   // two samples' independent products interleave
         for (int kk = k; kk < k1; kk += TB) {
             visit(kk, fma((double)kk, ifs, -th[0]), zr, zi);
             const double zr2 = zr * wr - zi * wi;

@@ -147,10 +147,11 @@ def assert_decomposition_parity(gpu, ref, grid, oracle, signals, label, refine_s
                 if J_g < J_o - band:
                     # a slower climb on another path: the oracle, continued
                     # from the GPU's end point, must reach the oracle's own
-                    # long-run optimum, and the GPU must have climbed
+                    # long-run optimum (within the same band: both long runs
+                    # may still be climbing), and the GPU must have climbed
                     _, J_cont, _ = oracle.refine(grid, rg, th_g, 10 * max(refine_steps, 1))
                     J_0 = oracle.objective(grid.fs, th0, rg)[0]
-                    assert J_cont >= J_long - (1e-6 * J_long + 1e-9 * sn * sn) and J_g > J_0, \
+                    assert J_cont >= J_long - band and J_g > J_0, \
                         (label, b, k, cond, J_g, J_o, J_long, J_cont, J_0, dth)
                 chain = False
             gu, _ = oracle.atom_unit(grid.fs, grid.n, th_g)
