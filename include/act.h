@@ -339,15 +339,18 @@ typedef struct {
     int32_t chan_per_fc;    /* FP16 synthesis of several channels: channels that share an f_c among a
                                tile's 128 columns (power of two <= 64); 0 for the other searches */
     int32_t from_cache;     /* 1: taken from the cache file without timing */
-    int32_t reserved;
+    int32_t form;           /* lag-table search of real atoms on >= 32 channels: 0 keeps each group of
+                               32 channels' residual copy resident in LDS (where the grid allows it;
+                               grid_per_cu is then unused), 1 stages the residual per tile */
     double ms;              /* mean search time per launch with this shape */
 } act_launch_shape;
 
 /* Autotuner of the batched search's tile and grid shapes (the stacked channels
  * of Sec. V-A and uneven batches): times the plan's pass-0 coarse search on
  * `batch` channels of resid_dev for every candidate shape -- workgroups per CU
- * of the persistent grid and, for the FP16 synthesis of several channels, the
- * channels per f_c of a tile -- `reps` launches each, and keeps the fastest for
+ * of the persistent grid, the lag-table search's form and, for the FP16
+ * synthesis of several channels, the channels per f_c of a tile -- `reps`
+ * launches each, and keeps the fastest for
  * later act_decompose / act_correlate calls with this batch size (captured
  * graphs are rebuilt).
  *   resid_dev, len_dev, off_dev  as act_decompose; read only.  The plan's
@@ -358,7 +361,7 @@ typedef struct {
  *               device, plan shape and batch is applied without timing; a new
  *               choice is appended (one line: device, CU count, dict, prec,
  *               n_samples, axis counts, ragged, divisor, support_cut,
- *               complex_atoms, batch, grid_per_cu, chan_per_fc, ms).
+ *               complex_atoms, batch, grid_per_cu, chan_per_fc, form, ms).
  *   out         the choice, or NULL.
  * Synchronises `stream`.  Errors: ACT_ERR_INVALID (batch outside
  * [1, max_batch], reps outside [1, 100], NULL residual, ragged pointers
@@ -367,6 +370,13 @@ typedef struct {
 act_status act_tune(act_plan_t plan, int32_t batch, const int32_t* len_dev, const int64_t* off_dev,
                     const double* resid_dev, int32_t reps, const char* cache_path, act_launch_shape* out,
                     void* stream);
+
+/* Applies `shape` (grid_per_cu in [1, 64], chan_per_fc in [0, 64], form 0 or
+ * 1; from_cache and ms ignored) to later searches of `batch` channels, as an
+ * act_tune choice would (captured graphs are rebuilt).  Results do not depend
+ * on the shape.  Errors: ACT_ERR_INVALID (NULL plan or shape, batch outside
+ * [1, max_batch], fields outside their ranges). */
+act_status act_set_launch_shape(act_plan_t plan, int32_t batch, const act_launch_shape* shape);
 
 /* Phase timing of act_decompose, for measurement.  While enabled, every
  * launch of each phase of an order -- 0: search, 1: exact-threshold rerun,

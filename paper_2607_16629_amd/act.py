@@ -57,7 +57,7 @@ EXPORTS = ("act_plan", "act_plan_destroy", "act_plan_query", "act_search_flops",
            "act_decompose", "act_lem_decompose", "act_probe_read", "act_probe_mfma", "act_refine_f32",
            "act_lem_decompose_noalloc",
            "act_refine", "act_value_and_grad", "act_reconstruct", "act_correlate", "act_tune",
-           "act_timing_enable", "act_timing_read", "act_status_string", "act_last_error")
+           "act_set_launch_shape", "act_timing_enable", "act_timing_read", "act_status_string", "act_last_error")
 PHASES = ("search", "rerun", "rescore", "select_refine_update")
 
 _lib = None
@@ -65,7 +65,7 @@ _lib = None
 
 class _LaunchShape(ctypes.Structure):
     _fields_ = [("grid_per_cu", ctypes.c_int32), ("chan_per_fc", ctypes.c_int32),
-                ("from_cache", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("from_cache", ctypes.c_int32), ("form", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class _LemDesc(ctypes.Structure):
@@ -127,6 +127,8 @@ def load() -> ctypes.CDLL:
     lib.act_correlate.restype = ctypes.c_int
     lib.act_tune.argtypes = [vp, i32, vp, vp, vp, i32, ctypes.c_char_p, ctypes.POINTER(_LaunchShape), vp]
     lib.act_tune.restype = ctypes.c_int
+    lib.act_set_launch_shape.argtypes = [vp, i32, ctypes.POINTER(_LaunchShape)]
+    lib.act_set_launch_shape.restype = ctypes.c_int
     lib.act_timing_enable.argtypes = [vp, i32]
     lib.act_timing_enable.restype = ctypes.c_int
     lib.act_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64)]
@@ -428,8 +430,13 @@ class Plan:
         shape = _LaunchShape()
         _check(load().act_tune(self._h, B, lp, op, _ptr(resid), int(reps),
                                cache.encode() if cache else None, ctypes.byref(shape), _stream()))
-        return {"grid_per_cu": shape.grid_per_cu, "chan_per_fc": shape.chan_per_fc,
+        return {"grid_per_cu": shape.grid_per_cu, "chan_per_fc": shape.chan_per_fc, "form": shape.form,
                 "from_cache": bool(shape.from_cache), "ms": shape.ms}
+
+    def act_set_launch_shape(self, batch: int, grid_per_cu: int = 1, chan_per_fc: int = 0, form: int = 0):
+        """Applies a search launch shape to later calls with `batch` channels."""
+        shape = _LaunchShape(grid_per_cu=grid_per_cu, chan_per_fc=chan_per_fc, form=form)
+        _check(load().act_set_launch_shape(self._h, int(batch), ctypes.byref(shape)))
 
     def act_correlate(self, resid, begin: int, count: int) -> torch.Tensor:
         resid = _device_tensor(resid, torch.float64).reshape(-1, self.grid.n)

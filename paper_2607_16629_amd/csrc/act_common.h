@@ -320,6 +320,16 @@ struct act_plan_s {
     float* lag_rho = nullptr;  // ragged ACT_DICT_LAG: [256-column blocks][lag_rho_d] bound of |g_full| / |g_w|
     int lag_rho_d = 0;         // ragged ACT_DICT_LAG: distances to the signal end below which lag_rho applies
     int* lag_rows = nullptr;   // ragged ACT_DICT_LAG: per call, [channel groups + 1] prefix of time groups
+    // ACT_DICT_LAG, real atoms of plain plans: the resident-residual search
+    // (lag_rs_cp null when the grid does not allow it)
+    int* lag_rs_cp = nullptr;     // [8][lag_rs_cp_per_x] column pairs per XCD, longest band first
+    int* lag_rs_count = nullptr;  // [8] column pairs per XCD
+    int lag_rs_cp_per_x = 0, lag_rs_ncg = 0;
+    int lag_rs_glo = 0, lag_rs_len = 0, lag_rs_stride = 0;  // LDS copy: guard, samples, row stride
+    int* lag_rs_units = nullptr;  // unit descriptors in list order (k_search_lag_rs)
+    float* lag_rs_map = nullptr;  // [lag_rs_ncg][units][32] pass-0 largest |score| per channel and unit
+    int* lag_rs_pairs = nullptr;  // pass 1: count, then the flagged (unit, channel) map entries
+    long long lag_rs_mfma = 0;    // MFMA instructions of one channel group's units
     std::vector<int> tc_shift_host;  // host copy of tc_shift
     double shift_eps = 0.0;   // synthesised / lag searches: relative score error of rounding the
                               // time centres to integer samples

@@ -355,7 +355,7 @@ static void free_plan(act_plan_s* p) {
     void* ptrs[] = {p->axis_dev, p->inv_norm, p->table, p->fac_u, p->fac_v, p->fac_c, p->fac_s,
                     p->inv_norm32, p->tc_shift, p->lag_energy, p->items, p->fac_u16, p->fac_v16, p->fac_c16, p->fac_s16, p->env_q, p->rscale, p->ebmul, p->perm, p->tmax, p->ld_half, p->inv_full32, p->prior_s, p->prior_part, p->prior_pidx, p->lem_cand, p->lem_score, p->shadow_alloc, p->cand_idx, p->cand_score, p->cand_p64, p->exec_count,
                     p->cand_count, p->gmax, p->ebound, p->rnorm, p->need_rerun, p->lag_inv, p->lag_span, p->lag_order,
-                    p->lag_rho, p->lag_rows};
+                    p->lag_rho, p->lag_rows, p->lag_rs_cp, p->lag_rs_count, p->lag_rs_units, p->lag_rs_map, p->lag_rs_pairs};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto& ge : p->graphs) {
@@ -773,6 +773,7 @@ extern "C" act_status act_search_flops(act_plan_t p, int32_t batch, double* flop
         set_error("act_search_flops: only the lag-table search of plain plans has a counted matrix-core workload");
         return ACT_ERR_UNSUPPORTED;
     }
+    select_shape(p, batch);  // the form of the lag-table search depends on the batch's shape
     *flops = lag_search_flops(p, batch);
     return ACT_OK;
 }

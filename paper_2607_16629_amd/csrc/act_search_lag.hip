@@ -110,6 +110,16 @@ struct LagDev {
     // pass-0 searches: [0] += MFMA instructions the launch executed (every
     // wave's), [1] += 1 per launch; NULL when not counting
     unsigned long long* exec;
+    // resident-residual form (k_search_lag_rs): per XCD its column pairs,
+    // longest band first ([8][rs_cp_per_x]) and their count; each channel's
+    // copy in LDS holds samples [-rs_glo, rs_len - rs_glo) at a row stride of
+    // rs_stride elements
+    const int* rs_cp;
+    const int* rs_cp_count;
+    int rs_cp_per_x;
+    float* rs_map;   // [channel groups][8 rs_cp_per_x n_tg units][32] the pass-0 max map
+    int* rs_pairs;   // pass 1's count and list of flagged map entries; pass 0 clears the count
+    int rs_glo, rs_len, rs_stride;
 };
 
 struct LagLds {
@@ -572,6 +582,444 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
     }
 }
 
+// ---------------------------------------------------------------------------
+// Resident-residual form: real atoms of plain plans, at least 32 channels.
+//
+// A workgroup of 8 waves holds the FP16/BF16 search copies of one group of 32
+// channels in LDS, each with zero guards wide enough for every lag a unit
+// reads, so that a row (channel, time centre m) of the Hankel operand at lag e
+// is the channel's copy at sample e - N_pad + m and no stage is staged or
+// synchronised.  A wave's unit of work is 128 rows (4 time centres x 32
+// channels; row block rb = time centre, row in block = channel slot) x 64
+// columns (two column blocks) over the k-steps where those columns' nonzero
+// band meets the rows' lags, padded to a multiple of 4 k-steps (the products
+// added by the padding are exact zeros: table entries outside the band, or
+// residual samples outside the signal).  Each (channel group, XCD) pair has a
+// list of units: the column pairs dealt to that XCD, longest band first, each
+// with its time groups in a row, so that the units of a column pair run
+// together and share its band in that XCD's L2.  The list is dealt to the
+// pair's waves in a fixed schedule (no atomics).
+//
+// Selection in two launches.  Pass 0 (this kernel) computes every unit and
+// keeps per (channel, unit) the unit's largest |p~| (the max map), raising
+// each channel's running maximum M; it emits nothing.  Pass 1
+// (k_lag_rs_emit) scores again, one (unit, channel) pair per workgroup, only
+// the pairs whose map entry reaches M - 2 E_b, and emits every score that
+// reaches that threshold.  The lists then hold the certified set and nothing
+// else, whatever order the units ran in.
+constexpr int RS_WAVES = 8;
+constexpr int RS_CH = 32;   // channels per group (one per row of a 32-row block)
+constexpr int RS_TB = 4;    // time centres per unit
+constexpr int RS_U = 4;     // k-steps per loop trip; B fragments load one trip ahead
+
+constexpr int RS_MAPB = 8;  // units whose map entries a wave holds in LDS before writing them out
+
+struct RsScratch {
+    float map[RS_WAVES][RS_MAPB][RS_CH];  // per wave: map entries of its last units
+    float um[RS_WAVES][RS_CH];    // per wave: the unit's max |p| per channel slot (before 1/s_b)
+    int mapu[RS_WAVES][RS_MAPB];  // per wave: the units of the entries in map
+    float rinv[RS_CH];            // 1/s_b per channel slot (0 past the batch)
+    unsigned wmax[RS_CH];         // the workgroup's maximum per channel slot (float bits)
+};
+
+// Unit descriptors, RS_UD ints per unit in list order ([8 XCDs][column pairs
+// per XCD][time groups]): column pair, first time centre, first k-step, k-steps
+// (a multiple of RS_U), and per row block the LDS element offset
+// glo - N_pad + m_rb + 16 kb of its rows' first sample (lane part excluded).
+// Read through the scalar cache: a kernel argument the kernel never writes.
+constexpr int RS_UD = 8;
+
+// DUMP: act_correlate's score dump instead of the max map.
+template <bool DUMP, bool BF>
+__global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, LagDev ld, SearchCtl ctl,
+                                                                 const int* __restrict__ units, int batch,
+                                                                 int n_cg, int n_tg) {
+    extern __shared__ f16x8 rs_res[];  // [RS_CH][rs_stride / 8] copies, then RsScratch
+    RsScratch& S = *reinterpret_cast<RsScratch*>(rs_res + RS_CH * (ld.rs_stride / 8));
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xcd = blockIdx.x & 7, cg = (int)(blockIdx.x >> 3) % n_cg;
+    const int ch0 = cg * RS_CH;
+    if (!DUMP && blockIdx.x == 0 && threadIdx.x == 0) ld.rs_pairs[0] = 0;  // pass 1's list, filled after this launch
+    // per channel slot: 1/s_b
+    if (threadIdx.x < RS_CH) {
+        const int b = ch0 + (int)threadIdx.x;
+        float ri = 0.0f;
+        if (b < batch) {
+            const float sc = ld.rscale[b];
+            ri = sc > 0.0f ? 1.0f / sc : 0.0f;
+        }
+        S.rinv[threadIdx.x] = ri;
+        S.wmax[threadIdx.x] = 0u;
+    }
+    // the group's copies: samples [-glo, len - glo) of each channel (zero
+    // outside the signal, also past the batch), 16 bytes per thread and step,
+    // RS_FILL steps' loads in flight at a time
+    {
+        constexpr int RS_FILL = 10;
+        const int per = ld.rs_len / 8, chunks = RS_CH * per;
+        for (int c0 = threadIdx.x; c0 < chunks; c0 += RS_FILL * 64 * RS_WAVES) {
+            f16x8 v[RS_FILL];
+#pragma unroll
+            for (int i = 0; i < RS_FILL; ++i) {
+                const int c = c0 + i * 64 * RS_WAVES, sl = c / per, j = c - sl * per, b = ch0 + sl;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[i][k] = (_Float16)0.0f;
+                if (c < chunks && b < batch)
+                    v[i] = *reinterpret_cast<const f16x8*>(
+                        ld.shadow + 2 * ((size_t)g.n_pad + (size_t)b * ld.sh_stride + 8 * j - ld.rs_glo));
+            }
+#pragma unroll
+            for (int i = 0; i < RS_FILL; ++i) {
+                const int c = c0 + i * 64 * RS_WAVES, sl = c / per, j = c - sl * per;
+                if (c < chunks) rs_res[sl * (ld.rs_stride / 8) + j] = v[i];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int total = ld.rs_cp_count[xcd] * n_tg;
+    const int qbase = xcd * ld.rs_cp_per_x * n_tg;  // the pair's first unit in list order
+    const int* qunits = units + (size_t)qbase * RS_UD;
+    float* qmap = ld.rs_map + ((size_t)cg * 8 * ld.rs_cp_per_x * n_tg + qbase) * RS_CH;
+    const char* lds_base = reinterpret_cast<const char*>(rs_res);
+    const unsigned glane = 16u * (unsigned)lane;
+    const unsigned alane = 2u * (unsigned)((lane & 31) * ld.rs_stride + 8 * (lane >> 5));
+    unsigned long long mfma_run = 0;  // MFMA instructions this wave executed (pass 0)
+
+    // The pair's units, longest band first, are dealt to its waves in rounds,
+    // in snake order (round r gives unit r W + i for even r, r W + W - 1 - i
+    // for odd r; W waves, i the wave's index); the second wave of each SIMD
+    // (waves 4-7) starts half-way through the rounds, so that the two waves of
+    // a SIMD reach their epilogues at different times.
+    const int J = ((int)gridDim.x - xcd + 7) / 8;                  // workgroups on this XCD
+    const int nwq = RS_WAVES * ((J - cg + n_cg - 1) / n_cg);       // waves of this (channel group, XCD)
+    const int qi = RS_WAVES * ((int)(blockIdx.x >> 3) / n_cg) + w;
+    const int rounds = (total + nwq - 1) / nwq;
+    const int r0 = w >= RS_WAVES / 2 ? rounds / 2 : 0;
+    auto unit_at = [&](int k) {  // the wave's k-th unit, or -1 (a partial last round)
+        int r = k + r0;
+        if (r >= rounds) r -= rounds;
+        const int u = r * nwq + ((r & 1) ? nwq - 1 - qi : qi);
+        return u < total ? u : -1;
+    };
+    auto next_k = [&](int k) {  // the wave's first position k' >= k with a unit (rounds if none)
+        while (k < rounds && unit_at(k) < 0) ++k;
+        return k;
+    };
+    struct Unit {
+        int u, cp, tc0, kb, nk, a[RS_TB];
+    };
+    auto decode = [&](int u) {
+        const int* d = qunits + (size_t)u * RS_UD;
+        Unit x;
+        x.u = u;
+        x.cp = d[0];
+        x.tc0 = d[1];
+        x.kb = d[2];
+        x.nk = d[3];
+#pragma unroll
+        for (int rb = 0; rb < RS_TB; ++rb) x.a[rb] = d[4 + rb];
+        return x;
+    };
+    // B fragments of the current trip's RS_U k-steps.  Every trip issues
+    // exactly 2 RS_U loads (the last trip's fetch the next unit's first
+    // k-steps, or repeat a valid address).
+    f16x8 ring[RS_U][2];
+    // wave-uniform block addresses; a lane reads 16 bytes at glane past them
+    auto gaddr = [&](const Unit& x, int cb) {
+        return reinterpret_cast<const char*>(ld.G) + (size_t)(2 * x.cp + cb) * ld.LS * 1024;
+    };
+    // first k-steps of unit x (a unit without k-steps, or none: k-step 0 of block 0)
+    auto first_addr = [&](bool has, const Unit& x, int cb) {
+        return has && x.nk > 0 ? gaddr(x, cb) + 1024 * (size_t)x.kb : reinterpret_cast<const char*>(ld.G);
+    };
+    auto ldg = [&](const char* ub) { return *reinterpret_cast<const f16x8*>(ub + glane); };
+    auto load_first = [&](const char* a0, const char* a1) {
+#pragma unroll
+        for (int j = 0; j < RS_U; ++j) {
+            ring[j][0] = ldg(a0 + 1024 * j);
+            ring[j][1] = ldg(a1 + 1024 * j);
+        }
+    };
+
+    // One wait per unit.  A unit's B fragments of its first trip and its
+    // epilogue inputs (the lane's 1/|g| per time centre and column) are issued
+    // at the end of the previous unit's products, land during its epilogue,
+    // and are taken together at the unit's start; the unit's descriptor comes
+    // through the scalar cache.
+    float sc[RS_TB][2];
+    auto load_eps = [&](const Unit& x, float (&dsc)[RS_TB][2]) {
+#pragma unroll
+        for (int rb = 0; rb < RS_TB; ++rb) {
+            const float* src = ld.inv + (size_t)min(x.tc0 + rb, ld.n_tc - 1) * ld.Qp + x.cp * 64 + (lane & 31);
+            dsc[rb][0] = src[0];
+            dsc[rb][1] = src[32];
+        }
+    };
+    // pass 0: the count of map entries held in LDS
+    int nmap = 0;
+    auto flush_map = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < RS_CH) {
+#pragma unroll
+            for (int i = 0; i < RS_MAPB; ++i)
+                if (i < nmap) qmap[(size_t)S.mapu[w][i] * RS_CH + lane] = S.map[w][i][lane];
+        }
+        nmap = 0;
+    };
+    int k = next_k(0);
+    Unit cur;
+    if (k < rounds) {
+        cur = decode(unit_at(k));
+        load_first(first_addr(true, cur, 0), first_addr(true, cur, 1));
+        load_eps(cur, sc);
+    }
+    while (k < rounds) {
+        // everything issued for this unit has landed
+#pragma unroll
+        for (int rb = 0; rb < RS_TB; ++rb) asm volatile("" : "+v"(sc[rb][0]), "+v"(sc[rb][1]));
+        const int k_next = next_k(k + 1);
+        const int tc0 = cur.tc0;
+        Unit nxt;
+        const bool has_next = k_next < rounds;
+        if (has_next) nxt = decode(unit_at(k_next));
+        const char* n0 = first_addr(has_next, nxt, 0);
+        const char* n1 = first_addr(has_next, nxt, 1);
+
+        // A fragments: the lane's 8 lags of its channel's copy for row block rb
+        // at k-step ks: element sl stride + glo - N_pad + m_rb + 16 ks + 8 (lane / 32)
+        unsigned aoff[RS_TB];
+#pragma unroll
+        for (int rb = 0; rb < RS_TB; ++rb) aoff[rb] = alane + 2u * (unsigned)cur.a[rb];
+        f32x16 acc[RS_TB][2];
+#pragma unroll
+        for (int rb = 0; rb < RS_TB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.0f;
+        const char* g0 = gaddr(cur, 0);
+        const char* g1 = gaddr(cur, 1);
+        // each row block's next A fragment is read as soon as its two
+        // products of this k-step have issued (across trips; the last trip's
+        // look-ahead reads one k-step past the unit, inside the copy's guard)
+        f16x8 af[RS_TB];
+#pragma unroll
+        for (int rb = 0; rb < RS_TB; ++rb) af[rb] = *reinterpret_cast<const f16x8*>(lds_base + aoff[rb]);
+        for (int t = 0; t < cur.nk; t += RS_U) {
+            const bool more = t + RS_U < cur.nk;
+#pragma unroll
+            for (int j = 0; j < RS_U; ++j) {
+#pragma unroll
+                for (int rb = 0; rb < RS_TB; ++rb) {
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        if constexpr (BF)
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, af[rb]), __builtin_bit_cast(bf16x8, ring[j][cb]),
+                                acc[rb][cb], 0, 0, 0);
+                        else
+                            acc[rb][cb] =
+                                __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb], ring[j][cb], acc[rb][cb], 0, 0, 0);
+                    }
+                    af[rb] = *reinterpret_cast<const f16x8*>(lds_base + aoff[rb] + 32u * (unsigned)(t + j + 1));
+                }
+                const size_t o = 1024 * (size_t)(cur.kb + t + RS_U + j);
+                const char* a0 = more ? g0 + o : n0 + 1024 * j;
+                const char* a1 = more ? g1 + o : n1 + 1024 * j;
+                ring[j][0] = ldg(a0);
+                ring[j][1] = ldg(a1);
+            }
+            // order: per k-step and row block its 2 MFMAs, then the read of the
+            // row block's next A fragment; per k-step the 2 loads that refill
+            // its B fragments
+#pragma unroll
+            for (int j = 0; j < RS_U; ++j) {
+#pragma unroll
+                for (int rb = 0; rb < RS_TB; ++rb) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+            }
+        }
+        if (cur.nk == 0) load_first(n0, n1);
+        mfma_run += (unsigned long long)cur.nk * (RS_TB * 2);
+#pragma unroll
+        for (int rb = 0; rb < RS_TB; ++rb)
+            if (tc0 + rb >= ld.n_tc) sc[rb][0] = sc[rb][1] = 0.0f;
+        // the next unit's epilogue inputs
+        float sc_n[RS_TB][2];
+        if (has_next) load_eps(nxt, sc_n);
+
+        // ---- epilogue.  Lane holds column ecol0 + 32 cb of rows
+        // (tc0 + rb, slot lg_row(v, lane)); p = (raw / |g|) / s_b.  Its
+        // lane-dependent addresses use an opaque copy of the lane index, so
+        // that they are formed here and not kept live across the unit loop.
+        int elane = lane;
+        asm volatile("" : "+v"(elane));
+        const int ecol0 = cur.cp * 64 + (elane & 31);
+        if (DUMP) {
+#pragma unroll
+            for (int rb = 0; rb < RS_TB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int sl = lg_row(v, elane), b = ch0 + sl, tc = tc0 + rb;
+                    const float ri = S.rinv[sl];
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        const int c = ecol0 + 32 * cb;
+                        const float p = (acc[rb][cb][v] * sc[rb][cb]) * ri;
+                        if (b < batch && tc < ld.n_tc && c < ld.Q) {
+                            const long long i = lag_atom(ld, tc, c);
+                            if (i >= ctl.dump_begin && i < ctl.dump_begin + ctl.dump_count)
+                                ctl.dump[(size_t)b * ctl.dump_count + (i - ctl.dump_begin)] = p;
+                        }
+                    }
+                }
+        } else {
+            // per row group v: max over the lane's rows and columns of |raw| / |g|,
+            // then over the half-wave's 32 columns (the factor 1/s_b of a
+            // channel is applied to its maximum: it is positive, and FP32
+            // rounding is monotonic)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                float m = 0.0f;
+#pragma unroll
+                for (int rb = 0; rb < RS_TB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) m = fmaxf(m, fabsf(acc[rb][cb][v] * sc[rb][cb]));
+                m = half_wave_max(m);
+                if ((elane & 31) == 31) S.um[w][lg_row(v, elane)] = m;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // per channel slot (lane < 32): the unit's map entry, kept in LDS
+            // with the wave's last RS_MAPB entries and written out with them,
+            // and the workgroup's maximum (the running maxima are raised once,
+            // when the workgroup ends: global writes here would hold up the
+            // next unit's start, which waits for the memory operations issued
+            // before its inputs)
+            if (lane < RS_CH) {
+                const float um = S.um[w][lane] * S.rinv[lane];
+                S.map[w][nmap][lane] = um;
+                atomicMax(&S.wmax[lane], fbits(um));
+            }
+            if (lane == 0) S.mapu[w][nmap] = cur.u;
+            if (++nmap == RS_MAPB || !has_next) flush_map();
+            __builtin_amdgcn_wave_barrier();
+        }
+        k = k_next;
+        cur = nxt;
+#pragma unroll
+        for (int rb = 0; rb < RS_TB; ++rb) {
+            sc[rb][0] = sc_n[rb][0];
+            sc[rb][1] = sc_n[rb][1];
+        }
+    }
+    if (!DUMP && ld.exec && lane == 0) {
+        if (mfma_run) atomicAdd(&ld.exec[0], mfma_run);
+        if (blockIdx.x == 0 && w == 0) atomicAdd(&ld.exec[1], 1ull);
+    }
+    if (!DUMP) {
+        // the workgroup's maxima raise the channels' running maxima
+        __syncthreads();
+        if (threadIdx.x < RS_CH && ch0 + (int)threadIdx.x < batch && S.wmax[threadIdx.x])
+            atomicMax(&ctl.gmax[ch0 + threadIdx.x], S.wmax[threadIdx.x]);
+    }
+}
+
+// Pass 1 of the resident form, in two launches.  k_lag_rs_flag checks every
+// (list slot, channel) map entry against its channel's threshold
+// T = M - 2 E_b (rounded down to FP32; none without a bound) and appends the
+// pairs that reach it to a list (pairs[0] counts them; pass 0 clears it).
+// k_lag_rs_emit then takes the pairs one workgroup at a time and computes the
+// unit's 4 x 64 scores of that channel again, one per thread: FP32
+// multiply-adds of the table's and the search copy's 16-bit values over the
+// unit's k-steps in four interleaved chains (the certified bound E_b holds
+// for any order of the FP32 sums), scaled as the search scales them, and
+// emits those that reach T (one device atomic per pair reserves the list
+// entries).  A true arg-max atom has a pass-0 score of at least T, so its
+// pair is flagged, and its pass-1 score, within E_b of its true score,
+// reaches T too.
+__device__ __forceinline__ float rs_threshold(const SearchCtl& ctl, int b) {
+    const double eb = ctl.ebound[b];
+    if (eb < 0.0) return INFINITY;
+    const double Td = (double)load_gmax(&ctl.gmax[b]) - 2.0 * eb;
+    float T = (float)Td;
+    if ((double)T > Td) T = nextafterf(T, -INFINITY);
+    return T;
+}
+
+__global__ void __launch_bounds__(256) k_lag_rs_flag(LagDev ld, SearchCtl ctl, int batch, int n_cg, int n_tg,
+                                                     int* __restrict__ pairs) {
+    const int perq = ld.rs_cp_per_x * n_tg, U = 8 * perq;
+    const long long n = (long long)n_cg * U * RS_CH;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long sl = e / RS_CH;
+        const int ch = (int)(e % RS_CH), cg = (int)(sl / U), us = (int)(sl % U), x = us / perq;
+        const int b = cg * RS_CH + ch;
+        if (us - x * perq >= ld.rs_cp_count[x] * n_tg || b >= batch) continue;
+        if (ld.rs_map[e] >= rs_threshold(ctl, b)) pairs[1 + atomicAdd(&pairs[0], 1)] = (int)e;
+    }
+}
+
+template <bool BF>
+__global__ void __launch_bounds__(256) k_lag_rs_emit(LagDev ld, SearchCtl ctl, const int* __restrict__ units,
+                                                     int n_tg, const int* __restrict__ pairs) {
+    __shared__ unsigned s_cnt;
+    __shared__ int s_base;
+    const int U = 8 * ld.rs_cp_per_x * n_tg;
+    const int t = threadIdx.x, rb = t >> 6, c = t & 63;
+    const int np = pairs[0];
+    auto cvt = [](_Float16 h) {
+        if constexpr (BF) return __uint_as_float((unsigned)__builtin_bit_cast(unsigned short, h) << 16);
+        else return (float)h;
+    };
+    for (int q = blockIdx.x; q < np; q += gridDim.x) {
+        const int e = pairs[1 + q], ch = e % RS_CH, sl = e / RS_CH;
+        const int cg = sl / U, us = sl - cg * U, b = cg * RS_CH + ch;
+        const int* d = units + (size_t)us * RS_UD;
+        const int cp = d[0], tc0 = d[1], kb = d[2], nk = d[3];
+        const int tc = tc0 + rb, col = cp * 64 + c;
+        const int m = ld.tc_shift[min(tc, ld.n_tc - 1)];
+        // the thread's column in its 32-column block: lanes c % 32 (lags
+        // 0-7 of a k-step) and c % 32 + 32 (lags 8-15) of each fragment;
+        // the search copy's row b at element n_pad + b stride, sample e - N_pad + m
+        const char* gp = reinterpret_cast<const char*>(ld.G) +
+                         ((size_t)(2 * cp + (c >> 5)) * ld.LS + kb) * 1024 + 16 * (c & 31);
+        const char* rp = ld.shadow + 2 * ((size_t)b * ld.sh_stride + 16 * kb + m);
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+        for (int ks = 0; ks < nk; ++ks) {
+            const f16x8 g0 = *reinterpret_cast<const f16x8*>(gp + 1024 * (size_t)ks);
+            const f16x8 g1 = *reinterpret_cast<const f16x8*>(gp + 1024 * (size_t)ks + 512);
+            const f16x8 x0 = *reinterpret_cast<const f16x8*>(rp + 32 * (size_t)ks);
+            const f16x8 x1 = *reinterpret_cast<const f16x8*>(rp + 32 * (size_t)ks + 16);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j & 3] = fmaf(cvt(g0[j]), cvt(x0[j]), acc[j & 3]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j & 3] = fmaf(cvt(g1[j]), cvt(x1[j]), acc[j & 3]);
+        }
+        const float raw = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        const float sc = tc < ld.n_tc ? ld.inv[(size_t)tc * ld.Qp + col] : 0.0f;
+        const float rs = ld.rscale[b], ri = rs > 0.0f ? 1.0f / rs : 0.0f;
+        const float p = (raw * sc) * ri;
+        const bool hit = fabsf(p) >= rs_threshold(ctl, b) && tc < ld.n_tc && col < ld.Q;
+        if (t == 0) s_cnt = 0u;
+        __syncthreads();
+        const unsigned pos = hit ? atomicAdd(&s_cnt, 1u) : 0u;
+        __syncthreads();
+        if (t == 0) s_base = s_cnt ? atomicAdd(&ctl.cand_count[b], (int)s_cnt) : 0;
+        __syncthreads();
+        const int j = s_base + (int)pos;
+        if (hit && j < ctl.cap) {
+            ctl.cand_idx[(size_t)b * ctl.cap + j] = (unsigned)lag_atom(ld, tc, col);
+            ctl.cand_score[(size_t)b * ctl.cap + j] = p;
+        }
+        __syncthreads();
+    }
+}
+
 // The lag table: G_q(d) in FP64, rounded to FP32 and then FP16 or BF16 (RNE;
 // BF16 entries below 2^-25 are zero), written
 // in MFMA B-operand order; columns past Q are zero.  Columns run log-duration
@@ -731,6 +1179,90 @@ static std::vector<int> lag_block_order(const std::vector<int2>& span, int Q, in
     return order;
 }
 
+// Resident-residual form, at plan time: the LDS copy's guards (every lag a
+// unit reads, its k-steps padded to RS_U), and the column pairs by decreasing
+// band dealt round-robin to the 8 XCDs.  The form is left out (lag_rs_cp
+// null) for complex atoms, ragged plans, time centres off multiples of 8
+// samples (16-byte LDS reads) or copies that do not fit one workgroup's LDS.
+static act_status prepare_lag_rs(act_plan_s* p, const std::vector<int2>& span, hipStream_t s) {
+    if (p->desc.complex_atoms || p->desc.ragged) return ACT_OK;
+    const int n_tc = p->grid.cnt[0], n = p->grid.n, n_pad = p->n_pad;
+    const std::vector<int>& sh = p->tc_shift_host;
+    int spread = 0;
+    for (int m : sh)
+        if (m % 8 != 0) return ACT_OK;
+    for (int tc0 = 0; tc0 < n_tc; tc0 += RS_TB) spread = std::max(spread, sh[std::min(tc0 + RS_TB, n_tc) - 1] - sh[tc0]);
+    // a unit's k-steps start at most 15 + 16 (RS_U - 1) lags before its
+    // earliest row's first sample and end as far past its last row's, and
+    // the A fragments look one k-step further ahead
+    const int glo = (spread + 16 * RS_U - 1 + 7) / 8 * 8, ghi = (spread + 16 * RS_U + 15 + 7) / 8 * 8;
+    if (glo > n_pad || (n + 7) / 8 * 8 + ghi > 2 * n_pad) return ACT_OK;
+    const int len = glo + (n + 7) / 8 * 8 + ghi;
+    const int stride = ((len / 8) & 1) ? len : len + 8;  // an odd count of 16-byte units per channel
+    if ((size_t)RS_CH * stride * 2 + sizeof(RsScratch) > (size_t)device_lds_per_block()) return ACT_OK;
+    const int n_cp = (int)span.size() / 2;
+    std::vector<std::pair<int, int>> band(n_cp);
+    for (int k = 0; k < n_cp; ++k) {
+        const int lo = std::min(span[2 * k].x, span[2 * k + 1].x), hi = std::max(span[2 * k].y, span[2 * k + 1].y);
+        band[k] = {hi > lo ? hi - lo : 0, k};
+    }
+    std::stable_sort(band.begin(), band.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    const int per_x = (n_cp + 7) / 8;
+    std::vector<int> lists((size_t)8 * per_x, -1), counts(8, 0);
+    for (int k = 0; k < n_cp; ++k) {
+        const int x = k % 8;
+        lists[(size_t)x * per_x + counts[x]++] = band[k].second;
+    }
+    // unit descriptors in list order (k-step ranges as the tiles' in
+    // k_search_lag, cut to whole k-steps and padded to RS_U)
+    const int n_tg = (n_tc + RS_TB - 1) / RS_TB, LS = 2 * n_pad / 16;
+    std::vector<int> units((size_t)8 * per_x * n_tg * RS_UD, 0);
+    long long mfma = 0;
+    for (int x = 0; x < 8; ++x)
+        for (int k = 0; k < counts[x]; ++k) {
+            const int cp = lists[(size_t)x * per_x + k];
+            const int lo = std::min(span[2 * cp].x, span[2 * cp + 1].x);
+            const int hi = std::max(span[2 * cp].y, span[2 * cp + 1].y);
+            for (int tg = 0; tg < n_tg; ++tg) {
+                const int tc0 = tg * RS_TB, m_min = sh[tc0], m_max = sh[std::min(tc0 + RS_TB, n_tc) - 1];
+                const int klo = std::max(lo, (n_pad - m_max) >> 4);
+                const int khi = std::min(hi, (n_pad + n - m_min + 15) >> 4);
+                const int nk = (std::max(khi - klo, 0) + RS_U - 1) / RS_U * RS_U;
+                const int kb = std::min(klo + nk, LS) - nk;
+                int* d = &units[(((size_t)x * per_x + k) * n_tg + tg) * RS_UD];
+                d[0] = cp;
+                d[1] = tc0;
+                d[2] = kb;
+                d[3] = nk;
+                for (int rb = 0; rb < RS_TB; ++rb)
+                    d[4 + rb] = glo - n_pad + sh[std::min(tc0 + rb, n_tc - 1)] + 16 * kb;
+                mfma += (long long)nk * RS_TB * 2;
+            }
+        }
+    const int ncg = (p->max_batch + RS_CH - 1) / RS_CH;
+    ACT_HIP(hipMalloc((void**)&p->lag_rs_map, (size_t)ncg * 8 * per_x * n_tg * RS_CH * sizeof(float)));
+    ACT_HIP(hipMalloc((void**)&p->lag_rs_pairs, (1 + (size_t)ncg * 8 * per_x * n_tg * RS_CH) * sizeof(int)));
+    ACT_HIP(hipMalloc((void**)&p->lag_rs_units, units.size() * sizeof(int)));
+    ACT_HIP(hipMemcpyAsync(p->lag_rs_units, units.data(), units.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    p->lag_rs_mfma = mfma;
+    ACT_HIP(hipMalloc((void**)&p->lag_rs_cp, lists.size() * sizeof(int)));
+    ACT_HIP(hipMalloc((void**)&p->lag_rs_count, 8 * sizeof(int)));
+    ACT_HIP(hipMemcpyAsync(p->lag_rs_cp, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    ACT_HIP(hipMemcpyAsync(p->lag_rs_count, counts.data(), 8 * sizeof(int), hipMemcpyHostToDevice, s));
+    ACT_HIP(hipStreamSynchronize(s));
+    p->lag_rs_cp_per_x = per_x;
+    p->lag_rs_ncg = ncg;
+    p->lag_rs_glo = glo;
+    p->lag_rs_len = len;
+    p->lag_rs_stride = stride;
+    return ACT_OK;
+}
+
+// Whether a search of `batch` channels runs in the resident-residual form.
+static bool lag_rs_use(const act_plan_s* p, int batch) {
+    return p->lag_rs_cp && batch >= RS_CH && (batch + RS_CH - 1) / RS_CH <= p->lag_rs_ncg && p->shape.form == 0;
+}
+
 act_status build_lag_table(act_plan_s* p, hipStream_t s) {
     const int Q_pad = p->lag_q_pad;
     const int LS = 2 * p->n_pad / 16;
@@ -768,7 +1300,7 @@ act_status build_lag_table(act_plan_s* p, hipStream_t s) {
     order.insert(order.end(), wide.begin(), wide.end());
     ACT_HIP(hipMemcpyAsync(p->lag_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
     ACT_HIP(hipStreamSynchronize(s));
-    return ACT_OK;
+    return prepare_lag_rs(p, span, s);
 }
 
 // Flops one pass-0 launch executes on the matrix cores: every tile's stages
@@ -776,6 +1308,12 @@ act_status build_lag_table(act_plan_s* p, hipStream_t s) {
 // columns x 128 lags x 2 -- the tiling of launch_search_lag and k_search_lag.
 double lag_search_flops(const act_plan_s* p, int batch) {
     const int n_tc = p->grid.cnt[0], Q = p->grid.cnt[1] * p->n_cl, n_pad = p->n_pad, n = p->grid.n;
+    if (lag_rs_use(p, batch)) {
+        // resident-residual form: per (channel group, unit) its k-steps x 4
+        // row blocks x 2 column blocks, counted when the units were laid out
+        const int n_cg = (batch + RS_CH - 1) / RS_CH;
+        return (double)p->lag_rs_mfma * n_cg * (32.0 * 32.0 * 16.0 * 2.0);
+    }
     const bool cplx = p->desc.complex_atoms != 0;
     const int ncols = cplx ? 2 * ((Q + 31) / 32 * 32) : Q;
     int CB = 1;
@@ -853,7 +1391,7 @@ act_status launch_lag_ragged_prep(act_plan_s* p, int batch, hipStream_t s) {
 }
 
 act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hipStream_t s) {
-    LagDev ld;
+    LagDev ld{};
     ld.G = (const f16x8*)p->table;
     ld.inv = p->lag_inv;
     ld.span = (const int2*)p->lag_span;
@@ -878,6 +1416,51 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
     if (rag && ctl.dump) {
         set_error("act_correlate: the ragged lag-table search has no score dump");
         return ACT_ERR_UNSUPPORTED;
+    }
+    if (lag_rs_use(p, batch) && !rag) {
+        ld.rs_cp = p->lag_rs_cp;
+        ld.rs_cp_count = p->lag_rs_count;
+        ld.rs_cp_per_x = p->lag_rs_cp_per_x;
+        ld.rs_glo = p->lag_rs_glo;
+        ld.rs_len = p->lag_rs_len;
+        ld.rs_stride = p->lag_rs_stride;
+        const int n_cg = (batch + RS_CH - 1) / RS_CH, n_tg = (ld.n_tc + RS_TB - 1) / RS_TB;
+        // every (channel group, XCD) pair gets the same number of workgroups
+        const int per = 8 * n_cg, cus = device_cus();
+        const dim3 grid((unsigned)((cus + per - 1) / per * per)), blk(64 * RS_WAVES);
+        const size_t dyn = (size_t)RS_CH * ld.rs_stride * 2 + sizeof(RsScratch);
+        const bool bf = p->desc.prec == ACT_PREC_BF16;
+        ld.rs_map = p->lag_rs_map;
+        // pass 0 builds the max map (and clears pass 1's list), pass 1 lists
+        // the flagged pairs and emits from them
+        ld.rs_pairs = p->lag_rs_pairs;
+        if (ctl.pass && !ctl.dump) {
+            const long long n = (long long)n_cg * 8 * ld.rs_cp_per_x * n_tg * RS_CH;
+            hipLaunchKernelGGL(k_lag_rs_flag, dim3((unsigned)std::min<long long>((n + 255) / 256, 16LL * cus)), dim3(256),
+                               0, s, ld, ctl, batch, n_cg, n_tg, p->lag_rs_pairs);
+            ACT_HIP(hipGetLastError());
+            if (bf)
+                hipLaunchKernelGGL((k_lag_rs_emit<true>), dim3(8 * cus), dim3(256), 0, s, ld, ctl, p->lag_rs_units,
+                                   n_tg, p->lag_rs_pairs);
+            else
+                hipLaunchKernelGGL((k_lag_rs_emit<false>), dim3(8 * cus), dim3(256), 0, s, ld, ctl, p->lag_rs_units,
+                                   n_tg, p->lag_rs_pairs);
+            ACT_HIP(hipGetLastError());
+            return ACT_OK;
+        }
+#define RS_LAUNCH(D, B)                                                                                        \
+    hipLaunchKernelGGL((k_search_lag_rs<D, B>), grid, blk, dyn, s, p->grid, ld, ctl, p->lag_rs_units, batch, n_cg, \
+                       n_tg)
+        if (bf) {
+            if (ctl.dump) RS_LAUNCH(true, true);
+            else RS_LAUNCH(false, true);
+        } else {
+            if (ctl.dump) RS_LAUNCH(true, false);
+            else RS_LAUNCH(false, false);
+        }
+#undef RS_LAUNCH
+        ACT_HIP(hipGetLastError());
+        return ACT_OK;
     }
     // rows: the smallest power of two of channels covering the batch (at most
     // 32) times the time centres that fill 128 rows

@@ -57,11 +57,20 @@ static std::vector<act_launch_shape> candidates(const act_plan_s* p, int batch) 
         }
     }
     std::vector<act_launch_shape> out;
+    // lag-table search: the resident-residual form (its own grid) where it
+    // applies, then the staged tiles
+    const bool rs = d.dict == ACT_DICT_LAG && p->lag_rs_cp && batch >= 32;
+    if (rs) {
+        act_launch_shape s{};
+        s.grid_per_cu = 1;
+        out.push_back(s);
+    }
     for (int g : grids)
         for (int c : cpfs) {
             act_launch_shape s{};
             s.grid_per_cu = g;
             s.chan_per_fc = c;
+            s.form = rs ? 1 : 0;
             out.push_back(s);
         }
     return out;
@@ -99,8 +108,8 @@ static bool cache_lookup(const char* path, const std::string& key, act_launch_sh
         std::string tok, k;
         for (int i = 0; i < kKeyFields && (in >> tok); ++i) k += (i ? " " : "") + tok;
         act_launch_shape v{};
-        if (k == key && (in >> v.grid_per_cu >> v.chan_per_fc >> v.ms) && v.grid_per_cu > 0 &&
-            v.grid_per_cu <= 64 && v.chan_per_fc >= 0 && v.chan_per_fc <= 64) {
+        if (k == key && (in >> v.grid_per_cu >> v.chan_per_fc >> v.form >> v.ms) && v.grid_per_cu > 0 &&
+            v.grid_per_cu <= 64 && v.chan_per_fc >= 0 && v.chan_per_fc <= 64 && (v.form == 0 || v.form == 1)) {
             v.from_cache = 1;
             *s = v;  // the last matching line wins
             found = true;
@@ -112,7 +121,7 @@ static bool cache_lookup(const char* path, const std::string& key, act_launch_sh
 static void cache_append(const char* path, const std::string& key, const act_launch_shape& s) {
     FILE* f = std::fopen(path, "a");
     if (!f) return;  // the choice still applies; the cache is best effort
-    std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), s.grid_per_cu, s.chan_per_fc, s.ms);
+    std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), s.grid_per_cu, s.chan_per_fc, s.form, s.ms);
     std::fclose(f);
 }
 
@@ -138,6 +147,19 @@ static void keep_shape(act_plan_s* p, int batch, const act_launch_shape& s) {
 }  // namespace act
 
 using namespace act;
+
+extern "C" act_status act_set_launch_shape(act_plan_t p, int32_t batch, const act_launch_shape* shape) {
+    ACT_REQUIRE(p != nullptr && shape != nullptr, "act_set_launch_shape: plan or shape is NULL");
+    ACT_REQUIRE(batch >= 1 && batch <= p->max_batch, "act_set_launch_shape: batch outside [1, max_batch]");
+    ACT_REQUIRE(shape->grid_per_cu >= 1 && shape->grid_per_cu <= 64 && shape->chan_per_fc >= 0 &&
+                    shape->chan_per_fc <= 64 && (shape->form == 0 || shape->form == 1),
+                "act_set_launch_shape: grid_per_cu outside [1, 64], chan_per_fc outside [0, 64] or form not 0/1");
+    act_launch_shape v = *shape;
+    v.from_cache = 0;
+    v.ms = 0.0;
+    keep_shape(p, batch, v);
+    return ACT_OK;
+}
 
 extern "C" act_status act_tune(act_plan_t p, int32_t batch, const int32_t* len_dev, const int64_t* off_dev,
                                const double* resid_dev, int32_t reps, const char* cache_path,

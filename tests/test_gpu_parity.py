@@ -1122,22 +1122,31 @@ def test_lag_table_partial_tiles_and_edge_channels(oracle):
 
 
 def test_lag_search_flops_counts_the_band_stages():
-    """The executed matrix-core work of the lag-table search: a whole number
-    of 128-lag stages of 128-row tiles, the same for every batch with the same
-    channel groups, below the dense count of the table's full lag range, and
-    unsupported for other dictionaries."""
+    """The executed matrix-core work of the lag-table search.  Resident form
+    (32 or more channels): a whole number of 4-k-step trips of 128-row x
+    64-column units, per group of 32 channels.  Staged tiles (form 1, and
+    fewer channels): a whole number of 128-lag stages of 128-row tiles.  Both
+    below the dense count of the table's full lag range; the form of a batch
+    follows its launch shape; other dictionaries have no count."""
     act = A()
     g = W.eeg_grid(2048, 64, 64, 32, 16)
     plan = act.Plan(g, dict_="lag", prec="f16", max_batch=64)
-    unit = 128 * 256 * 128 * 2.0  # one stage of a 256-column tile
+    n_pad = plan.query(act.Q_N_PAD)
+    trip = 128 * 64 * 64 * 2.0           # 4 k-steps of a 128 x 64 unit
     f64 = plan.search_flops(64)
-    assert f64 > 0 and f64 % unit == 0
+    assert f64 > 0 and f64 % trip == 0
     assert plan.search_flops(33) == f64  # two groups of 32 channels either way
     assert plan.search_flops(32) == f64 / 2
-    # every tile running all 2 n_pad lags of the table
-    n_pad = plan.query(act.Q_N_PAD)
-    full = (g.size // g.tc.count // 256) * 2 * (g.tc.count // 4) * (2 * n_pad // 128) * unit
+    # every unit running all 2 n_pad lags of the table
+    full = (g.size // g.tc.count // 64) * (g.tc.count // 4) * 2 * (2 * n_pad // 16) * 8 * 32768.0
     assert f64 < 0.7 * full
+    stage = 128 * 256 * 128 * 2.0        # one stage of a 256-column tile
+    plan.act_set_launch_shape(64, grid_per_cu=2, form=1)
+    f64s = plan.search_flops(64)
+    assert f64s % stage == 0 and f64s < 0.7 * full
+    assert f64 < f64s                    # the units cut the band to whole k-steps, not stages
+    plan.act_set_launch_shape(64, grid_per_cu=1, form=0)
+    assert plan.search_flops(64) == f64
     assert plan.search_flops(1) % (128 * 128 * 128 * 2.0) == 0
     # the BF16 table zeroes entries below FP16's floor: the same bands (up to
     # the k-step that a value at the floor itself may add)
@@ -1146,27 +1155,66 @@ def test_lag_search_flops_counts_the_band_stages():
     with pytest.raises(act.ActError) as e:
         plan.search_flops(65)
     assert e.value.status == act.ACT_ERR_INVALID
+    with pytest.raises(act.ActError) as e:
+        plan.act_set_launch_shape(64, grid_per_cu=1, form=2)
+    assert e.value.status == act.ACT_ERR_INVALID
     other = act.Plan(W.eeg_grid(512, 8, 8, 4, 2), dict_="synth", prec="f32")
     with pytest.raises(act.ActError) as e:
         other.search_flops(1)
     assert e.value.status == act.ACT_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("prec", ["f16", "bf16"])
-def test_search_executed_counts_match_the_band_stages(prec):
+@pytest.mark.parametrize("prec,form", [("f16", 0), ("bf16", 0), ("f16", 1), ("bf16", 1)])
+def test_search_executed_counts_match_the_band_stages(prec, form):
     """The device's count of executed MFMA instructions of the lag-table
-    search (act_search_executed) equals the host's count of the tiles' band
-    stages (act_search_flops) for every pass-0 launch of a decomposition, and
-    resets when read."""
+    search (act_search_executed) equals the host's count of the units' or
+    tiles' band k-steps (act_search_flops) for every pass-0 launch of a
+    decomposition, in both forms, and resets when read."""
     act = A()
     wl = W.batched_64x2048(channels=64, grid=W.eeg_grid(1024, 32, 16, 8, 6), order=3)
     plan = act.Plan(wl.grid, dict_="lag", prec=prec, max_batch=64, refine_steps=0)
+    plan.act_set_launch_shape(64, grid_per_cu=2, form=form)
     plan.decompose(torch.from_numpy(wl.signals), 3)
     torch.cuda.synchronize()
     flops, launches = plan.search_executed()
     assert launches == 3
     assert flops == 3 * plan.search_flops(64)
     assert plan.search_executed() == (0.0, 0)
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_lag_forms_agree_bit_for_bit(oracle, prec):
+    """The two forms of the lag-table search on 40 channels (a partial second
+    group of 32): the resident form (each group's residual copy held in LDS;
+    pass 0 builds the per-unit max map, pass 1 emits from the units it flags)
+    and the staged tiles return bit-identical decompositions (the exact FP64
+    rescoring of a certified candidate set decides in both) and identical
+    scores, which match the oracle within the certified bound; the first
+    order's atoms are the oracle's exhaustive arg-max."""
+    act = A()
+    g = W.eeg_grid(1024, 32, 16, 8, 6)
+    wl = W.batched_64x2048(channels=40, grid=g, order=4)
+    begin, count = g.size - 777, 777
+    res = {}
+    for form in (0, 1):
+        plan = act.Plan(g, dict_="lag", prec=prec, max_batch=40, refine_steps=30)
+        plan.act_set_launch_shape(40, grid_per_cu=2, form=form)
+        out = plan.decompose(torch.from_numpy(wl.signals), 4)
+        p = plan.act_correlate(wl.signals, begin, count).cpu().numpy()
+        torch.cuda.synchronize()
+        res[form] = ({k: v.cpu().numpy() for k, v in out.items() if v is not None}, p)
+        plan.close()
+    for k in res[0][0]:
+        np.testing.assert_array_equal(res[0][0][k], res[1][0][k], err_msg=k)
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    ref = oracle.correlate_many(g, wl.signals, begin, count)
+    tol = 8.2e-3 if prec == "bf16" else 1.5e-3
+    for b in range(40):
+        err = float(np.max(np.abs(res[0][1][b] - ref[b]))) / float(np.linalg.norm(wl.signals[b]))
+        assert err <= tol, (prec, b, err)
+    for b in (0, 31, 32, 39):
+        i_o, gap = oracle.argmax(oracle.correlate(g, wl.signals[b]))
+        assert int(res[0][0]["index"][b, 0]) == i_o or gap <= GAP_EXCUSE, (prec, b)
 
 
 def test_search_executed_counts_fp16_synthesis():
