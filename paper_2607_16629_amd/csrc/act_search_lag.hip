@@ -933,10 +933,11 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
 // T = M - 2 E_b (rounded down to FP32; none without a bound) and appends the
 // pairs that reach it to a list (pairs[0] counts them; pass 0 clears it).
 // k_lag_rs_emit then takes the pairs one workgroup at a time and computes the
-// unit's 4 x 64 scores of that channel again, one per thread: FP32
-// multiply-adds of the table's and the search copy's 16-bit values over the
-// unit's k-steps in four interleaved chains (the certified bound E_b holds
-// for any order of the FP32 sums), scaled as the search scales them, and
+// unit's 4 x 64 scores of that channel again, each by RS_ES threads: FP32
+// multiply-adds of the table's and the search copy's 16-bit values over
+// every RS_ES-th k-step of the unit in four interleaved chains, then the
+// threads' partial sums (the certified bound E_b holds for any order of the
+// FP32 sums), scaled as the search scales them, and
 // emits those that reach T (one device atomic per pair reserves the list
 // entries).  A true arg-max atom has a pass-0 score of at least T, so its
 // pair is flagged, and its pass-1 score, within E_b of its true score,
@@ -963,13 +964,16 @@ __global__ void __launch_bounds__(256) k_lag_rs_flag(LagDev ld, SearchCtl ctl, i
     }
 }
 
+constexpr int RS_ES = 4;  // pass 1: threads sharing one score's k-steps
+
 template <bool BF>
-__global__ void __launch_bounds__(256) k_lag_rs_emit(LagDev ld, SearchCtl ctl, const int* __restrict__ units,
-                                                     int n_tg, const int* __restrict__ pairs) {
+__global__ void __launch_bounds__(256 * RS_ES) k_lag_rs_emit(LagDev ld, SearchCtl ctl, const int* __restrict__ units,
+                                                            int n_tg, const int* __restrict__ pairs) {
+    __shared__ float part[RS_ES][256];
     __shared__ unsigned s_cnt;
     __shared__ int s_base;
     const int U = 8 * ld.rs_cp_per_x * n_tg;
-    const int t = threadIdx.x, rb = t >> 6, c = t & 63;
+    const int t = threadIdx.x & 255, part_i = threadIdx.x >> 8, rb = t >> 6, c = t & 63;
     const int np = pairs[0];
     auto cvt = [](_Float16 h) {
         if constexpr (BF) return __uint_as_float((unsigned)__builtin_bit_cast(unsigned short, h) << 16);
@@ -984,13 +988,14 @@ __global__ void __launch_bounds__(256) k_lag_rs_emit(LagDev ld, SearchCtl ctl, c
         const int m = ld.tc_shift[min(tc, ld.n_tc - 1)];
         // the thread's column in its 32-column block: lanes c % 32 (lags
         // 0-7 of a k-step) and c % 32 + 32 (lags 8-15) of each fragment;
-        // the search copy's row b at element n_pad + b stride, sample e - N_pad + m
+        // the search copy's row b at element n_pad + b stride, sample e - N_pad + m.
+        // Thread part_i takes k-steps part_i, part_i + RS_ES, ...
         const char* gp = reinterpret_cast<const char*>(ld.G) +
                          ((size_t)(2 * cp + (c >> 5)) * ld.LS + kb) * 1024 + 16 * (c & 31);
         const char* rp = ld.shadow + 2 * ((size_t)b * ld.sh_stride + 16 * kb + m);
         float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 2
-        for (int ks = 0; ks < nk; ++ks) {
+        for (int ks = part_i; ks < nk; ks += RS_ES) {
             const f16x8 g0 = *reinterpret_cast<const f16x8*>(gp + 1024 * (size_t)ks);
             const f16x8 g1 = *reinterpret_cast<const f16x8*>(gp + 1024 * (size_t)ks + 512);
             const f16x8 x0 = *reinterpret_cast<const f16x8*>(rp + 32 * (size_t)ks);
@@ -1000,16 +1005,24 @@ __global__ void __launch_bounds__(256) k_lag_rs_emit(LagDev ld, SearchCtl ctl, c
 #pragma unroll
             for (int j = 0; j < 8; ++j) acc[j & 3] = fmaf(cvt(g1[j]), cvt(x1[j]), acc[j & 3]);
         }
-        const float raw = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        const float sc = tc < ld.n_tc ? ld.inv[(size_t)tc * ld.Qp + col] : 0.0f;
-        const float rs = ld.rscale[b], ri = rs > 0.0f ? 1.0f / rs : 0.0f;
-        const float p = (raw * sc) * ri;
-        const bool hit = fabsf(p) >= rs_threshold(ctl, b) && tc < ld.n_tc && col < ld.Q;
-        if (t == 0) s_cnt = 0u;
+        part[part_i][t] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        if (threadIdx.x == 0) s_cnt = 0u;
         __syncthreads();
-        const unsigned pos = hit ? atomicAdd(&s_cnt, 1u) : 0u;
+        bool hit = false;
+        unsigned pos = 0u;
+        float p = 0.0f;
+        if (part_i == 0) {
+            float raw = part[0][t];
+#pragma unroll
+            for (int i = 1; i < RS_ES; ++i) raw += part[i][t];
+            const float sc = tc < ld.n_tc ? ld.inv[(size_t)tc * ld.Qp + col] : 0.0f;
+            const float rs = ld.rscale[b], ri = rs > 0.0f ? 1.0f / rs : 0.0f;
+            p = (raw * sc) * ri;
+            hit = fabsf(p) >= rs_threshold(ctl, b) && tc < ld.n_tc && col < ld.Q;
+            if (hit) pos = atomicAdd(&s_cnt, 1u);
+        }
         __syncthreads();
-        if (t == 0) s_base = s_cnt ? atomicAdd(&ctl.cand_count[b], (int)s_cnt) : 0;
+        if (threadIdx.x == 0) s_base = s_cnt ? atomicAdd(&ctl.cand_count[b], (int)s_cnt) : 0;
         __syncthreads();
         const int j = s_base + (int)pos;
         if (hit && j < ctl.cap) {
@@ -1440,11 +1453,11 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
                                0, s, ld, ctl, batch, n_cg, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
             if (bf)
-                hipLaunchKernelGGL((k_lag_rs_emit<true>), dim3(8 * cus), dim3(256), 0, s, ld, ctl, p->lag_rs_units,
-                                   n_tg, p->lag_rs_pairs);
+                hipLaunchKernelGGL((k_lag_rs_emit<true>), dim3(2 * cus), dim3(256 * RS_ES), 0, s, ld, ctl,
+                                   p->lag_rs_units, n_tg, p->lag_rs_pairs);
             else
-                hipLaunchKernelGGL((k_lag_rs_emit<false>), dim3(8 * cus), dim3(256), 0, s, ld, ctl, p->lag_rs_units,
-                                   n_tg, p->lag_rs_pairs);
+                hipLaunchKernelGGL((k_lag_rs_emit<false>), dim3(2 * cus), dim3(256 * RS_ES), 0, s, ld, ctl,
+                                   p->lag_rs_units, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
             return ACT_OK;
         }
