@@ -260,6 +260,10 @@ def run_workload(name: str, steps: int, warmup: int):
     phases, search_ms, executed = _phase_pass(plan, step, min(steps, 3))
     chans = [0] if B == 1 else [0, B - 1]
     keep = _keep_results(plan, out, chans, order, wl.signals, g, bool(plan_kw.get("complex_atoms")))
+    # the lag-table search of 32+ channels keeps the residual copies in LDS
+    # unless the tuner chose the staged tiles (launch-shape form 1)
+    resident = (plan_kw["dict_"] == "lag" and not plan_kw.get("complex_atoms") and B >= 32
+                and plan.query(act.Q_LAG_RESIDENT) == 1 and (shape is None or shape.get("form", 0) == 0))
     plan.close()
 
     res = {
@@ -280,6 +284,9 @@ def run_workload(name: str, steps: int, warmup: int):
         "_keep": keep,
     }
     kname, ksrc = KERNELS[(plan_kw["dict_"], plan_kw["prec"])]
+    if resident:
+        kname = "k_search_lag_rs"
+        res["phases_note"] = "rerun: the emission pass of the resident form (flagged units scored again)"
     if kind == "hbm":
         algo_bytes = g.size * g.n * elt + B * g.n * elt
         achieved = algo_bytes / (search_ms * 1e-3) / 1e9

@@ -164,9 +164,12 @@ void act_plan_destroy(act_plan_t plan);
 
 /* Plan facts: ACT_Q_ATOMS (dictionary size), ACT_Q_TABLE_BYTES (table bytes,
  * 0 for synthesis), ACT_Q_N_PAD (padded row length of tables and shadows),
- * ACT_Q_CAND_CAP, ACT_Q_WORKSPACE_BYTES.  Returns -1 for an unknown key. */
+ * ACT_Q_CAND_CAP, ACT_Q_WORKSPACE_BYTES, ACT_Q_LAG_RESIDENT (1 when the
+ * lag-table search of 32 or more channels can keep each group of 32
+ * channels' residual copy resident in LDS: launch-shape form 0).  Returns -1
+ * for an unknown key. */
 enum { ACT_Q_ATOMS = 0, ACT_Q_TABLE_BYTES = 1, ACT_Q_N_PAD = 2, ACT_Q_CAND_CAP = 3,
-       ACT_Q_WORKSPACE_BYTES = 4 };
+       ACT_Q_WORKSPACE_BYTES = 4, ACT_Q_LAG_RESIDENT = 5 };
 int64_t act_plan_query(act_plan_t plan, int32_t key);
 
 /* Matrix-core work of one pass-0 coarse search of `batch` channels, in flops

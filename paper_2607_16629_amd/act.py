@@ -21,7 +21,7 @@ ACT_OK, ACT_ERR_INVALID, ACT_ERR_NOMEM, ACT_ERR_HIP, ACT_ERR_UNSUPPORTED = range
 ACT_DICT_SYNTH, ACT_DICT_TABLE, ACT_DICT_LAG = 0, 1, 2
 ACT_PREC_F64, ACT_PREC_F32, ACT_PREC_BF16, ACT_PREC_F16 = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_REFINE_REJECTED, FLAG_CAND_OVERFLOW, FLAG_RAGGED_EMPTY, FLAG_BAD_LENGTH = 1, 2, 8, 16, 32
-Q_ATOMS, Q_TABLE_BYTES, Q_N_PAD, Q_CAND_CAP, Q_WORKSPACE_BYTES = range(5)
+Q_ATOMS, Q_TABLE_BYTES, Q_N_PAD, Q_CAND_CAP, Q_WORKSPACE_BYTES, Q_LAG_RESIDENT = range(6)
 LEM_SCRATCH_BYTES = 16 << 20  # ACT_LEM_SCRATCH_BYTES: act_lem_decompose_noalloc's device array
 
 _DICTS = {"synth": ACT_DICT_SYNTH, "table": ACT_DICT_TABLE, "lag": ACT_DICT_LAG}

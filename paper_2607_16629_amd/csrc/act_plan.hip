@@ -744,6 +744,7 @@ extern "C" int64_t act_plan_query(act_plan_t p, int32_t key) {
         case ACT_Q_N_PAD: return p->n_pad;
         case ACT_Q_CAND_CAP: return p->cap;
         case ACT_Q_WORKSPACE_BYTES: return (int64_t)p->workspace_bytes;
+        case ACT_Q_LAG_RESIDENT: return p->lag_rs_cp ? 1 : 0;
         default: return -1;
     }
 }
