@@ -466,7 +466,10 @@ __device__ __forceinline__ void walk_atom(int k0, int k1, double fs, const doubl
 //   w(tau + H) = w(tau) v,       v = exp(2 a H^2),
 // (|w| and arg w are the rho and psi of walk_atom, |v| and arg v its
 // exp(-H^2/dt^2) and 4 pi c H^2): two complex products per sample, and no
-// separate envelope.  The window rule, ranges and rounding are walk_atom's.
+// separate envelope.  Its steps cost less than walk_atom's, so the recurrence
+// starts at 2 TB window samples (two per thread): inside such a window
+// dt >= (2 TB - 1)/18 samples, so |w| lies in [e^-122, e^41] and |v| >= e^-81,
+// far inside FP64's range; the rounding is walk_atom's.
 // visit(k, tau, E cos phi, E sin phi).
 template <int TB, typename F>
 __device__ __forceinline__ void walk_chirp(int k0, int k1, double fs, const double th[4], double inv_dt,
@@ -474,7 +477,7 @@ __device__ __forceinline__ void walk_chirp(int k0, int k1, double fs, const doub
     const double c = th[2], fc = th[1];
     const double ifs = 1.0 / fs;
     const int k = k0 + (int)(threadIdx.x % TB);
-    if (k1 - k0 >= 4 * TB) {
+    if (k1 - k0 >= 2 * TB) {
         const double H = (double)TB / fs, idt2 = inv_dt * inv_dt;
         const double tau0 = fma((double)k, ifs, -th[0]);
         const double u = tau0 * inv_dt;

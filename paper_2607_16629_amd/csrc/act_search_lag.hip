@@ -933,15 +933,17 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
 // T = M - 2 E_b (rounded down to FP32; none without a bound) and appends the
 // pairs that reach it to a list (pairs[0] counts them; pass 0 clears it).
 // k_lag_rs_emit then takes the pairs one workgroup at a time and computes the
-// unit's 4 x 64 scores of that channel again, each by RS_ES threads: FP32
-// multiply-adds of the table's and the search copy's 16-bit values over
-// every RS_ES-th k-step of the unit in four interleaved chains, then the
-// threads' partial sums (the certified bound E_b holds for any order of the
-// FP32 sums), scaled as the search scales them, and
-// emits those that reach T (one device atomic per pair reserves the list
-// entries).  A true arg-max atom has a pass-0 score of at least T, so its
-// pair is flagged, and its pass-1 score, within E_b of its true score,
-// reaches T too.
+// unit's 4 x 64 scores of that channel again on the matrix cores: wave w
+// runs every RS_EP-th k-step of the unit from w, as two MFMAs per k-step (the
+// unit's two column blocks, the table fragments as the search reads them)
+// whose A operand holds the four time centres' windows of the search copy in
+// rows 0..3 and zeros below; the workgroup then adds the RS_EP partial sums
+// of each score in a fixed order.
+// The certified bound E_b holds for any order and grouping of these FP32
+// sums.  Scores are scaled as the search scales them, and those that reach T
+// are emitted (one device atomic per pair reserves the list entries).  A true
+// arg-max atom has a pass-0 score of at least T, so its pair is flagged, and
+// its pass-1 score, within E_b of its true score, reaches T too.
 __device__ __forceinline__ float rs_threshold(const SearchCtl& ctl, int b) {
     const double eb = ctl.ebound[b];
     if (eb < 0.0) return INFINITY;
@@ -964,61 +966,94 @@ __global__ void __launch_bounds__(256) k_lag_rs_flag(LagDev ld, SearchCtl ctl, i
     }
 }
 
-constexpr int RS_ES = 4;  // pass 1: threads sharing one score's k-steps
+constexpr int RS_EP = 16;  // pass 1: k-step parts of a pair (one wave each, 64 columns)
+constexpr int RS_EK = 2;   // pass 1: k-steps whose operands a wave loads before their MFMAs
 
 template <bool BF>
-__global__ void __launch_bounds__(256 * RS_ES) k_lag_rs_emit(LagDev ld, SearchCtl ctl, const int* __restrict__ units,
-                                                            int n_tg, const int* __restrict__ pairs) {
-    __shared__ float part[RS_ES][256];
+__global__ void __launch_bounds__(64 * RS_EP) k_lag_rs_emit(LagDev ld, SearchCtl ctl, const int* __restrict__ units,
+                                                           int n_tg, const int* __restrict__ pairs) {
+    __shared__ float part[RS_EP][RS_TB * 64];
     __shared__ unsigned s_cnt;
     __shared__ int s_base;
     const int U = 8 * ld.rs_cp_per_x * n_tg;
-    const int t = threadIdx.x & 255, part_i = threadIdx.x >> 8, rb = t >> 6, c = t & 63;
+    const int lane = threadIdx.x & 63, part_i = threadIdx.x >> 6;
+    const int t = threadIdx.x, rb_t = t >> 6, c = t & 63;  // score (rb_t, c) of threads t < 4 x 64
+    // A fragment: lane row lane % 32 (time centre rb of the unit when below
+    // RS_TB, else a zero row), lags 8 (lane / 32) .. + 8 of each k-step
+    const int arow = lane & 31, ahalf = lane >> 5;
+    const f16x8 zero8 = {};
     const int np = pairs[0];
-    auto cvt = [](_Float16 h) {
-        if constexpr (BF) return __uint_as_float((unsigned)__builtin_bit_cast(unsigned short, h) << 16);
-        else return (float)h;
-    };
+    int e_next = blockIdx.x < np ? pairs[1 + blockIdx.x] : 0;
     for (int q = blockIdx.x; q < np; q += gridDim.x) {
-        const int e = pairs[1 + q], ch = e % RS_CH, sl = e / RS_CH;
+        const int e = e_next, ch = e % RS_CH, sl = e / RS_CH;
+        if (q + (int)gridDim.x < np) e_next = pairs[1 + q + gridDim.x];  // the next pair's entry, early
         const int cg = sl / U, us = sl - cg * U, b = cg * RS_CH + ch;
         const int* d = units + (size_t)us * RS_UD;
         const int cp = d[0], tc0 = d[1], kb = d[2], nk = d[3];
-        const int tc = tc0 + rb, col = cp * 64 + c;
-        const int m = ld.tc_shift[min(tc, ld.n_tc - 1)];
-        // the thread's column in its 32-column block: lanes c % 32 (lags
-        // 0-7 of a k-step) and c % 32 + 32 (lags 8-15) of each fragment;
-        // the search copy's row b at element n_pad + b stride, sample e - N_pad + m.
-        // Thread part_i takes k-steps part_i, part_i + RS_ES, ...
-        const char* gp = reinterpret_cast<const char*>(ld.G) +
-                         ((size_t)(2 * cp + (c >> 5)) * ld.LS + kb) * 1024 + 16 * (c & 31);
-        const char* rp = ld.shadow + 2 * ((size_t)b * ld.sh_stride + 16 * kb + m);
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 2
-        for (int ks = part_i; ks < nk; ks += RS_ES) {
-            const f16x8 g0 = *reinterpret_cast<const f16x8*>(gp + 1024 * (size_t)ks);
-            const f16x8 g1 = *reinterpret_cast<const f16x8*>(gp + 1024 * (size_t)ks + 512);
-            const f16x8 x0 = *reinterpret_cast<const f16x8*>(rp + 32 * (size_t)ks);
-            const f16x8 x1 = *reinterpret_cast<const f16x8*>(rp + 32 * (size_t)ks + 16);
+        // what the epilogue needs, requested before the k-steps
+        const float T = rs_threshold(ctl, b);
+        const float rs = ld.rscale[b], ri = rs > 0.0f ? 1.0f / rs : 0.0f;
+        const int tc = tc0 + rb_t, col = cp * 64 + c;
+        const float sc = t < RS_TB * 64 && tc < ld.n_tc ? ld.inv[(size_t)tc * ld.Qp + col] : 0.0f;
+        // time centre rb's window in the search copy's row b starts at
+        // element b stride + 16 kb + m_rb (sample 16 kb - N_pad + m_rb); the
+        // unit's descriptor holds glo - N_pad + m_rb + 16 kb (lag plans keep
+        // N_pad guards: the row stride is 2 N_pad)
+        const int arb = arow < RS_TB ? arow : 0;
+        const char* ap = ld.shadow + 2 * ((size_t)b * ld.sh_stride + d[4 + arb] - ld.rs_glo + ld.sh_stride / 2) +
+                         16 * ahalf;
+        // B fragments: the two column blocks' k-step fragments, 16 bytes per lane
+        const char* gp0 = reinterpret_cast<const char*>(ld.G) + ((size_t)(2 * cp) * ld.LS + kb) * 1024 + 16 * lane;
+        const char* gp1 = gp0 + (size_t)ld.LS * 1024;
+        f32x16 acc0 = {}, acc1 = {};
+        // RS_EK k-steps' operands in flight per wave, then their MFMAs
+        for (int k0 = part_i; k0 < nk; k0 += RS_EP * RS_EK) {
+            f16x8 a[RS_EK], b0[RS_EK], b1[RS_EK];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) acc[j & 3] = fmaf(cvt(g0[j]), cvt(x0[j]), acc[j & 3]);
+            for (int i = 0; i < RS_EK; ++i) {
+                const int ks = k0 + i * RS_EP;
+                a[i] = b0[i] = b1[i] = zero8;
+                if (ks < nk) {
+                    if (arow < RS_TB) a[i] = *reinterpret_cast<const f16x8*>(ap + 32 * (size_t)ks);
+                    b0[i] = *reinterpret_cast<const f16x8*>(gp0 + 1024 * (size_t)ks);
+                    b1[i] = *reinterpret_cast<const f16x8*>(gp1 + 1024 * (size_t)ks);
+                }
+            }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) acc[j & 3] = fmaf(cvt(g1[j]), cvt(x1[j]), acc[j & 3]);
+            for (int i = 0; i < RS_EK; ++i) {
+                if (k0 + i * RS_EP < nk) {
+                    if constexpr (BF) {
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[i]),
+                                                                       __builtin_bit_cast(bf16x8, b0[i]), acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[i]),
+                                                                       __builtin_bit_cast(bf16x8, b1[i]), acc1, 0, 0, 0);
+                    } else {
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[i], b0[i], acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[i], b1[i], acc1, 0, 0, 0);
+                    }
+                }
+            }
         }
-        part[part_i][t] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        // rows 0..3 (the unit's time centres) sit in accumulator slots 0..3
+        // of lanes 0..31, column lane
+        if (lane < 32) {
+#pragma unroll
+            for (int rb = 0; rb < RS_TB; ++rb) {
+                part[part_i][rb * 64 + lane] = acc0[rb];
+                part[part_i][rb * 64 + 32 + lane] = acc1[rb];
+            }
+        }
         if (threadIdx.x == 0) s_cnt = 0u;
         __syncthreads();
         bool hit = false;
         unsigned pos = 0u;
         float p = 0.0f;
-        if (part_i == 0) {
+        if (t < RS_TB * 64) {
             float raw = part[0][t];
 #pragma unroll
-            for (int i = 1; i < RS_ES; ++i) raw += part[i][t];
-            const float sc = tc < ld.n_tc ? ld.inv[(size_t)tc * ld.Qp + col] : 0.0f;
-            const float rs = ld.rscale[b], ri = rs > 0.0f ? 1.0f / rs : 0.0f;
+            for (int i = 1; i < RS_EP; ++i) raw += part[i][t];
             p = (raw * sc) * ri;
-            hit = fabsf(p) >= rs_threshold(ctl, b) && tc < ld.n_tc && col < ld.Q;
+            hit = fabsf(p) >= T && tc < ld.n_tc && col < ld.Q;
             if (hit) pos = atomicAdd(&s_cnt, 1u);
         }
         __syncthreads();
@@ -1453,10 +1488,10 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
                                0, s, ld, ctl, batch, n_cg, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
             if (bf)
-                hipLaunchKernelGGL((k_lag_rs_emit<true>), dim3(2 * cus), dim3(256 * RS_ES), 0, s, ld, ctl,
+                hipLaunchKernelGGL((k_lag_rs_emit<true>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
                                    p->lag_rs_units, n_tg, p->lag_rs_pairs);
             else
-                hipLaunchKernelGGL((k_lag_rs_emit<false>), dim3(2 * cus), dim3(256 * RS_ES), 0, s, ld, ctl,
+                hipLaunchKernelGGL((k_lag_rs_emit<false>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
                                    p->lag_rs_units, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
             return ACT_OK;
