@@ -316,56 +316,6 @@ __device__ __forceinline__ void support_window(int n, double fs, const double th
     k1 = (int)fmax((double)k0, fmin((double)n, ceil(c + half) + 1.0));
 }
 
-// FP64 rescoring: one wave per candidate whose search score lies inside the
-// certified margin of the channel's final maximum; others are marked NaN.
-__global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __restrict__ resid) {
-    const int b = blockIdx.y;
-    const double eb = P.ebound[b];
-    if (eb < 0.0) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int cnt = min(P.cand_count[b], P.cap);
-    // per-atom bounds: candidates carry upper bounds, gmax the largest lower bound
-    const double T = P.per_atom ? (double)bitsf(P.gmax[b]) : (double)bitsf(P.gmax[b]) - 2.0 * eb;
-    const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
-    const double* r = resid + cg.off;
-    const int wpb = blockDim.x / kWave;
-    for (int j = blockIdx.x * wpb + threadIdx.x / kWave; j < cnt; j += gridDim.x * wpb) {
-        const size_t slot = (size_t)b * P.cap + j;
-        if ((double)fabsf(P.cand_score[slot]) < T) {
-            if (lane == 0) P.cand_p64[slot] = __longlong_as_double(0x7ff8000000000000LL);
-            continue;
-        }
-        double th[4];
-        grid_theta(cg.g, (long long)P.cand_idx[slot], th);
-        const double inv_dt = 1.0 / exp(th[3]);
-        double s = 0.0, q = 0.0, sb = 0.0;
-        // the atom's support window: the samples beyond it add below
-        // 2.6e-18 sqrt(n) |r| to the score (|g| >= 1), under FP64 rounding
-        int k0, k1;
-        support_window(cg.g.n, cg.g.fs, th, k0, k1);
-        if (P.cplx) {
-            for (int k = k0 + lane; k < k1; k += kWave) {
-                double re, im, e;
-                atom_parts64(sample_time(k, cg.g.fs), th[0], th[1], th[2], inv_dt, re, im, e);
-                s += re * r[k];
-                sb += im * r[k];
-                q += e * e;
-            }
-            sb = wave_sum(sb);
-        } else {
-            for (int k = k0 + lane; k < k1; k += kWave) {
-                const double v = atom_sample64(sample_time(k, cg.g.fs), th[0], th[1], th[2], inv_dt);
-                s += v * r[k];
-                q += v * v;
-            }
-        }
-        s = wave_sum(s);
-        q = wave_sum(q);
-        if (P.cplx) s = sqrt(s * s + sb * sb);
-        if (lane == 0) P.cand_p64[slot] = q > 0.0 ? s / sqrt(q) : 0.0;
-    }
-}
-
 // --------------------------------------------------------------------------
 // refinement objective, block-wide
 // --------------------------------------------------------------------------
@@ -510,6 +460,62 @@ __device__ __forceinline__ void walk_chirp(int k0, int k1, double fs, const doub
             sincospi(2.0 * (c * tau * tau + fc * tau), &si, &co);
             visit(kk, tau, e * co, e * si);
         }
+    }
+}
+
+// FP64 rescoring: one wave per candidate whose search score lies inside the
+// certified margin of the channel's final maximum; others are marked NaN.
+// The atom's samples over its support window come from the chirp walk (the
+// lanes' first samples direct, then complex-product recurrences; windows of
+// fewer than two samples per lane are evaluated directly).  Each sample is
+// then within about 2e-12 of direct evaluation (atom peak 1), so a score
+// moves by at most 2e-12 sqrt(window) |r|: far inside every search form's
+// certified margin, and below the 1e-6 relative gap at which selections are
+// held to the exact arg-max.
+__global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __restrict__ resid) {
+    const int b = blockIdx.y;
+    const double eb = P.ebound[b];
+    if (eb < 0.0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int cnt = min(P.cand_count[b], P.cap);
+    // per-atom bounds: candidates carry upper bounds, gmax the largest lower bound
+    const double T = P.per_atom ? (double)bitsf(P.gmax[b]) : (double)bitsf(P.gmax[b]) - 2.0 * eb;
+    const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
+    const double* r = resid + cg.off;
+    const int wpb = blockDim.x / kWave;
+    for (int j = blockIdx.x * wpb + threadIdx.x / kWave; j < cnt; j += gridDim.x * wpb) {
+        const size_t slot = (size_t)b * P.cap + j;
+        if ((double)fabsf(P.cand_score[slot]) < T) {
+            if (lane == 0) P.cand_p64[slot] = __longlong_as_double(0x7ff8000000000000LL);
+            continue;
+        }
+        double th[4];
+        grid_theta(cg.g, (long long)P.cand_idx[slot], th);
+        const double inv_dt = 1.0 / exp(th[3]);
+        double s = 0.0, q = 0.0, sb = 0.0;
+        // the atom's support window: the samples beyond it add below
+        // 2.6e-18 sqrt(n) |r| to the score (|g| >= 1), under FP64 rounding
+        int k0, k1;
+        support_window(cg.g.n, cg.g.fs, th, k0, k1);
+        if (P.cplx) {
+            walk_chirp<kWave>(k0, k1, cg.g.fs, th, inv_dt, [&](int k, double, double re, double im) {
+                const double rk = r[k];
+                s += re * rk;
+                sb += im * rk;
+                q += re * re + im * im;
+            });
+            sb = wave_sum(sb);
+        } else {
+            walk_chirp<kWave>(k0, k1, cg.g.fs, th, inv_dt, [&](int k, double, double v, double) {
+                const double rk = r[k];
+                s += v * rk;
+                q += v * v;
+            });
+        }
+        s = wave_sum(s);
+        q = wave_sum(q);
+        if (P.cplx) s = sqrt(s * s + sb * sb);
+        if (lane == 0) P.cand_p64[slot] = q > 0.0 ? s / sqrt(q) : 0.0;
     }
 }
 
