@@ -1192,30 +1192,36 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
 
     // unit atom at theta*, coefficient and update (Sec. III-A, Eq. (4)):
     // |w|^2 and <w, r> of the raw atom w in one pass, c = <w, r>/|w|,
-    // r -= c w/|w|.  A staged kernel keeps w in the LDS copy of the residual
-    // (the refinement, which read it, has passed its last barrier; each thread
-    // reads back only the samples it wrote).
-    const double ifs = 1.0 / G.fs;
+    // r -= c w/|w|, over the atom's support window (w below 2.6e-18 of its
+    // peak outside it, where the update would not move r beyond rounding), w
+    // from the chirp walk.  A staged kernel keeps w in the LDS copy of the
+    // residual (the refinement, which read it, has passed its last barrier;
+    // each thread reads back only the samples it wrote: the walk's samples of
+    // thread i are k0 + i + TB j).
+    int k0, k1;
+    support_window(G.n, G.fs, th, k0, k1);
     double acc[2] = {0.0, 0.0};
-    for (int t = threadIdx.x; t < G.n; t += TB) {
-        const double v = atom_sample64((double)t * ifs, th[0], th[1], th[2], inv_dt);
+    walk_chirp<TB>(k0, k1, G.fs, th, inv_dt, [&](int t, double, double v, double) {
         if constexpr (STAGE) s_dyn[t] = v;
         acc[0] += v * v;
         acc[1] += v * r[t];
-    }
+    });
     block_sum<TB, 2>(acc, red);
     const double nrm = sqrt(acc[0]);
     const double inrm = nrm >= 1e-300 ? 1.0 / nrm : 0.0;
     const double ck = acc[1] * inrm;
-    for (int t = threadIdx.x; t < G.n; t += TB) {
-        double w;
-        if constexpr (STAGE)
-            w = s_dyn[t];
-        else
-            w = atom_sample64((double)t * ifs, th[0], th[1], th[2], inv_dt);
-        const double v = w * inrm;
-        r[t] = r[t] - ck * v;
-        if (approx) approx[cg.off + t] = approx[cg.off + t] + ck * v;
+    if constexpr (STAGE) {
+        for (int t = k0 + (int)threadIdx.x; t < k1; t += TB) {
+            const double v = s_dyn[t] * inrm;
+            r[t] = r[t] - ck * v;
+            if (approx) approx[cg.off + t] = approx[cg.off + t] + ck * v;
+        }
+    } else {
+        walk_chirp<TB>(k0, k1, G.fs, th, inv_dt, [&](int t, double, double w, double) {
+            const double v = w * inrm;
+            r[t] = r[t] - ck * v;
+            if (approx) approx[cg.off + t] = approx[cg.off + t] + ck * v;
+        });
     }
     __syncthreads();
     const double E = refresh_channel<TB>(P, b, r, G.n, red, false);
