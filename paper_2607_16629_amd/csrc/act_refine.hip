@@ -1123,10 +1123,12 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
         box.lo[0] = cg.box_lo0;
         box.hi[0] = cg.box_hi0;
     }
+    if constexpr (STAGE) {  // the residual's LDS copy, read by the refinement and the update
+        for (int t = threadIdx.x; t < G.n; t += TB) s_dyn[t] = r[t];
+        __syncthreads();
+    }
     if (steps > 0) {
         if constexpr (STAGE) {
-            for (int t = threadIdx.x; t < G.n; t += TB) s_dyn[t] = r[t];
-            __syncthreads();
             if constexpr (CPLX)
                 fl |= refine_block<TB, kObjComplex>(s_dyn, G, box, th0, steps, th, &J, red);
             else
@@ -1146,17 +1148,22 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
     if constexpr (CPLX) {
         // complex atom: amplitudes (alpha, beta) of u = E cos phi and v = E sin
         // phi by least squares, r -= alpha u + beta v (a pair that is singular
-        // to working precision falls back to the fit on u alone)
+        // to working precision falls back to the fit on u alone).  Both
+        // passes run over the atom's support window (E below 2.6e-18 of its
+        // peak outside it) with u and v from the chirp walk.
+        int k0, k1;
+        support_window(G.n, G.fs, th, k0, k1);
         double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int t = threadIdx.x; t < G.n; t += TB) {
-            double re, im, e;
-            atom_parts64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt, re, im, e);
+        walk_chirp<TB>(k0, k1, G.fs, th, inv_dt, [&](int t, double, double re, double im) {
+            double rt;
+            if constexpr (STAGE) rt = s_dyn[t];
+            else rt = r[t];
             acc5[0] += re * re;
             acc5[1] += im * im;
             acc5[2] += re * im;
-            acc5[3] += re * r[t];
-            acc5[4] += im * r[t];
-        }
+            acc5[3] += re * rt;
+            acc5[4] += im * rt;
+        });
         block_sum<TB, 5>(acc5, red);
         const double uu = acc5[0], vv = acc5[1], uv = acc5[2], ur = acc5[3], vr = acc5[4];
         const double det = uu * vv - uv * uv;
@@ -1168,13 +1175,11 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
             al = (vv * ur - uv * vr) / det;
             be = (uu * vr - uv * ur) / det;
         }
-        for (int t = threadIdx.x; t < G.n; t += TB) {
-            double re, im, e;
-            atom_parts64(sample_time(t, G.fs), th[0], th[1], th[2], inv_dt, re, im, e);
+        walk_chirp<TB>(k0, k1, G.fs, th, inv_dt, [&](int t, double, double re, double im) {
             const double w = al * re + be * im;
             r[t] = r[t] - w;
             if (approx) approx[cg.off + t] = approx[cg.off + t] + w;
-        }
+        });
         __syncthreads();
         const double E = refresh_channel<TB>(P, b, r, G.n, red, false);
         if (threadIdx.x == 0) {
@@ -1194,17 +1199,23 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
     // |w|^2 and <w, r> of the raw atom w in one pass, c = <w, r>/|w|,
     // r -= c w/|w|, over the atom's support window (w below 2.6e-18 of its
     // peak outside it, where the update would not move r beyond rounding), w
-    // from the chirp walk.  A staged kernel keeps w in the LDS copy of the
-    // residual (the refinement, which read it, has passed its last barrier;
-    // each thread reads back only the samples it wrote: the walk's samples of
-    // thread i are k0 + i + TB j).
+    // from the chirp walk.  A staged kernel reads r from its LDS copy and
+    // keeps w in its place (the refinement, which read the copy, has passed
+    // its last barrier; each thread reads and writes only its own samples:
+    // the walk's samples of thread i are k0 + i + TB j).
     int k0, k1;
     support_window(G.n, G.fs, th, k0, k1);
     double acc[2] = {0.0, 0.0};
     walk_chirp<TB>(k0, k1, G.fs, th, inv_dt, [&](int t, double, double v, double) {
-        if constexpr (STAGE) s_dyn[t] = v;
+        double rt;
+        if constexpr (STAGE) {
+            rt = s_dyn[t];  // the residual's LDS copy, then the atom in its place
+            s_dyn[t] = v;
+        } else {
+            rt = r[t];
+        }
         acc[0] += v * v;
-        acc[1] += v * r[t];
+        acc[1] += v * rt;
     });
     block_sum<TB, 2>(acc, red);
     const double nrm = sqrt(acc[0]);

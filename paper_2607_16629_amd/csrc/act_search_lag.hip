@@ -953,16 +953,42 @@ __device__ __forceinline__ float rs_threshold(const SearchCtl& ctl, int b) {
     return T;
 }
 
-__global__ void __launch_bounds__(256) k_lag_rs_flag(LagDev ld, SearchCtl ctl, int batch, int n_cg, int n_tg,
-                                                     int* __restrict__ pairs) {
+constexpr int RS_FL_TB = 1024;                     // flag pass: threads per block
+constexpr int RS_FL_PER = 2;                       // map entries per thread (channels of one slot)
+constexpr int RS_FL_CHUNK = RS_FL_TB * RS_FL_PER;  // entries per block and step
+
+__global__ void __launch_bounds__(RS_FL_TB) k_lag_rs_flag(LagDev ld, SearchCtl ctl, int batch, int n_cg,
+                                                          int n_tg, int* __restrict__ pairs) {
+    // a block gathers the flagged entries of its chunk in LDS and reserves
+    // their list positions with one device atomic: flagged entries are
+    // sparse, so per-entry or per-wave reservations on the one list counter
+    // serialise
+    __shared__ int s_list[RS_FL_CHUNK];
+    __shared__ int s_n, s_base;
     const int perq = ld.rs_cp_per_x * n_tg, U = 8 * perq;
-    const long long n = (long long)n_cg * U * RS_CH;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        const long long sl = e / RS_CH;
-        const int ch = (int)(e % RS_CH), cg = (int)(sl / U), us = (int)(sl % U), x = us / perq;
-        const int b = cg * RS_CH + ch;
-        if (us - x * perq >= ld.rs_cp_count[x] * n_tg || b >= batch) continue;
-        if (ld.rs_map[e] >= rs_threshold(ctl, b)) pairs[1 + atomicAdd(&pairs[0], 1)] = (int)e;
+    const int n = n_cg * U * RS_CH;  // a multiple of RS_CH; the launch checks that it fits an int
+    for (int c0 = blockIdx.x * RS_FL_CHUNK; c0 < n; c0 += gridDim.x * RS_FL_CHUNK) {
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+        const int e0 = c0 + RS_FL_PER * (int)threadIdx.x;  // RS_FL_PER divides RS_CH: one slot
+        if (e0 < n) {
+            const int sl = e0 / RS_CH, ch0 = e0 % RS_CH, cg = sl / U, us = sl - cg * U, x = us / perq;
+            if (us - x * perq < ld.rs_cp_count[x] * n_tg) {
+                const float2 m = *reinterpret_cast<const float2*>(ld.rs_map + e0);
+                const float mv[RS_FL_PER] = {m.x, m.y};
+#pragma unroll
+                for (int j = 0; j < RS_FL_PER; ++j) {
+                    const int b = cg * RS_CH + ch0 + j;
+                    if (b < batch && mv[j] >= rs_threshold(ctl, b)) s_list[atomicAdd(&s_n, 1)] = e0 + j;
+                }
+            }
+        }
+        __syncthreads();
+        const int cnt = s_n;
+        if (threadIdx.x == 0 && cnt) s_base = atomicAdd(&pairs[0], cnt);
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) pairs[1 + s_base + i] = s_list[i];
+        __syncthreads();  // s_n and s_list are reused by the next chunk
     }
 }
 
@@ -1484,7 +1510,11 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
         ld.rs_pairs = p->lag_rs_pairs;
         if (ctl.pass && !ctl.dump) {
             const long long n = (long long)n_cg * 8 * ld.rs_cp_per_x * n_tg * RS_CH;
-            hipLaunchKernelGGL(k_lag_rs_flag, dim3((unsigned)std::min<long long>((n + 255) / 256, 16LL * cus)), dim3(256),
+            if (n > INT_MAX) {
+                set_error("lag-table search: the resident form's map exceeds 2^31 entries");
+                return ACT_ERR_UNSUPPORTED;
+            }
+            hipLaunchKernelGGL(k_lag_rs_flag, dim3((unsigned)std::min<long long>((n + RS_FL_CHUNK - 1) / RS_FL_CHUNK, cus)), dim3(RS_FL_TB),
                                0, s, ld, ctl, batch, n_cg, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
             if (bf)
