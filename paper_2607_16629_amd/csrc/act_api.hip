@@ -61,7 +61,7 @@ static act_status enqueue_order(act_plan_s* p, int batch, int k, int order, doub
                                 double* energy, double* gap, int* flags, hipStream_t s) {
     act_status st;
     if ((st = timed(p, 0, s, [&] { return launch_search(p, batch, 0, s); })) != ACT_OK) return st;
-    if ((st = launch_overflow_check(p, batch, s)) != ACT_OK) return st;
+    if (!search_emits_certified_set(p, batch) && (st = launch_overflow_check(p, batch, s)) != ACT_OK) return st;
     if ((st = timed(p, 1, s, [&] { return launch_search(p, batch, 1, s); })) != ACT_OK) return st;
     if ((st = timed(p, 2, s, [&] { return launch_rescore(p, batch, resid, s); })) != ACT_OK) return st;
     return timed(p, 3, s, [&] {

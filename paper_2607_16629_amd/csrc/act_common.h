@@ -428,6 +428,10 @@ act_status launch_select_refine_update(act_plan_s* p, int batch, int k, int orde
                                        long long* index, double* energy, double* gap, int* flags,
                                        hipStream_t s);
 act_status launch_overflow_check(act_plan_s* p, int batch, hipStream_t s);
+// True when a search of `batch` channels lists exactly the certified set in its
+// second pass (the lag table's resident form): no overflow check or rerun
+// applies to it.
+bool search_emits_certified_set(const act_plan_s* p, int batch);
 act_status launch_refine_many(act_plan_s* p, int m, const double* resid, const double* theta0,
                               int steps, double* theta, double* value, int* flags, hipStream_t s);
 act_status launch_refine_many_f32(act_plan_s* p, int m, const float* resid, const double* theta0, int steps,

@@ -1123,7 +1123,7 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
         box.lo[0] = cg.box_lo0;
         box.hi[0] = cg.box_hi0;
     }
-    if constexpr (STAGE) {  // the residual's LDS copy, read by the refinement and the update
+    if constexpr (STAGE) {  // the residual's LDS copy, read by the refinement (and the complex fit)
         for (int t = threadIdx.x; t < G.n; t += TB) s_dyn[t] = r[t];
         __syncthreads();
     }
@@ -1199,23 +1199,17 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
     // |w|^2 and <w, r> of the raw atom w in one pass, c = <w, r>/|w|,
     // r -= c w/|w|, over the atom's support window (w below 2.6e-18 of its
     // peak outside it, where the update would not move r beyond rounding), w
-    // from the chirp walk.  A staged kernel reads r from its LDS copy and
-    // keeps w in its place (the refinement, which read the copy, has passed
-    // its last barrier; each thread reads and writes only its own samples:
-    // the walk's samples of thread i are k0 + i + TB j).
+    // from the chirp walk.  A staged kernel keeps w in the LDS copy of the
+    // residual (the refinement, which read it, has passed its last barrier;
+    // each thread reads back only the samples it wrote: the walk's samples of
+    // thread i are k0 + i + TB j).
     int k0, k1;
     support_window(G.n, G.fs, th, k0, k1);
     double acc[2] = {0.0, 0.0};
     walk_chirp<TB>(k0, k1, G.fs, th, inv_dt, [&](int t, double, double v, double) {
-        double rt;
-        if constexpr (STAGE) {
-            rt = s_dyn[t];  // the residual's LDS copy, then the atom in its place
-            s_dyn[t] = v;
-        } else {
-            rt = r[t];
-        }
+        if constexpr (STAGE) s_dyn[t] = v;
         acc[0] += v * v;
-        acc[1] += v * rt;
+        acc[1] += v * r[t];
     });
     block_sum<TB, 2>(acc, red);
     const double nrm = sqrt(acc[0]);

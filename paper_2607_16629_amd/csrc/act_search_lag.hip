@@ -651,32 +651,6 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
         S.rinv[threadIdx.x] = ri;
         S.wmax[threadIdx.x] = 0u;
     }
-    // the group's copies: samples [-glo, len - glo) of each channel (zero
-    // outside the signal, also past the batch), 16 bytes per thread and step,
-    // RS_FILL steps' loads in flight at a time
-    {
-        constexpr int RS_FILL = 10;
-        const int per = ld.rs_len / 8, chunks = RS_CH * per;
-        for (int c0 = threadIdx.x; c0 < chunks; c0 += RS_FILL * 64 * RS_WAVES) {
-            f16x8 v[RS_FILL];
-#pragma unroll
-            for (int i = 0; i < RS_FILL; ++i) {
-                const int c = c0 + i * 64 * RS_WAVES, sl = c / per, j = c - sl * per, b = ch0 + sl;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) v[i][k] = (_Float16)0.0f;
-                if (c < chunks && b < batch)
-                    v[i] = *reinterpret_cast<const f16x8*>(
-                        ld.shadow + 2 * ((size_t)g.n_pad + (size_t)b * ld.sh_stride + 8 * j - ld.rs_glo));
-            }
-#pragma unroll
-            for (int i = 0; i < RS_FILL; ++i) {
-                const int c = c0 + i * 64 * RS_WAVES, sl = c / per, j = c - sl * per;
-                if (c < chunks) rs_res[sl * (ld.rs_stride / 8) + j] = v[i];
-            }
-        }
-    }
-    __syncthreads();
-
     const int total = ld.rs_cp_count[xcd] * n_tg;
     const int qbase = xcd * ld.rs_cp_per_x * n_tg;  // the pair's first unit in list order
     const int* qunits = units + (size_t)qbase * RS_UD;
@@ -767,6 +741,8 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
         }
         nmap = 0;
     };
+    // the first unit's table fragments and epilogue inputs are requested
+    // before the copies are filled, so that they arrive together
     int k = next_k(0);
     Unit cur;
     if (k < rounds) {
@@ -774,6 +750,31 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
         load_first(first_addr(true, cur, 0), first_addr(true, cur, 1));
         load_eps(cur, sc);
     }
+    // the group's copies: samples [-glo, len - glo) of each channel (zero
+    // outside the signal, also past the batch), 16 bytes per thread and step,
+    // RS_FILL steps' loads in flight at a time
+    {
+        constexpr int RS_FILL = 10;
+        const int per = ld.rs_len / 8, chunks = RS_CH * per;
+        for (int c0 = threadIdx.x; c0 < chunks; c0 += RS_FILL * 64 * RS_WAVES) {
+            f16x8 v[RS_FILL];
+#pragma unroll
+            for (int i = 0; i < RS_FILL; ++i) {
+                const int c = c0 + i * 64 * RS_WAVES, sl = c / per, j = c - sl * per, b = ch0 + sl;
+#pragma unroll
+                for (int h = 0; h < 8; ++h) v[i][h] = (_Float16)0.0f;
+                if (c < chunks && b < batch)
+                    v[i] = *reinterpret_cast<const f16x8*>(
+                        ld.shadow + 2 * ((size_t)g.n_pad + (size_t)b * ld.sh_stride + 8 * j - ld.rs_glo));
+            }
+#pragma unroll
+            for (int i = 0; i < RS_FILL; ++i) {
+                const int c = c0 + i * 64 * RS_WAVES, sl = c / per, j = c - sl * per;
+                if (c < chunks) rs_res[sl * (ld.rs_stride / 8) + j] = v[i];
+            }
+        }
+    }
+    __syncthreads();
     while (k < rounds) {
         // everything issued for this unit has landed
 #pragma unroll
@@ -1335,6 +1336,10 @@ static act_status prepare_lag_rs(act_plan_s* p, const std::vector<int2>& span, h
 // Whether a search of `batch` channels runs in the resident-residual form.
 static bool lag_rs_use(const act_plan_s* p, int batch) {
     return p->lag_rs_cp && batch >= RS_CH && (batch + RS_CH - 1) / RS_CH <= p->lag_rs_ncg && p->shape.form == 0;
+}
+
+bool search_emits_certified_set(const act_plan_s* p, int batch) {
+    return p->desc.dict == ACT_DICT_LAG && !p->desc.ragged && lag_rs_use(p, batch);
 }
 
 act_status build_lag_table(act_plan_s* p, hipStream_t s) {
