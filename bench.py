@@ -262,7 +262,7 @@ def run_workload(name: str, steps: int, warmup: int):
     keep = _keep_results(plan, out, chans, order, wl.signals, g, bool(plan_kw.get("complex_atoms")))
     # the lag-table search of 32+ channels keeps the residual copies in LDS
     # unless the tuner chose the staged tiles (launch-shape form 1)
-    resident = (plan_kw["dict_"] == "lag" and not plan_kw.get("complex_atoms") and B >= 32
+    resident = (plan_kw["dict_"] == "lag" and B >= 32
                 and plan.query(act.Q_LAG_RESIDENT) == 1 and (shape is None or shape.get("form", 0) == 0))
     plan.close()
 

@@ -342,7 +342,7 @@ typedef struct {
     int32_t chan_per_fc;    /* FP16 synthesis of several channels: channels that share an f_c among a
                                tile's 128 columns (power of two <= 64); 0 for the other searches */
     int32_t from_cache;     /* 1: taken from the cache file without timing */
-    int32_t form;           /* lag-table search of real atoms on >= 32 channels: 0 keeps each group of
+    int32_t form;           /* lag-table search of plain plans on >= 32 channels: 0 keeps each group of
                                32 channels' residual copy resident in LDS (where the grid allows it;
                                grid_per_cu is then unused), 1 stages the residual per tile */
     double ms;              /* mean search time per launch with this shape */

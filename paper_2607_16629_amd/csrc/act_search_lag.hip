@@ -583,7 +583,8 @@ __global__ void __launch_bounds__(256, 1) k_search_lag(GridDev g, LagDev ld, Sea
 }
 
 // ---------------------------------------------------------------------------
-// Resident-residual form: real atoms of plain plans, at least 32 channels.
+// Resident-residual form: plain plans (real or complex atoms), at least 32
+// channels.
 //
 // A workgroup of 8 waves holds the FP16/BF16 search copies of one group of 32
 // channels in LDS, each with zero guards wide enough for every lag a unit
@@ -629,8 +630,11 @@ struct RsScratch {
 // Read through the scalar cache: a kernel argument the kernel never writes.
 constexpr int RS_UD = 8;
 
-// DUMP: act_correlate's score dump instead of the max map.
-template <bool DUMP, bool BF>
+// DUMP: act_correlate's score dump instead of the max map.  CPLX: complex
+// atoms; a unit's two column blocks are the cos and sin parts of the same 32
+// atoms, so a lane's two accumulators are (a, b) of one atom and its score is
+// sqrt(a^2 + b^2) / |E_w|, as in the staged tiles.
+template <bool DUMP, bool BF, bool CPLX>
 __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, LagDev ld, SearchCtl ctl,
                                                                  const int* __restrict__ units, int batch,
                                                                  int n_cg, int n_tg) {
@@ -725,9 +729,14 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
     auto load_eps = [&](const Unit& x, float (&dsc)[RS_TB][2]) {
 #pragma unroll
         for (int rb = 0; rb < RS_TB; ++rb) {
-            const float* src = ld.inv + (size_t)min(x.tc0 + rb, ld.n_tc - 1) * ld.Qp + x.cp * 64 + (lane & 31);
-            dsc[rb][0] = src[0];
-            dsc[rb][1] = src[32];
+            const size_t row = (size_t)min(x.tc0 + rb, ld.n_tc - 1) * ld.Qp;
+            if constexpr (CPLX) {  // one atom per lane: the same 1/|E_w| for its cos and sin columns
+                dsc[rb][0] = dsc[rb][1] = ld.inv[row + x.cp * 32 + (lane & 31)];
+            } else {
+                const float* src = ld.inv + row + x.cp * 64 + (lane & 31);
+                dsc[rb][0] = src[0];
+                dsc[rb][1] = src[32];
+            }
         }
     };
     // pass 0: the count of map entries held in LDS
@@ -854,12 +863,18 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
         if (has_next) load_eps(nxt, sc_n);
 
         // ---- epilogue.  Lane holds column ecol0 + 32 cb of rows
-        // (tc0 + rb, slot lg_row(v, lane)); p = (raw / |g|) / s_b.  Its
-        // lane-dependent addresses use an opaque copy of the lane index, so
-        // that they are formed here and not kept live across the unit loop.
+        // (tc0 + rb, slot lg_row(v, lane)) (complex atoms: atom ecol0, its
+        // cos and sin parts); p = (raw / |g|) / s_b.  Its lane-dependent
+        // addresses use an opaque copy of the lane index, so that they are
+        // formed here and not kept live across the unit loop.
         int elane = lane;
         asm volatile("" : "+v"(elane));
-        const int ecol0 = cur.cp * 64 + (elane & 31);
+        const int ecol0 = cur.cp * (CPLX ? 32 : 64) + (elane & 31);
+        // the raw score of accumulator block cb (complex: of the lane's atom)
+        auto raw = [&](int rb, int cb, int v) {
+            return CPLX ? sqrtf(acc[rb][0][v] * acc[rb][0][v] + acc[rb][1][v] * acc[rb][1][v]) : acc[rb][cb][v];
+        };
+        constexpr int NA = CPLX ? 1 : 2;  // atoms of a lane per row
         if (DUMP) {
 #pragma unroll
             for (int rb = 0; rb < RS_TB; ++rb)
@@ -868,9 +883,9 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
                     const int sl = lg_row(v, elane), b = ch0 + sl, tc = tc0 + rb;
                     const float ri = S.rinv[sl];
 #pragma unroll
-                    for (int cb = 0; cb < 2; ++cb) {
+                    for (int cb = 0; cb < NA; ++cb) {
                         const int c = ecol0 + 32 * cb;
-                        const float p = (acc[rb][cb][v] * sc[rb][cb]) * ri;
+                        const float p = (raw(rb, cb, v) * sc[rb][cb]) * ri;
                         if (b < batch && tc < ld.n_tc && c < ld.Q) {
                             const long long i = lag_atom(ld, tc, c);
                             if (i >= ctl.dump_begin && i < ctl.dump_begin + ctl.dump_count)
@@ -889,7 +904,7 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 1) k_search_lag_rs(GridDev g, L
 #pragma unroll
                 for (int rb = 0; rb < RS_TB; ++rb)
 #pragma unroll
-                    for (int cb = 0; cb < 2; ++cb) m = fmaxf(m, fabsf(acc[rb][cb][v] * sc[rb][cb]));
+                    for (int cb = 0; cb < NA; ++cb) m = fmaxf(m, fabsf(raw(rb, cb, v) * sc[rb][cb]));
                 m = half_wave_max(m);
                 if ((elane & 31) == 31) S.um[w][lg_row(v, elane)] = m;
             }
@@ -996,7 +1011,7 @@ __global__ void __launch_bounds__(RS_FL_TB) k_lag_rs_flag(LagDev ld, SearchCtl c
 constexpr int RS_EP = 16;  // pass 1: k-step parts of a pair (one wave each, 64 columns)
 constexpr int RS_EK = 2;   // pass 1: k-steps whose operands a wave loads before their MFMAs
 
-template <bool BF>
+template <bool BF, bool CPLX>
 __global__ void __launch_bounds__(64 * RS_EP) k_lag_rs_emit(LagDev ld, SearchCtl ctl, const int* __restrict__ units,
                                                            int n_tg, const int* __restrict__ pairs) {
     __shared__ float part[RS_EP][RS_TB * 64];
@@ -1004,7 +1019,10 @@ __global__ void __launch_bounds__(64 * RS_EP) k_lag_rs_emit(LagDev ld, SearchCtl
     __shared__ int s_base;
     const int U = 8 * ld.rs_cp_per_x * n_tg;
     const int lane = threadIdx.x & 63, part_i = threadIdx.x >> 6;
-    const int t = threadIdx.x, rb_t = t >> 6, c = t & 63;  // score (rb_t, c) of threads t < 4 x 64
+    // score (rb_t, c) of threads t < NS: 4 time centres x 64 columns, or x 32
+    // complex atoms (their cos and sin columns c and 32 + c)
+    constexpr int NS = RS_TB * (CPLX ? 32 : 64);
+    const int t = threadIdx.x, rb_t = CPLX ? t >> 5 : t >> 6, c = CPLX ? t & 31 : t & 63;
     // A fragment: lane row lane % 32 (time centre rb of the unit when below
     // RS_TB, else a zero row), lags 8 (lane / 32) .. + 8 of each k-step
     const int arow = lane & 31, ahalf = lane >> 5;
@@ -1020,8 +1038,8 @@ __global__ void __launch_bounds__(64 * RS_EP) k_lag_rs_emit(LagDev ld, SearchCtl
         // what the epilogue needs, requested before the k-steps
         const float T = rs_threshold(ctl, b);
         const float rs = ld.rscale[b], ri = rs > 0.0f ? 1.0f / rs : 0.0f;
-        const int tc = tc0 + rb_t, col = cp * 64 + c;
-        const float sc = t < RS_TB * 64 && tc < ld.n_tc ? ld.inv[(size_t)tc * ld.Qp + col] : 0.0f;
+        const int tc = tc0 + rb_t, col = cp * (CPLX ? 32 : 64) + c;
+        const float sc = t < NS && tc < ld.n_tc ? ld.inv[(size_t)tc * ld.Qp + col] : 0.0f;
         // time centre rb's window in the search copy's row b starts at
         // element b stride + 16 kb + m_rb (sample 16 kb - N_pad + m_rb); the
         // unit's descriptor holds glo - N_pad + m_rb + 16 kb (lag plans keep
@@ -1075,10 +1093,21 @@ __global__ void __launch_bounds__(64 * RS_EP) k_lag_rs_emit(LagDev ld, SearchCtl
         bool hit = false;
         unsigned pos = 0u;
         float p = 0.0f;
-        if (t < RS_TB * 64) {
-            float raw = part[0][t];
+        if (t < NS) {
+            float raw;
+            if constexpr (CPLX) {
+                float a = part[0][rb_t * 64 + c], bq = part[0][rb_t * 64 + 32 + c];
 #pragma unroll
-            for (int i = 1; i < RS_EP; ++i) raw += part[i][t];
+                for (int i = 1; i < RS_EP; ++i) {
+                    a += part[i][rb_t * 64 + c];
+                    bq += part[i][rb_t * 64 + 32 + c];
+                }
+                raw = sqrtf(a * a + bq * bq);
+            } else {
+                raw = part[0][t];
+#pragma unroll
+                for (int i = 1; i < RS_EP; ++i) raw += part[i][t];
+            }
             p = (raw * sc) * ri;
             hit = fabsf(p) >= T && tc < ld.n_tc && col < ld.Q;
             if (hit) pos = atomicAdd(&s_cnt, 1u);
@@ -1256,11 +1285,12 @@ static std::vector<int> lag_block_order(const std::vector<int2>& span, int Q, in
 
 // Resident-residual form, at plan time: the LDS copy's guards (every lag a
 // unit reads, its k-steps padded to RS_U), and the column pairs by decreasing
-// band dealt round-robin to the 8 XCDs.  The form is left out (lag_rs_cp
-// null) for complex atoms, ragged plans, time centres off multiples of 8
-// samples (16-byte LDS reads) or copies that do not fit one workgroup's LDS.
+// band dealt round-robin to the 8 XCDs (complex atoms: a column pair is the
+// cos and sin blocks of 32 atoms).  The form is left out (lag_rs_cp null) for
+// ragged plans, time centres off multiples of 8 samples (16-byte LDS reads)
+// or copies that do not fit one workgroup's LDS.
 static act_status prepare_lag_rs(act_plan_s* p, const std::vector<int2>& span, hipStream_t s) {
-    if (p->desc.complex_atoms || p->desc.ragged) return ACT_OK;
+    if (p->desc.ragged) return ACT_OK;
     const int n_tc = p->grid.cnt[0], n = p->grid.n, n_pad = p->n_pad;
     const std::vector<int>& sh = p->tc_shift_host;
     int spread = 0;
@@ -1508,7 +1538,7 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
         const int per = 8 * n_cg, cus = device_cus();
         const dim3 grid((unsigned)((cus + per - 1) / per * per)), blk(64 * RS_WAVES);
         const size_t dyn = (size_t)RS_CH * ld.rs_stride * 2 + sizeof(RsScratch);
-        const bool bf = p->desc.prec == ACT_PREC_BF16;
+        const bool bf = p->desc.prec == ACT_PREC_BF16, cx = p->desc.complex_atoms != 0;
         ld.rs_map = p->lag_rs_map;
         // pass 0 builds the max map (and clears pass 1's list), pass 1 lists
         // the flagged pairs and emits from them
@@ -1522,24 +1552,31 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
             hipLaunchKernelGGL(k_lag_rs_flag, dim3((unsigned)std::min<long long>((n + RS_FL_CHUNK - 1) / RS_FL_CHUNK, cus)), dim3(RS_FL_TB),
                                0, s, ld, ctl, batch, n_cg, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
+            // (BF16 lag tables hold real atoms only)
             if (bf)
-                hipLaunchKernelGGL((k_lag_rs_emit<true>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
+                hipLaunchKernelGGL((k_lag_rs_emit<true, false>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
+                                   p->lag_rs_units, n_tg, p->lag_rs_pairs);
+            else if (cx)
+                hipLaunchKernelGGL((k_lag_rs_emit<false, true>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
                                    p->lag_rs_units, n_tg, p->lag_rs_pairs);
             else
-                hipLaunchKernelGGL((k_lag_rs_emit<false>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
+                hipLaunchKernelGGL((k_lag_rs_emit<false, false>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
                                    p->lag_rs_units, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
             return ACT_OK;
         }
-#define RS_LAUNCH(D, B)                                                                                        \
-    hipLaunchKernelGGL((k_search_lag_rs<D, B>), grid, blk, dyn, s, p->grid, ld, ctl, p->lag_rs_units, batch, n_cg, \
-                       n_tg)
+#define RS_LAUNCH(D, B, C)                                                                                        \
+    hipLaunchKernelGGL((k_search_lag_rs<D, B, C>), grid, blk, dyn, s, p->grid, ld, ctl, p->lag_rs_units, batch, \
+                       n_cg, n_tg)
         if (bf) {
-            if (ctl.dump) RS_LAUNCH(true, true);
-            else RS_LAUNCH(false, true);
+            if (ctl.dump) RS_LAUNCH(true, true, false);
+            else RS_LAUNCH(false, true, false);
+        } else if (cx) {
+            if (ctl.dump) RS_LAUNCH(true, false, true);
+            else RS_LAUNCH(false, false, true);
         } else {
-            if (ctl.dump) RS_LAUNCH(true, false);
-            else RS_LAUNCH(false, false);
+            if (ctl.dump) RS_LAUNCH(true, false, false);
+            else RS_LAUNCH(false, false, false);
         }
 #undef RS_LAUNCH
         ACT_HIP(hipGetLastError());

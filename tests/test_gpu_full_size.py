@@ -276,14 +276,15 @@ def test_correlate_full_size_elementwise(corr_inputs, prec, dict_, cut, cplx, ch
           f"max |p - p_oracle| / |r| = {worst:.3e}")
 
 
-@pytest.mark.parametrize("prec,tol", [("f16", 1.5e-3), ("bf16", 8.2e-3)])
-def test_correlate_full_size_lag_forms(corr_inputs, prec, tol):
+@pytest.mark.parametrize("prec,cplx,tol", [("f16", False, 1.5e-3), ("bf16", False, 8.2e-3), ("f16", True, 2.5e-3)])
+def test_correlate_full_size_lag_forms(corr_inputs, prec, cplx, tol):
     """The 64-channel lag-table search in its staged-tile form (the
     autotuner's alternative to the resident form) element by element against
-    the oracle on the same ranges, and bit-identical to the resident form."""
+    the oracle on the same ranges, and bit-identical to the resident form
+    (real and complex atoms)."""
     wl, ranges, ref = corr_inputs
-    plan = A().Plan(wl.grid, dict_="lag", prec=prec, max_batch=64)
-    for (begin, count), p_ref in zip(ranges, ref[False]):
+    plan = A().Plan(wl.grid, dict_="lag", prec=prec, max_batch=64, complex_atoms=cplx)
+    for (begin, count), p_ref in zip(ranges, ref[cplx]):
         plan.act_set_launch_shape(64, grid_per_cu=2, form=1)
         staged = plan.act_correlate(wl.signals, begin, count).cpu().numpy()
         plan.act_set_launch_shape(64, grid_per_cu=1, form=0)
