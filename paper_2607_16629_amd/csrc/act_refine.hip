@@ -30,6 +30,7 @@ struct PlanDev {
     const int* len;          // ragged plans: channel lengths and offsets
     const long long* off;
     int* items;              // ragged synthesised plans: tile queue (counters after [B])
+    const int* by_length;    // ragged lag and FP16 plans: the call's channels by decreasing length
     int batch;
     float* rscale;           // ACT_PREC_F16: [B] power-of-two scale of the FP16 search copy
     double* ebmul;           // ACT_PREC_F16: [B] per-atom bound factor
@@ -63,6 +64,9 @@ static PlanDev view(const act_plan_s* p) {
     v.len = p->call_len;
     v.off = p->call_off;
     v.items = p->items;
+    // filled by the call's ragged set-up for lag-table and FP16 plans only
+    v.by_length = p->desc.ragged && (p->desc.dict == ACT_DICT_LAG || p->desc.prec == ACT_PREC_F16) ? p->perm
+                                                                                                  : nullptr;
     v.batch = 0;
     v.rscale = p->rscale;
     v.ebmul = p->ebmul;
@@ -473,7 +477,7 @@ __device__ __forceinline__ void walk_chirp(int k0, int k1, double fs, const doub
 // certified margin, and below the 1e-6 relative gap at which selections are
 // held to the exact arg-max.
 __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __restrict__ resid) {
-    const int b = blockIdx.y;
+    const int b = P.by_length ? P.by_length[blockIdx.y] : (int)blockIdx.y;  // uneven batches: longest first
     const double eb = P.ebound[b];
     if (eb < 0.0) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -482,40 +486,51 @@ __global__ void __launch_bounds__(256) k_rescore(PlanDev P, const double* __rest
     const double T = P.per_atom ? (double)bitsf(P.gmax[b]) : (double)bitsf(P.gmax[b]) - 2.0 * eb;
     const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
     const double* r = resid + cg.off;
-    const int wpb = blockDim.x / kWave;
-    for (int j = blockIdx.x * wpb + threadIdx.x / kWave; j < cnt; j += gridDim.x * wpb) {
-        const size_t slot = (size_t)b * P.cap + j;
-        if ((double)fabsf(P.cand_score[slot]) < T) {
-            if (lane == 0) P.cand_p64[slot] = __longlong_as_double(0x7ff8000000000000LL);
-            continue;
+    const int wpb = blockDim.x / kWave, stride = gridDim.x * wpb;
+    // wave w takes the list entries w, w + stride, ...: its lanes test the
+    // next 64 of them against T at once (marking those below it), then the
+    // wave rescores the ones that pass, in list order
+    for (int j0 = blockIdx.x * wpb + threadIdx.x / kWave; j0 < cnt; j0 += stride * kWave) {
+        const int jl = j0 + stride * lane;
+        bool keep = false;
+        if (jl < cnt) {
+            const size_t sl = (size_t)b * P.cap + jl;
+            keep = !((double)fabsf(P.cand_score[sl]) < T);
+            if (!keep) P.cand_p64[sl] = __longlong_as_double(0x7ff8000000000000LL);
         }
-        double th[4];
-        grid_theta(cg.g, (long long)P.cand_idx[slot], th);
-        const double inv_dt = 1.0 / exp(th[3]);
-        double s = 0.0, q = 0.0, sb = 0.0;
-        // the atom's support window: the samples beyond it add below
-        // 2.6e-18 sqrt(n) |r| to the score (|g| >= 1), under FP64 rounding
-        int k0, k1;
-        support_window(cg.g.n, cg.g.fs, th, k0, k1);
-        if (P.cplx) {
-            walk_chirp<kWave>(k0, k1, cg.g.fs, th, inv_dt, [&](int k, double, double re, double im) {
-                const double rk = r[k];
-                s += re * rk;
-                sb += im * rk;
-                q += re * re + im * im;
-            });
-            sb = wave_sum(sb);
-        } else {
-            walk_chirp<kWave>(k0, k1, cg.g.fs, th, inv_dt, [&](int k, double, double v, double) {
-                const double rk = r[k];
-                s += v * rk;
-                q += v * v;
-            });
+        unsigned long long pend = __ballot(keep);
+        while (pend) {
+            const int l = __ffsll(pend) - 1;
+            pend &= pend - 1ull;
+            const size_t slot = (size_t)b * P.cap + (j0 + stride * l);
+            double th[4];
+            grid_theta(cg.g, (long long)P.cand_idx[slot], th);
+            const double inv_dt = 1.0 / exp(th[3]);
+            double s = 0.0, q = 0.0, sb = 0.0;
+            // the atom's support window: the samples beyond it add below
+            // 2.6e-18 sqrt(n) |r| to the score (|g| >= 1), under FP64 rounding
+            int k0, k1;
+            support_window(cg.g.n, cg.g.fs, th, k0, k1);
+            if (P.cplx) {
+                walk_chirp<kWave>(k0, k1, cg.g.fs, th, inv_dt, [&](int k, double, double re, double im) {
+                    const double rk = r[k];
+                    s += re * rk;
+                    sb += im * rk;
+                    q += re * re + im * im;
+                });
+                sb = wave_sum(sb);
+            } else {
+                walk_chirp<kWave>(k0, k1, cg.g.fs, th, inv_dt, [&](int k, double, double v, double) {
+                    const double rk = r[k];
+                    s += v * rk;
+                    q += v * v;
+                });
+            }
+            s = wave_sum(s);
+            q = wave_sum(q);
+            if (P.cplx) s = sqrt(s * s + sb * sb);
+            if (lane == 0) P.cand_p64[slot] = q > 0.0 ? s / sqrt(q) : 0.0;
         }
-        s = wave_sum(s);
-        q = wave_sum(q);
-        if (P.cplx) s = sqrt(s * s + sb * sb);
-        if (lane == 0) P.cand_p64[slot] = q > 0.0 ? s / sqrt(q) : 0.0;
     }
 }
 
@@ -1019,7 +1034,9 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
     __shared__ double red[block_sum_tr_lds(TB, 13)];
     __shared__ double s_a1[NWB], s_a2[NWB];
     __shared__ unsigned s_i1[NWB];
-    const int b = blockIdx.x;
+    // uneven batches: the longest channels take the first blocks, so that each
+    // starts at once and shares its compute unit with shorter ones
+    const int b = P.by_length ? P.by_length[blockIdx.x] : (int)blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const ChanGeom cg = chan_geom(P.g, b, P.len, P.off);
     const GridDev& G = cg.g;
@@ -1028,7 +1045,7 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
     const double eb = P.ebound[b];
     const size_t o = (size_t)b * order + k;
     // the search of this order has drained its tile queue: reset it for the next
-    if (b == 0 && threadIdx.x == 0 && P.items) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && P.items) {
         P.items[P.batch + 1] = 0;
         P.items[P.batch + 3] = 0;
     }
@@ -1057,17 +1074,28 @@ __global__ void __launch_bounds__(TB) k_select_refine_update(
         const int cnt_raw = P.cand_count[b];
         const int cnt = min(cnt_raw, P.cap);
         if (cnt_raw > P.cap) fl |= ACT_FLAG_CAND_OVERFLOW;
-        for (int j = threadIdx.x; j < cnt; j += TB) {
-            const double v = P.cand_p64[(size_t)b * P.cap + j];
-            if (isnan(v)) continue;
-            const double a = fabs(v);
-            const unsigned id = P.cand_idx[(size_t)b * P.cap + j];
-            if (a > a1 || (a == a1 && id < i1)) {
-                a2 = a1;
-                a1 = a;
-                i1 = id;
-            } else if (a > a2) {
-                a2 = a;
+        // SU entries per thread and step requested together (long lists of
+        // an uneven batch are mostly entries the rescoring marked NaN)
+        constexpr int SU = 8;
+        for (int j0 = threadIdx.x; j0 < cnt; j0 += SU * TB) {
+            double vv[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int j = j0 + u * TB;
+                vv[u] = j < cnt ? P.cand_p64[(size_t)b * P.cap + j] : __longlong_as_double(0x7ff8000000000000LL);
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                if (isnan(vv[u])) continue;
+                const double a = fabs(vv[u]);
+                const unsigned id = P.cand_idx[(size_t)b * P.cap + j0 + u * TB];
+                if (a > a1 || (a == a1 && id < i1)) {
+                    a2 = a1;
+                    a1 = a;
+                    i1 = id;
+                } else if (a > a2) {
+                    a2 = a;
+                }
             }
         }
     }
