@@ -108,7 +108,7 @@ typedef struct {
     int32_t prec;           /* ACT_PREC_* */
     int32_t max_batch;      /* most channels one call may pass (>= 1) */
     int32_t cand_cap;       /* candidate list capacity per channel; 0 = 4096 (16384 for BF16
-                               and FP16-synthesis plans, 131072 for ragged plans, 262144
+                               and FP16-synthesis plans, 131072 for ragged plans, 524288
                                for ragged lag plans) */
     int32_t refine_steps;   /* L-BFGS iterations per order in act_decompose; 0 = none */
     int32_t ragged;         /* 1: channels have their own lengths (len_dev/off_dev) and

@@ -466,12 +466,12 @@ extern "C" act_status act_plan(const act_plan_desc* desc, void* stream, act_plan
     // many grid neighbours inside the certified margin, and rescoring them
     // costs far less than a rerun of the search
     // (the ragged lag table's rows near a signal's end emit by a widened bound:
-    // a longer list, 4 MiB per channel, spares most exact-threshold reruns, as
+    // a longer list, 8 MiB per channel, spares the exact-threshold reruns, as
     // 2 MiB do for the ragged synthesis and its per-atom bounds; the
     // BF16 searches' margin (unit roundoff 2^-8) is 8x FP16's, and the FP16
     // synthesis' support cut widens its per-atom bounds)
     p->cap = desc->cand_cap > 0 ? desc->cand_cap
-             : desc->ragged     ? (desc->dict == ACT_DICT_LAG ? 262144 : 131072)
+             : desc->ragged     ? (desc->dict == ACT_DICT_LAG ? 524288 : 131072)
              : (desc->prec == ACT_PREC_BF16 || (desc->prec == ACT_PREC_F16 && desc->dict == ACT_DICT_SYNTH))
                  ? 16384
                  : 4096;

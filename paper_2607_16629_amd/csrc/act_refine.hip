@@ -702,33 +702,45 @@ __device__ __forceinline__ double dot4(const double* a, const double* b) {
 template <int TB>
 __device__ void sums_obj_cplx(const double* __restrict__ r, int n, double fs, const double th[4],
                               double (&acc)[13], double* red) {
+    // as for real atoms, the sums regroup into moments M_m(x) = sum x tau^m
+    // (m = 0, 1, 2) of x in {r E cos phi, r E sin phi, E^2}, with E cos phi
+    // and E sin phi from the chirp walk (E^2 = their squares' sum):
+    //   da_tc = M_1(rC)/dt^2 + 2 pi (2 c M_1(rS) + f_c M_0(rS)),
+    //   da_fc = -2 pi M_1(rS), da_c = -2 pi M_2(rS), da_logdt = M_2(rC)/dt^2,
+    //   db_tc = M_1(rS)/dt^2 - 2 pi (2 c M_1(rC) + f_c M_0(rC)),
+    //   db_fc = 2 pi M_1(rC), db_c = 2 pi M_2(rC), db_logdt = M_2(rS)/dt^2,
+    //   dq_tc = 2 M_1(E^2)/dt^2, dq_logdt = 2 M_2(E^2)/dt^2.
     const double inv_dt = 1.0 / exp(th[3]);
-    const double idt2 = inv_dt * inv_dt;
-    const double fc = th[1], c = th[2];
-#pragma unroll
-    for (int j = 0; j < 13; ++j) acc[j] = 0.0;
     int k0, k1;
     support_window(n, fs, th, k0, k1);
-    walk_atom<TB>(k0, k1, fs, th, inv_dt, [&](int k, double tau, double e, double co, double si) {
-        const double rk = r[k];
-        const double de0 = e * tau * idt2, de3 = e * tau * tau * idt2;
-        const double dp0 = -kTwoPi * (2.0 * c * tau + fc), dp1 = kTwoPi * tau, dp2 = kTwoPi * tau * tau;
-        const double ec = e * co, es = e * si;
-        acc[0] += rk * ec;
-        acc[1] += rk * es;
-        acc[2] += e * e;
-        acc[3] += rk * (co * de0 - es * dp0);
-        acc[4] += rk * (-es * dp1);
-        acc[5] += rk * (-es * dp2);
-        acc[6] += rk * (co * de3);
-        acc[7] += rk * (si * de0 + ec * dp0);
-        acc[8] += rk * (ec * dp1);
-        acc[9] += rk * (ec * dp2);
-        acc[10] += rk * (si * de3);
-        acc[11] += 2.0 * e * de0;
-        acc[12] += 2.0 * e * de3;
+    double m[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) m[j] = 0.0;
+    walk_chirp<TB>(k0, k1, fs, th, inv_dt, [&](int k, double tau, double gc, double gs) {
+        const double rk = r[k], t2 = tau * tau;
+        const double x[3] = {rk * gc, rk * gs, gc * gc + gs * gs};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            m[3 * q] += x[q];
+            m[3 * q + 1] = fma(x[q], tau, m[3 * q + 1]);
+            m[3 * q + 2] = fma(x[q], t2, m[3 * q + 2]);
+        }
     });
-    block_sum_tr<TB, 13>(acc, red);
+    block_sum_tr<TB, 9>(m, red);
+    const double idt2 = inv_dt * inv_dt, c2 = 2.0 * th[2], fc = th[1];
+    acc[0] = m[0];
+    acc[1] = m[3];
+    acc[2] = m[6];
+    acc[3] = m[1] * idt2 + kTwoPi * (c2 * m[4] + fc * m[3]);
+    acc[4] = -kTwoPi * m[4];
+    acc[5] = -kTwoPi * m[5];
+    acc[6] = m[2] * idt2;
+    acc[7] = m[4] * idt2 - kTwoPi * (c2 * m[1] + fc * m[0]);
+    acc[8] = kTwoPi * m[1];
+    acc[9] = kTwoPi * m[2];
+    acc[10] = m[5] * idt2;
+    acc[11] = 2.0 * m[7] * idt2;
+    acc[12] = 2.0 * m[8] * idt2;
 }
 
 // Coordinate scales for complex atoms: the metric of the unit complex atom
