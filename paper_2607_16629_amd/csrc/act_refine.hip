@@ -940,6 +940,7 @@ __device__ int refine_block(const RT* __restrict__ r, const GridDev& g, const Bo
 #pragma unroll
     for (int t = 0; t < 8; ++t) S[t] = Y[t] = RHO[t] = 0.0;
     int nmem = 0;
+    double gam = 1.0;  // H0 = gam I: s'y / y'y of the newest pair, formed when it is stored
     for (int it = 0; it < steps; ++it) {
         double pgj = gj;
         if (uj <= bloj && gj > 0.0) pgj = 0.0;
@@ -958,7 +959,7 @@ __device__ int refine_block(const RT* __restrict__ r, const GridDev& g, const Bo
                 dj -= a * Y[t];
             }
         }
-        if (nmem > 0) dj *= quad_sum(S[0] * Y[0]) / quad_sum(Y[0] * Y[0]);
+        if (nmem > 0) dj *= gam;
 #pragma unroll
         for (int t = 7; t >= 0; --t) {
             if (t < nmem) {
@@ -992,8 +993,8 @@ __device__ int refine_block(const RT* __restrict__ r, const GridDev& g, const Bo
         }
         if (!ok) break;
         const double svj = unj - uj, yvj = gnj - gj;
-        const double sy = quad_sum(svj * yvj);
-        if (sy > 1e-12 * sqrt(quad_sum(svj * svj)) * sqrt(quad_sum(yvj * yvj))) {
+        const double sy = quad_sum(svj * yvj), yy = quad_sum(yvj * yvj);
+        if (sy > 1e-12 * sqrt(quad_sum(svj * svj)) * sqrt(yy)) {
 #pragma unroll
             for (int t = 7; t > 0; --t) {
                 S[t] = S[t - 1];
@@ -1003,6 +1004,7 @@ __device__ int refine_block(const RT* __restrict__ r, const GridDev& g, const Bo
             S[0] = svj;
             Y[0] = yvj;
             RHO[0] = 1.0 / sy;
+            gam = sy / yy;
             if (nmem < 8) ++nmem;
         }
         uj = unj;
