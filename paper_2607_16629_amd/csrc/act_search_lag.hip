@@ -1028,10 +1028,20 @@ __global__ void __launch_bounds__(64 * RS_EP) k_lag_rs_emit(LagDev ld, SearchCtl
     const int arow = lane & 31, ahalf = lane >> 5;
     const f16x8 zero8 = {};
     const int np = pairs[0];
-    int e_next = blockIdx.x < np ? pairs[1 + blockIdx.x] : 0;
-    for (int q = blockIdx.x; q < np; q += gridDim.x) {
+    // The flag pass lists each 2048-entry chunk of the map (four column pairs
+    // of one channel group) as one run, and flagged pairs crowd onto few
+    // column pairs (late BF16 orders: 3,919 pairs on 457).  Each XCD takes one
+    // eighth of the list as a contiguous segment, its workgroups the
+    // segment's pairs in turn, so the pairs of a column pair run together
+    // and share its band in that XCD's L2.  (The grid is a multiple of 8:
+    // workgroup w runs on XCD w mod 8.)
+    const int xcd = blockIdx.x & 7, J = (int)gridDim.x >> 3;
+    const int q_lo = (int)((long long)np * xcd / 8), q_hi = (int)((long long)np * (xcd + 1) / 8);
+    const int q0 = q_lo + (int)(blockIdx.x >> 3);
+    int e_next = q0 < q_hi ? pairs[1 + q0] : 0;
+    for (int q = q0; q < q_hi; q += J) {
         const int e = e_next, ch = e % RS_CH, sl = e / RS_CH;
-        if (q + (int)gridDim.x < np) e_next = pairs[1 + q + gridDim.x];  // the next pair's entry, early
+        if (q + J < q_hi) e_next = pairs[1 + q + J];  // the next pair's entry, early
         const int cg = sl / U, us = sl - cg * U, b = cg * RS_CH + ch;
         const int* d = units + (size_t)us * RS_UD;
         const int cp = d[0], tc0 = d[1], kb = d[2], nk = d[3];
@@ -1552,15 +1562,17 @@ act_status launch_search_lag(act_plan_s* p, int batch, const SearchCtl& ctl, hip
             hipLaunchKernelGGL(k_lag_rs_flag, dim3((unsigned)std::min<long long>((n + RS_FL_CHUNK - 1) / RS_FL_CHUNK, cus)), dim3(RS_FL_TB),
                                0, s, ld, ctl, batch, n_cg, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
-            // (BF16 lag tables hold real atoms only)
+            // (BF16 lag tables hold real atoms only); the emission grid is a
+            // multiple of 8: its workgroups split the list by XCD
+            const unsigned emit_grid = (unsigned)((2 * cus + 7) / 8 * 8);
             if (bf)
-                hipLaunchKernelGGL((k_lag_rs_emit<true, false>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
+                hipLaunchKernelGGL((k_lag_rs_emit<true, false>), dim3(emit_grid), dim3(64 * RS_EP), 0, s, ld, ctl,
                                    p->lag_rs_units, n_tg, p->lag_rs_pairs);
             else if (cx)
-                hipLaunchKernelGGL((k_lag_rs_emit<false, true>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
+                hipLaunchKernelGGL((k_lag_rs_emit<false, true>), dim3(emit_grid), dim3(64 * RS_EP), 0, s, ld, ctl,
                                    p->lag_rs_units, n_tg, p->lag_rs_pairs);
             else
-                hipLaunchKernelGGL((k_lag_rs_emit<false, false>), dim3(2 * cus), dim3(64 * RS_EP), 0, s, ld, ctl,
+                hipLaunchKernelGGL((k_lag_rs_emit<false, false>), dim3(emit_grid), dim3(64 * RS_EP), 0, s, ld, ctl,
                                    p->lag_rs_units, n_tg, p->lag_rs_pairs);
             ACT_HIP(hipGetLastError());
             return ACT_OK;
