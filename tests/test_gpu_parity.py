@@ -482,6 +482,27 @@ def test_small_candidate_capacity_reruns_exactly(oracle, prec, dict_, cap):
     assert_decomposition_parity(gpu, ref, wl.grid, oracle, wl.signals, prec, 0)
 
 
+def test_resident_lag_form_small_capacity():
+    """The resident lag form has no rerun pass: its second pass lists exactly
+    the certified set.  A 64-entry list (FP16 lag table, 40 channels) must
+    then hold every channel's set without overflow, and the decomposition
+    must be bit-identical to the one with the default 16384-entry lists."""
+    act = A()
+    g = W.eeg_grid(1024, 32, 16, 8, 6)
+    wl = W.batched_64x2048(channels=40, grid=g, order=4)
+    res = {}
+    for cap in (0, 64):
+        plan = act.Plan(g, dict_="lag", prec="f16", max_batch=40, refine_steps=30, cand_cap=cap)
+        assert plan.query(act.Q_LAG_RESIDENT) == 1
+        out = plan.decompose(torch.from_numpy(wl.signals), 4)
+        torch.cuda.synchronize()
+        res[cap] = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+        plan.close()
+    assert np.all(res[64]["flags"] & act.FLAG_CAND_OVERFLOW == 0), res[64]["flags"]
+    for k in res[0]:
+        np.testing.assert_array_equal(res[0][k], res[64][k], err_msg=k)
+
+
 @pytest.mark.parametrize("prec,dict_", [("bf16", "table"), ("f16", "synth"), ("f16", "lag"), ("bf16", "lag")])
 def test_batch_of_70_channels(oracle, prec, dict_):
     """More than one 64-channel tile, a reduced grid; the oracle checks a
